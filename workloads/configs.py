@@ -1,0 +1,282 @@
+"""Seeded synthetic programs for the benchmark configurations and the tests.
+
+Every random draw uses ``numpy.random.default_rng([220813707, config, rank,
+step])`` (PCG64), so the oracle and the GPU path see the same bytes.  Nothing
+here computes a result of the method: these functions only lay out buffers
+and the operations each rank issues.
+
+Configurations (one MI355X; ranks are host threads):
+  1  ping-pong: 2 ranks, 1000 blocking messages of 1024 int32 (uniform over
+     the full int32 range), tag 0, one communicator.
+  2  ring halo: 8 ranks; per rank A, H float32[count * 8] ~ N(0, 1);
+     datatype vector(count, 3, 8, float32); per step s (tag s) each rank
+     isends columns 0..2 of A to its right neighbour and columns 3..5 to its
+     left neighbour and receives them into H; count in {2730, 5461, 10922,
+     21845, 43690} (payload 32,760 .. 524,280 bytes).
+  3  allreduce: 16 ranks, SUM on int64 (uniform in [-2^40, 2^40]) and float32
+     (~ N(0, 1)), 4 KiB, 1 MiB and 64 MiB per rank.
+  4  batch: 32 ranks, 10,000 send/recv pairs, bytes log-uniform in
+     [8, 262144], tags uniform in 0..63, 30 % vector datatypes.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Optional
+
+import numpy as np
+
+from .program import (
+    IN_PLACE, Allreduce, Program, Recv, Send, User, Wait, as_bytes, footprint_bound,
+    single_stream,
+)
+
+SEED = 220813707
+
+HALO_COUNTS = (2730, 5461, 10922, 21845, 43690)
+ALLREDUCE_BYTES = (4 * 1024, 1024 * 1024, 64 * 1024 * 1024)
+
+
+def rng(config: int, rank: int = 0, step: int = 0) -> np.random.Generator:
+    return np.random.default_rng([SEED, config, rank, step])
+
+
+# --------------------------------------------------------------------------- 1
+def pingpong(nmsg: int = 1000, n: int = 1024, increment: bool = False,
+             seed_config: int = 1) -> Program:
+    """Config 1: rank 0 sends x to rank 1 and receives it back; rank 1 does
+    the reverse.  With ``increment`` rank 1 adds 1 to every element between
+    its receive and its send (a user kernel on its stream)."""
+    assert nmsg % 2 == 0
+    x0 = rng(seed_config, 0).integers(-2**31, 2**31, size=n, dtype=np.int64).astype(np.int32)
+    bufs = [{"x": as_bytes(x0)}, {"x": np.zeros(4 * n, dtype=np.uint8)}]
+    r0, r1 = [], []
+    for _ in range(nmsg // 2):
+        r0 += [Send("x", 0, n, "int32", 1, 0), Recv("x", 0, n, "int32", 1, 0)]
+        r1 += [Recv("x", 0, n, "int32", 0, 0)]
+        if increment:
+            r1 += [User(("add_const_i32", "x", 0, n, 1))]
+        r1 += [Send("x", 0, n, "int32", 0, 0)]
+    return single_stream(2, bufs, [r0, r1], name=f"pingpong_{nmsg}x{n}")
+
+
+# --------------------------------------------------------------------------- 2
+def halo_type(count: int):
+    return ("vector", count, 3, 8, "float32")
+
+
+def ring_halo(count: int = 2730, steps: int = 100, nranks: int = 8,
+              update: bool = False, blocking_recv: bool = True) -> Program:
+    """Config 2: bidirectional ring halo exchange with a vector datatype."""
+    vt = halo_type(count)
+    bufs, ops = [], []
+    for r in range(nranks):
+        g = rng(2, r)
+        a = g.standard_normal(count * 8, dtype=np.float32)
+        h = g.standard_normal(count * 8, dtype=np.float32)
+        bufs.append({"A": as_bytes(a), "H": as_bytes(h)})
+        right, left = (r + 1) % nranks, (r - 1) % nranks
+        lst = []
+        for s in range(steps):
+            lst += [Send("A", 0, 1, vt, right, s, req=f"s{s}a"),
+                    Send("A", 12, 1, vt, left, s, req=f"s{s}b")]
+            if blocking_recv:
+                lst += [Recv("H", 0, 1, vt, left, s, status=f"st{s}a"),
+                        Recv("H", 12, 1, vt, right, s, status=f"st{s}b")]
+                lst += [Wait([f"s{s}a", f"s{s}b"], [None, None])]
+            else:
+                lst += [Recv("H", 0, 1, vt, left, s, req=f"r{s}a"),
+                        Recv("H", 12, 1, vt, right, s, req=f"r{s}b")]
+                lst += [Wait([f"s{s}a", f"s{s}b", f"r{s}a", f"r{s}b"],
+                             [None, None, f"st{s}a", f"st{s}b"])]
+            if update:
+                lst += [User(("add_rows_f32", "A", 0, "H", 0, count, 8, 0, 6))]
+        ops.append(lst)
+    return single_stream(nranks, bufs, ops, name=f"ring_halo_{nranks}r_c{count}_s{steps}")
+
+
+# --------------------------------------------------------------------------- 3
+def allreduce(nbytes: int, dtype: str = "int64", nranks: int = 16, calls: int = 1,
+              op: str = "sum", in_place: bool = False) -> Program:
+    """Config 3: ``calls`` allreduces of ``nbytes`` per rank."""
+    esize = {"int32": 4, "int64": 8, "float32": 4, "float64": 8}[dtype]
+    count = nbytes // esize
+    bufs, ops = [], []
+    for r in range(nranks):
+        g = rng(3, r)
+        if dtype in ("int64", "int32"):
+            lim = 2**40 if dtype == "int64" else 2**30
+            x = g.integers(-lim, lim + 1, size=count, dtype=np.int64).astype(dtype)
+        else:
+            x = g.standard_normal(count).astype(dtype)
+        if in_place:
+            bufs.append({"recv": as_bytes(x)})
+            ops.append([Allreduce(IN_PLACE, 0, "recv", 0, count, dtype, op)
+                        for _ in range(calls)])
+        else:
+            bufs.append({"send": as_bytes(x), "recv": np.zeros(nbytes, np.uint8)})
+            ops.append([Allreduce("send", 0, "recv", 0, count, dtype, op)
+                        for _ in range(calls)])
+    return single_stream(nranks, bufs, ops, name=f"allreduce_{nranks}r_{dtype}_{nbytes}B")
+
+
+# --------------------------------------------------------------------------- 4
+def batch_messages(npairs: int = 10000, nranks: int = 32, max_bytes: int = 262144,
+                   min_bytes: int = 8, vec_frac: float = 0.3, seed_config: int = 4):
+    """Config 4 message list: (src, dst, tag, dtype tree, count, nbytes)."""
+    g = rng(seed_config, 0)
+    msgs = []
+    for _ in range(npairs):
+        src = int(g.integers(nranks))
+        dst = int(g.integers(nranks - 1))
+        dst = dst + 1 if dst >= src else dst
+        tag = int(g.integers(64))
+        nbytes = int(math.floor(math.exp(g.uniform(math.log(min_bytes), math.log(max_bytes)))))
+        if g.uniform() < vec_frac:
+            bl = int(g.integers(1, 17))
+            base = "float32" if g.uniform() < 0.5 else "int32"
+            c = max(1, -(-nbytes // (4 * bl)))
+            tree = ("vector", c, bl, 2 * bl, base)
+            size = 4 * bl * c
+        else:
+            base = ("uint8", "int32", "float32")[int(g.integers(3))]
+            es = 1 if base == "uint8" else 4
+            c = max(1, nbytes // es)
+            tree = base
+            size = c * es
+        count = 1 if isinstance(tree, tuple) else c
+        msgs.append(dict(src=src, dst=dst, tag=tag, tree=tree, count=count,
+                         size=size, foot=footprint_bound(tree, count)))
+    return msgs
+
+
+def batch(npairs: int = 10000, nranks: int = 32, max_bytes: int = 262144,
+          min_bytes: int = 8) -> Program:
+    """Config 4: every rank isends all its messages in global order, then
+    irecvs all its messages in global order, then waits for all of them."""
+    msgs = batch_messages(npairs, nranks, max_bytes, min_bytes)
+    send_off = [0] * nranks
+    recv_off = [0] * nranks
+    ops: List[list] = [[] for _ in range(nranks)]
+    recvs: List[list] = [[] for _ in range(nranks)]
+    align = 256
+    for i, m in enumerate(msgs):
+        s, d = m["src"], m["dst"]
+        ops[s].append(Send("sbuf", send_off[s], m["count"], m["tree"], d, m["tag"], req=f"s{i}"))
+        recvs[d].append(Recv("rbuf", recv_off[d], m["count"], m["tree"], s, m["tag"],
+                             req=f"r{i}"))
+        send_off[s] += -(-m["foot"] // align) * align
+        recv_off[d] += -(-m["foot"] // align) * align
+    bufs = []
+    for r in range(nranks):
+        g = rng(4, r, 1)
+        sb = g.integers(0, 256, size=max(send_off[r], 1), dtype=np.uint8)
+        rb = g.integers(0, 256, size=max(recv_off[r], 1), dtype=np.uint8)
+        bufs.append({"sbuf": sb, "rbuf": rb})
+        reqs = [o.req for o in ops[r]] + [o.req for o in recvs[r]]
+        stats = [None] * len(ops[r]) + [f"st_{o.req}" for o in recvs[r]]
+        ops[r] = ops[r] + recvs[r]
+        if reqs:
+            ops[r].append(Wait(reqs, stats))
+    return single_stream(nranks, bufs, ops, name=f"batch_{npairs}p_{nranks}r")
+
+
+# ------------------------------------------------------------------- examples
+def saxpy_example(n: int = 4096) -> Program:
+    """The paper's GPU enqueue example (§6): rank 0 sends x (all 1.0) to rank
+    1, which receives it and computes y = a*x + y with a = 2, y = 2."""
+    x = np.full(n, 1.0, np.float32)
+    y = np.full(n, 2.0, np.float32)
+    bufs = [{"x": as_bytes(x)},
+            {"x": np.zeros(4 * n, np.uint8), "y": as_bytes(y)}]
+    r0 = [Send("x", 0, n, "float32", 1, 0)]
+    r1 = [Recv("x", 0, n, "float32", 0, 0),
+          User(("saxpy_f32", "x", 0, "y", 0, n, 2.0))]
+    return single_stream(2, bufs, [r0, r1], name="saxpy")
+
+
+def threads_example(nthreads: int = 4, n: int = 100) -> Program:
+    """The paper's MPI+OpenMP example (§6): 2 ranks, each with ``nthreads``
+    streams and one stream communicator per stream; context i of rank 0
+    sends 100 chars to context i of rank 1."""
+    bufs = []
+    for r in range(2):
+        g = rng(6, r)
+        bufs.append({f"buf{i}": g.integers(0, 256, size=n, dtype=np.uint8)
+                     for i in range(nthreads)})
+    ops = [[[Send(f"buf{i}", 0, n, "uint8", 1, 0, comm=i)] for i in range(nthreads)],
+           [[Recv(f"buf{i}", 0, n, "uint8", 0, 0, comm=i)] for i in range(nthreads)]]
+    comm_streams = [[i, i] for i in range(nthreads)]
+    return Program(nranks=2, buffers=bufs, ops=ops, streams_per_rank=nthreads,
+                   comm_streams=comm_streams, name=f"threads_{nthreads}")
+
+
+# --------------------------------------------------------------- random safe
+def random_program(seed: int, nranks: int = 4, nmsg: int = 40, max_elems: int = 300,
+                   tags: int = 3, ncomms: int = 2, allreduces: int = 2,
+                   types: Optional[list] = None) -> Program:
+    """A random program that is safe under synchronous-send semantics.
+
+    Messages are drawn as (src, dst, comm, tag, datatype); each rank issues
+    its isends in message order, then its irecvs in message order, then
+    waits for all.  Allreduces are placed after the waits.  Send buffers are
+    read-only; every receive gets its own region of the receive buffer, and
+    the gaps between regions keep their initial bytes.
+    """
+    g = np.random.default_rng([SEED, 100, seed])
+    if types is None:
+        types = [
+            lambda n: ("int32", n),
+            lambda n: ("float32", n),
+            lambda n: ("uint8", n * 4),
+            lambda n: (("vector", max(1, n // 3), 3, 5, "int32"), 1),
+            lambda n: (("vector", max(1, n // 2), 2, 7, "float64"), 1),
+            lambda n: (("contiguous", 2, ("vector", max(1, n // 4), 1, 3, "int32")), 2),
+            lambda n: (("indexed", [3, 1, 4, 2], [0, 5, 7, 13], "int32"), max(1, n // 10)),
+            lambda n: (("vector", 2, 2, 3, ("indexed", [1, 2], [4, 0], "int64")), max(1, n // 12)),
+        ]
+    msgs = []
+    for i in range(nmsg):
+        s = int(g.integers(nranks))
+        d = int(g.integers(nranks))
+        if nranks > 1 and d == s and g.uniform() < 0.8:
+            d = (s + 1 + int(g.integers(nranks - 1))) % nranks
+        comm = int(g.integers(ncomms))
+        tag = int(g.integers(tags))
+        n = int(g.integers(0, max_elems + 1))
+        tree, cnt = types[int(g.integers(len(types)))](n)
+        msgs.append((s, d, comm, tag, tree, cnt))
+    send_off = [0] * nranks
+    recv_off = [0] * nranks
+    sends: List[list] = [[] for _ in range(nranks)]
+    recvs: List[list] = [[] for _ in range(nranks)]
+    for i, (s, d, comm, tag, tree, cnt) in enumerate(msgs):
+        foot = footprint_bound(tree, cnt)
+        sends[s].append(Send("sbuf", send_off[s], cnt, tree, d, tag, comm=comm, req=f"s{i}"))
+        recvs[d].append(Recv("rbuf", recv_off[d], cnt, tree, s, tag, comm=comm, req=f"r{i}"))
+        send_off[s] += foot + int(g.integers(0, 3)) * 8
+        recv_off[d] += foot + 16
+    bufs, ops = [], []
+    for r in range(nranks):
+        gr = np.random.default_rng([SEED, 100, seed, r])
+        red_n = 64
+        b = {"sbuf": gr.integers(0, 256, size=send_off[r] + 64, dtype=np.uint8),
+             "rbuf": gr.integers(0, 256, size=recv_off[r] + 64, dtype=np.uint8),
+             "ared": as_bytes(gr.integers(-2**40, 2**40, size=red_n, dtype=np.int64)),
+             "afl": as_bytes(gr.standard_normal(red_n).astype(np.float32)),
+             "aout": np.zeros(8 * red_n, np.uint8)}
+        bufs.append(b)
+        lst = sends[r] + recvs[r]
+        reqs = [o.req for o in lst]
+        if reqs:
+            # waits of one communicator's stream at a time
+            lst = list(lst)
+            lst.append(Wait(reqs, [f"st_{q}" if q.startswith("r") else None for q in reqs]))
+        for a in range(allreduces):
+            if a % 2 == 0:
+                lst.append(Allreduce("ared", 0, "aout", 0, red_n, "int64", "sum"))
+            else:
+                lst.append(Allreduce("afl", 0, "aout", 0, red_n, "float32", "sum"))
+        ops.append(lst)
+    return Program(nranks=nranks, buffers=bufs, ops=[[o] for o in ops], streams_per_rank=1,
+                   comm_streams=[[0] * nranks for _ in range(ncomms)],
+                   name=f"random_{seed}")
