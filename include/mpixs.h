@@ -1,0 +1,305 @@
+/*
+ * mpixs.h -- stream-ordered point-to-point and allreduce traffic enqueued on
+ * HIP streams of one MI355X (gfx950).
+ *
+ * This is the C ABI of libmpixs.so.  It implements the "MPIX stream" idea of
+ * Zhou, Raffenetti, Guo and Thakur, "MPIX Stream: An Explicit Solution to
+ * Hybrid MPI+X Programming" (EuroMPI/USA'22): a stream object names a serial
+ * execution context (here: a HIP stream), a stream communicator attaches one
+ * such context per rank, and enqueue calls put point-to-point and collective
+ * operations on that context, to run there in order, with no host
+ * synchronisation.
+ *
+ * Ranks are host threads of one process sharing one GPU: a "world" of N
+ * ranks stands in for MPI_COMM_WORLD, and every rank thread calls the
+ * functions below with its own communicator handle.  Payload work (datatype
+ * gather/scatter, the copy into the matched receive buffer, the reduction)
+ * runs in the library's HIP kernels on the streams.
+ *
+ * General rules
+ *  - Every function returns MPIXS_SUCCESS (0) or an error class below.  An
+ *    error returned by an enqueue call is synchronous and has no side
+ *    effect: nothing was enqueued and no matching sequence advanced.
+ *  - Errors found while an operation runs on the GPU (truncation, datatype
+ *    signature mismatch, a device wait that timed out or was aborted) are
+ *    written to the receive status (if one was given) and to the stream's
+ *    sticky error word, read with mpixs_stream_get_error().
+ *  - Objects (world, info, stream, comm, request, derived datatypes) are
+ *    owned by the library; *_free calls set the caller's handle to NULL/0.
+ *  - Buffers and statuses are owned by the caller and must be device
+ *    memory of the world's GPU (hipMalloc, torch tensors) or, for statuses
+ *    only, host memory allocated with hipHostMalloc.  They must stay valid
+ *    and untouched until the stream has passed the operation, as with any
+ *    enqueued GPU work.
+ *  - The hipStream_t given to mpixs_stream_create() stays owned by the
+ *    caller and must outlive the mpixs_stream.
+ *  - Threading: a stream, and every communicator built on it, is used by one
+ *    host thread at a time (the serial-context contract, §3.1).  World,
+ *    info and datatype calls are thread-safe.
+ */
+#ifndef MPIXS_H
+#define MPIXS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+enum {
+    MPIXS_SUCCESS = 0,
+    MPIXS_ERR_ARG = 1,          /* invalid argument (NULL handle, size out of range) */
+    MPIXS_ERR_COUNT = 2,        /* negative count */
+    MPIXS_ERR_TYPE = 3,         /* bad or uncommitted datatype; overlapping receive type;
+                                   signature mismatch (asynchronous) */
+    MPIXS_ERR_RANK = 4,         /* peer rank out of range, or MPIXS_ANY_SOURCE */
+    MPIXS_ERR_TAG = 5,          /* negative tag, or MPIXS_ANY_TAG */
+    MPIXS_ERR_COMM = 6,         /* communicator has no local GPU stream (§3.4) */
+    MPIXS_ERR_STREAM = 7,       /* waitall over requests of different streams (§3.4) */
+    MPIXS_ERR_REQUEST = 8,      /* NULL or foreign request */
+    MPIXS_ERR_BUFFER = 9,       /* buffer or status not accessible by the GPU */
+    MPIXS_ERR_NO_ENDPOINT = 10, /* stream pool exhausted (§3.1) */
+    MPIXS_ERR_PENDING = 11,     /* free of an object with operations in flight (§3.1) */
+    MPIXS_ERR_NOMEM = 12,       /* device tables or host memory exhausted */
+    MPIXS_ERR_OP = 13,          /* unknown reduction operation */
+    MPIXS_ERR_TRUNCATE = 14,    /* message longer than the receive buffer (asynchronous) */
+    MPIXS_ERR_TIMEOUT = 15,     /* a host or device wait gave up */
+    MPIXS_ERR_ABORTED = 16,     /* mpixs_world_abort() was called */
+    MPIXS_ERR_GPU = 17,         /* a HIP runtime call failed */
+    MPIXS_ERR_INTERN = 18
+};
+
+/* ----------------------------------------------------------------- handles */
+typedef struct mpixs_world_s *mpixs_world;
+typedef struct mpixs_info_s *mpixs_info;
+typedef struct mpixs_stream_s *mpixs_stream;
+typedef struct mpixs_comm_s *mpixs_comm;
+typedef struct mpixs_request_s *mpixs_request;
+typedef int32_t mpixs_datatype;
+typedef int32_t mpixs_op;
+
+#define MPIXS_INFO_NULL ((mpixs_info)0)
+#define MPIXS_STREAM_NULL ((mpixs_stream)0)
+#define MPIXS_REQUEST_NULL ((mpixs_request)0)
+#define MPIXS_DATATYPE_NULL ((mpixs_datatype)0)
+#define MPIXS_ANY_SOURCE (-2)
+#define MPIXS_ANY_TAG (-1)
+#define MPIXS_IN_PLACE ((const void *)1)
+
+/* basic datatypes (homogeneous; derived types are built from one of them) */
+#define MPIXS_UINT8 ((mpixs_datatype)1)
+#define MPIXS_INT8 ((mpixs_datatype)2)
+#define MPIXS_INT32 ((mpixs_datatype)3)
+#define MPIXS_FLOAT32 ((mpixs_datatype)4)
+#define MPIXS_INT64 ((mpixs_datatype)5)
+#define MPIXS_FLOAT64 ((mpixs_datatype)6)
+
+/* reduction operations */
+#define MPIXS_SUM ((mpixs_op)1)
+#define MPIXS_PROD ((mpixs_op)2)
+#define MPIXS_MIN ((mpixs_op)3)
+#define MPIXS_MAX ((mpixs_op)4)
+
+/* Receive status (the MPI_Status of §3.4's receive calls).  count_bytes is
+ * the number of bytes written into the receive buffer.  Pass NULL to ignore. */
+typedef struct {
+    int32_t source;
+    int32_t tag;
+    int32_t error;
+    int32_t reserved;
+    int64_t count_bytes;
+} mpixs_status;
+
+/* World configuration.  Zero fields take the default in brackets. */
+typedef struct {
+    int32_t max_streams;      /* stream (endpoint) pool size [256]; the pool is finite
+                                 as network endpoints are (§2.2, §3.1) */
+    int32_t endpoint_policy;  /* 0: stream_create fails when the pool is empty;
+                                 1: share endpoints round-robin (§3.1) [0] */
+    int32_t fuse_max_bytes;   /* messages up to this size wait and copy in one kernel
+                                 launch; larger ones use a one-wave wait kernel followed by
+                                 a full-grid copy [65536]; -1: never fuse */
+    int32_t timeout_ms;       /* host waits for a peer's enqueue, and device waits for a
+                                 peer's stream, give up after this [30000] */
+    int32_t max_channels;     /* device matching-table capacity in channels [1<<20] */
+    int32_t profile;          /* 1: time copy and reduce kernels with HIP events */
+    int32_t max_collectives;  /* device collective-slot capacity [4096] */
+    int32_t reserved[9];
+} mpixs_config;
+
+/* -------------------------------------------------------------- world (N ranks)
+ * mpixs_world_create: make a world of nranks (1..4096) ranks on the current
+ *   HIP device.  cfg may be NULL (defaults).  Allocates and clears the device
+ *   tables once, here, so that no later call allocates or synchronises.
+ * mpixs_world_comm: rank's handle to the world communicator (no stream
+ *   attached: enqueue calls on it fail with MPIXS_ERR_COMM, as on a
+ *   conventional communicator, §3.1's MPIX_STREAM_NULL semantics).
+ * mpixs_world_free: MPIXS_ERR_PENDING if streams or communicators are alive.
+ */
+int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *w);
+int mpixs_world_comm(mpixs_world w, int rank, mpixs_comm *comm);
+int mpixs_world_free(mpixs_world *w);
+/* Block until every stream attached to the world's communicators is idle,
+ * or timeout_ms passes (MPIXS_ERR_TIMEOUT).  A host-side watchdog for tests. */
+int mpixs_world_wait(mpixs_world w, int timeout_ms);
+/* Wake every device and host wait of the world with MPIXS_ERR_ABORTED (they
+ * skip their data movement).  The world is unusable afterwards. */
+int mpixs_world_abort(mpixs_world w);
+
+/* -------------------------------------------------------------------- info
+ * Key/value hints (§3.2).  mpixs_info_set_hex stores vallen bytes of value as
+ * lower-case hex text (two characters per byte, memory order).  A stream for
+ * a HIP stream is created from an info with type="hipStream_t" and value set
+ * with mpixs_info_set_hex(info, "value", &stream, sizeof(hipStream_t)), as in
+ * the paper's GPU example (§6).
+ */
+int mpixs_info_create(mpixs_info *info);
+int mpixs_info_set(mpixs_info info, const char *key, const char *value);
+int mpixs_info_set_hex(mpixs_info info, const char *key, const void *value, int vallen);
+int mpixs_info_get(mpixs_info info, const char *key, char *value, int valuelen, int *flag);
+int mpixs_info_free(mpixs_info *info);
+
+/* ------------------------------------------------------------------ stream
+ * mpixs_stream_create (§3.1, MPIX_Stream_create): a serial execution context
+ *   bound to an endpoint of the world's pool.  info NULL: a host-thread
+ *   stream (no GPU stream; enqueue calls on its communicators fail).
+ *   type="hipStream_t": a GPU stream, value decoded from hex.  Fails with
+ *   MPIXS_ERR_NO_ENDPOINT when the pool is empty (policy 0).
+ * mpixs_stream_free (§3.1, MPIX_Stream_free): may fail with
+ *   MPIXS_ERR_PENDING while communicators use the stream or operations
+ *   enqueued on it have not completed; the stream then stays valid.
+ * mpixs_stream_get_error: the first asynchronous error of operations that
+ *   ran on the stream (0 if none).  Synchronise the HIP stream first.
+ */
+int mpixs_stream_create(mpixs_world w, mpixs_info info, mpixs_stream *s);
+int mpixs_stream_free(mpixs_stream *s);
+int mpixs_stream_get_error(mpixs_stream s, int *first_error);
+
+/* ------------------------------------------------------------ communicator
+ * mpixs_comm_create_with_stream (§3.3, MPIX_Stream_comm_create): collective
+ *   over the parent's ranks; every rank thread calls it with its own parent
+ *   handle and stream (MPIXS_STREAM_NULL allowed per rank).  A stream
+ *   attached to the parent is not inherited (§3.3).  Blocks until all
+ *   ranks have called it.  Communicators match messages independently of
+ *   each other (§2.1).
+ * mpixs_comm_free: frees this rank's handle; MPIXS_ERR_PENDING while
+ *   requests of the handle are outstanding.
+ */
+int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm *newcomm);
+int mpixs_comm_free(mpixs_comm *comm);
+int mpixs_comm_rank(mpixs_comm comm, int *rank);
+int mpixs_comm_size(mpixs_comm comm, int *size);
+
+/* --------------------------------------------------------------- datatypes
+ * MPI derived datatypes over one basic type (§3.4 takes MPI datatypes; §4.5
+ * notes GPU collective libraries move only contiguous intrinsic types).
+ * Typemap meaning is MPI's: contiguous(n, T) places copy i at i*extent(T);
+ * vector(count, bl, stride, T) places element j of block i at
+ * (i*stride + j)*extent(T); indexed(count, bls, displs, T) places element j
+ * of block i at (displs[i] + j)*extent(T).  Counts, blocklengths, strides
+ * and displacements must be >= 0.  A type must be committed before use;
+ * commit compiles it into the form the copy kernels read.
+ */
+int mpixs_type_contiguous(int count, mpixs_datatype oldtype, mpixs_datatype *newtype);
+int mpixs_type_vector(int count, int blocklength, int stride, mpixs_datatype oldtype,
+                      mpixs_datatype *newtype);
+int mpixs_type_indexed(int count, const int blocklengths[], const int displacements[],
+                       mpixs_datatype oldtype, mpixs_datatype *newtype);
+int mpixs_type_commit(mpixs_datatype *type);
+int mpixs_type_free(mpixs_datatype *type);
+int mpixs_type_size(mpixs_datatype type, int64_t *bytes);
+int mpixs_type_get_extent(mpixs_datatype type, int64_t *lb, int64_t *extent);
+
+/* -------------------------------------------------------- enqueue calls (§3.4)
+ * All take a stream communicator whose local stream is a GPU stream
+ * (else MPIXS_ERR_COMM, §3.4).  Each returns once the operation is
+ * registered; the operation runs on the stream after the operations enqueued
+ * before it (§3.4).  Matching: the k-th send from rank s to rank d with tag
+ * t on a communicator matches the k-th receive of rank d from s with tag t
+ * on it (MPI's non-overtaking order without wildcards, §2.1).
+ *
+ *  send_enqueue:  later work on the stream starts once buf may be reused
+ *                 (the data has been copied into the matched receive buffer).
+ *  recv_enqueue:  later work on the stream sees the received data; status
+ *                 (may be NULL) is written on the stream.
+ *  isend/irecv_enqueue: later work may start before the transfer; *req
+ *                 completes with wait_enqueue / waitall_enqueue.
+ *  wait_enqueue:  later work on the stream starts after the request's
+ *                 transfer; *req is consumed and set to NULL at this call.
+ *  waitall_enqueue: requests must all belong to one stream (§3.4), else
+ *                 MPIXS_ERR_STREAM; statuses may be NULL.
+ *
+ * Host blocking: a call never waits for the GPU.  A call whose stream must
+ * wait for the peer's stream may wait, on the host, until the peer thread
+ * has *enqueued* its matching operation (blocking send/recv, wait of a
+ * request whose peer has not arrived yet, allreduce of a rank that is not
+ * the last to arrive), so that a device wait is never queued ahead of what
+ * it waits for.  That host wait gives up after cfg.timeout_ms with
+ * MPIXS_ERR_TIMEOUT.  Wildcards are not supported (MPIXS_ERR_RANK /
+ * MPIXS_ERR_TAG).
+ */
+int mpixs_send_enqueue(const void *buf, int count, mpixs_datatype datatype, int dest, int tag,
+                       mpixs_comm comm);
+int mpixs_recv_enqueue(void *buf, int count, mpixs_datatype datatype, int source, int tag,
+                       mpixs_comm comm, mpixs_status *status);
+int mpixs_isend_enqueue(const void *buf, int count, mpixs_datatype datatype, int dest, int tag,
+                        mpixs_comm comm, mpixs_request *request);
+int mpixs_irecv_enqueue(void *buf, int count, mpixs_datatype datatype, int source, int tag,
+                        mpixs_comm comm, mpixs_request *request);
+int mpixs_wait_enqueue(mpixs_request *request, mpixs_status *status);
+int mpixs_waitall_enqueue(int count, mpixs_request requests[], mpixs_status statuses[]);
+
+/* allreduce_enqueue (§3.4 extends enqueue to collectives): MPI_Allreduce on
+ * a contiguous basic type (int32, int64, float32, float64) with SUM, PROD,
+ * MIN or MAX.  Every rank of the communicator calls it; the k-th call of
+ * each rank forms one instance.  The result is, element by element, the
+ * left fold over ranks 0..N-1 in that order (so float results are
+ * reproducible).  sendbuf may be MPIXS_IN_PLACE (input taken from recvbuf).
+ * At most 64 ranks per communicator. */
+int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
+                            mpixs_datatype datatype, mpixs_op op, mpixs_comm comm);
+
+/* ------------------------------------ conventional, host-synchronised calls
+ * The comparison path of §2.4: MPI calls that run in the CPU context and
+ * fully synchronise with the GPU.  Each call synchronises its rank's HIP
+ * stream, matches on the host, launches one copy (or reduce) kernel -- the
+ * same kernels as the enqueue path -- and synchronises again before it
+ * returns.  They take stream communicators (they need the HIP stream) and
+ * match only among themselves: mixing them with enqueue calls on one
+ * channel is not supported.
+ */
+int mpixs_send(const void *buf, int count, mpixs_datatype datatype, int dest, int tag,
+               mpixs_comm comm);
+int mpixs_recv(void *buf, int count, mpixs_datatype datatype, int source, int tag,
+               mpixs_comm comm, mpixs_status *status);
+int mpixs_allreduce(const void *sendbuf, void *recvbuf, int count, mpixs_datatype datatype,
+                    mpixs_op op, mpixs_comm comm);
+
+/* ------------------------------------------------------------- diagnostics */
+typedef struct {
+    uint64_t kernels_post;      /* one-thread "stream reached this point" kernels */
+    uint64_t kernels_wait;      /* one-wave wait kernels */
+    uint64_t kernels_copy;      /* copy kernels (fused or not) */
+    uint64_t kernels_reduce;    /* reduce kernels */
+    uint64_t bytes_copied;      /* payload bytes moved by copy kernels */
+    uint64_t bytes_reduced;     /* bytes read + written by reduce kernels */
+    uint64_t host_waits;        /* enqueue calls that waited for a peer's enqueue */
+    uint64_t timed_copy;        /* profile=1: copy kernels timed with HIP events */
+    double copy_ms;             /* profile=1: sum of their event durations */
+    uint64_t timed_reduce;
+    double reduce_ms;
+} mpixs_stats;
+
+/* Counters of the world since creation (or the last reset).  With
+ * cfg.profile = 1 the event durations are collected here, which requires
+ * the streams to be idle (call after synchronising). */
+int mpixs_world_get_stats(mpixs_world w, mpixs_stats *stats);
+int mpixs_world_reset_stats(mpixs_world w);
+const char *mpixs_error_string(int err);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPIXS_H */

@@ -1,0 +1,33 @@
+/*
+ * mpixs_debug.h -- host-side introspection of libmpixs for tests.
+ *
+ * Not part of the enqueue interface; nothing here touches the GPU.
+ */
+#ifndef MPIXS_DEBUG_H
+#define MPIXS_DEBUG_H
+
+#include <stdint.h>
+
+#include "mpixs.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The copy plan the library would launch for a matched message of nbytes
+ * packed bytes sent as (sbuf, scount, stype) and received into (rbuf,
+ * rcount, rtype): *unit_bytes receives the unit size of the copy kernel,
+ * *nunits the number of units, and for the first min(nunits, max_units)
+ * units src_addr[u] / dst_addr[u] receive the byte addresses unit u is read
+ * from and written to (either array may be NULL).  sbuf and rbuf are only
+ * used as numbers.  Datatypes need not be committed.  Errors:
+ * MPIXS_ERR_TYPE for an unknown datatype, MPIXS_ERR_ARG for NULL outputs. */
+int mpixs_debug_copy_plan(uint64_t sbuf, int scount, mpixs_datatype stype, uint64_t rbuf,
+                          int rcount, mpixs_datatype rtype, int64_t nbytes, int64_t max_units,
+                          uint64_t *src_addr, uint64_t *dst_addr, int *unit_bytes,
+                          int64_t *nunits);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,324 @@
+// CDNA4 (gfx950) kernels of libmpixs: stream-ordered flags, typemap-driven
+// copy of a matched message, and the canonical-order allreduce.
+//
+// Memory ordering.  The eight XCDs of an MI355X each have their own L2, so
+// a flag that another stream polls is written with a release store at agent
+// scope and read with acquire loads at agent scope; data written by a
+// multi-workgroup kernel is released by every wave before the workgroup
+// draws a completion ticket, and only the last workgroup publishes the done
+// counter.  Kernel boundaries on one stream order everything else.
+//
+// Waits never run forever: they poll with s_sleep, check the world's abort
+// word and give up after a wall-clock timeout, recording the error in the
+// stream's block; kernels that find their stream failed skip data movement
+// but still publish completion, so every waiter downstream also finishes.
+#include <hip/hip_runtime.h>
+
+#include "../../include/mpixs.h"
+#include "mpixs_dev.h"
+#include "mpixs_launch.h"
+
+namespace mpixs {
+
+// ------------------------------------------------------------ primitives
+__device__ __forceinline__ uint64_t ld_acquire(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_release(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t ld_relaxed32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_first_error(DevStream *s, uint32_t e) {
+    uint32_t expected = 0;
+    __hip_atomic_compare_exchange_strong(&s->first_error, &expected, e, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_fatal(DevStream *s, uint32_t e) {
+    uint32_t expected = 0;
+    __hip_atomic_compare_exchange_strong(&s->fatal, &expected, e, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    set_first_error(s, e);
+}
+
+// Poll until *p >= target.  Returns 0, MPIXS_ERR_ABORTED or MPIXS_ERR_TIMEOUT.
+__device__ uint32_t spin_wait(const uint64_t *p, uint64_t target, const WaitCtl &ctl) {
+    if (ld_acquire(p) >= target) return 0;
+    const uint64_t t0 = wall_clock64();
+    uint32_t it = 0;
+    for (;;) {
+        __builtin_amdgcn_s_sleep(2);
+        if (ld_acquire(p) >= target) return 0;
+        if ((++it & 31u) == 0) {
+            if (__hip_atomic_load(ctl.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+                return MPIXS_ERR_ABORTED;
+            if (wall_clock64() - t0 > ctl.timeout_ticks) return MPIXS_ERR_TIMEOUT;
+        }
+    }
+}
+
+__device__ __forceinline__ void write_status(void *dst, const StatusVal &v, uint32_t fatal) {
+    StatusVal *s = reinterpret_cast<StatusVal *>(dst);
+    s->source = v.source;
+    s->tag = v.tag;
+    s->error = fatal ? int32_t(fatal) : v.error;
+    s->reserved = 0;
+    s->count_bytes = fatal ? 0 : v.count_bytes;
+}
+
+// ----------------------------------------------------------- post / wait
+// "This stream reached this point": one release store.
+__global__ void __launch_bounds__(64) k_post(uint64_t *p, uint64_t v) {
+    if (threadIdx.x == 0) st_release(p, v);
+}
+
+// Lane q waits for *ptr[q] >= target[q]; then lane 0 writes the optional
+// status and the stream's first error.
+__global__ void __launch_bounds__(64) k_wait(WaitArgs a) {
+    const int lane = threadIdx.x;
+    uint32_t err = 0;
+    const uint32_t fatal0 = ld_relaxed32(&a.me->fatal);
+    if (!fatal0 && lane < a.n) err = spin_wait(a.ptr[lane], a.target[lane], a.ctl);
+    if (err) set_fatal(a.me, err);
+    __syncthreads();
+    if (lane == 0) {
+        const uint32_t fatal = ld_relaxed32(&a.me->fatal);
+        if (a.status) write_status(a.status, a.st, fatal);
+        if (!fatal && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
+    }
+}
+
+// ------------------------------------------------------------------ maps
+template <int W> struct Unit;
+template <> struct Unit<1> { using T = uint8_t; };
+template <> struct Unit<2> { using T = uint16_t; };
+template <> struct Unit<4> { using T = uint32_t; };
+template <> struct Unit<8> { using T = uint64_t; };
+template <> struct Unit<16> { using T = __attribute__((ext_vector_type(4))) uint32_t; };
+
+// Shared tail of the copy and reduce kernels: every wave releases its
+// stores, the workgroups draw tickets, the last one publishes completion.
+__device__ __forceinline__ bool last_workgroup(DevStream *me, uint64_t ticket_last) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        s_last = 1;
+        if (gridDim.x > 1) {
+            const uint64_t t = __hip_atomic_fetch_add(&me->ticket, uint64_t(1), __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            s_last = (t == ticket_last);
+        }
+    }
+    __syncthreads();
+    return s_last != 0;
+}
+
+// ------------------------------------------------------------------ copy
+// Unit u of the packed message goes from map_src(u) to map_dst(u); W is the
+// largest power of two (<= 16) that divides every block boundary and base
+// address of both sides, so each unit is one aligned load and one store.
+constexpr int COPY_THREADS = 256;
+constexpr int COPY_UNROLL = 4;
+
+template <int W, int SK, int DK>
+__global__ void __launch_bounds__(COPY_THREADS) k_copy(CopyArgs a) {
+    using T = typename Unit<W>::T;
+    __shared__ uint32_t s_fatal;
+    if (threadIdx.x == 0) {
+        uint32_t f = ld_relaxed32(&a.me->fatal);
+        if (!f && a.wait_ptr) {
+            f = spin_wait(a.wait_ptr, a.wait_target, a.ctl);
+            if (f) set_fatal(a.me, f);
+        }
+        s_fatal = f;
+    }
+    __syncthreads();
+    if (a.wait_ptr) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!s_fatal) {
+        const uint64_t n = a.units;
+        const uint64_t stride = uint64_t(gridDim.x) * COPY_THREADS;
+        for (uint64_t u0 = uint64_t(blockIdx.x) * COPY_THREADS + threadIdx.x; u0 < n;
+             u0 += stride * COPY_UNROLL) {
+            T v[COPY_UNROLL];
+#pragma unroll
+            for (int k = 0; k < COPY_UNROLL; ++k) {
+                const uint64_t u = u0 + uint64_t(k) * stride;
+                if (u < n) v[k] = *reinterpret_cast<const T *>(map_addr<SK, W>(a.src, u));
+            }
+#pragma unroll
+            for (int k = 0; k < COPY_UNROLL; ++k) {
+                const uint64_t u = u0 + uint64_t(k) * stride;
+                if (u < n) *reinterpret_cast<T *>(map_addr<DK, W>(a.dst, u)) = v[k];
+            }
+        }
+    }
+    if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
+        const uint32_t fatal = ld_relaxed32(&a.me->fatal);
+        if (a.status) write_status(a.status, a.st, fatal);
+        if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
+        if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+    }
+}
+
+// ---------------------------------------------------------------- reduce
+template <typename T> struct Uns { using U = T; };
+template <> struct Uns<int32_t> { using U = uint32_t; };
+template <> struct Uns<int64_t> { using U = uint64_t; };
+
+template <typename T, int OP>
+__device__ __forceinline__ T combine(T acc, T x) {
+    if constexpr (OP == OP_SUM) {
+        using U = typename Uns<T>::U;
+        return T(U(acc) + U(x));
+    } else if constexpr (OP == OP_PROD) {
+        using U = typename Uns<T>::U;
+        return T(U(acc) * U(x));
+    } else if constexpr (OP == OP_MIN) {
+        return x < acc ? x : acc;
+    } else {
+        return x > acc ? x : acc;
+    }
+}
+
+constexpr int RED_THREADS = 256;
+constexpr int RED_GROUP = 8;    // inputs loaded back to back before folding
+
+// out_q[i] = (((in_0[i] op in_1[i]) op in_2[i]) ... op in_{n-1}[i]) for every q:
+// the left fold in rank order, each element owned by one lane.
+template <typename T, int OP, bool VEC>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
+    __shared__ uint32_t s_fatal;
+    if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
+    __syncthreads();
+    if (a.arrive && !s_fatal) {
+        uint32_t err = 0;
+        const int q = threadIdx.x;
+        if (q < a.n && q != a.me_rank) err = spin_wait(a.arrive + q * 16, a.arrive_target, a.ctl);
+        if (err) set_fatal(a.me, err);
+        __syncthreads();
+        if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (!s_fatal) {
+        const int n = a.n;
+        const uint64_t gtid = uint64_t(blockIdx.x) * RED_THREADS + threadIdx.x;
+        const uint64_t nthreads = uint64_t(gridDim.x) * RED_THREADS;
+        if constexpr (VEC) {
+            constexpr int L = 16 / sizeof(T);
+            using V = T __attribute__((ext_vector_type(L)));
+            const uint64_t nvec = a.count / L;
+            for (uint64_t v = gtid; v < nvec; v += nthreads) {
+                V acc = reinterpret_cast<const V *>(a.in[0])[v];
+                for (int q0 = 1; q0 < n; q0 += RED_GROUP) {
+                    V x[RED_GROUP];
+#pragma unroll
+                    for (int j = 0; j < RED_GROUP; ++j)
+                        if (q0 + j < n) x[j] = reinterpret_cast<const V *>(a.in[q0 + j])[v];
+#pragma unroll
+                    for (int j = 0; j < RED_GROUP; ++j)
+                        if (q0 + j < n) {
+#pragma unroll
+                            for (int l = 0; l < L; ++l) acc[l] = combine<T, OP>(acc[l], x[j][l]);
+                        }
+                }
+                for (int q = 0; q < n; ++q) reinterpret_cast<V *>(a.out[q])[v] = acc;
+            }
+            // tail elements
+            for (uint64_t i = nvec * L + gtid; i < a.count; i += nthreads) {
+                T acc = reinterpret_cast<const T *>(a.in[0])[i];
+                for (int q = 1; q < n; ++q)
+                    acc = combine<T, OP>(acc, reinterpret_cast<const T *>(a.in[q])[i]);
+                for (int q = 0; q < n; ++q) reinterpret_cast<T *>(a.out[q])[i] = acc;
+            }
+        } else {
+            for (uint64_t i = gtid; i < a.count; i += nthreads) {
+                T acc = reinterpret_cast<const T *>(a.in[0])[i];
+                for (int q = 1; q < n; ++q)
+                    acc = combine<T, OP>(acc, reinterpret_cast<const T *>(a.in[q])[i]);
+                for (int q = 0; q < n; ++q) reinterpret_cast<T *>(a.out[q])[i] = acc;
+            }
+        }
+    }
+    if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
+        if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+    }
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_post(hipStream_t s, uint64_t *p, uint64_t v) {
+    hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_wait(hipStream_t s, const WaitArgs &a) {
+    hipLaunchKernelGGL(k_wait, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+int copy_block_units() { return COPY_THREADS * COPY_UNROLL; }
+
+template <int W, int SK>
+static hipError_t copy_dk(hipStream_t s, const CopyArgs &a, int dk, int nwg) {
+    switch (dk) {
+    case MAP_CONTIG: hipLaunchKernelGGL((k_copy<W, SK, MAP_CONTIG>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case MAP_VEC: hipLaunchKernelGGL((k_copy<W, SK, MAP_VEC>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_copy<W, SK, MAP_SEG>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t copy_w(hipStream_t s, const CopyArgs &a, int nwg) {
+    switch (a.src.kind) {
+    case MAP_CONTIG: return copy_dk<W, MAP_CONTIG>(s, a, a.dst.kind, nwg);
+    case MAP_VEC: return copy_dk<W, MAP_VEC>(s, a, a.dst.kind, nwg);
+    default: return copy_dk<W, MAP_SEG>(s, a, a.dst.kind, nwg);
+    }
+}
+
+hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg) {
+    switch (w) {
+    case 16: return copy_w<16>(s, a, nwg);
+    case 8: return copy_w<8>(s, a, nwg);
+    case 4: return copy_w<4>(s, a, nwg);
+    case 2: return copy_w<2>(s, a, nwg);
+    default: return copy_w<1>(s, a, nwg);
+    }
+}
+
+int reduce_threads() { return RED_THREADS; }
+
+template <typename T, int OP>
+static hipError_t reduce_op(hipStream_t s, const ReduceArgs &a, bool vec, int nwg) {
+    if (vec) hipLaunchKernelGGL((k_reduce<T, OP, true>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_reduce<T, OP, false>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t reduce_t(hipStream_t s, const ReduceArgs &a, int op, bool vec, int nwg) {
+    switch (op) {
+    case OP_SUM: return reduce_op<T, OP_SUM>(s, a, vec, nwg);
+    case OP_PROD: return reduce_op<T, OP_PROD>(s, a, vec, nwg);
+    case OP_MIN: return reduce_op<T, OP_MIN>(s, a, vec, nwg);
+    default: return reduce_op<T, OP_MAX>(s, a, vec, nwg);
+    }
+}
+
+hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg) {
+    switch (basic) {
+    case MPIXS_INT32: return reduce_t<int32_t>(s, a, op, vec, nwg);
+    case MPIXS_INT64: return reduce_t<int64_t>(s, a, op, vec, nwg);
+    case MPIXS_FLOAT32: return reduce_t<float>(s, a, op, vec, nwg);
+    default: return reduce_t<double>(s, a, op, vec, nwg);
+    }
+}
+
+}  // namespace mpixs

@@ -1,0 +1,191 @@
+// Device-side data layout and kernel argument blocks of libmpixs.
+//
+// Everything the kernels read arrives either in the kernel argument block
+// (maps, pointers, counts: the host knows both sides of a matched message
+// when it launches the copy) or in the world's device pool, which holds
+//   - one 64-byte "channel" block per (communicator, source, destination,
+//     tag): two ready counters (one per side) and a done counter.  These
+//     monotone counters are the device matching table: the k-th operation
+//     of a side on a channel posts ready = k+1 when its stream reaches it,
+//     and the copy of message k publishes done = k+1 (§2.1: matching order
+//     is per channel, in issue order);
+//   - one 128-byte block per stream (first asynchronous error, fatal flag,
+//     completion ticket counter);
+//   - per communicator, one arrive counter per rank and a done counter for
+//     collectives.
+#pragma once
+#include <stdint.h>
+
+#ifndef MPIXS_HD
+#if defined(__HIPCC__)
+#define MPIXS_HD __host__ __device__
+#else
+#define MPIXS_HD
+#endif
+#endif
+
+namespace mpixs {
+
+// ------------------------------------------------------------ fast division
+// Division of a 32-bit n by an invariant d >= 1 with one multiply-high
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, §4): with l = ceil(log2 d) and
+// m = floor(2^32 * (2^l - d) / d) + 1, n / d = (mulhi(n, m) + n) >> l,
+// the sum taken in 64 bits.
+struct FastDiv {
+    uint32_t d;
+    uint32_t m;
+    uint32_t l;
+    uint32_t pad;
+};
+
+static inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    f.l = l;
+    f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    f.pad = 0;
+    return f;
+}
+
+MPIXS_HD static inline uint32_t fd_div(uint32_t n, const FastDiv &f) {
+    uint32_t t = uint32_t((uint64_t(n) * f.m) >> 32);
+    return uint32_t((uint64_t(t) + n) >> f.l);
+}
+
+// ---------------------------------------------------------------- typemaps
+enum MapKind : uint32_t { MAP_CONTIG = 0, MAP_VEC = 1, MAP_SEG = 2 };
+
+// One segment of a flattened typemap: byte offset from the start of a copy
+// (the buffer address plus copy * extent) and the packed bytes before it.
+struct SegEnt {
+    int64_t off;
+    int64_t pre;
+};
+
+// Map from packed unit u (units of W bytes) of one side of a message to the
+// byte address holding it.
+//   CONTIG: base + u * W
+//   VEC:    c = u / upc, r = u % upc, b = r / bu, o = r % bu
+//           base + c * s_copy + b * s_blk + o * W
+//   SEG:    c = u / upc, rb = (u % upc) * W, i = last segment with pre <= rb
+//           base + c * s_copy + seg[i].off + (rb - seg[i].pre)
+struct DMap {
+    uint64_t base;
+    uint32_t kind;
+    uint32_t upc;     // units per copy (VEC, SEG)
+    uint32_t bu;      // units per block (VEC)
+    uint32_t nseg;    // segments per copy (SEG)
+    int64_t s_copy;   // bytes between copies
+    int64_t s_blk;    // bytes between blocks (VEC)
+    FastDiv d_upc;
+    FastDiv d_bu;
+    const SegEnt *seg;  // SEG table (nseg entries), in host-pinned memory
+};
+
+template <int K, int W>
+MPIXS_HD inline uint64_t map_addr(const DMap &m, uint64_t u) {
+    if constexpr (K == MAP_CONTIG) {
+        return m.base + u * W;
+    } else if constexpr (K == MAP_VEC) {
+        const uint32_t u32 = uint32_t(u);
+        const uint32_t c = fd_div(u32, m.d_upc);
+        const uint32_t r = u32 - c * m.upc;
+        const uint32_t b = fd_div(r, m.d_bu);
+        const uint32_t o = r - b * m.bu;
+        return m.base + uint64_t(int64_t(c) * m.s_copy + int64_t(b) * m.s_blk) + uint64_t(o) * W;
+    } else {
+        const uint32_t u32 = uint32_t(u);
+        const uint32_t c = fd_div(u32, m.d_upc);
+        const int64_t rb = int64_t(u32 - c * m.upc) * W;
+        // last segment whose packed prefix is <= rb
+        uint32_t lo = 0, hi = m.nseg;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (m.seg[mid].pre <= rb) lo = mid; else hi = mid;
+        }
+        const SegEnt e = m.seg[lo];
+        return m.base + uint64_t(int64_t(c) * m.s_copy + e.off + (rb - e.pre));
+    }
+}
+
+// ------------------------------------------------------------ device state
+struct alignas(64) DevChan {
+    uint64_t ready[2];    // [0]: sender side, [1]: receiver side
+    uint64_t done;
+    uint64_t pad[5];
+};
+
+struct alignas(128) DevStream {
+    uint32_t first_error;  // first asynchronous error of this stream (0: none)
+    uint32_t fatal;        // non-zero: a wait gave up; later data movement is skipped
+    uint64_t ticket;       // completion tickets of multi-workgroup kernels
+    uint64_t pad[14];
+};
+
+// -------------------------------------------------------------- arguments
+struct StatusVal {
+    int32_t source;
+    int32_t tag;
+    int32_t error;
+    int32_t reserved;
+    int64_t count_bytes;
+};
+
+struct WaitCtl {
+    const uint32_t *abort;           // host-pinned abort word of the world
+    uint64_t timeout_ticks;          // wall-clock ticks before a wait gives up
+};
+
+// Up to 64 (pointer, target) pairs: wait until *ptr >= target for each.
+struct WaitArgs {
+    const uint64_t *ptr[64];
+    uint64_t target[64];
+    int32_t n;
+    int32_t pad;
+    WaitCtl ctl;
+    DevStream *me;          // stream the kernel runs on
+    void *status;           // optional receive status to write after the wait
+    StatusVal st;
+};
+
+struct CopyArgs {
+    DMap src;
+    DMap dst;
+    uint64_t units;               // W-byte units to copy
+    // fused wait (nullptr: the stream already waited)
+    const uint64_t *wait_ptr;
+    uint64_t wait_target;
+    WaitCtl ctl;
+    // completion
+    uint64_t *done_ptr;           // nullptr: no channel to signal
+    uint64_t done_val;
+    DevStream *me;
+    uint64_t ticket_last;         // ticket value that the last workgroup draws
+    void *status;                 // optional receive status
+    StatusVal st;
+    int32_t set_error;            // copy st.error into me->first_error
+    int32_t pad;
+};
+
+enum RedOp : int32_t { OP_SUM = 1, OP_PROD = 2, OP_MIN = 3, OP_MAX = 4 };
+
+struct ReduceArgs {
+    const void *in[64];
+    void *out[64];
+    int32_t n;
+    int32_t me_rank;
+    uint64_t count;               // elements
+    // fused wait on the other ranks' arrive counters (nullptr: waited already)
+    const uint64_t *arrive;
+    uint64_t arrive_target;
+    WaitCtl ctl;
+    uint64_t *done_ptr;
+    uint64_t done_val;
+    DevStream *me;
+    uint64_t ticket_last;
+};
+
+}  // namespace mpixs

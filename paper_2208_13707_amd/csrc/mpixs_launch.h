@@ -1,0 +1,16 @@
+// Host-side launchers of the kernels in kernels.hip.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include "mpixs_dev.h"
+
+namespace mpixs {
+
+hipError_t launch_post(hipStream_t s, uint64_t *p, uint64_t v);
+hipError_t launch_wait(hipStream_t s, const WaitArgs &a);
+hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg);
+hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg);
+int copy_block_units();   // units one copy workgroup moves per loop trip
+int reduce_threads();
+
+}  // namespace mpixs

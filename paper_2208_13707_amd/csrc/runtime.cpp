@@ -1,0 +1,1299 @@
+// libmpixs host runtime: worlds, info, streams, stream communicators and
+// the enqueue protocol.
+//
+// Matching (§2.1).  A channel is (communicator, source, destination, tag).
+// The source thread numbers its sends on a channel 0, 1, 2 ... and the
+// destination thread numbers its receives the same way; send k matches
+// receive k.  Because a stream is a strictly serial context used by one
+// thread (§3.1), the two counters need no lock.
+//
+// Enqueue protocol (§3.4).  For message k the side whose thread arrives
+// first enqueues a one-thread "post" kernel that stores ready[side] = k+1
+// when its stream reaches the operation, then records its descriptor.  The
+// side that arrives second enqueues, on its own stream, the copy: wait until
+// the other side's ready counter reaches k+1, move the bytes from the
+// sender's typemap into the receiver's, publish done = k+1.  The first side
+// later (blocking call: at once; nonblocking call: at its wait) enqueues a
+// one-wave wait for done >= k+1, after the copy has been enqueued.
+//
+// So every device wait is enqueued after the work it waits for.  HIP maps
+// streams onto a few hardware queues that run their packets in order, so a
+// wait queued ahead of its producer on a shared queue could never finish;
+// with this rule the earliest unfinished packet never waits for a later one
+// and the system always makes progress.  The price is that a call may wait
+// on the host until the peer thread has *enqueued* its side (never until
+// any GPU work has finished).
+//
+// Allreduce: the last rank to arrive runs the whole reduction on its
+// stream after waiting for the other ranks' arrive counters; the others
+// post their arrival and wait for the done counter.
+#include <hip/hip_runtime.h>
+
+#include <immintrin.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "mpixs_launch.h"
+#include "runtime.h"
+#include "../../include/mpixs_debug.h"
+
+namespace mpixs {
+
+namespace {
+
+constexpr uint64_t kModeHost = uint64_t(1) << 63;
+
+int gpu_err(hipError_t e) { return e == hipSuccess ? MPIXS_SUCCESS : MPIXS_ERR_GPU; }
+
+uint64_t chan_key(int src, int dst, int tag) {
+    return (uint64_t(uint32_t(src)) << 44) ^ (uint64_t(uint32_t(dst)) << 24) ^ uint64_t(uint32_t(tag));
+}
+
+// Wait on the host until pred() holds.  Spins briefly, then yields, then
+// sleeps; gives up on abort or after the world's timeout (which aborts the
+// world so that every device wait ends too).
+template <class Pred>
+int host_wait(World *w, Pred pred) {
+    if (pred()) return MPIXS_SUCCESS;
+    w->host_waits.fetch_add(1, std::memory_order_relaxed);
+    const auto t0 = std::chrono::steady_clock::now();
+    const auto limit = std::chrono::milliseconds(w->cfg.timeout_ms);
+    for (uint64_t it = 1;; ++it) {
+        if (pred()) return MPIXS_SUCCESS;
+        if (w->aborted.load(std::memory_order_acquire)) return MPIXS_ERR_ABORTED;
+        if (it < 4096) {
+            _mm_pause();
+        } else if (it < 8192) {
+            std::this_thread::yield();
+        } else {
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        if ((it & 255) == 0 && std::chrono::steady_clock::now() - t0 > limit) {
+            mpixs_world_abort(reinterpret_cast<mpixs_world>(w));
+            return MPIXS_ERR_TIMEOUT;
+        }
+    }
+}
+
+WaitCtl ctl_of(World *w) {
+    WaitCtl c;
+    c.abort = w->h_abort;
+    c.timeout_ticks = w->timeout_ticks;
+    return c;
+}
+
+bool profile_on(World *w) { return w->cfg.profile != 0; }
+
+void prof_begin(World *w, hipStream_t s, hipEvent_t *e0) {
+    (void)hipEventCreate(e0);
+    (void)hipEventRecord(*e0, s);
+}
+
+void prof_end(World *w, hipStream_t s, hipEvent_t e0, int kind) {
+    hipEvent_t e1;
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e1, s);
+    std::lock_guard<std::mutex> g(w->prof_mu);
+    w->prof.push_back(ProfPair{e0, e1, kind});
+}
+
+// ------------------------------------------------------------------ maps
+int64_t lowbit(int64_t g) { return g ? (g & -g) : int64_t(1) << 62; }
+
+// One side of a copy: the map kind and base, and `g`, the OR of every
+// quantity the unit size must divide (its lowest set bit bounds the unit).
+struct MapPlan {
+    DMap m{};
+    int64_t g = 0;
+};
+
+void plan_map(const Side &sd, MapPlan &p) {
+    const Layout &L = sd.t->L;
+    const uint64_t buf = reinterpret_cast<uint64_t>(sd.buf);
+    std::memset(&p.m, 0, sizeof(p.m));
+    if (L.reg && L.nblk == 1) {
+        // count copies of a dense block are one dense run
+        p.m.kind = MAP_CONTIG;
+        p.m.base = buf + uint64_t(L.first);
+        p.g = int64_t(p.m.base);
+        return;
+    }
+    if (L.reg) {
+        p.m.kind = MAP_VEC;
+        p.m.base = buf + uint64_t(L.first);
+        p.m.s_blk = L.stride;
+        p.m.s_copy = L.extent;
+        int64_t g = int64_t(p.m.base) | L.blen | (L.stride < 0 ? -L.stride : L.stride);
+        if (sd.count > 1) g |= L.extent;
+        p.g = g;
+        return;
+    }
+    p.m.kind = MAP_SEG;
+    p.m.base = buf;
+    p.m.s_copy = L.extent;
+    p.m.seg = sd.t->table;
+    p.m.nseg = uint32_t(sd.t->nseg);
+    int64_t g = int64_t(buf) | L.gcd;
+    if (sd.count > 1) g |= L.extent;
+    p.g = g;
+}
+
+void finish_map(const Side &sd, MapPlan &p, int w, uint64_t units) {
+    const Layout &L = sd.t->L;
+    if (p.m.kind == MAP_VEC) {
+        p.m.bu = uint32_t(L.blen / w);
+        const bool periodic = sd.count == 1 || L.extent == L.nblk * L.stride;
+        p.m.upc = periodic ? uint32_t(std::max<uint64_t>(units, 1)) : uint32_t(L.nblk * (L.blen / w));
+        if (periodic) p.m.s_copy = 0;
+        p.m.d_bu = make_fastdiv(std::max<uint32_t>(p.m.bu, 1));
+        p.m.d_upc = make_fastdiv(std::max<uint32_t>(p.m.upc, 1));
+    } else if (p.m.kind == MAP_SEG) {
+        p.m.upc = uint32_t(L.size / w);
+        p.m.d_upc = make_fastdiv(std::max<uint32_t>(p.m.upc, 1));
+    }
+}
+
+}  // namespace
+
+int plan_copy(const Side &S, const Side &R, int64_t nbytes, DMap *src, DMap *dst, int *wsz,
+              uint64_t *units) {
+    MapPlan ps, pr;
+    *wsz = 16;
+    *units = 0;
+    if (nbytes <= 0) {
+        std::memset(src, 0, sizeof(*src));
+        std::memset(dst, 0, sizeof(*dst));
+        return MPIXS_SUCCESS;
+    }
+    plan_map(S, ps);
+    plan_map(R, pr);
+    const int64_t g = nbytes | ps.g | pr.g;
+    *wsz = int(std::min<int64_t>(16, lowbit(g)));
+    *units = uint64_t(nbytes / *wsz);
+    finish_map(S, ps, *wsz, *units);
+    finish_map(R, pr, *wsz, *units);
+    *src = ps.m;
+    *dst = pr.m;
+    return MPIXS_SUCCESS;
+}
+
+namespace {
+
+StatusVal match_status(const Side &s, const Side &r, int tag) {
+    StatusVal st{};
+    st.source = s.rank;
+    st.tag = tag;
+    const int64_t cap = r.bytes;
+    if (s.bytes > 0 && cap > 0 && s.t->L.basic != r.t->L.basic) {
+        st.error = MPIXS_ERR_TYPE;
+        st.count_bytes = 0;
+    } else if (s.bytes > cap) {
+        st.error = MPIXS_ERR_TRUNCATE;
+        st.count_bytes = cap;
+    } else {
+        st.error = MPIXS_SUCCESS;
+        st.count_bytes = s.bytes;
+    }
+    return st;
+}
+
+// ------------------------------------------------------------- launchers
+int do_post(World *w, StreamObj *st, uint64_t *p, uint64_t v) {
+    w->n_post.fetch_add(1, std::memory_order_relaxed);
+    return gpu_err(launch_post(st->hs, p, v));
+}
+
+int do_wait(World *w, StreamObj *st, WaitArgs &a) {
+    a.ctl = ctl_of(w);
+    a.me = st->dev;
+    w->n_wait.fetch_add(1, std::memory_order_relaxed);
+    return gpu_err(launch_wait(st->hs, a));
+}
+
+WaitArgs wait_one(const uint64_t *p, uint64_t target) {
+    WaitArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = 1;
+    a.ptr[0] = p;
+    a.target[0] = target;
+    return a;
+}
+
+// Copy message S -> R on stream `on`.  wait_ptr/target: the other side's
+// ready counter (nullptr on the host-synchronised path).  done_ptr: the
+// channel's done counter (nullptr: none).  status/set_error: the receive
+// status and sticky error when `on` is the receiver's stream.
+int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusVal &st,
+            const uint64_t *wait_ptr, uint64_t wait_target, uint64_t *done_ptr, uint64_t done_val,
+            void *status, bool set_error) {
+    const int64_t nbytes = st.count_bytes;
+    DMap ms, mr;
+    int wsz = 16;
+    uint64_t units = 0;
+    plan_copy(S, R, nbytes, &ms, &mr, &wsz, &units);
+    const bool fuse = w->cfg.fuse_max_bytes >= 0 && nbytes <= w->cfg.fuse_max_bytes;
+    const uint64_t per_wg = uint64_t(copy_block_units());
+    uint64_t nwg = std::max<uint64_t>(1, (units + per_wg - 1) / per_wg);
+    nwg = std::min<uint64_t>(nwg, fuse ? 16 : 2048);
+    int rc = MPIXS_SUCCESS;
+    if (wait_ptr && !fuse) {
+        WaitArgs wa = wait_one(wait_ptr, wait_target);
+        rc = do_wait(w, on, wa);
+        if (rc) return rc;
+        wait_ptr = nullptr;
+    }
+    CopyArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = ms;
+    a.dst = mr;
+    a.units = units;
+    a.wait_ptr = wait_ptr;
+    a.wait_target = wait_target;
+    a.ctl = ctl_of(w);
+    a.done_ptr = done_ptr;
+    a.done_val = done_val;
+    a.me = on->dev;
+    a.ticket_last = on->tickets + nwg - 1;
+    a.status = status;
+    a.st = st;
+    a.set_error = set_error ? 1 : 0;
+    hipEvent_t e0 = nullptr;
+    if (profile_on(w)) prof_begin(w, on->hs, &e0);
+    rc = gpu_err(launch_copy(on->hs, a, wsz, int(nwg)));
+    if (profile_on(w)) prof_end(w, on->hs, e0, 0);
+    if (rc) return rc;
+    if (nwg > 1) on->tickets += nwg;
+    w->n_copy.fetch_add(1, std::memory_order_relaxed);
+    w->bytes_copied.fetch_add(uint64_t(nbytes), std::memory_order_relaxed);
+    return MPIXS_SUCCESS;
+}
+
+// --------------------------------------------------------------- channels
+Channel *get_channel(mpixs_comm_s *c, int src, int dst, int tag, bool host_mode) {
+    const uint64_t key = chan_key(src, dst, tag) | (host_mode ? kModeHost : 0);
+    auto it = c->cache.find(key);
+    if (it != c->cache.end()) return it->second;
+    CommShared *sh = c->sh;
+    Channel *ch = nullptr;
+    {
+        std::lock_guard<std::mutex> g(sh->dir_mu);
+        auto jt = sh->dir.find(key);
+        if (jt != sh->dir.end()) {
+            ch = jt->second;
+        } else {
+            World *w = sh->w;
+            const uint32_t idx = w->chan_next.fetch_add(1);
+            if (idx >= w->chan_cap) return nullptr;
+            ch = new Channel();
+            ch->d = w->d_chans + idx;
+            sh->dir.emplace(key, ch);
+        }
+    }
+    c->cache.emplace(key, ch);
+    return ch;
+}
+
+void rec_release(Channel *ch, Rec *r) {
+    if (r->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+        std::lock_guard<std::mutex> g(ch->mu);
+        ch->collect();
+    }
+}
+
+bool type_ok(mpixs_datatype dt, const TypeObj **t) {
+    *t = type_lookup(dt);
+    return *t != nullptr;
+}
+
+// Argument checks in a fixed order: communicator, count, datatype, peer,
+// tag, overlapping receive type, buffer.
+int check_p2p(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, int peer, int tag,
+              bool recv, const TypeObj **t) {
+    if (!c || !c->sh) return MPIXS_ERR_COMM;
+    if (!c->stream || !c->stream->gpu) return MPIXS_ERR_COMM;
+    if (count < 0) return MPIXS_ERR_COUNT;
+    if (!type_ok(dt, t)) return MPIXS_ERR_TYPE;
+    if (peer < 0 || peer >= c->sh->size) return MPIXS_ERR_RANK;
+    if (tag < 0) return MPIXS_ERR_TAG;
+    if (recv && count > 0 && (*t)->L.overlap) return MPIXS_ERR_TYPE;
+    const int64_t bytes = int64_t(count) * (*t)->L.size;
+    if (bytes > 0 && !buf) return MPIXS_ERR_BUFFER;
+    if (!(*t)->L.dense() && bytes >= (int64_t(1) << 32)) return MPIXS_ERR_COUNT;
+    if (c->sh->w->aborted.load()) return MPIXS_ERR_ABORTED;
+    return MPIXS_SUCCESS;
+}
+
+// First side: wait (host) for the second side's copy launch, then make the
+// stream wait for done >= k+1.  For a receive, the wait kernel writes the
+// status and the sticky error.
+int complete_first(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, int side,
+                   mpixs_status *status) {
+    int rc = host_wait(w, [&] { return rec->copy_enq.load(std::memory_order_acquire) != 0; });
+    if (rc) return rc;
+    WaitArgs a = wait_one(&ch->d->done, k + 1);
+    if (side == 1) {
+        a.status = status;
+        a.st = rec->st;
+    }
+    rc = do_wait(w, st, a);
+    rec_release(ch, rec);
+    return rc;
+}
+
+int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt, int peer,
+        int tag, mpixs_status *status, mpixs_request *req) {
+    const TypeObj *t = nullptr;
+    int rc = check_p2p(c, buf, count, dt, peer, tag, side == 1, &t);
+    if (rc) return rc;
+    World *w = c->sh->w;
+    StreamObj *st = c->stream;
+    const int src = side == 0 ? c->rank : peer;
+    const int dst = side == 0 ? peer : c->rank;
+    Channel *ch = get_channel(c, src, dst, tag, false);
+    if (!ch) return MPIXS_ERR_NOMEM;
+    mpixs_request_s *r = nullptr;
+    if (req) r = new mpixs_request_s();
+    const uint64_t k = ch->seq[side]++;
+    Side me;
+    me.buf = buf;
+    me.count = count;
+    me.t = t;
+    me.bytes = int64_t(count) * t->L.size;
+    me.st = st;
+    me.rank = c->rank;
+    const uint32_t mine = side == 0 ? ARR_S : ARR_R;
+    const uint32_t other = side == 0 ? ARR_R : ARR_S;
+
+    ch->mu.lock();
+    Rec *rec = ch->at(k);
+    (side == 0 ? rec->s : rec->r) = me;
+    const bool second = (rec->arrived.load(std::memory_order_relaxed) & other) != 0;
+    if (second) {
+        ch->mu.unlock();
+        const Side &S = rec->s;
+        const Side &R = rec->r;
+        const StatusVal sv = match_status(S, R, tag);
+        const bool recv_here = side == 1;
+        rc = do_copy(w, st, S, R, sv, &ch->d->ready[1 - side], k + 1, &ch->d->done, k + 1,
+                     (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
+        rec->st = sv;
+        rec->copy_enq.store(1, std::memory_order_release);
+        rec_release(ch, rec);
+        if (r) {
+            r->comm = c;
+            r->side = side;
+            r->second = true;
+            r->st = sv;
+            r->k = k;
+            c->pending.fetch_add(1);
+            *req = r;
+        }
+        return rc;
+    }
+    rc = do_post(w, st, &ch->d->ready[side], k + 1);
+    rec->arrived.fetch_or(mine, std::memory_order_release);
+    ch->mu.unlock();
+    if (rc) {
+        delete r;
+        return rc;
+    }
+    if (!r) return complete_first(w, st, ch, rec, k, side, status);
+    r->comm = c;
+    r->ch = ch;
+    r->rec = rec;
+    r->k = k;
+    r->side = side;
+    r->second = false;
+    c->pending.fetch_add(1);
+    *req = r;
+    return MPIXS_SUCCESS;
+}
+
+// ----------------------------------------------------------------- waits
+int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_status) {
+    if (n < 0) return MPIXS_ERR_COUNT;
+    if (n == 0) return MPIXS_SUCCESS;
+    if (!reqs) return MPIXS_ERR_REQUEST;
+    StreamObj *st = nullptr;
+    for (int i = 0; i < n; ++i) {
+        mpixs_request_s *r = reqs[i];
+        if (!r || !r->comm) return MPIXS_ERR_REQUEST;
+        if (st && r->comm->stream != st) return MPIXS_ERR_STREAM;
+        st = r->comm->stream;
+    }
+    World *w = reqs[0]->comm->sh->w;
+    int rc = MPIXS_SUCCESS;
+    // first-side requests: host-wait for each copy launch, then one wait
+    // kernel per 64 of them; second-side receives only need their status.
+    WaitArgs a;
+    std::memset(&a, 0, sizeof(a));
+    std::vector<std::pair<int, mpixs_request_s *>> batch;
+    auto flush = [&]() -> int {
+        if (a.n == 0) return MPIXS_SUCCESS;
+        int r2 = do_wait(w, st, a);
+        for (auto &pr : batch)
+            if (pr.second->rec) rec_release(pr.second->ch, pr.second->rec);
+        std::memset(&a, 0, sizeof(a));
+        batch.clear();
+        return r2;
+    };
+    for (int i = 0; i < n && !rc; ++i) {
+        mpixs_request_s *r = reqs[i];
+        mpixs_status *status = statuses ? (array_status ? &statuses[i] : statuses) : nullptr;
+        if (r->second) {
+            if (r->side == 1 && status) {
+                // the copy ran on this stream; only the status remains
+                WaitArgs s;
+                std::memset(&s, 0, sizeof(s));
+                s.status = status;
+                s.st = r->st;
+                rc = flush();
+                if (!rc) rc = do_wait(w, st, s);
+            }
+            continue;
+        }
+        rc = host_wait(w, [&] { return r->rec->copy_enq.load(std::memory_order_acquire) != 0; });
+        if (rc) break;
+        if (r->side == 1 && status) {
+            // one status per wait kernel
+            rc = flush();
+            if (rc) break;
+            WaitArgs s = wait_one(&r->ch->d->done, r->k + 1);
+            s.status = status;
+            s.st = r->rec->st;
+            rc = do_wait(w, st, s);
+            rec_release(r->ch, r->rec);
+            r->rec = nullptr;
+            continue;
+        }
+        if (r->side == 1 && r->rec->st.error) {
+            rc = flush();
+            if (rc) break;
+            WaitArgs s = wait_one(&r->ch->d->done, r->k + 1);
+            s.st = r->rec->st;
+            rc = do_wait(w, st, s);
+            rec_release(r->ch, r->rec);
+            r->rec = nullptr;
+            continue;
+        }
+        a.ptr[a.n] = &r->ch->d->done;
+        a.target[a.n] = r->k + 1;
+        a.n++;
+        batch.emplace_back(i, r);
+        if (a.n == 64) rc = flush();
+    }
+    if (!rc) rc = flush();
+    for (int i = 0; i < n; ++i) {
+        mpixs_request_s *r = reqs[i];
+        r->comm->pending.fetch_sub(1);
+        delete r;
+        reqs[i] = nullptr;
+    }
+    return rc;
+}
+
+// -------------------------------------------------------------- allreduce
+int check_allreduce(mpixs_comm_s *c, const void *sendbuf, void *recvbuf, int count,
+                    mpixs_datatype dt, mpixs_op op, bool need_stream) {
+    if (!c || !c->sh) return MPIXS_ERR_COMM;
+    if (need_stream && (!c->stream || !c->stream->gpu)) return MPIXS_ERR_COMM;
+    if (count < 0) return MPIXS_ERR_COUNT;
+    if (dt != MPIXS_INT32 && dt != MPIXS_INT64 && dt != MPIXS_FLOAT32 && dt != MPIXS_FLOAT64)
+        return MPIXS_ERR_TYPE;
+    if (op < MPIXS_SUM || op > MPIXS_MAX) return MPIXS_ERR_OP;
+    if (c->sh->size > 64) return MPIXS_ERR_COMM;
+    if (count > 0 && (!recvbuf || !sendbuf)) return MPIXS_ERR_BUFFER;
+    if (c->sh->w->aborted.load()) return MPIXS_ERR_ABORTED;
+    return MPIXS_SUCCESS;
+}
+
+int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64_t *arrive,
+              uint64_t target, uint64_t *done_ptr, uint64_t done_val) {
+    ReduceArgs a;
+    std::memset(&a, 0, sizeof(a));
+    bool vec = true;
+    for (int q = 0; q < n; ++q) {
+        a.in[q] = rec->in[q];
+        a.out[q] = rec->out[q];
+        vec = vec && (reinterpret_cast<uintptr_t>(rec->in[q]) % 16 == 0) &&
+              (reinterpret_cast<uintptr_t>(rec->out[q]) % 16 == 0);
+    }
+    a.n = n;
+    a.me_rank = me;
+    a.count = uint64_t(rec->count);
+    const int es = basic_size(rec->dtype);
+    const int64_t bytes = int64_t(rec->count) * es;
+    const bool fuse = w->cfg.fuse_max_bytes >= 0 && bytes * n <= int64_t(w->cfg.fuse_max_bytes) * 4;
+    const uint64_t per_thread = vec ? uint64_t(16 / es) : 1;
+    const uint64_t work = (a.count + per_thread - 1) / per_thread;
+    uint64_t nwg = std::max<uint64_t>(1, (work + reduce_threads() - 1) / reduce_threads());
+    nwg = std::min<uint64_t>(nwg, fuse ? 16 : 2048);
+    int rc = MPIXS_SUCCESS;
+    if (arrive && n > 1) {
+        if (fuse) {
+            a.arrive = arrive;
+            a.arrive_target = target;
+        } else {
+            WaitArgs wa;
+            std::memset(&wa, 0, sizeof(wa));
+            for (int q = 0; q < n; ++q) {
+                if (q == me) continue;
+                wa.ptr[wa.n] = arrive + 16 * q;
+                wa.target[wa.n] = target;
+                wa.n++;
+            }
+            rc = do_wait(w, on, wa);
+            if (rc) return rc;
+        }
+    }
+    a.ctl = ctl_of(w);
+    a.done_ptr = done_ptr;
+    a.done_val = done_val;
+    a.me = on->dev;
+    a.ticket_last = on->tickets + nwg - 1;
+    hipEvent_t e0 = nullptr;
+    if (profile_on(w)) prof_begin(w, on->hs, &e0);
+    rc = gpu_err(launch_reduce(on->hs, a, rec->dtype, rec->op, vec, int(nwg)));
+    if (profile_on(w)) prof_end(w, on->hs, e0, 1);
+    if (rc) return rc;
+    if (nwg > 1) on->tickets += nwg;
+    w->n_reduce.fetch_add(1, std::memory_order_relaxed);
+    w->bytes_reduced.fetch_add(uint64_t(2 * bytes * n), std::memory_order_relaxed);
+    return MPIXS_SUCCESS;
+}
+
+CollRec *coll_at(std::deque<CollRec *> &q, uint64_t &base, uint64_t k, int size) {
+    while (base + q.size() <= k) {
+        CollRec *r = new CollRec();
+        r->refs.store(size);
+        q.push_back(r);
+    }
+    return q[k - base];
+}
+
+void coll_collect(std::deque<CollRec *> &q, uint64_t &base) {
+    while (!q.empty() && q.front()->refs.load() == 0) {
+        delete q.front();
+        q.pop_front();
+        ++base;
+    }
+}
+
+int parse_hex(const std::string &s, void *out, size_t n) {
+    if (s.size() != 2 * n) return MPIXS_ERR_ARG;
+    unsigned char *o = static_cast<unsigned char *>(out);
+    for (size_t i = 0; i < n; ++i) {
+        unsigned v = 0;
+        for (int j = 0; j < 2; ++j) {
+            const char ch = s[2 * i + j];
+            unsigned d;
+            if (ch >= '0' && ch <= '9') d = unsigned(ch - '0');
+            else if (ch >= 'a' && ch <= 'f') d = unsigned(ch - 'a' + 10);
+            else if (ch >= 'A' && ch <= 'F') d = unsigned(ch - 'A' + 10);
+            else return MPIXS_ERR_ARG;
+            v = v * 16 + d;
+        }
+        o[i] = static_cast<unsigned char>(v);
+    }
+    return MPIXS_SUCCESS;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ Channel
+Channel::~Channel() {
+    for (Rec *r : recs) delete r;
+}
+
+Rec *Channel::at(uint64_t k) {
+    while (base + recs.size() <= k) recs.push_back(new Rec());
+    return recs[k - base];
+}
+
+void Channel::collect() {
+    while (!recs.empty() && recs.front()->refs.load(std::memory_order_acquire) == 0) {
+        delete recs.front();
+        recs.pop_front();
+        ++base;
+    }
+}
+
+CommShared::~CommShared() {
+    for (auto &kv : dir) delete kv.second;
+    for (CollRec *r : colls) delete r;
+    for (CollRec *r : hcolls) delete r;
+}
+
+}  // namespace mpixs
+
+using namespace mpixs;
+
+extern "C" {
+
+// ================================================================== world
+int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
+    if (!out || nranks < 1 || nranks > 4096) return MPIXS_ERR_ARG;
+    World *w = new World();
+    w->nranks = nranks;
+    if (cfg) w->cfg = *cfg;
+    mpixs_config &c = w->cfg;
+    if (c.max_streams <= 0) c.max_streams = 256;
+    if (c.fuse_max_bytes == 0) c.fuse_max_bytes = 65536;
+    if (c.timeout_ms <= 0) c.timeout_ms = 30000;
+    if (c.max_channels <= 0) c.max_channels = 1 << 20;
+    if (c.max_collectives <= 0) c.max_collectives = 4096;
+    if (hipGetDevice(&w->device) != hipSuccess) {
+        delete w;
+        return MPIXS_ERR_GPU;
+    }
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, w->device) != hipSuccess ||
+        rate_khz <= 0)
+        rate_khz = 100000;
+    w->timeout_ticks = uint64_t(c.timeout_ms) * uint64_t(rate_khz);
+
+    w->stream_cap = std::max(1024, 4 * c.max_streams);
+    w->chan_cap = uint32_t(c.max_channels);
+    w->coll_words = size_t(c.max_collectives) * 16;
+    const size_t s_bytes = size_t(w->stream_cap) * sizeof(DevStream);
+    const size_t c_bytes = size_t(w->chan_cap) * sizeof(DevChan);
+    const size_t k_bytes = w->coll_words * sizeof(uint64_t);
+    const size_t total = s_bytes + c_bytes + k_bytes;
+    if (hipMalloc(reinterpret_cast<void **>(&w->d_pool), total) != hipSuccess) {
+        delete w;
+        return MPIXS_ERR_NOMEM;
+    }
+    if (hipMemset(w->d_pool, 0, total) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(w->d_pool);
+        delete w;
+        return MPIXS_ERR_GPU;
+    }
+    w->d_streams = reinterpret_cast<DevStream *>(w->d_pool);
+    w->d_chans = reinterpret_cast<DevChan *>(w->d_pool + s_bytes);
+    w->d_coll = reinterpret_cast<uint64_t *>(w->d_pool + s_bytes + c_bytes);
+    if (hipHostMalloc(reinterpret_cast<void **>(&w->h_abort), 64, hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipFree(w->d_pool);
+        delete w;
+        return MPIXS_ERR_NOMEM;
+    }
+    *w->h_abort = 0;
+    w->ep_users.assign(size_t(c.max_streams), 0);
+
+    CommShared *sh = new CommShared();
+    sh->w = w;
+    sh->size = nranks;
+    sh->id = 0;
+    sh->streams.assign(size_t(nranks), nullptr);
+    sh->handles.store(nranks);
+    w->world_sh = sh;
+    for (int r = 0; r < nranks; ++r) {
+        mpixs_comm_s *h = new mpixs_comm_s();
+        h->sh = sh;
+        h->rank = r;
+        h->world_handle = true;
+        w->world_handles.push_back(h);
+    }
+    *out = static_cast<mpixs_world>(w);
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_world_comm(mpixs_world w, int rank, mpixs_comm *comm) {
+    if (!w || !comm || rank < 0 || rank >= w->nranks) return MPIXS_ERR_ARG;
+    *comm = w->world_handles[size_t(rank)];
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_world_free(mpixs_world *pw) {
+    if (!pw || !*pw) return MPIXS_ERR_ARG;
+    World *w = *pw;
+    {
+        std::lock_guard<std::mutex> g(w->reg_mu);
+        if (!w->streams.empty() || w->live_comms.load() > 0) return MPIXS_ERR_PENDING;
+    }
+    {
+        std::lock_guard<std::mutex> g(w->prof_mu);
+        for (auto &p : w->prof) {
+            (void)hipEventDestroy(p.e0);
+            (void)hipEventDestroy(p.e1);
+        }
+        w->prof.clear();
+    }
+    (void)hipDeviceSynchronize();
+    (void)hipFree(w->d_pool);
+    (void)hipHostFree(w->h_abort);
+    for (auto *h : w->world_handles) delete h;
+    delete w->world_sh;
+    delete w;
+    *pw = nullptr;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_world_wait(mpixs_world w, int timeout_ms) {
+    if (!w) return MPIXS_ERR_ARG;
+    std::vector<hipStream_t> hs;
+    {
+        std::lock_guard<std::mutex> g(w->reg_mu);
+        for (auto *s : w->streams)
+            if (s->gpu) hs.push_back(s->hs);
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (hipStream_t s : hs) {
+        for (;;) {
+            hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) return MPIXS_ERR_GPU;
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms))
+                return MPIXS_ERR_TIMEOUT;
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+        }
+    }
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_world_abort(mpixs_world w) {
+    if (!w) return MPIXS_ERR_ARG;
+    w->aborted.store(1, std::memory_order_release);
+    __atomic_store_n(w->h_abort, 1u, __ATOMIC_RELEASE);
+    return MPIXS_SUCCESS;
+}
+
+// =================================================================== info
+int mpixs_info_create(mpixs_info *info) {
+    if (!info) return MPIXS_ERR_ARG;
+    *info = new mpixs_info_s();
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_info_set(mpixs_info info, const char *key, const char *value) {
+    if (!info || !key || !value) return MPIXS_ERR_ARG;
+    info->kv[key] = value;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_info_set_hex(mpixs_info info, const char *key, const void *value, int vallen) {
+    if (!info || !key || (vallen > 0 && !value) || vallen < 0) return MPIXS_ERR_ARG;
+    static const char digits[] = "0123456789abcdef";
+    std::string s;
+    s.reserve(size_t(vallen) * 2);
+    const unsigned char *p = static_cast<const unsigned char *>(value);
+    for (int i = 0; i < vallen; ++i) {
+        s.push_back(digits[p[i] >> 4]);
+        s.push_back(digits[p[i] & 15]);
+    }
+    info->kv[key] = s;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_info_get(mpixs_info info, const char *key, char *value, int valuelen, int *flag) {
+    if (!info || !key || !flag) return MPIXS_ERR_ARG;
+    auto it = info->kv.find(key);
+    *flag = it != info->kv.end();
+    if (*flag && value && valuelen > 0) {
+        std::snprintf(value, size_t(valuelen), "%s", it->second.c_str());
+    }
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_info_free(mpixs_info *info) {
+    if (!info || !*info) return MPIXS_ERR_ARG;
+    delete *info;
+    *info = nullptr;
+    return MPIXS_SUCCESS;
+}
+
+// ================================================================= stream
+int mpixs_stream_create(mpixs_world w, mpixs_info info, mpixs_stream *out) {
+    if (!w || !out) return MPIXS_ERR_ARG;
+    bool gpu = false;
+    hipStream_t hs = nullptr;
+    if (info) {
+        auto t = info->kv.find("type");
+        if (t != info->kv.end()) {
+            if (t->second != "hipStream_t") return MPIXS_ERR_ARG;
+            auto v = info->kv.find("value");
+            if (v == info->kv.end()) return MPIXS_ERR_ARG;
+            if (parse_hex(v->second, &hs, sizeof(hs))) return MPIXS_ERR_ARG;
+            gpu = true;
+        }
+    }
+    int ep = -1;
+    {
+        std::lock_guard<std::mutex> g(w->ep_mu);
+        for (int i = 0; i < w->cfg.max_streams; ++i)
+            if (w->ep_users[size_t(i)] == 0) {
+                ep = i;
+                break;
+            }
+        if (ep < 0) {
+            if (w->cfg.endpoint_policy != 1) return MPIXS_ERR_NO_ENDPOINT;
+            ep = w->ep_rr;
+            w->ep_rr = (w->ep_rr + 1) % w->cfg.max_streams;
+        }
+        const int slot = w->stream_next.fetch_add(1);
+        if (slot >= w->stream_cap) return MPIXS_ERR_NOMEM;
+        w->ep_users[size_t(ep)]++;
+        mpixs_stream_s *s = new mpixs_stream_s();
+        s->w = w;
+        s->gpu = gpu;
+        s->hs = hs;
+        s->endpoint = ep;
+        s->dev = w->d_streams + slot;
+        *out = s;
+    }
+    {
+        std::lock_guard<std::mutex> g(w->reg_mu);
+        w->streams.insert(*out);
+    }
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_stream_free(mpixs_stream *ps) {
+    if (!ps || !*ps) return MPIXS_ERR_ARG;
+    mpixs_stream_s *s = *ps;
+    World *w = s->w;
+    if (s->comm_refs.load() > 0) return MPIXS_ERR_PENDING;
+    if (s->gpu) {
+        hipError_t e = hipStreamQuery(s->hs);
+        if (e == hipErrorNotReady) return MPIXS_ERR_PENDING;
+    }
+    {
+        std::lock_guard<std::mutex> g(w->ep_mu);
+        w->ep_users[size_t(s->endpoint)]--;
+    }
+    {
+        std::lock_guard<std::mutex> g(w->reg_mu);
+        w->streams.erase(s);
+    }
+    delete s;
+    *ps = nullptr;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_stream_get_error(mpixs_stream s, int *first_error) {
+    if (!s || !first_error) return MPIXS_ERR_ARG;
+    uint32_t v = 0;
+    // read on the stream itself, so no other stream is waited for
+    if (!s->gpu) {
+        *first_error = 0;
+        return MPIXS_SUCCESS;
+    }
+    if (hipMemcpyAsync(&v, &s->dev->first_error, sizeof(v), hipMemcpyDeviceToHost, s->hs) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->hs) != hipSuccess)
+        return MPIXS_ERR_GPU;
+    *first_error = int(v);
+    return MPIXS_SUCCESS;
+}
+
+// ========================================================== communicator
+int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm *newcomm) {
+    if (!parent || !parent->sh || !newcomm) return MPIXS_ERR_COMM;
+    CommShared *ps = parent->sh;
+    World *w = ps->w;
+    if (s && s->w != w) return MPIXS_ERR_STREAM;
+    const uint64_t k = parent->create_seq++;
+    CommShared *sh = nullptr;
+    {
+        std::unique_lock<std::mutex> g(ps->create_mu);
+        CreateRec &cr = ps->creates[k];
+        if (!cr.sh) {
+            const size_t words = size_t(16) * size_t(ps->size + 1);
+            const size_t off = w->coll_next.fetch_add(words);
+            if (off + words > w->coll_words) return MPIXS_ERR_NOMEM;
+            cr.sh = new CommShared();
+            cr.sh->w = w;
+            cr.sh->size = ps->size;
+            cr.sh->id = w->next_comm_id.fetch_add(1);
+            cr.sh->streams.assign(size_t(ps->size), nullptr);
+            cr.sh->d_coll = w->d_coll + off;
+        }
+        cr.sh->streams[size_t(parent->rank)] = s;
+        cr.arrived++;
+        sh = cr.sh;
+    }
+    // all ranks of the parent must arrive (a collective call, §3.3)
+    int rc = host_wait(w, [&] {
+        std::lock_guard<std::mutex> g(ps->create_mu);
+        return ps->creates[k].arrived == ps->size;
+    });
+    {
+        std::lock_guard<std::mutex> g(ps->create_mu);
+        CreateRec &cr = ps->creates[k];
+        if (++cr.left == ps->size) ps->creates.erase(k);
+    }
+    if (rc) return rc;
+    mpixs_comm_s *c = new mpixs_comm_s();
+    c->sh = sh;
+    c->rank = parent->rank;
+    c->stream = s;
+    if (s) s->comm_refs.fetch_add(1);
+    sh->handles.fetch_add(1);
+    w->live_comms.fetch_add(1);
+    *newcomm = c;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_comm_free(mpixs_comm *pc) {
+    if (!pc || !*pc) return MPIXS_ERR_ARG;
+    mpixs_comm_s *c = *pc;
+    if (c->world_handle) return MPIXS_ERR_COMM;
+    if (c->pending.load() > 0) return MPIXS_ERR_PENDING;
+    World *w = c->sh->w;
+    if (c->stream) c->stream->comm_refs.fetch_sub(1);
+    if (c->sh->handles.fetch_sub(1) == 1) delete c->sh;
+    w->live_comms.fetch_sub(1);
+    delete c;
+    *pc = nullptr;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_comm_rank(mpixs_comm c, int *rank) {
+    if (!c || !rank) return MPIXS_ERR_ARG;
+    *rank = c->rank;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_comm_size(mpixs_comm c, int *size) {
+    if (!c || !size) return MPIXS_ERR_ARG;
+    *size = c->sh->size;
+    return MPIXS_SUCCESS;
+}
+
+// ================================================================ enqueue
+int mpixs_send_enqueue(const void *buf, int count, mpixs_datatype dt, int dest, int tag,
+                       mpixs_comm comm) {
+    return p2p(comm, 0, buf, count, dt, dest, tag, nullptr, nullptr);
+}
+
+int mpixs_recv_enqueue(void *buf, int count, mpixs_datatype dt, int source, int tag,
+                       mpixs_comm comm, mpixs_status *status) {
+    return p2p(comm, 1, buf, count, dt, source, tag, status, nullptr);
+}
+
+int mpixs_isend_enqueue(const void *buf, int count, mpixs_datatype dt, int dest, int tag,
+                        mpixs_comm comm, mpixs_request *request) {
+    if (!request) return MPIXS_ERR_ARG;
+    return p2p(comm, 0, buf, count, dt, dest, tag, nullptr, request);
+}
+
+int mpixs_irecv_enqueue(void *buf, int count, mpixs_datatype dt, int source, int tag,
+                        mpixs_comm comm, mpixs_request *request) {
+    if (!request) return MPIXS_ERR_ARG;
+    return p2p(comm, 1, buf, count, dt, source, tag, nullptr, request);
+}
+
+int mpixs_wait_enqueue(mpixs_request *request, mpixs_status *status) {
+    if (!request) return MPIXS_ERR_REQUEST;
+    return wait_many(1, request, status, false);
+}
+
+int mpixs_waitall_enqueue(int count, mpixs_request requests[], mpixs_status statuses[]) {
+    return wait_many(count, requests, statuses, true);
+}
+
+int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count, mpixs_datatype dt,
+                            mpixs_op op, mpixs_comm c) {
+    int rc = check_allreduce(c, sendbuf, recvbuf, count, dt, op, true);
+    if (rc) return rc;
+    CommShared *sh = c->sh;
+    World *w = sh->w;
+    StreamObj *st = c->stream;
+    const uint64_t k = c->coll_seq++;
+    const int n = sh->size;
+    const void *in = sendbuf == MPIXS_IN_PLACE ? recvbuf : sendbuf;
+    uint64_t *arrive = sh->d_coll;
+    uint64_t *done = sh->d_coll + 16 * n;
+    sh->coll_mu.lock();
+    CollRec *rec = coll_at(sh->colls, sh->coll_base, k, n);
+    rec->in[c->rank] = in;
+    rec->out[c->rank] = recvbuf;
+    if (rec->arrived == 0) {
+        rec->count = count;
+        rec->dtype = dt;
+        rec->op = op;
+    }
+    rec->arrived++;
+    if (rec->arrived == n) {
+        sh->coll_mu.unlock();
+        rc = do_reduce(w, st, rec, n, c->rank, arrive, k + 1, done, k + 1);
+        rec->reduce_enq.store(1, std::memory_order_release);
+    } else {
+        rc = do_post(w, st, arrive + 16 * c->rank, k + 1);
+        sh->coll_mu.unlock();
+        if (!rc) rc = host_wait(w, [&] { return rec->reduce_enq.load(std::memory_order_acquire) != 0; });
+        if (!rc) {
+            WaitArgs a = wait_one(done, k + 1);
+            rc = do_wait(w, st, a);
+        }
+    }
+    if (rec->refs.fetch_sub(1) == 1) {
+        std::lock_guard<std::mutex> g(sh->coll_mu);
+        coll_collect(sh->colls, sh->coll_base);
+    }
+    return rc;
+}
+
+// ========================================================= host-synchronised
+int mpixs_send(const void *buf, int count, mpixs_datatype dt, int dest, int tag, mpixs_comm c) {
+    const TypeObj *t = nullptr;
+    int rc = check_p2p(c, buf, count, dt, dest, tag, false, &t);
+    if (rc) return rc;
+    World *w = c->sh->w;
+    StreamObj *st = c->stream;
+    if (hipStreamSynchronize(st->hs) != hipSuccess) return MPIXS_ERR_GPU;
+    Channel *ch = get_channel(c, c->rank, dest, tag, true);
+    if (!ch) return MPIXS_ERR_NOMEM;
+    const uint64_t k = ch->seq[0]++;
+    Rec *rec;
+    {
+        std::lock_guard<std::mutex> g(ch->mu);
+        rec = ch->at(k);
+        rec->s.buf = buf;
+        rec->s.count = count;
+        rec->s.t = t;
+        rec->s.bytes = int64_t(count) * t->L.size;
+        rec->s.st = st;
+        rec->s.rank = c->rank;
+        rec->arrived.fetch_or(ARR_S, std::memory_order_release);
+    }
+    rc = host_wait(w, [&] { return rec->done_host.load(std::memory_order_acquire) != 0; });
+    rec_release(ch, rec);
+    return rc;
+}
+
+int mpixs_recv(void *buf, int count, mpixs_datatype dt, int source, int tag, mpixs_comm c,
+               mpixs_status *status) {
+    const TypeObj *t = nullptr;
+    int rc = check_p2p(c, buf, count, dt, source, tag, true, &t);
+    if (rc) return rc;
+    World *w = c->sh->w;
+    StreamObj *st = c->stream;
+    if (hipStreamSynchronize(st->hs) != hipSuccess) return MPIXS_ERR_GPU;
+    Channel *ch = get_channel(c, source, c->rank, tag, true);
+    if (!ch) return MPIXS_ERR_NOMEM;
+    const uint64_t k = ch->seq[1]++;
+    Rec *rec;
+    {
+        std::lock_guard<std::mutex> g(ch->mu);
+        rec = ch->at(k);
+        rec->r.buf = buf;
+        rec->r.count = count;
+        rec->r.t = t;
+        rec->r.bytes = int64_t(count) * t->L.size;
+        rec->r.st = st;
+        rec->r.rank = c->rank;
+        rec->arrived.fetch_or(ARR_R, std::memory_order_release);
+    }
+    rc = host_wait(w, [&] { return (rec->arrived.load(std::memory_order_acquire) & ARR_S) != 0; });
+    if (rc) {
+        rec_release(ch, rec);
+        return rc;
+    }
+    Side S, R;
+    {
+        std::lock_guard<std::mutex> g(ch->mu);
+        S = rec->s;
+        R = rec->r;
+    }
+    const StatusVal sv = match_status(S, R, tag);
+    rc = do_copy(w, st, S, R, sv, nullptr, 0, nullptr, 0, status, true);
+    if (!rc && hipStreamSynchronize(st->hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    rec->done_host.store(1, std::memory_order_release);
+    rec_release(ch, rec);
+    return rc;
+}
+
+int mpixs_allreduce(const void *sendbuf, void *recvbuf, int count, mpixs_datatype dt, mpixs_op op,
+                    mpixs_comm c) {
+    int rc = check_allreduce(c, sendbuf, recvbuf, count, dt, op, true);
+    if (rc) return rc;
+    CommShared *sh = c->sh;
+    World *w = sh->w;
+    StreamObj *st = c->stream;
+    if (hipStreamSynchronize(st->hs) != hipSuccess) return MPIXS_ERR_GPU;
+    const uint64_t k = c->hcoll_seq++;
+    const int n = sh->size;
+    CollRec *rec;
+    bool last;
+    {
+        std::lock_guard<std::mutex> g(sh->coll_mu);
+        rec = coll_at(sh->hcolls, sh->hcoll_base, k, n);
+        rec->in[c->rank] = sendbuf == MPIXS_IN_PLACE ? recvbuf : sendbuf;
+        rec->out[c->rank] = recvbuf;
+        if (rec->arrived == 0) {
+            rec->count = count;
+            rec->dtype = dt;
+            rec->op = op;
+        }
+        last = ++rec->arrived == n;
+    }
+    if (last) {
+        rc = do_reduce(w, st, rec, n, c->rank, nullptr, 0, nullptr, 0);
+        if (!rc && hipStreamSynchronize(st->hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+        rec->done_host.store(1, std::memory_order_release);
+    } else {
+        rc = host_wait(w, [&] { return rec->done_host.load(std::memory_order_acquire) != 0; });
+    }
+    if (rec->refs.fetch_sub(1) == 1) {
+        std::lock_guard<std::mutex> g(sh->coll_mu);
+        coll_collect(sh->hcolls, sh->hcoll_base);
+    }
+    return rc;
+}
+
+// ============================================================ diagnostics
+int mpixs_world_get_stats(mpixs_world w, mpixs_stats *s) {
+    if (!w || !s) return MPIXS_ERR_ARG;
+    {
+        std::lock_guard<std::mutex> g(w->prof_mu);
+        std::vector<ProfPair> keep;
+        for (auto &p : w->prof) {
+            float ms = 0;
+            hipError_t e = hipEventElapsedTime(&ms, p.e0, p.e1);
+            if (e == hipErrorNotReady) {
+                keep.push_back(p);
+                continue;
+            }
+            if (e == hipSuccess) {
+                if (p.kind == 0) {
+                    w->timed_copy++;
+                    w->copy_ms += ms;
+                } else {
+                    w->timed_reduce++;
+                    w->reduce_ms += ms;
+                }
+            }
+            (void)hipEventDestroy(p.e0);
+            (void)hipEventDestroy(p.e1);
+        }
+        w->prof.swap(keep);
+    }
+    s->kernels_post = w->n_post.load();
+    s->kernels_wait = w->n_wait.load();
+    s->kernels_copy = w->n_copy.load();
+    s->kernels_reduce = w->n_reduce.load();
+    s->bytes_copied = w->bytes_copied.load();
+    s->bytes_reduced = w->bytes_reduced.load();
+    s->host_waits = w->host_waits.load();
+    s->timed_copy = w->timed_copy;
+    s->copy_ms = w->copy_ms;
+    s->timed_reduce = w->timed_reduce;
+    s->reduce_ms = w->reduce_ms;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_world_reset_stats(mpixs_world w) {
+    if (!w) return MPIXS_ERR_ARG;
+    mpixs_stats tmp;
+    mpixs_world_get_stats(w, &tmp);
+    w->n_post = 0;
+    w->n_wait = 0;
+    w->n_copy = 0;
+    w->n_reduce = 0;
+    w->bytes_copied = 0;
+    w->bytes_reduced = 0;
+    w->host_waits = 0;
+    std::lock_guard<std::mutex> g(w->prof_mu);
+    w->timed_copy = w->timed_reduce = 0;
+    w->copy_ms = w->reduce_ms = 0;
+    return MPIXS_SUCCESS;
+}
+
+// Host-side introspection of the copy plan (no GPU work): the unit size
+// and the source / destination address of every unit the copy kernel would
+// move for a message of `nbytes` packed bytes.
+int mpixs_debug_copy_plan(uint64_t sbuf, int scount, mpixs_datatype stype, uint64_t rbuf,
+                          int rcount, mpixs_datatype rtype, int64_t nbytes, int64_t max_units,
+                          uint64_t *src_addr, uint64_t *dst_addr, int *unit_bytes,
+                          int64_t *nunits) {
+    const TypeObj *ts = type_any(stype);
+    const TypeObj *tr = type_any(rtype);
+    if (!ts || !tr) return MPIXS_ERR_TYPE;
+    if (!unit_bytes || !nunits) return MPIXS_ERR_ARG;
+    // host copies of SEG tables, so uncommitted types can be planned too
+    auto host_table = [](const TypeObj *t, std::vector<SegEnt> &tab) {
+        int64_t pre = 0;
+        for (auto &sg : t->L.segs) {
+            tab.push_back(SegEnt{sg.first, pre});
+            pre += sg.second;
+        }
+    };
+    std::vector<SegEnt> tab_s, tab_r;
+    host_table(ts, tab_s);
+    host_table(tr, tab_r);
+    TypeObj cs = *ts, cr = *tr;
+    cs.table = tab_s.data();
+    cs.nseg = int64_t(tab_s.size());
+    cr.table = tab_r.data();
+    cr.nseg = int64_t(tab_r.size());
+    Side S, R;
+    S.buf = reinterpret_cast<const void *>(sbuf);
+    S.count = scount;
+    S.t = &cs;
+    S.bytes = int64_t(scount) * cs.L.size;
+    R.buf = reinterpret_cast<const void *>(rbuf);
+    R.count = rcount;
+    R.t = &cr;
+    R.bytes = int64_t(rcount) * cr.L.size;
+    DMap ms, mr;
+    int w = 16;
+    uint64_t units = 0;
+    plan_copy(S, R, nbytes, &ms, &mr, &w, &units);
+    *unit_bytes = w;
+    *nunits = int64_t(units);
+    const uint64_t n = std::min<uint64_t>(units, uint64_t(std::max<int64_t>(max_units, 0)));
+    auto addr = [&](const DMap &m, uint64_t u) -> uint64_t {
+        switch (w * 4 + int(m.kind)) {
+#define MPIXS_CASE(W)                                              \
+    case W * 4 + MAP_CONTIG: return map_addr<MAP_CONTIG, W>(m, u); \
+    case W * 4 + MAP_VEC: return map_addr<MAP_VEC, W>(m, u);       \
+    case W * 4 + MAP_SEG: return map_addr<MAP_SEG, W>(m, u);
+            MPIXS_CASE(1)
+            MPIXS_CASE(2)
+            MPIXS_CASE(4)
+            MPIXS_CASE(8)
+            MPIXS_CASE(16)
+#undef MPIXS_CASE
+        default: return ~uint64_t(0);
+        }
+    };
+    for (uint64_t u = 0; u < n; ++u) {
+        if (src_addr) src_addr[u] = addr(ms, u);
+        if (dst_addr) dst_addr[u] = addr(mr, u);
+    }
+    return MPIXS_SUCCESS;
+}
+
+const char *mpixs_error_string(int err) {
+    switch (err) {
+    case MPIXS_SUCCESS: return "SUCCESS";
+    case MPIXS_ERR_ARG: return "ERR_ARG";
+    case MPIXS_ERR_COUNT: return "ERR_COUNT";
+    case MPIXS_ERR_TYPE: return "ERR_TYPE";
+    case MPIXS_ERR_RANK: return "ERR_RANK";
+    case MPIXS_ERR_TAG: return "ERR_TAG";
+    case MPIXS_ERR_COMM: return "ERR_COMM";
+    case MPIXS_ERR_STREAM: return "ERR_STREAM";
+    case MPIXS_ERR_REQUEST: return "ERR_REQUEST";
+    case MPIXS_ERR_BUFFER: return "ERR_BUFFER";
+    case MPIXS_ERR_NO_ENDPOINT: return "ERR_NO_ENDPOINT";
+    case MPIXS_ERR_PENDING: return "ERR_PENDING";
+    case MPIXS_ERR_NOMEM: return "ERR_NOMEM";
+    case MPIXS_ERR_OP: return "ERR_OP";
+    case MPIXS_ERR_TRUNCATE: return "ERR_TRUNCATE";
+    case MPIXS_ERR_TIMEOUT: return "ERR_TIMEOUT";
+    case MPIXS_ERR_ABORTED: return "ERR_ABORTED";
+    case MPIXS_ERR_GPU: return "ERR_GPU";
+    case MPIXS_ERR_INTERN: return "ERR_INTERN";
+    default: return "ERR_UNKNOWN";
+    }
+}
+
+}  // extern "C"

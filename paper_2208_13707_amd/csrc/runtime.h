@@ -1,0 +1,214 @@
+// Host-side objects of libmpixs.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "../../include/mpixs.h"
+#include "mpixs_dev.h"
+
+namespace mpixs {
+
+// ------------------------------------------------------------- datatypes
+// Layout of ONE element of a datatype as byte segments in packed order.
+// REG: nblk segments of blen bytes, segment i at first + i * stride.
+// SEG: an explicit list (adjacent segments merged).
+struct Layout {
+    int basic = 0;
+    int esize = 0;
+    int64_t size = 0;       // sum of entry sizes
+    int64_t lb = 0, ub = 0, extent = 0;
+    bool overlap = false;   // two entries share a byte
+    bool reg = true;
+    int64_t nblk = 0, blen = 0, stride = 0, first = 0;
+    std::vector<std::pair<int64_t, int64_t>> segs;  // (offset, length)
+    int64_t gcd = 0;        // gcd of every segment offset and length
+    bool dense() const { return reg && nblk == 1; }
+};
+
+struct TypeObj {
+    Layout L;
+    bool predefined = false;
+    bool committed = false;
+    SegEnt *table = nullptr;   // SEG form: nseg entries in host-pinned memory
+    int64_t nseg = 0;
+};
+
+// Returns nullptr unless `dt` names a committed datatype.
+const TypeObj *type_lookup(mpixs_datatype dt);
+// Any datatype, committed or not (nullptr if unknown).
+const TypeObj *type_any(mpixs_datatype dt);
+int basic_size(int basic);
+
+// ----------------------------------------------------------------- world
+struct World;
+struct CommShared;
+
+struct StreamObj {
+    World *w = nullptr;
+    bool gpu = false;
+    hipStream_t hs = nullptr;
+    int endpoint = -1;
+    DevStream *dev = nullptr;
+    uint64_t tickets = 0;                 // tickets issued on dev->ticket
+    std::atomic<int> comm_refs{0};
+};
+
+struct Side {
+    const void *buf = nullptr;
+    int count = 0;
+    const TypeObj *t = nullptr;
+    int64_t bytes = 0;
+    StreamObj *st = nullptr;
+    int rank = -1;
+};
+
+enum : uint32_t { ARR_S = 1, ARR_R = 2 };
+
+// Unit size and both address maps of a copy of `nbytes` packed bytes from
+// S's typemap into R's.  seg_s / seg_r override the SEG tables (host-side
+// planning of uncommitted types); nullptr uses the committed tables.
+int plan_copy(const Side &S, const Side &R, int64_t nbytes, DMap *src, DMap *dst, int *wsz,
+              uint64_t *units);
+
+// Host record of message k of a channel: the first side to arrive stores
+// its descriptor, the second side reads it and launches the copy.
+struct Rec {
+    std::atomic<uint32_t> arrived{0};
+    std::atomic<int> copy_enq{0};      // second side launched the copy
+    std::atomic<int> done_host{0};     // host-synchronised path: copy finished
+    std::atomic<int> refs{2};
+    Side s, r;
+    StatusVal st{};
+};
+
+struct Channel {
+    DevChan *d = nullptr;
+    uint64_t seq[2] = {0, 0};          // [0] touched by the source thread, [1] by the destination
+    std::mutex mu;
+    std::deque<Rec *> recs;
+    uint64_t base = 0;                 // sequence number of recs.front()
+    ~Channel();
+    Rec *at(uint64_t k);               // caller holds mu
+    void collect();                    // caller holds mu
+};
+
+struct CollRec {
+    int arrived = 0;
+    std::atomic<int> reduce_enq{0};
+    std::atomic<int> done_host{0};
+    std::atomic<int> refs{0};
+    const void *in[64] = {};
+    void *out[64] = {};
+    int count = 0, dtype = 0, op = 0;
+};
+
+struct CreateRec {
+    int arrived = 0;
+    int left = 0;
+    CommShared *sh = nullptr;
+};
+
+struct CommShared {
+    World *w = nullptr;
+    int size = 0;
+    uint32_t id = 0;
+    std::vector<StreamObj *> streams;
+    std::mutex dir_mu;
+    std::unordered_map<uint64_t, Channel *> dir;
+    std::mutex coll_mu;
+    std::deque<CollRec *> colls;
+    uint64_t coll_base = 0;
+    std::deque<CollRec *> hcolls;      // host-synchronised allreduce instances
+    uint64_t hcoll_base = 0;
+    uint64_t *d_coll = nullptr;        // arrive[q] at 16*q, done at 16*size
+    std::mutex create_mu;
+    std::map<uint64_t, CreateRec> creates;
+    std::atomic<int> handles{0};
+    ~CommShared();
+};
+
+}  // namespace mpixs
+
+struct mpixs_info_s {
+    std::map<std::string, std::string> kv;
+};
+
+struct mpixs_stream_s : mpixs::StreamObj {};
+
+struct mpixs_comm_s {
+    mpixs::CommShared *sh = nullptr;
+    int rank = -1;
+    mpixs::StreamObj *stream = nullptr;
+    std::unordered_map<uint64_t, mpixs::Channel *> cache;
+    uint64_t coll_seq = 0, hcoll_seq = 0, create_seq = 0;
+    std::atomic<int> pending{0};
+    bool world_handle = false;
+};
+
+struct mpixs_request_s {
+    mpixs_comm_s *comm = nullptr;
+    mpixs::Channel *ch = nullptr;
+    mpixs::Rec *rec = nullptr;
+    uint64_t k = 0;
+    int side = 0;                      // 0 send, 1 receive
+    bool second = false;               // this side launched the copy itself
+    mpixs::StatusVal st{};
+};
+
+namespace mpixs {
+
+struct ProfPair {
+    hipEvent_t e0, e1;
+    int kind;                           // 0 copy, 1 reduce
+};
+
+struct World {
+    int nranks = 0;
+    int device = 0;
+    mpixs_config cfg{};
+    char *d_pool = nullptr;
+    DevStream *d_streams = nullptr;
+    int stream_cap = 0;
+    std::atomic<int> stream_next{0};
+    DevChan *d_chans = nullptr;
+    uint32_t chan_cap = 0;
+    std::atomic<uint32_t> chan_next{0};
+    uint64_t *d_coll = nullptr;
+    size_t coll_words = 0;
+    std::atomic<size_t> coll_next{0};
+    uint32_t *h_abort = nullptr;       // host-pinned, read by device waits
+    std::atomic<int> aborted{0};
+    uint64_t timeout_ticks = 0;
+    // endpoints: finite, shared round-robin under policy 1
+    std::mutex ep_mu;
+    std::vector<int> ep_users;
+    int ep_rr = 0;
+    std::atomic<uint32_t> next_comm_id{1};
+    CommShared *world_sh = nullptr;
+    std::vector<mpixs_comm_s *> world_handles;
+    std::mutex reg_mu;
+    std::set<StreamObj *> streams;
+    std::atomic<int> live_comms{0};
+    // statistics
+    std::atomic<uint64_t> n_post{0}, n_wait{0}, n_copy{0}, n_reduce{0};
+    std::atomic<uint64_t> bytes_copied{0}, bytes_reduced{0}, host_waits{0};
+    std::mutex prof_mu;
+    std::vector<ProfPair> prof;
+    uint64_t timed_copy = 0, timed_reduce = 0;
+    double copy_ms = 0, reduce_ms = 0;
+};
+
+}  // namespace mpixs
+
+struct mpixs_world_s : mpixs::World {};

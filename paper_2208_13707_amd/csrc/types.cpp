@@ -1,0 +1,351 @@
+// Datatype table and typemap compiler.
+//
+// A datatype is MPI's typemap (list of basic entries and byte displacements)
+// built by contiguous / vector / indexed from one basic type.  The compiler
+// keeps the typemap of one element as byte segments in packed order and
+// reduces it to one of two forms the copy kernels read:
+//   REG  nblk blocks of blen bytes, block i at first + i * stride
+//        (a basic type, contiguous, a vector of dense blocks, any indexed
+//        type whose blocks turn out evenly spaced);
+//   SEG  an explicit segment list (anything else), uploaded at commit into
+//        host-pinned memory with the packed prefix of every segment.
+// Composition never expands a REG layout unless the result is irregular, so
+// vectors with millions of blocks stay O(1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "runtime.h"
+
+namespace mpixs {
+
+namespace {
+
+constexpr int64_t kMaxSegs = int64_t(1) << 24;
+
+std::mutex g_types_mu;
+std::vector<TypeObj *> g_types;   // index = handle
+
+int64_t gcd64(int64_t a, int64_t b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+void finish_reg(Layout &L) {
+    if (L.nblk == 0 || L.blen == 0) {
+        L.nblk = 0;
+        L.blen = 0;
+        L.stride = 0;
+        L.first = 0;
+        L.size = 0;
+        L.lb = L.ub = L.extent = 0;
+        L.overlap = false;
+        L.gcd = 0;
+        return;
+    }
+    if (L.nblk > 1 && L.stride == L.blen) {      // blocks touch: one dense block
+        L.blen *= L.nblk;
+        L.nblk = 1;
+    }
+    if (L.nblk == 1) L.stride = L.blen;
+    const int64_t last = L.first + (L.nblk - 1) * L.stride;
+    L.lb = std::min(L.first, last);
+    L.ub = std::max(L.first, last) + L.blen;
+    L.extent = L.ub - L.lb;
+    L.size = L.nblk * L.blen;
+    const int64_t as = L.stride < 0 ? -L.stride : L.stride;
+    L.overlap = L.nblk > 1 && as < L.blen;
+    L.gcd = gcd64(gcd64(L.first, L.blen), L.nblk > 1 ? L.stride : 0);
+}
+
+// Adopt a segment list: merge touching neighbours, then reduce to REG when
+// the segments are evenly spaced blocks of one length.
+void finish_seg(Layout &L, std::vector<std::pair<int64_t, int64_t>> segs) {
+    std::vector<std::pair<int64_t, int64_t>> m;
+    m.reserve(segs.size());
+    for (auto &s : segs) {
+        if (s.second == 0) continue;
+        if (!m.empty() && m.back().first + m.back().second == s.first)
+            m.back().second += s.second;
+        else
+            m.push_back(s);
+    }
+    L.segs.clear();
+    if (m.empty()) {
+        L.reg = true;
+        L.nblk = 0;
+        finish_reg(L);
+        return;
+    }
+    bool regular = true;
+    const int64_t len = m[0].second;
+    const int64_t step = m.size() > 1 ? m[1].first - m[0].first : len;
+    for (size_t i = 1; i < m.size() && regular; ++i)
+        regular = m[i].second == len && m[i].first - m[i - 1].first == step;
+    if (regular) {
+        L.reg = true;
+        L.nblk = int64_t(m.size());
+        L.blen = len;
+        L.stride = step;
+        L.first = m[0].first;
+        finish_reg(L);
+        return;
+    }
+    L.reg = false;
+    int64_t lb = m[0].first, ub = m[0].first + m[0].second, size = 0, g = 0;
+    for (auto &s : m) {
+        lb = std::min(lb, s.first);
+        ub = std::max(ub, s.first + s.second);
+        size += s.second;
+        g = gcd64(gcd64(g, s.first), s.second);
+    }
+    L.lb = lb;
+    L.ub = ub;
+    L.extent = ub - lb;
+    L.size = size;
+    L.gcd = g;
+    std::vector<std::pair<int64_t, int64_t>> sorted = m;
+    std::sort(sorted.begin(), sorted.end());
+    L.overlap = false;
+    for (size_t i = 1; i < sorted.size(); ++i)
+        if (sorted[i].first < sorted[i - 1].first + sorted[i - 1].second) L.overlap = true;
+    L.segs = std::move(m);
+}
+
+bool expand(const Layout &T, std::vector<std::pair<int64_t, int64_t>> &out, int64_t shift,
+            int64_t &budget) {
+    if (T.reg) {
+        if (T.nblk > budget) return false;
+        budget -= T.nblk;
+        for (int64_t i = 0; i < T.nblk; ++i) out.emplace_back(shift + T.first + i * T.stride, T.blen);
+    } else {
+        if (int64_t(T.segs.size()) > budget) return false;
+        budget -= int64_t(T.segs.size());
+        for (auto &s : T.segs) out.emplace_back(shift + s.first, s.second);
+    }
+    return true;
+}
+
+// n copies of T, copy i shifted by i * step bytes.
+int hrepeat(int64_t n, int64_t step, const Layout &T, Layout &R) {
+    R = Layout();
+    R.basic = T.basic;
+    R.esize = T.esize;
+    if (n == 0 || T.size == 0) {
+        R.reg = true;
+        R.nblk = 0;
+        finish_reg(R);
+        return MPIXS_SUCCESS;
+    }
+    if (T.reg && T.nblk == 1) {
+        R.reg = true;
+        R.nblk = n;
+        R.blen = T.blen;
+        R.stride = step;
+        R.first = T.first;
+        finish_reg(R);
+        return MPIXS_SUCCESS;
+    }
+    if (T.reg && step == T.nblk * T.stride) {
+        R.reg = true;
+        R.nblk = n * T.nblk;
+        R.blen = T.blen;
+        R.stride = T.stride;
+        R.first = T.first;
+        finish_reg(R);
+        return MPIXS_SUCCESS;
+    }
+    std::vector<std::pair<int64_t, int64_t>> segs;
+    int64_t budget = kMaxSegs;
+    for (int64_t i = 0; i < n; ++i)
+        if (!expand(T, segs, i * step, budget)) return MPIXS_ERR_NOMEM;
+    finish_seg(R, std::move(segs));
+    return MPIXS_SUCCESS;
+}
+
+int add_type(TypeObj *t, mpixs_datatype *out) {
+    std::lock_guard<std::mutex> g(g_types_mu);
+    if (g_types.empty()) g_types.resize(64, nullptr);
+    g_types.push_back(t);
+    *out = mpixs_datatype(g_types.size() - 1);
+    return MPIXS_SUCCESS;
+}
+
+TypeObj *predefined(int basic) {
+    static TypeObj basics[7];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int b = 1; b <= 6; ++b) {
+            TypeObj &t = basics[b];
+            t.predefined = true;
+            t.committed = true;
+            t.L.basic = b;
+            t.L.esize = basic_size(b);
+            t.L.reg = true;
+            t.L.nblk = 1;
+            t.L.blen = t.L.esize;
+            t.L.first = 0;
+            finish_reg(t.L);
+        }
+    });
+    return &basics[basic];
+}
+
+TypeObj *any_type(mpixs_datatype dt) {
+    if (dt >= 1 && dt <= 6) return predefined(dt);
+    std::lock_guard<std::mutex> g(g_types_mu);
+    if (dt < 64 || size_t(dt) >= g_types.size()) return nullptr;
+    return g_types[dt];
+}
+
+int make_derived(const Layout &L, mpixs_datatype *newtype) {
+    if (!newtype) return MPIXS_ERR_ARG;
+    TypeObj *t = new TypeObj();
+    t->L = L;
+    return add_type(t, newtype);
+}
+
+}  // namespace
+
+int basic_size(int basic) {
+    switch (basic) {
+    case MPIXS_UINT8:
+    case MPIXS_INT8: return 1;
+    case MPIXS_INT32:
+    case MPIXS_FLOAT32: return 4;
+    case MPIXS_INT64:
+    case MPIXS_FLOAT64: return 8;
+    default: return 0;
+    }
+}
+
+const TypeObj *type_lookup(mpixs_datatype dt) {
+    const TypeObj *t = any_type(dt);
+    return (t && t->committed) ? t : nullptr;
+}
+
+const TypeObj *type_any(mpixs_datatype dt) { return any_type(dt); }
+
+}  // namespace mpixs
+
+using namespace mpixs;
+
+extern "C" {
+
+int mpixs_type_contiguous(int count, mpixs_datatype oldtype, mpixs_datatype *newtype) {
+    const TypeObj *o = any_type(oldtype);
+    if (!o) return MPIXS_ERR_TYPE;
+    if (count < 0) return MPIXS_ERR_COUNT;
+    Layout R;
+    int rc = hrepeat(count, o->L.extent, o->L, R);
+    if (rc) return rc;
+    return make_derived(R, newtype);
+}
+
+int mpixs_type_vector(int count, int blocklength, int stride, mpixs_datatype oldtype,
+                      mpixs_datatype *newtype) {
+    const TypeObj *o = any_type(oldtype);
+    if (!o) return MPIXS_ERR_TYPE;
+    if (count < 0 || blocklength < 0) return MPIXS_ERR_COUNT;
+    if (stride < 0) return MPIXS_ERR_TYPE;
+    Layout block, R;
+    int rc = hrepeat(blocklength, o->L.extent, o->L, block);
+    if (rc) return rc;
+    if (blocklength == 0 || o->L.size == 0) {
+        rc = hrepeat(0, 0, block, R);
+    } else {
+        rc = hrepeat(count, int64_t(stride) * o->L.extent, block, R);
+    }
+    if (rc) return rc;
+    return make_derived(R, newtype);
+}
+
+int mpixs_type_indexed(int count, const int blocklengths[], const int displacements[],
+                       mpixs_datatype oldtype, mpixs_datatype *newtype) {
+    const TypeObj *o = any_type(oldtype);
+    if (!o) return MPIXS_ERR_TYPE;
+    if (count < 0) return MPIXS_ERR_COUNT;
+    if (count > 0 && (!blocklengths || !displacements)) return MPIXS_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (blocklengths[i] < 0) return MPIXS_ERR_COUNT;
+        if (displacements[i] < 0) return MPIXS_ERR_TYPE;
+    }
+    std::vector<std::pair<int64_t, int64_t>> segs;
+    int64_t budget = kMaxSegs;
+    for (int i = 0; i < count; ++i) {
+        Layout block;
+        int rc = hrepeat(blocklengths[i], o->L.extent, o->L, block);
+        if (rc) return rc;
+        if (!expand(block, segs, int64_t(displacements[i]) * o->L.extent, budget))
+            return MPIXS_ERR_NOMEM;
+    }
+    Layout R;
+    R.basic = o->L.basic;
+    R.esize = o->L.esize;
+    finish_seg(R, std::move(segs));
+    return make_derived(R, newtype);
+}
+
+int mpixs_type_commit(mpixs_datatype *type) {
+    if (!type) return MPIXS_ERR_ARG;
+    TypeObj *t = any_type(*type);
+    if (!t) return MPIXS_ERR_TYPE;
+    if (t->committed) return MPIXS_SUCCESS;
+    if (!t->L.reg) {
+        const int64_t n = int64_t(t->L.segs.size());
+        SegEnt *tab = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void **>(&tab), size_t(n) * sizeof(SegEnt),
+                          hipHostMallocDefault) != hipSuccess)
+            return MPIXS_ERR_NOMEM;
+        int64_t pre = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            tab[i].off = t->L.segs[i].first;
+            tab[i].pre = pre;
+            pre += t->L.segs[i].second;
+        }
+        t->table = tab;
+        t->nseg = n;
+    }
+    t->committed = true;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_type_free(mpixs_datatype *type) {
+    if (!type) return MPIXS_ERR_ARG;
+    if (*type >= 1 && *type <= 6) return MPIXS_ERR_TYPE;
+    std::lock_guard<std::mutex> g(g_types_mu);
+    if (*type < 64 || size_t(*type) >= g_types.size() || !g_types[*type]) return MPIXS_ERR_TYPE;
+    // Tables stay allocated: enqueued operations may still read them, and
+    // freeing pinned memory can synchronise the device.
+    g_types[*type] = nullptr;
+    *type = MPIXS_DATATYPE_NULL;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_type_size(mpixs_datatype type, int64_t *bytes) {
+    const TypeObj *t = any_type(type);
+    if (!t) return MPIXS_ERR_TYPE;
+    if (!bytes) return MPIXS_ERR_ARG;
+    *bytes = t->L.size;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_type_get_extent(mpixs_datatype type, int64_t *lb, int64_t *extent) {
+    const TypeObj *t = any_type(type);
+    if (!t) return MPIXS_ERR_TYPE;
+    if (lb) *lb = t->L.lb;
+    if (extent) *extent = t->L.extent;
+    return MPIXS_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every entry point of include/mpixs.h
+(CPU only: no call here touches the GPU)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpixs.h")
+LIB = os.path.join(ROOT, "paper_2208_13707_amd", "libmpixs.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpixs_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libmpixs.so is not built (run __graft_entry__.build())")
+    from paper_2208_13707_amd import mpixs as M
+    return M.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for required in ("mpixs_stream_create", "mpixs_stream_free", "mpixs_comm_create_with_stream",
+                     "mpixs_send_enqueue", "mpixs_recv_enqueue", "mpixs_isend_enqueue",
+                     "mpixs_wait_enqueue", "mpixs_allreduce_enqueue", "mpixs_info_set_hex"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (mpixs_[a-z_0-9]+)", out))
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    for n in declared():
+        assert hasattr(lib, n)
+
+
+def test_binding_covers_the_header():
+    from paper_2208_13707_amd import mpixs as M
+    missing = [n for n in declared() if n not in M.SIGNATURES or not hasattr(M, n)]
+    assert not missing, missing
+
+
+def test_error_strings(lib):
+    from paper_2208_13707_amd import mpixs as M
+    for code, name in M.ERR_NAMES.items():
+        assert M.mpixs_error_string(code) == name
+
+
+def test_info_hex_encoding(lib):
+    """Info objects are host-only: the hex text of a binary value (§3.2)."""
+    from paper_2208_13707_amd import mpixs as M
+    rc, info = M.mpixs_info_create()
+    assert rc == 0
+    assert M.mpixs_info_set(info, "type", "hipStream_t") == 0
+    assert M.mpixs_info_set_hex(info, "value", bytes([0x00, 0x1f, 0xa0, 0xff])) == 0
+    assert M.mpixs_info_get(info, "value") == (0, "001fa0ff")
+    assert M.mpixs_info_get(info, "type") == (0, "hipStream_t")
+    assert M.mpixs_info_get(info, "nope") == (0, None)
+    assert M.mpixs_info_free(info) == 0

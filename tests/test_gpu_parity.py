@@ -1,0 +1,185 @@
+"""GPU parity: programs run through the libmpixs C ABI on the GPU must give
+exactly the oracle's buffers, statuses and synchronous error codes.
+
+Integer payloads, matching and ordering are compared bit for bit; float32
+reductions are compared bit for bit as well, because both sides fold in
+the canonical rank order with one IEEE rounding per step.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import simulate as sim
+from tests.gpu_runner import compare, run_program
+from workloads import configs as C
+from workloads.program import (
+    ANY_SOURCE, ANY_TAG, Allreduce, Program, Recv, Send, Wait, as_bytes, single_stream,
+)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+def check(p, cfg=None, host_synced=False, name=None):
+    _say(name or p.name)
+    ref = sim.run(p)
+    assert not ref.deadlock, "test program must be safe"
+    g = run_program(p, cfg=cfg, host_synced=host_synced)
+    diffs = compare(p, g, ref)
+    assert not diffs, "\n".join(diffs[:20])
+    return g, ref
+
+
+def cfg_with(**kw):
+    from paper_2208_13707_amd import mpixs as M
+    c = M.Config()
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+# ------------------------------------------------------------------ config 1
+def test_pingpong_small():
+    check(C.pingpong(nmsg=20))
+
+
+def test_pingpong_increment_full_size():
+    g, _ = check(C.pingpong(nmsg=1000, increment=True))
+
+
+# ------------------------------------------------------------- paper examples
+def test_saxpy_example():
+    g, _ = check(C.saxpy_example(n=4099))
+    y = np.frombuffer(g.buffers[1]["y"].tobytes(), np.float32)
+    assert np.all(y == 4.0)
+
+
+def test_threads_example_four_streams_per_rank():
+    check(C.threads_example(nthreads=4))
+
+
+# ------------------------------------------------------------------ config 2
+@pytest.mark.parametrize("count,steps,update,blocking", [
+    (37, 4, False, True), (37, 4, True, False), (2730, 3, True, True), (5461, 2, False, False),
+])
+def test_ring_halo(count, steps, update, blocking):
+    check(C.ring_halo(count=count, steps=steps, update=update, blocking_recv=blocking))
+
+
+def test_ring_halo_full_size_message():
+    """Largest configuration message (count 43690, 524,280 payload bytes)."""
+    check(C.ring_halo(count=43690, steps=3, update=True))
+
+
+@pytest.mark.parametrize("fuse", [-1, 1 << 30])
+def test_ring_halo_fused_and_split_waits(fuse):
+    check(C.ring_halo(count=2730, steps=3, update=True), cfg=cfg_with(fuse_max_bytes=fuse),
+          name=f"halo fuse={fuse}")
+
+
+# ------------------------------------------------------------------ config 3
+@pytest.mark.parametrize("dtype", ["int64", "float32"])
+@pytest.mark.parametrize("nbytes", [4096, 1 << 20])
+def test_allreduce_sum(dtype, nbytes):
+    check(C.allreduce(nbytes, dtype, nranks=16, calls=2))
+
+
+@pytest.mark.parametrize("dtype", ["int64", "float32"])
+def test_allreduce_sum_64mib(dtype):
+    check(C.allreduce(64 << 20, dtype, nranks=16, calls=1))
+
+
+@pytest.mark.parametrize("op", ["prod", "min", "max"])
+@pytest.mark.parametrize("dtype", ["int32", "float64"])
+def test_allreduce_other_ops(op, dtype):
+    check(C.allreduce(12345 * 8, dtype, nranks=5, calls=1, op=op))
+
+
+def test_allreduce_in_place_and_ragged():
+    check(C.allreduce(4 * 1001, "float32", nranks=7, calls=3, in_place=True))
+    check(C.allreduce(8 * 3, "int64", nranks=3, calls=1))
+
+
+# --------------------------------------------------------------- generality
+@pytest.mark.parametrize("seed", range(8))
+def test_random_programs(seed):
+    check(C.random_program(seed, nranks=4, nmsg=40))
+
+
+def test_random_program_many_ranks():
+    check(C.random_program(100, nranks=12, nmsg=150, tags=5, ncomms=3, allreduces=3))
+
+
+def test_batch_small():
+    check(C.batch(npairs=300, nranks=8, max_bytes=65536))
+
+
+# -------------------------------------------------------------- error paths
+def test_truncation_type_mismatch_zero_count():
+    b0 = {"s": as_bytes(np.arange(1, 11, dtype=np.int32))}
+    b1 = {"r": np.full(64, 0xEE, np.uint8)}
+    r0 = [Send("s", 0, 10, "int32", 1, 0), Send("s", 0, 3, "int32", 1, 1),
+          Send("s", 0, 0, "int32", 1, 2)]
+    r1 = [Recv("r", 0, 6, "int32", 0, 0, status="t"),
+          Recv("r", 32, 3, "float32", 0, 1, status="m"),
+          Recv("r", 48, 4, "int32", 0, 2, status="z")]
+    g, _ = check(single_stream(2, [b0, b1], [r0, r1], name="errors"))
+    assert g.stream_errors[1][0] == "ERR_TRUNCATE"
+    assert g.stream_errors[0][0] == "SUCCESS"
+
+
+def test_sync_errors_have_no_side_effects():
+    b0 = {"s": as_bytes(np.array([9, 10], np.int32))}
+    b1 = {"r": np.zeros(8, np.uint8)}
+    r0 = [Send("s", 0, 1, "int32", 5, 0), Send("s", 0, 1, "int32", 1, -3),
+          Send("s", 0, -1, "int32", 1, 0), Send("s", 0, 1, "complex", 1, 0),
+          Send("s", 0, 1, "int32", 1, 0, comm=1), Send("s", 4, 1, "int32", 1, 0)]
+    r1 = [Recv("r", 0, 1, "int32", ANY_SOURCE, 0), Recv("r", 0, 1, "int32", 0, ANY_TAG),
+          Recv("r", 0, 1, ("vector", 2, 2, 1, "int32"), 0, 0),
+          Recv("r", 4, 1, "int32", 0, 0, status="ok"), Wait(["nope"], [None])]
+    check(Program(2, [b0, b1], [[r0], [r1]], 1, [[0, 0], [None, 0]], name="sync-errors"))
+
+
+def test_waitall_across_streams_is_rejected():
+    b0 = {"s": as_bytes(np.array([1, 2], np.int32))}
+    b1 = {"r": np.zeros(8, np.uint8)}
+    r0 = [[Send("s", 0, 1, "int32", 1, 0, comm=0, req="a"),
+           Send("s", 4, 1, "int32", 1, 0, comm=1, req="b"),
+           Wait(["a", "b"], [None, None]), Wait(["a"], [None]), Wait(["b"], [None])]]
+    r1 = [[Recv("r", 0, 1, "int32", 0, 0, comm=0), Recv("r", 4, 1, "int32", 0, 0, comm=1)]]
+    check(Program(2, [b0, b1], [r0, r1], 2, [[0, 0], [1, 1]], name="waitall-streams"))
+
+
+def test_self_messages_and_tag_reordering():
+    b = [{"s": as_bytes(np.arange(100, 106, dtype=np.int32)), "r": np.zeros(24, np.uint8)}]
+    ops = [[Send("s", 0, 1, "int32", 0, 0, req="a"), Send("s", 4, 1, "int32", 0, 1, req="b"),
+            Send("s", 8, 1, "int32", 0, 0, req="c"),
+            Recv("r", 0, 1, "int32", 0, 1, status="x"), Recv("r", 4, 1, "int32", 0, 0),
+            Recv("r", 8, 1, "int32", 0, 0), Wait(["a", "b", "c"], [None] * 3)]]
+    g, _ = check(single_stream(1, b, ops, name="self"))
+    assert np.frombuffer(g.buffers[0]["r"][:12].tobytes(), np.int32).tolist() == [101, 100, 102]
+
+
+# ------------------------------------------------------ host-synced comparator
+def test_host_synced_pingpong_matches():
+    check(C.pingpong(nmsg=40, increment=True), host_synced=True, name="host-synced pingpong")
+
+
+def test_host_synced_allreduce_matches():
+    check(C.allreduce(1 << 16, "float32", nranks=16, calls=2), host_synced=True,
+          name="host-synced allreduce")
+
+
+def test_host_synced_vector_messages_match():
+    count = 2730
+    vt = C.halo_type(count)
+    g = np.random.default_rng(5)
+    bufs = [{"A": as_bytes(g.standard_normal(count * 8).astype(np.float32))},
+            {"H": np.zeros(count * 32, np.uint8)}]
+    ops = [[Send("A", 0, 1, vt, 1, 0), Send("A", 12, 1, vt, 1, 1)],
+           [Recv("H", 0, 1, vt, 0, 0, status="a"), Recv("H", 12, 1, vt, 0, 1, status="b")]]
+    check(single_stream(2, bufs, ops, name="host-synced vector"), host_synced=True)
