@@ -1,0 +1,467 @@
+#!/usr/bin/env python3
+"""Benchmark of stream-ordered enqueue traffic on one MI355X.
+
+Default workload (a "step" = one pass of the ring halo exchange): 8 ranks
+(host threads, one HIP stream each) in a bidirectional ring; every step each
+rank isend_enqueue()s columns 0..2 and 3..5 of its float32[count, 8] array A
+as vector(count, 3, 8, float32) to its right and left neighbours, receives
+the neighbours' halos into H with recv_enqueue() and waitall_enqueue()s its
+sends; tag = step.  count = 43690 (524,280 payload bytes per message), 16
+messages per step.
+
+Prints ONE JSON line: enqueued messages/s (value), payload and algorithmic
+GB/s, the same workload through the host-synchronised path, p50/p99 step
+latency, the roofline of the dominant kernel (the typemap copy), and the CPU
+oracle timed on a bounded sample of the same workload.
+
+Other workloads (--workload): pingpong (2 ranks, 1000 x 4 KiB int32),
+allreduce (16 ranks, SUM, --bytes per rank, --dtype), copy (one contiguous
+message of --bytes between two ranks).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
+
+
+# ------------------------------------------------------------------ helpers
+def make_vector(M, count, bl, stride, base):
+    rc, t = M.mpixs_type_vector(count, bl, stride, base)
+    assert rc == 0
+    rc, t = M.mpixs_type_commit(t)
+    assert rc == 0
+    return t
+
+
+def halo_ops(D, r, n, A, H, vt, steps, tag0, mode, marks=False, status_ptr=0):
+    right, left = (r + 1) % n, (r - 1) % n
+    rows = []
+    a0, a3 = A.data_ptr(), A.data_ptr() + 12
+    h0, h3 = H.data_ptr(), H.data_ptr() + 12
+    for s in range(steps):
+        tag = tag0 + s
+        if marks:
+            rows.append(dict(kind=D.MARK, req=2 * s))
+        if mode == 0:
+            rows += [dict(kind=D.ISEND, peer=right, tag=tag, count=1, datatype=vt, buf=a0, req=0),
+                     dict(kind=D.ISEND, peer=left, tag=tag, count=1, datatype=vt, buf=a3, req=1),
+                     dict(kind=D.RECV, peer=left, tag=tag, count=1, datatype=vt, buf=h0,
+                          status=status_ptr),
+                     dict(kind=D.RECV, peer=right, tag=tag, count=1, datatype=vt, buf=h3),
+                     dict(kind=D.WAITALL, req=0, nreq=2)]
+        else:
+            # blocking, deadlock-free ring order for an even number of ranks
+            sr = dict(kind=D.SEND, peer=right, tag=tag, count=1, datatype=vt, buf=a0)
+            rl = dict(kind=D.RECV, peer=left, tag=tag, count=1, datatype=vt, buf=h0,
+                      status=status_ptr)
+            sl = dict(kind=D.SEND, peer=left, tag=tag, count=1, datatype=vt, buf=a3)
+            rr = dict(kind=D.RECV, peer=right, tag=tag, count=1, datatype=vt, buf=h3)
+            rows += [sr, rl, sl, rr] if r % 2 == 0 else [rl, sr, rr, sl]
+        if marks:
+            rows.append(dict(kind=D.MARK, req=2 * s + 1))
+    return D.ops_array(rows)
+
+
+def run_checked(sess, ops, mode=0, nmarks=0):
+    from paper_2208_13707_amd import mpixs as M
+    rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks)
+    if rc:
+        raise RuntimeError(f"driver: {M.errname(rc)} at thread {res.error_thread} op {res.error_op}")
+    return res.seconds, marks
+
+
+def step_latencies(marks, steps):
+    lat = []
+    for s in range(steps):
+        start = marks[:, 2 * s].min()
+        end = marks[:, 2 * s + 1].max()
+        lat.append((end - start) * 1000.0)   # us
+    return lat
+
+
+# ------------------------------------------------------------------ halo
+def halo_cpu_baseline(count, budget_s=15.0):
+    """The oracle as it stands on a bounded sample of the same workload."""
+    from oracle import simulate as sim
+    from workloads import configs as C
+    t0 = time.perf_counter()
+    sim.run(C.ring_halo(count=count, steps=1))
+    t1 = time.perf_counter() - t0
+    steps = int(max(1, min(100, budget_s / max(t1, 1e-3))))
+    p = C.ring_halo(count=count, steps=steps)
+    t0 = time.perf_counter()
+    sim.run(p)
+    dt = time.perf_counter() - t0
+    msgs = 16 * steps
+    return {"value": msgs / dt, "unit": "msgs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} ring-halo steps ({msgs} messages of {12 * count} bytes), "
+                      f"8 ranks, single-threaded numpy simulator, {dt:.1f} s"}
+
+
+def bench_halo(args):
+    import numpy as np
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    from workloads import configs as C
+
+    n, steps, warm = 8, args.steps, args.warmup
+    counts = [args.count] + ([c for c in C.HALO_COUNTS if c != args.count] if args.sweep else [])
+    out_sweep = []
+    headline = None
+    for count in counts:
+        p = C.ring_halo(count=count, steps=1)
+        A = [torch.from_numpy(p.buffers[r]["A"].copy()).cuda() for r in range(n)]
+        H = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
+        torch.cuda.synchronize()
+        vt = make_vector(M, count, 3, 8, M.FLOAT32)
+        payload = 12 * count
+        res = {"count": count, "payload_bytes": payload}
+        # ---- enqueue path: warmup, then K timed steps
+        sess = D.Session(n)
+        ops = [halo_ops(D, r, n, A[r], H[r], vt, warm, 0, 0) for r in range(n)]
+        run_checked(sess, ops)
+        ops = [halo_ops(D, r, n, A[r], H[r], vt, steps, 0, 0) for r in range(n)]
+        torch.cuda.synchronize()
+        sec, _ = run_checked(sess, ops)
+        st = sess.stats()
+        msgs = 16 * steps
+        res.update(msgs_per_s=msgs / sec, ms_per_step=1000 * sec / steps,
+                   gbps_payload=msgs * payload / sec / 1e9,
+                   gbps_algorithmic=2 * msgs * payload / sec / 1e9,
+                   kernels_per_msg=(st.kernels_post + st.kernels_wait + st.kernels_copy) /
+                   max(1, 16 * (steps + warm)))
+        # ---- latency pass (HIP events at step boundaries on every stream)
+        ops = [halo_ops(D, r, n, A[r], H[r], vt, steps, 0, 0, marks=True) for r in range(n)]
+        _, marks = run_checked(sess, ops, nmarks=2 * steps)
+        lat = step_latencies(marks, steps)
+        res.update(p50_step_us=pct(lat, 50), p99_step_us=pct(lat, 99))
+        sess.close()
+        # ---- correctness against the oracle (sampled: after any step, H holds
+        # the neighbours' halo columns; the oracle runs one full-size step)
+        if count == args.count:
+            from oracle import simulate as sim
+            ref = sim.run(p)
+            for r in range(n):
+                got = H[r].cpu().numpy()
+                if not np.array_equal(got, ref.buffers[r]["H"]):
+                    raise AssertionError(f"rank {r}: halo differs from the oracle")
+        # ---- host-synchronised path, same workload and buffers
+        if not args.no_host_synced:
+            H2 = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
+            torch.cuda.synchronize()
+            hs_steps = max(1, min(steps, args.hs_steps))
+            sess = D.Session(n)
+            ops = [halo_ops(D, r, n, A[r], H2[r], vt, min(warm, 5), 10000, 1) for r in range(n)]
+            run_checked(sess, ops, mode=1)
+            ops = [halo_ops(D, r, n, A[r], H2[r], vt, hs_steps, 10000, 1) for r in range(n)]
+            sec_hs, _ = run_checked(sess, ops, mode=1)
+            sess.close()
+            res["host_synced_msgs_per_s"] = 16 * hs_steps / sec_hs
+            res["speedup_vs_host_synced"] = res["msgs_per_s"] / res["host_synced_msgs_per_s"]
+            for r in range(n):
+                if not torch.equal(H2[r], H[r]):
+                    raise AssertionError(f"rank {r}: host-synced path differs from enqueue path")
+        # ---- profiled pass: HIP events around every copy kernel; copies run
+        # split (wait kernel, data kernel, signal kernel) so that the timed
+        # kernel only moves data
+        if count == args.count:
+            cfg = M.Config()
+            cfg.profile = 1
+            cfg.fuse_max_bytes = -1
+            sess = D.Session(n, cfg)
+            ops = [halo_ops(D, r, n, A[r], H[r], vt, steps, 0, 0) for r in range(n)]
+            sec_p, _ = run_checked(sess, ops)
+            torch.cuda.synchronize()
+            st = sess.stats()
+            sess.close()
+            avg_ms = st.copy_ms / max(1, st.timed_copy)
+            res["copy_kernels_timed"] = int(st.timed_copy)
+            res["copy_kernel_avg_us"] = avg_ms * 1000
+            res["profiled_msgs_per_s"] = 16 * steps / sec_p
+            headline = res
+        out_sweep.append(res)
+        log(f"[halo] count={count}: {res['msgs_per_s']:.0f} msgs/s, "
+            f"{res['gbps_algorithmic']:.1f} GB/s alg, "
+            f"host-synced {res.get('host_synced_msgs_per_s', 0):.0f} msgs/s")
+
+    h = headline
+    per_launch = 2 * h["payload_bytes"]
+    achieved = per_launch / (h["copy_kernel_avg_us"] * 1e-6) / 1e9
+    line = {
+        "metric": "enqueued msgs/s + GB/s (frac of HBM peak) vs host-synced path; p50/p99 latency",
+        "value": h["msgs_per_s"],
+        "unit": "msgs/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ring_halo_8ranks_vector(count={h['count']},bl=3,stride=8)_f32",
+                   "ranks": n, "count": h["count"], "payload_bytes": h["payload_bytes"],
+                   "msgs_per_step": 16, "parallelism": "1 GPU, 8 rank threads"},
+        "gbps_payload": h["gbps_payload"],
+        "gbps_algorithmic": h["gbps_algorithmic"],
+        "hbm_frac": h["gbps_algorithmic"] / HBM_PEAK_GBS,
+        "host_synced": {"value": h.get("host_synced_msgs_per_s"), "unit": "msgs/s",
+                        "speedup": h.get("speedup_vs_host_synced")},
+        "latency_us": {"p50": h["p50_step_us"], "p99": h["p99_step_us"], "of": "halo step"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_copy<4,VEC,VEC,split>", "bytes_per_launch": per_launch,
+                     "avg_launch_us": h["copy_kernel_avg_us"],
+                     "launches_timed": h["copy_kernels_timed"]},
+        "sweep": out_sweep if args.sweep else None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = halo_cpu_baseline(h["count"], args.cpu_budget)
+    return line
+
+
+# --------------------------------------------------------------- allreduce
+def bench_allreduce(args):
+    import numpy as np
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    from workloads import configs as C
+
+    n = args.ranks
+    nbytes = args.bytes
+    dtype = args.dtype
+    esize = {"int32": 4, "int64": 8, "float32": 4, "float64": 8}[dtype]
+    count = nbytes // esize
+    p = C.allreduce(nbytes, dtype, nranks=n, calls=1)
+    S = [torch.from_numpy(p.buffers[r]["send"]).cuda() for r in range(n)]
+    R = [torch.zeros(nbytes, dtype=torch.uint8, device="cuda") for _ in range(n)]
+    torch.cuda.synchronize()
+
+    def ops(k, marks=False):
+        out = []
+        for r in range(n):
+            rows = []
+            for s in range(k):
+                if marks:
+                    rows.append(dict(kind=D.MARK, req=2 * s))
+                rows.append(dict(kind=D.ALLREDUCE, count=count, datatype=M.BASIC[dtype],
+                                 op=M.SUM, buf=S[r].data_ptr(), buf2=R[r].data_ptr()))
+                if marks:
+                    rows.append(dict(kind=D.MARK, req=2 * s + 1))
+            out.append(D.ops_array(rows))
+        return out
+
+    sess = D.Session(n)
+    run_checked(sess, ops(args.warmup))
+    sec, _ = run_checked(sess, ops(args.steps))
+    _, marks = run_checked(sess, ops(args.steps, True), nmarks=2 * args.steps)
+    lat = step_latencies(marks, args.steps)
+    sess.close()
+    # sampled check against the oracle's fold (every 4097th element)
+    from oracle import reduce as red
+    idx = np.arange(0, count, 4097)
+    ins = [np.frombuffer(p.buffers[r]["send"].tobytes(), dtype=dtype)[idx] for r in range(n)]
+    want = red.fold("sum", ins)
+    for r in (0, n - 1):
+        got = np.frombuffer(R[r].cpu().numpy().tobytes(), dtype=dtype)[idx]
+        assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), "allreduce != oracle"
+    hs = None
+    if not args.no_host_synced:
+        sess = D.Session(n)
+        run_checked(sess, ops(min(args.warmup, 3)), mode=1)
+        k = max(1, min(args.steps, args.hs_steps))
+        sec_hs, _ = run_checked(sess, ops(k), mode=1)
+        sess.close()
+        hs = k / sec_hs
+    cfg = M.Config()
+    cfg.profile = 1
+    sess = D.Session(n, cfg)
+    run_checked(sess, ops(args.steps))
+    torch.cuda.synchronize()
+    st = sess.stats()
+    sess.close()
+    avg_us = 1000 * st.reduce_ms / max(1, st.timed_reduce)
+    per_launch = 2 * n * nbytes
+    achieved = per_launch / (avg_us * 1e-6) / 1e9
+    calls_per_s = args.steps / sec
+    line = {
+        "metric": "enqueued allreduce calls/s + GB/s (frac of HBM peak) vs host-synced path",
+        "value": calls_per_s, "unit": "calls/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000 * sec / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"float32": "f32", "int64": "int64",
+                                                          "int32": "int32", "float64": "f64"}[dtype],
+        "data": "synthetic",
+        "config": {"workload": f"allreduce_sum_{n}ranks_{dtype}_{nbytes}B_per_rank", "ranks": n,
+                   "bytes_per_rank": nbytes},
+        "gbps_algorithmic": per_launch * calls_per_s / 1e9,
+        "hbm_frac": per_launch * calls_per_s / 1e9 / HBM_PEAK_GBS,
+        "host_synced": {"value": hs, "unit": "calls/s",
+                        "speedup": calls_per_s / hs if hs else None},
+        "latency_us": {"p50": pct(lat, 50), "p99": pct(lat, 99), "of": "allreduce call"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_reduce<{dtype},SUM,vec>", "bytes_per_launch": per_launch,
+                     "avg_launch_us": avg_us, "launches_timed": int(st.timed_reduce)},
+    }
+    return line
+
+
+# ---------------------------------------------------------------- pingpong
+def bench_pingpong(args):
+    import numpy as np
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    from workloads import configs as C
+
+    nmsg = 1000
+    p = C.pingpong(nmsg=2)
+    X = [torch.from_numpy(p.buffers[r]["x"].copy()).cuda() for r in range(2)]
+    torch.cuda.synchronize()
+
+    def ops(rounds, mode, marks=False):
+        r0, r1 = [], []
+        for s in range(rounds):
+            if marks:
+                r0.append(dict(kind=D.MARK, req=2 * s))
+            r0 += [dict(kind=D.SEND, peer=1, tag=0, count=1024, datatype=M.INT32, buf=X[0].data_ptr()),
+                   dict(kind=D.RECV, peer=1, tag=0, count=1024, datatype=M.INT32, buf=X[0].data_ptr())]
+            if marks:
+                r0.append(dict(kind=D.MARK, req=2 * s + 1))
+            r1 += [dict(kind=D.RECV, peer=0, tag=0, count=1024, datatype=M.INT32, buf=X[1].data_ptr()),
+                   dict(kind=D.SEND, peer=0, tag=0, count=1024, datatype=M.INT32, buf=X[1].data_ptr())]
+        return [D.ops_array(r0), D.ops_array(r1)]
+
+    out = {}
+    for mode in (0, 1):
+        if mode == 1 and args.no_host_synced:
+            continue
+        sess = D.Session(2)
+        run_checked(sess, ops(20, mode), mode=mode)
+        sec, _ = run_checked(sess, ops(nmsg // 2, mode), mode=mode)
+        if mode == 0:
+            _, marks = run_checked(sess, ops(nmsg // 2, mode, True), mode=mode, nmarks=nmsg)
+            rtt = [(marks[0, 2 * s + 1] - marks[0, 2 * s]) * 1000 for s in range(nmsg // 2)]
+            out["one_way_p50_us"] = pct(rtt, 50) / 2
+            out["one_way_p99_us"] = pct(rtt, 99) / 2
+        sess.close()
+        out[mode] = nmsg / sec
+    assert np.array_equal(X[0].cpu().numpy(), p.buffers[0]["x"]), "echo changed the data"
+    return {
+        "metric": "enqueued msgs/s vs host-synced path; p50/p99 one-way latency",
+        "value": out[0], "unit": "msgs/s", "n_gpus": 1, "steps": nmsg, "warmup": 40,
+        "ms_per_step": 1000 / out[0], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "pingpong_2ranks_1000x1024_int32"},
+        "host_synced": {"value": out.get(1), "unit": "msgs/s",
+                        "speedup": out[0] / out[1] if 1 in out else None},
+        "latency_us": {"p50": out["one_way_p50_us"], "p99": out["one_way_p99_us"],
+                       "of": "one-way (round trip / 2)"},
+    }
+
+
+# -------------------------------------------------------------------- copy
+def bench_copy(args):
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+
+    nbytes = args.bytes
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+
+    def ops(k):
+        r0 = [dict(kind=D.SEND, peer=1, tag=7, count=nbytes, datatype=M.UINT8, buf=src.data_ptr())
+              for _ in range(k)]
+        r1 = [dict(kind=D.RECV, peer=0, tag=7, count=nbytes, datatype=M.UINT8, buf=dst.data_ptr())
+              for _ in range(k)]
+        return [D.ops_array(r0), D.ops_array(r1)]
+
+    cfg = M.Config()
+    cfg.profile = 1 if args.profile_copy else 0
+    sess = D.Session(2, cfg)
+    run_checked(sess, ops(args.warmup))
+    sess.reset_stats()
+    sec, _ = run_checked(sess, ops(args.steps))
+    torch.cuda.synchronize()
+    st = sess.stats()
+    sess.close()
+    assert torch.equal(src, dst)
+    gbps = 2 * nbytes * args.steps / sec / 1e9
+    line = {
+        "metric": "contiguous message GB/s (frac of HBM peak)", "value": gbps, "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000 * sec / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"send_recv_contiguous_{nbytes}B_2ranks"},
+        "hbm_frac": gbps / HBM_PEAK_GBS,
+    }
+    if args.profile_copy:
+        avg_us = 1000 * st.copy_ms / max(1, st.timed_copy)
+        ach = 2 * nbytes / (avg_us * 1e-6) / 1e9
+        line["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                            "kernel": "k_copy<16,CONTIG,CONTIG>", "bytes_per_launch": 2 * nbytes,
+                            "avg_launch_us": avg_us, "launches_timed": int(st.timed_copy)}
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="halo",
+                    choices=["halo", "pingpong", "allreduce", "copy"])
+    ap.add_argument("--count", type=int, default=43690)
+    ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")
+    ap.add_argument("--bytes", type=int, default=None)
+    ap.add_argument("--dtype", default="float32")
+    ap.add_argument("--ranks", type=int, default=16)
+    ap.add_argument("--hs-steps", type=int, default=100)
+    ap.add_argument("--no-host-synced", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--profile-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(ranks are host threads sharing one MI355X)", file=sys.stderr)
+        sys.exit(2)
+    defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3)}
+    k, w = defaults[args.workload]
+    args.steps = args.steps or k
+    args.warmup = args.warmup if args.warmup is not None else w
+    if args.bytes is None:
+        args.bytes = {"allreduce": 64 << 20, "copy": 1 << 30}.get(args.workload, 0)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    fn = {"halo": bench_halo, "allreduce": bench_allreduce, "pingpong": bench_pingpong,
+          "copy": bench_copy}[args.workload]
+    line = fn(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

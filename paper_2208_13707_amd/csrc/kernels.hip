@@ -93,6 +93,17 @@ __global__ void __launch_bounds__(64) k_wait(WaitArgs a) {
     }
 }
 
+// Completion after a data kernel of the same stream: the kernel boundary
+// already made its stores visible at agent scope, so one release store
+// publishes them.
+__global__ void __launch_bounds__(64) k_signal(SignalArgs a) {
+    if (threadIdx.x != 0) return;
+    const uint32_t fatal = ld_relaxed32(&a.me->fatal);
+    if (a.status) write_status(a.status, a.st, fatal);
+    if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
+    if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+}
+
 // ------------------------------------------------------------------ maps
 template <int W> struct Unit;
 template <> struct Unit<1> { using T = uint8_t; };
@@ -101,13 +112,17 @@ template <> struct Unit<4> { using T = uint32_t; };
 template <> struct Unit<8> { using T = uint64_t; };
 template <> struct Unit<16> { using T = __attribute__((ext_vector_type(4))) uint32_t; };
 
-// Shared tail of the copy and reduce kernels: every wave releases its
-// stores, the workgroups draw tickets, the last one publishes completion.
+// Tail of the fused (small) copy and reduce kernels.  The barrier makes the
+// workgroup's stores complete in its XCD's L2; one agent-scope release by
+// thread 0 then writes that L2 back before the workgroup draws a ticket, and
+// the last workgroup publishes completion.  (A release in every wave costs
+// an L2 writeback per wave; large transfers instead end at the kernel
+// boundary and a separate signal kernel publishes them.)
 __device__ __forceinline__ bool last_workgroup(DevStream *me, uint64_t ticket_last) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     __shared__ int s_last;
     if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         s_last = 1;
         if (gridDim.x > 1) {
             const uint64_t t = __hip_atomic_fetch_add(&me->ticket, uint64_t(1), __ATOMIC_ACQ_REL,
@@ -123,46 +138,75 @@ __device__ __forceinline__ bool last_workgroup(DevStream *me, uint64_t ticket_la
 // Unit u of the packed message goes from map_src(u) to map_dst(u); W is the
 // largest power of two (<= 16) that divides every block boundary and base
 // address of both sides, so each unit is one aligned load and one store.
+// Workgroups take chunks of COPY_THREADS * U consecutive units; within a
+// chunk lane i handles units i, i + 256, ... so every load and store
+// instruction of a wave covers consecutive units.
+//
+// FUSED: small messages, at most kFusedMaxWG workgroups that loop over the
+// chunks with U = 4 units per lane in flight.  Thread 0 of every workgroup
+// first waits for the other side's ready counter, and the last workgroup
+// publishes completion.
+// Otherwise (large messages): one chunk of 256 units per workgroup, one
+// unit per lane, streaming (nontemporal) loads and stores -- the fastest
+// shape measured on gfx950 -- and nothing else: the stream waited before the
+// kernel and a k_signal follows it.
 constexpr int COPY_THREADS = 256;
-constexpr int COPY_UNROLL = 4;
+constexpr int COPY_UNROLL_FUSED = 4;
 
-template <int W, int SK, int DK>
+template <typename T, bool NT>
+__device__ __forceinline__ T ld_unit(uint64_t addr) {
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const T *>(addr));
+    else return *reinterpret_cast<const T *>(addr);
+}
+
+template <typename T, bool NT>
+__device__ __forceinline__ void st_unit(uint64_t addr, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<T *>(addr));
+    else *reinterpret_cast<T *>(addr) = v;
+}
+
+template <int W, int SK, int DK, bool FUSED>
 __global__ void __launch_bounds__(COPY_THREADS) k_copy(CopyArgs a) {
     using T = typename Unit<W>::T;
+    constexpr int COPY_UNROLL = FUSED ? COPY_UNROLL_FUSED : 1;
+    constexpr bool NT = !FUSED;
     __shared__ uint32_t s_fatal;
     if (threadIdx.x == 0) {
         uint32_t f = ld_relaxed32(&a.me->fatal);
-        if (!f && a.wait_ptr) {
+        if (FUSED && !f && a.wait_ptr) {
             f = spin_wait(a.wait_ptr, a.wait_target, a.ctl);
             if (f) set_fatal(a.me, f);
         }
         s_fatal = f;
     }
     __syncthreads();
-    if (a.wait_ptr) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (FUSED && a.wait_ptr) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!s_fatal) {
         const uint64_t n = a.units;
-        const uint64_t stride = uint64_t(gridDim.x) * COPY_THREADS;
-        for (uint64_t u0 = uint64_t(blockIdx.x) * COPY_THREADS + threadIdx.x; u0 < n;
-             u0 += stride * COPY_UNROLL) {
+        constexpr uint64_t CH = uint64_t(COPY_THREADS) * COPY_UNROLL;
+        const uint64_t nch = (n + CH - 1) / CH;
+        for (uint64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+            const uint64_t b = c * CH + threadIdx.x;
             T v[COPY_UNROLL];
 #pragma unroll
             for (int k = 0; k < COPY_UNROLL; ++k) {
-                const uint64_t u = u0 + uint64_t(k) * stride;
-                if (u < n) v[k] = *reinterpret_cast<const T *>(map_addr<SK, W>(a.src, u));
+                const uint64_t u = b + uint64_t(k) * COPY_THREADS;
+                if (u < n) v[k] = ld_unit<T, NT>(map_addr<SK, W>(a.src, u));
             }
 #pragma unroll
             for (int k = 0; k < COPY_UNROLL; ++k) {
-                const uint64_t u = u0 + uint64_t(k) * stride;
-                if (u < n) *reinterpret_cast<T *>(map_addr<DK, W>(a.dst, u)) = v[k];
+                const uint64_t u = b + uint64_t(k) * COPY_THREADS;
+                if (u < n) st_unit<T, NT>(map_addr<DK, W>(a.dst, u), v[k]);
             }
         }
     }
-    if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
-        const uint32_t fatal = ld_relaxed32(&a.me->fatal);
-        if (a.status) write_status(a.status, a.st, fatal);
-        if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
-        if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+    if constexpr (FUSED) {
+        if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
+            const uint32_t fatal = ld_relaxed32(&a.me->fatal);
+            if (a.status) write_status(a.status, a.st, fatal);
+            if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
+            if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+        }
     }
 }
 
@@ -187,16 +231,20 @@ __device__ __forceinline__ T combine(T acc, T x) {
 }
 
 constexpr int RED_THREADS = 256;
-constexpr int RED_GROUP = 8;    // inputs loaded back to back before folding
+constexpr int RED_GROUP = 16;   // inputs loaded back to back before folding
 
 // out_q[i] = (((in_0[i] op in_1[i]) op in_2[i]) ... op in_{n-1}[i]) for every q:
-// the left fold in rank order, each element owned by one lane.
-template <typename T, int OP, bool VEC>
+// the left fold in rank order, each element owned by one lane (16 bytes of
+// elements per lane when every buffer is 16-byte aligned).  Workgroups take
+// chunks of RED_THREADS vectors.  FUSED: small collectives; threads q < n
+// of every workgroup wait for rank q's arrive counter first and the last
+// workgroup publishes done.
+template <typename T, int OP, bool VEC, bool FUSED>
 __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
     __shared__ uint32_t s_fatal;
     if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
     __syncthreads();
-    if (a.arrive && !s_fatal) {
+    if (FUSED && a.arrive && !s_fatal) {
         uint32_t err = 0;
         const int q = threadIdx.x;
         if (q < a.n && q != a.me_rank) err = spin_wait(a.arrive + q * 16, a.arrive_target, a.ctl);
@@ -208,19 +256,22 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
     }
     if (!s_fatal) {
         const int n = a.n;
-        const uint64_t gtid = uint64_t(blockIdx.x) * RED_THREADS + threadIdx.x;
-        const uint64_t nthreads = uint64_t(gridDim.x) * RED_THREADS;
-        if constexpr (VEC) {
-            constexpr int L = 16 / sizeof(T);
-            using V = T __attribute__((ext_vector_type(L)));
-            const uint64_t nvec = a.count / L;
-            for (uint64_t v = gtid; v < nvec; v += nthreads) {
-                V acc = reinterpret_cast<const V *>(a.in[0])[v];
+        constexpr int L = VEC ? int(16 / sizeof(T)) : 1;
+        using V = T __attribute__((ext_vector_type(L)));
+        const uint64_t nvec = a.count / L;
+        const uint64_t nch = (nvec + RED_THREADS - 1) / RED_THREADS;
+        for (uint64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+            const uint64_t v = c * RED_THREADS + threadIdx.x;
+            if (v < nvec) {
+                constexpr bool NT = !FUSED;
+                V acc = ld_unit<V, NT>(reinterpret_cast<uint64_t>(reinterpret_cast<const V *>(a.in[0]) + v));
                 for (int q0 = 1; q0 < n; q0 += RED_GROUP) {
                     V x[RED_GROUP];
 #pragma unroll
                     for (int j = 0; j < RED_GROUP; ++j)
-                        if (q0 + j < n) x[j] = reinterpret_cast<const V *>(a.in[q0 + j])[v];
+                        if (q0 + j < n)
+                            x[j] = ld_unit<V, NT>(
+                                reinterpret_cast<uint64_t>(reinterpret_cast<const V *>(a.in[q0 + j]) + v));
 #pragma unroll
                     for (int j = 0; j < RED_GROUP; ++j)
                         if (q0 + j < n) {
@@ -228,17 +279,15 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
                             for (int l = 0; l < L; ++l) acc[l] = combine<T, OP>(acc[l], x[j][l]);
                         }
                 }
-                for (int q = 0; q < n; ++q) reinterpret_cast<V *>(a.out[q])[v] = acc;
+                for (int q = 0; q < n; ++q)
+                    st_unit<V, NT>(reinterpret_cast<uint64_t>(reinterpret_cast<V *>(a.out[q]) + v), acc);
             }
-            // tail elements
-            for (uint64_t i = nvec * L + gtid; i < a.count; i += nthreads) {
-                T acc = reinterpret_cast<const T *>(a.in[0])[i];
-                for (int q = 1; q < n; ++q)
-                    acc = combine<T, OP>(acc, reinterpret_cast<const T *>(a.in[q])[i]);
-                for (int q = 0; q < n; ++q) reinterpret_cast<T *>(a.out[q])[i] = acc;
-            }
-        } else {
-            for (uint64_t i = gtid; i < a.count; i += nthreads) {
+        }
+        if constexpr (VEC) {
+            // tail elements that do not fill a vector
+            const uint64_t gtid = uint64_t(blockIdx.x) * RED_THREADS + threadIdx.x;
+            const uint64_t i = nvec * L + gtid;
+            if (i < a.count) {
                 T acc = reinterpret_cast<const T *>(a.in[0])[i];
                 for (int q = 1; q < n; ++q)
                     acc = combine<T, OP>(acc, reinterpret_cast<const T *>(a.in[q])[i]);
@@ -246,8 +295,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
             }
         }
     }
-    if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
-        if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+    if constexpr (FUSED) {
+        if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
+            if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+        }
     }
 }
 
@@ -262,63 +313,80 @@ hipError_t launch_wait(hipStream_t s, const WaitArgs &a) {
     return hipGetLastError();
 }
 
-int copy_block_units() { return COPY_THREADS * COPY_UNROLL; }
+int copy_block_units(bool fused) { return COPY_THREADS * (fused ? COPY_UNROLL_FUSED : 1); }
 
-template <int W, int SK>
+hipError_t launch_signal(hipStream_t s, const SignalArgs &a) {
+    hipLaunchKernelGGL(k_signal, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int W, int SK, bool F>
 static hipError_t copy_dk(hipStream_t s, const CopyArgs &a, int dk, int nwg) {
     switch (dk) {
-    case MAP_CONTIG: hipLaunchKernelGGL((k_copy<W, SK, MAP_CONTIG>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
-    case MAP_VEC: hipLaunchKernelGGL((k_copy<W, SK, MAP_VEC>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_copy<W, SK, MAP_SEG>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case MAP_CONTIG: hipLaunchKernelGGL((k_copy<W, SK, MAP_CONTIG, F>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case MAP_VEC: hipLaunchKernelGGL((k_copy<W, SK, MAP_VEC, F>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_copy<W, SK, MAP_SEG, F>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
     }
     return hipGetLastError();
 }
 
-template <int W>
+template <int W, bool F>
 static hipError_t copy_w(hipStream_t s, const CopyArgs &a, int nwg) {
     switch (a.src.kind) {
-    case MAP_CONTIG: return copy_dk<W, MAP_CONTIG>(s, a, a.dst.kind, nwg);
-    case MAP_VEC: return copy_dk<W, MAP_VEC>(s, a, a.dst.kind, nwg);
-    default: return copy_dk<W, MAP_SEG>(s, a, a.dst.kind, nwg);
+    case MAP_CONTIG: return copy_dk<W, MAP_CONTIG, F>(s, a, a.dst.kind, nwg);
+    case MAP_VEC: return copy_dk<W, MAP_VEC, F>(s, a, a.dst.kind, nwg);
+    default: return copy_dk<W, MAP_SEG, F>(s, a, a.dst.kind, nwg);
     }
 }
 
-hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg) {
+template <bool F>
+static hipError_t copy_f(hipStream_t s, const CopyArgs &a, int w, int nwg) {
     switch (w) {
-    case 16: return copy_w<16>(s, a, nwg);
-    case 8: return copy_w<8>(s, a, nwg);
-    case 4: return copy_w<4>(s, a, nwg);
-    case 2: return copy_w<2>(s, a, nwg);
-    default: return copy_w<1>(s, a, nwg);
+    case 16: return copy_w<16, F>(s, a, nwg);
+    case 8: return copy_w<8, F>(s, a, nwg);
+    case 4: return copy_w<4, F>(s, a, nwg);
+    case 2: return copy_w<2, F>(s, a, nwg);
+    default: return copy_w<1, F>(s, a, nwg);
     }
+}
+
+hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg, bool fused) {
+    return fused ? copy_f<true>(s, a, w, nwg) : copy_f<false>(s, a, w, nwg);
 }
 
 int reduce_threads() { return RED_THREADS; }
 
-template <typename T, int OP>
+template <typename T, int OP, bool F>
 static hipError_t reduce_op(hipStream_t s, const ReduceArgs &a, bool vec, int nwg) {
-    if (vec) hipLaunchKernelGGL((k_reduce<T, OP, true>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_reduce<T, OP, false>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
+    if (vec) hipLaunchKernelGGL((k_reduce<T, OP, true, F>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_reduce<T, OP, false, F>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool F>
 static hipError_t reduce_t(hipStream_t s, const ReduceArgs &a, int op, bool vec, int nwg) {
     switch (op) {
-    case OP_SUM: return reduce_op<T, OP_SUM>(s, a, vec, nwg);
-    case OP_PROD: return reduce_op<T, OP_PROD>(s, a, vec, nwg);
-    case OP_MIN: return reduce_op<T, OP_MIN>(s, a, vec, nwg);
-    default: return reduce_op<T, OP_MAX>(s, a, vec, nwg);
+    case OP_SUM: return reduce_op<T, OP_SUM, F>(s, a, vec, nwg);
+    case OP_PROD: return reduce_op<T, OP_PROD, F>(s, a, vec, nwg);
+    case OP_MIN: return reduce_op<T, OP_MIN, F>(s, a, vec, nwg);
+    default: return reduce_op<T, OP_MAX, F>(s, a, vec, nwg);
     }
 }
 
-hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg) {
+template <bool F>
+static hipError_t reduce_f(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec,
+                           int nwg) {
     switch (basic) {
-    case MPIXS_INT32: return reduce_t<int32_t>(s, a, op, vec, nwg);
-    case MPIXS_INT64: return reduce_t<int64_t>(s, a, op, vec, nwg);
-    case MPIXS_FLOAT32: return reduce_t<float>(s, a, op, vec, nwg);
-    default: return reduce_t<double>(s, a, op, vec, nwg);
+    case MPIXS_INT32: return reduce_t<int32_t, F>(s, a, op, vec, nwg);
+    case MPIXS_INT64: return reduce_t<int64_t, F>(s, a, op, vec, nwg);
+    case MPIXS_FLOAT32: return reduce_t<float, F>(s, a, op, vec, nwg);
+    default: return reduce_t<double, F>(s, a, op, vec, nwg);
     }
+}
+
+hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg,
+                         bool fused) {
+    return fused ? reduce_f<true>(s, a, basic, op, vec, nwg) : reduce_f<false>(s, a, basic, op, vec, nwg);
 }
 
 }  // namespace mpixs

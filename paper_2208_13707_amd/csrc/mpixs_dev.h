@@ -170,6 +170,18 @@ struct CopyArgs {
     int32_t pad;
 };
 
+// Completion of a message or collective after the stream's data kernel:
+// optional status and sticky error, then done = val.
+struct SignalArgs {
+    uint64_t *done_ptr;
+    uint64_t done_val;
+    DevStream *me;
+    void *status;
+    StatusVal st;
+    int32_t set_error;
+    int32_t pad;
+};
+
 enum RedOp : int32_t { OP_SUM = 1, OP_PROD = 2, OP_MIN = 3, OP_MAX = 4 };
 
 struct ReduceArgs {

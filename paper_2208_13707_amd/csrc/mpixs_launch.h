@@ -8,9 +8,11 @@ namespace mpixs {
 
 hipError_t launch_post(hipStream_t s, uint64_t *p, uint64_t v);
 hipError_t launch_wait(hipStream_t s, const WaitArgs &a);
-hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg);
-hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg);
-int copy_block_units();   // units one copy workgroup moves per loop trip
+hipError_t launch_signal(hipStream_t s, const SignalArgs &a);
+hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg, bool fused);
+hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg,
+                         bool fused);
+int copy_block_units(bool fused);   // units in one copy chunk (one workgroup pass)
 int reduce_threads();
 
 }  // namespace mpixs

@@ -49,6 +49,12 @@ namespace {
 
 constexpr uint64_t kModeHost = uint64_t(1) << 63;
 
+// Largest grid of a fused kernel, whose workgroups poll before they work.
+// With at most 32 hardware queues per process (one running kernel each),
+// polling workgroups hold at most 32 * 32 * 4 = 4096 of the chip's 8192+
+// wave slots, so the kernels they wait for always find room.
+constexpr uint64_t kFusedMaxWG = 32;
+
 int gpu_err(hipError_t e) { return e == hipSuccess ? MPIXS_SUCCESS : MPIXS_ERR_GPU; }
 
 uint64_t chan_key(int src, int dst, int tag) {
@@ -238,37 +244,61 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
     uint64_t units = 0;
     plan_copy(S, R, nbytes, &ms, &mr, &wsz, &units);
     const bool fuse = w->cfg.fuse_max_bytes >= 0 && nbytes <= w->cfg.fuse_max_bytes;
-    const uint64_t per_wg = uint64_t(copy_block_units());
-    uint64_t nwg = std::max<uint64_t>(1, (units + per_wg - 1) / per_wg);
-    nwg = std::min<uint64_t>(nwg, fuse ? 16 : 2048);
-    int rc = MPIXS_SUCCESS;
-    if (wait_ptr && !fuse) {
-        WaitArgs wa = wait_one(wait_ptr, wait_target);
-        rc = do_wait(w, on, wa);
-        if (rc) return rc;
-        wait_ptr = nullptr;
-    }
+    const uint64_t per_chunk = uint64_t(copy_block_units(fuse));
+    const uint64_t nchunks = std::max<uint64_t>(1, (units + per_chunk - 1) / per_chunk);
     CopyArgs a;
     std::memset(&a, 0, sizeof(a));
     a.src = ms;
     a.dst = mr;
     a.units = units;
-    a.wait_ptr = wait_ptr;
-    a.wait_target = wait_target;
     a.ctl = ctl_of(w);
-    a.done_ptr = done_ptr;
-    a.done_val = done_val;
     a.me = on->dev;
-    a.ticket_last = on->tickets + nwg - 1;
-    a.status = status;
-    a.st = st;
-    a.set_error = set_error ? 1 : 0;
+    int rc = MPIXS_SUCCESS;
     hipEvent_t e0 = nullptr;
-    if (profile_on(w)) prof_begin(w, on->hs, &e0);
-    rc = gpu_err(launch_copy(on->hs, a, wsz, int(nwg)));
-    if (profile_on(w)) prof_end(w, on->hs, e0, 0);
-    if (rc) return rc;
-    if (nwg > 1) on->tickets += nwg;
+    if (fuse) {
+        // one kernel: wait, copy, publish (bounded grid, see kFusedMaxWG)
+        const uint64_t nwg = std::min<uint64_t>(nchunks, kFusedMaxWG);
+        a.wait_ptr = wait_ptr;
+        a.wait_target = wait_target;
+        a.done_ptr = done_ptr;
+        a.done_val = done_val;
+        a.ticket_last = on->tickets + nwg - 1;
+        a.status = status;
+        a.st = st;
+        a.set_error = set_error ? 1 : 0;
+        if (profile_on(w)) prof_begin(w, on->hs, &e0);
+        rc = gpu_err(launch_copy(on->hs, a, wsz, int(nwg), true));
+        if (profile_on(w)) prof_end(w, on->hs, e0, 0);
+        if (rc) return rc;
+        if (nwg > 1) on->tickets += nwg;
+    } else {
+        // wait kernel, full-grid data kernel, signal kernel
+        if (wait_ptr) {
+            WaitArgs wa = wait_one(wait_ptr, wait_target);
+            rc = do_wait(w, on, wa);
+            if (rc) return rc;
+        }
+        if (units > 0) {
+            const uint64_t nwg = std::min<uint64_t>(nchunks, uint64_t(1) << 22);
+            if (profile_on(w)) prof_begin(w, on->hs, &e0);
+            rc = gpu_err(launch_copy(on->hs, a, wsz, int(nwg), false));
+            if (profile_on(w)) prof_end(w, on->hs, e0, 0);
+            if (rc) return rc;
+        }
+        if (done_ptr || status || (set_error && st.error)) {
+            SignalArgs sg;
+            std::memset(&sg, 0, sizeof(sg));
+            sg.done_ptr = done_ptr;
+            sg.done_val = done_val;
+            sg.me = on->dev;
+            sg.status = status;
+            sg.st = st;
+            sg.set_error = set_error ? 1 : 0;
+            rc = gpu_err(launch_signal(on->hs, sg));
+            if (rc) return rc;
+            w->n_post.fetch_add(1, std::memory_order_relaxed);
+        }
+    }
     w->n_copy.fetch_add(1, std::memory_order_relaxed);
     w->bytes_copied.fetch_add(uint64_t(nbytes), std::memory_order_relaxed);
     return MPIXS_SUCCESS;
@@ -529,17 +559,30 @@ int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64
     a.count = uint64_t(rec->count);
     const int es = basic_size(rec->dtype);
     const int64_t bytes = int64_t(rec->count) * es;
-    const bool fuse = w->cfg.fuse_max_bytes >= 0 && bytes * n <= int64_t(w->cfg.fuse_max_bytes) * 4;
+    const bool fuse = w->cfg.fuse_max_bytes >= 0 && bytes * n <= int64_t(w->cfg.fuse_max_bytes);
     const uint64_t per_thread = vec ? uint64_t(16 / es) : 1;
     const uint64_t work = (a.count + per_thread - 1) / per_thread;
-    uint64_t nwg = std::max<uint64_t>(1, (work + reduce_threads() - 1) / reduce_threads());
-    nwg = std::min<uint64_t>(nwg, fuse ? 16 : 2048);
+    const uint64_t nchunks = std::max<uint64_t>(1, (work + reduce_threads() - 1) / reduce_threads());
     int rc = MPIXS_SUCCESS;
-    if (arrive && n > 1) {
-        if (fuse) {
+    a.ctl = ctl_of(w);
+    a.me = on->dev;
+    hipEvent_t e0 = nullptr;
+    if (fuse) {
+        const uint64_t nwg = std::min<uint64_t>(nchunks, kFusedMaxWG);
+        if (arrive && n > 1) {
             a.arrive = arrive;
             a.arrive_target = target;
-        } else {
+        }
+        a.done_ptr = done_ptr;
+        a.done_val = done_val;
+        a.ticket_last = on->tickets + nwg - 1;
+        if (profile_on(w)) prof_begin(w, on->hs, &e0);
+        rc = gpu_err(launch_reduce(on->hs, a, rec->dtype, rec->op, vec, int(nwg), true));
+        if (profile_on(w)) prof_end(w, on->hs, e0, 1);
+        if (rc) return rc;
+        if (nwg > 1) on->tickets += nwg;
+    } else {
+        if (arrive && n > 1) {
             WaitArgs wa;
             std::memset(&wa, 0, sizeof(wa));
             for (int q = 0; q < n; ++q) {
@@ -551,18 +594,22 @@ int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64
             rc = do_wait(w, on, wa);
             if (rc) return rc;
         }
+        const uint64_t nwg = std::min<uint64_t>(nchunks, uint64_t(1) << 22);
+        if (profile_on(w)) prof_begin(w, on->hs, &e0);
+        rc = gpu_err(launch_reduce(on->hs, a, rec->dtype, rec->op, vec, int(nwg), false));
+        if (profile_on(w)) prof_end(w, on->hs, e0, 1);
+        if (rc) return rc;
+        if (done_ptr) {
+            SignalArgs sg;
+            std::memset(&sg, 0, sizeof(sg));
+            sg.done_ptr = done_ptr;
+            sg.done_val = done_val;
+            sg.me = on->dev;
+            rc = gpu_err(launch_signal(on->hs, sg));
+            if (rc) return rc;
+            w->n_post.fetch_add(1, std::memory_order_relaxed);
+        }
     }
-    a.ctl = ctl_of(w);
-    a.done_ptr = done_ptr;
-    a.done_val = done_val;
-    a.me = on->dev;
-    a.ticket_last = on->tickets + nwg - 1;
-    hipEvent_t e0 = nullptr;
-    if (profile_on(w)) prof_begin(w, on->hs, &e0);
-    rc = gpu_err(launch_reduce(on->hs, a, rec->dtype, rec->op, vec, int(nwg)));
-    if (profile_on(w)) prof_end(w, on->hs, e0, 1);
-    if (rc) return rc;
-    if (nwg > 1) on->tickets += nwg;
     w->n_reduce.fetch_add(1, std::memory_order_relaxed);
     w->bytes_reduced.fetch_add(uint64_t(2 * bytes * n), std::memory_order_relaxed);
     return MPIXS_SUCCESS;
@@ -644,7 +691,7 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     if (cfg) w->cfg = *cfg;
     mpixs_config &c = w->cfg;
     if (c.max_streams <= 0) c.max_streams = 256;
-    if (c.fuse_max_bytes == 0) c.fuse_max_bytes = 65536;
+    if (c.fuse_max_bytes == 0) c.fuse_max_bytes = 2 << 20;
     if (c.timeout_ms <= 0) c.timeout_ms = 30000;
     if (c.max_channels <= 0) c.max_channels = 1 << 20;
     if (c.max_collectives <= 0) c.max_collectives = 4096;

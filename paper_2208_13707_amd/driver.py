@@ -1,0 +1,182 @@
+"""ctypes binding of the native program runner (include/mpixs_driver.h) and
+a small session helper that sets up a world, one HIP stream per rank and a
+stream communicator per rank.
+
+Everything here marshals arguments; all work happens in libmpixs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import struct
+import threading
+from typing import List, Optional
+
+import numpy as np
+
+from . import mpixs as M
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+DRIVER_PATH = os.path.join(_HERE, "libmpixs_driver.so")
+
+SEND, ISEND, RECV, IRECV, WAITALL, ALLREDUCE, MARK = 1, 2, 3, 4, 5, 6, 7
+
+OP_DTYPE = np.dtype([
+    ("kind", "<i4"), ("comm", "<i4"), ("peer", "<i4"), ("tag", "<i4"), ("count", "<i4"),
+    ("datatype", "<i4"), ("op", "<i4"), ("req", "<i4"), ("nreq", "<i4"), ("pad", "<i4"),
+    ("buf", "<u8"), ("buf2", "<u8"), ("status", "<u8"),
+])
+assert OP_DTYPE.itemsize == 64
+
+
+class DrvThread(ctypes.Structure):
+    _fields_ = [("comms", ctypes.c_void_p * 8), ("ncomms", ctypes.c_int32),
+                ("nmarks", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
+                ("ops", ctypes.c_void_p), ("nops", ctypes.c_int64),
+                ("max_reqs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class DrvResult(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("first_error", ctypes.c_int32),
+                ("error_thread", ctypes.c_int32), ("error_op", ctypes.c_int64)]
+
+
+_dlib = None
+_hip = None
+
+
+def _hiplib():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        _hip.hipStreamCreateWithFlags.restype = ctypes.c_int
+        _hip.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+        _hip.hipStreamDestroy.restype = ctypes.c_int
+    return _hip
+
+
+def hip_stream_create() -> int:
+    """A new non-blocking HIP stream at the default priority (its own handle,
+    unlike torch's pooled streams, so any number of ranks get distinct ones)."""
+    s = ctypes.c_void_p()
+    rc = _hiplib().hipStreamCreateWithFlags(ctypes.byref(s), 1)   # hipStreamNonBlocking
+    if rc != 0:
+        raise RuntimeError(f"hipStreamCreateWithFlags failed: {rc}")
+    return s.value
+
+
+def hip_stream_destroy(s: int) -> None:
+    _hiplib().hipStreamDestroy(s)
+
+
+def dlib():
+    global _dlib
+    if _dlib is None:
+        M.lib()
+        if not os.path.exists(DRIVER_PATH):
+            raise RuntimeError(f"{DRIVER_PATH} is missing: run `python -m paper_2208_13707_amd.build`")
+        L = ctypes.CDLL(DRIVER_PATH)
+        L.mpixs_drv_run.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(DrvThread),
+                                    ctypes.c_int, ctypes.POINTER(DrvResult),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.mpixs_drv_run.restype = ctypes.c_int
+        _dlib = L
+    return _dlib
+
+
+def ops_array(rows) -> np.ndarray:
+    """rows: list of dicts with OP_DTYPE field names (missing fields are 0)."""
+    a = np.zeros(len(rows), dtype=OP_DTYPE)
+    for i, r in enumerate(rows):
+        for k, v in r.items():
+            a[i][k] = v
+    return a
+
+
+def mpixs_drv_run(world, threads_ops: List[np.ndarray], comms: List[List[int]],
+                  streams: List[int], mode: int = 0, nmarks: int = 0, max_reqs: int = 64):
+    n = len(threads_ops)
+    arr = (DrvThread * n)()
+    keep = []
+    for i in range(n):
+        ops = np.ascontiguousarray(threads_ops[i], dtype=OP_DTYPE)
+        keep.append(ops)
+        for j, c in enumerate(comms[i]):
+            arr[i].comms[j] = c
+        arr[i].ncomms = len(comms[i])
+        arr[i].nmarks = nmarks
+        arr[i].hip_stream = streams[i]
+        arr[i].ops = ops.ctypes.data
+        arr[i].nops = len(ops)
+        arr[i].max_reqs = max_reqs
+    res = DrvResult()
+    marks = np.full(max(1, n * nmarks), -1.0)
+    rc = dlib().mpixs_drv_run(world, n, arr, mode, ctypes.byref(res),
+                              marks.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return rc, res, marks[: n * nmarks].reshape(n, nmarks) if nmarks else None
+
+
+class Session:
+    """A world of ``nranks`` ranks, each with its own torch stream, mpixs
+    stream and stream communicator (created collectively from rank threads)."""
+
+    def __init__(self, nranks: int, cfg: Optional[M.Config] = None):
+        import torch
+        torch.cuda.init()
+        self.nranks = nranks
+        self.hs = [hip_stream_create() for _ in range(nranks)]
+        rc, self.world = M.mpixs_world_create(nranks, cfg)
+        if rc:
+            raise RuntimeError(f"world_create: {M.errname(rc)}")
+        self.streams: List[Optional[int]] = [None] * nranks
+        self.comms: List[Optional[int]] = [None] * nranks
+        errs = []
+
+        def setup(r):
+            try:
+                rc, wc = M.mpixs_world_comm(self.world, r)
+                rc, info = M.mpixs_info_create()
+                M.mpixs_info_set(info, "type", "hipStream_t")
+                M.mpixs_info_set_hex(info, "value", struct.pack("<Q", self.hs[r]))
+                rc, s = M.mpixs_stream_create(self.world, info)
+                assert rc == 0, M.errname(rc)
+                M.mpixs_info_free(info)
+                self.streams[r] = s
+                rc, c = M.mpixs_comm_create_with_stream(wc, s)
+                assert rc == 0, M.errname(rc)
+                self.comms[r] = c
+            except Exception as e:  # pragma: no cover - reported below
+                errs.append(repr(e))
+
+        th = [threading.Thread(target=setup, args=(r,)) for r in range(nranks)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if errs:
+            raise RuntimeError("; ".join(errs))
+
+    @property
+    def hip_streams(self):
+        return list(self.hs)
+
+    def run(self, threads_ops, mode=0, nmarks=0, max_reqs=64):
+        return mpixs_drv_run(self.world, threads_ops, [[c] for c in self.comms],
+                             self.hip_streams, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
+
+    def stats(self):
+        return M.mpixs_world_get_stats(self.world)[1]
+
+    def reset_stats(self):
+        M.mpixs_world_reset_stats(self.world)
+
+    def close(self):
+        import torch
+        torch.cuda.synchronize()
+        for r in range(self.nranks):
+            M.mpixs_comm_free(self.comms[r])
+            M.mpixs_stream_free(self.streams[r])
+        M.mpixs_world_free(self.world)
+        for s in self.hs:
+            hip_stream_destroy(s)

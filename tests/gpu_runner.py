@@ -102,8 +102,9 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
     layout, wait_block = _status_layout(p)
     dstat = [torch.full((max(1, n) * M.STATUS_BYTES,), 0xEE, dtype=torch.uint8, device=dev)
              for _, n in layout]
-    tstreams = [[torch.cuda.Stream(device=dev) for _ in range(p.streams_per_rank)]
-                for _ in range(N)]
+    from paper_2208_13707_amd import driver as D
+    hip_streams = [[D.hip_stream_create() for _ in range(p.streams_per_rank)] for _ in range(N)]
+    tstreams = [[torch.cuda.ExternalStream(h, device=dev) for h in row] for row in hip_streams]
     torch.cuda.synchronize()
 
     rc, world = M.mpixs_world_create(N, cfg)
@@ -296,6 +297,9 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
             rc = M.mpixs_stream_free(mstreams[r][s])
             assert rc == 0, M.errname(rc)
     assert M.mpixs_world_free(world) == 0
+    for row in hip_streams:
+        for h in row:
+            D.hip_stream_destroy(h)
     return GpuResult(out_bufs, statuses, [sorted(e) for e in sync_errors], stream_errors, st)
 
 
