@@ -32,6 +32,25 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from the committed counter runs, or
+    None when the kernel sources changed since those counters were taken."""
+    import hashlib
+    import json as _json
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        rec = _json.load(open(path))
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_2208_13707_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "mpixs_dev.h"):
+        h.update(open(os.path.join(src, f), "rb").read())
+    if h.hexdigest() != rec.get("kernels_sha256") or key not in rec:
+        return None
+    return rec[key]["read_bytes"] + rec[key]["write_bytes"]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -97,6 +116,45 @@ def step_latencies(marks, steps):
 
 
 # ------------------------------------------------------------------ halo
+def vector_copy_roofline(count, k):
+    """The halo's dominant kernel at its real shape: the typemap copy of one
+    vector(count, 3, 8, float32) message into the same vector type.  Its data
+    kernel is launched k times back to back on one stream between one pair
+    of HIP events (on that stream), so the average is a per-launch duration
+    that a short kernel's per-launch event pairs would bury in marker
+    overhead."""
+    import ctypes
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    from workloads import configs as C
+    p = C.ring_halo(count=count, steps=1, nranks=2)
+    A = torch.from_numpy(p.buffers[0]["A"].copy()).cuda()
+    H = torch.from_numpy(p.buffers[1]["H"].copy()).cuda()
+    torch.cuda.synchronize()
+    vt = make_vector(M, count, 3, 8, M.FLOAT32)
+    f = M.lib().mpixs_debug_time_copy
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_void_p,
+                  ctypes.c_int, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_int)]
+    f.restype = ctypes.c_int
+    hs = D.hip_stream_create()
+    avg = ctypes.c_double()
+    w = ctypes.c_int()
+    rc = f(hs, A.data_ptr(), 1, vt, H.data_ptr(), 1, vt, k, ctypes.byref(avg), ctypes.byref(w))
+    D.hip_stream_destroy(hs)
+    if rc:
+        raise RuntimeError(f"mpixs_debug_time_copy: {M.errname(rc)}")
+    per_launch = 2 * 12 * count
+    ach = per_launch / (avg.value * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic(f"halo_vector_copy_count{count}"),
+            "kernel": f"mpixs::k_copy<{w.value}, 1, 1, false>", "bytes_per_launch": per_launch,
+            "avg_launch_us": avg.value, "launches_timed": k,
+            "note": "data kernel of one halo message, launched back to back between one event pair"}
+
+
 def halo_cpu_baseline(count, budget_s=15.0):
     """The oracle as it stands on a bounded sample of the same workload."""
     from oracle import simulate as sim
@@ -179,23 +237,7 @@ def bench_halo(args):
             for r in range(n):
                 if not torch.equal(H2[r], H[r]):
                     raise AssertionError(f"rank {r}: host-synced path differs from enqueue path")
-        # ---- profiled pass: HIP events around every copy kernel; copies run
-        # split (wait kernel, data kernel, signal kernel) so that the timed
-        # kernel only moves data
         if count == args.count:
-            cfg = M.Config()
-            cfg.profile = 1
-            cfg.fuse_max_bytes = -1
-            sess = D.Session(n, cfg)
-            ops = [halo_ops(D, r, n, A[r], H[r], vt, steps, 0, 0) for r in range(n)]
-            sec_p, _ = run_checked(sess, ops)
-            torch.cuda.synchronize()
-            st = sess.stats()
-            sess.close()
-            avg_ms = st.copy_ms / max(1, st.timed_copy)
-            res["copy_kernels_timed"] = int(st.timed_copy)
-            res["copy_kernel_avg_us"] = avg_ms * 1000
-            res["profiled_msgs_per_s"] = 16 * steps / sec_p
             headline = res
         out_sweep.append(res)
         log(f"[halo] count={count}: {res['msgs_per_s']:.0f} msgs/s, "
@@ -203,8 +245,8 @@ def bench_halo(args):
             f"host-synced {res.get('host_synced_msgs_per_s', 0):.0f} msgs/s")
 
     h = headline
-    per_launch = 2 * h["payload_bytes"]
-    achieved = per_launch / (h["copy_kernel_avg_us"] * 1e-6) / 1e9
+    roof = vector_copy_roofline(h["count"], steps)
+
     line = {
         "metric": "enqueued msgs/s + GB/s (frac of HBM peak) vs host-synced path; p50/p99 latency",
         "value": h["msgs_per_s"],
@@ -227,11 +269,7 @@ def bench_halo(args):
         "host_synced": {"value": h.get("host_synced_msgs_per_s"), "unit": "msgs/s",
                         "speedup": h.get("speedup_vs_host_synced")},
         "latency_us": {"p50": h["p50_step_us"], "p99": h["p99_step_us"], "of": "halo step"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_copy<4,VEC,VEC,split>", "bytes_per_launch": per_launch,
-                     "avg_launch_us": h["copy_kernel_avg_us"],
-                     "launches_timed": h["copy_kernels_timed"]},
+        "roofline": roof,
         "sweep": out_sweep if args.sweep else None,
     }
     if not args.no_cpu_baseline:
@@ -272,6 +310,14 @@ def bench_allreduce(args):
         return out
 
     sess = D.Session(n)
+    if args.via_host_synced:
+        # counter collection serialises dispatches, which the cross-stream
+        # device waits of the enqueue path cannot tolerate; the host-synced
+        # path runs the same reduce kernel without them
+        run_checked(sess, ops(args.warmup), mode=1)
+        run_checked(sess, ops(args.steps), mode=1)
+        sess.close()
+        return {"workload": f"allreduce_{n}r_{dtype}_{nbytes}B", "via": "host-synced"}
     run_checked(sess, ops(args.warmup))
     sec, _ = run_checked(sess, ops(args.steps))
     _, marks = run_checked(sess, ops(args.steps, True), nmarks=2 * args.steps)
@@ -319,7 +365,9 @@ def bench_allreduce(args):
                         "speedup": calls_per_s / hs if hs else None},
         "latency_us": {"p50": pct(lat, 50), "p99": pct(lat, 99), "of": "allreduce call"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"reduce_{n}x{nbytes >> 20}MiB_f32")
+                     if dtype == "float32" else None,
                      "kernel": f"k_reduce<{dtype},SUM,vec>", "bytes_per_launch": per_launch,
                      "avg_launch_us": avg_us, "launches_timed": int(st.timed_reduce)},
     }
@@ -401,6 +449,11 @@ def bench_copy(args):
     cfg = M.Config()
     cfg.profile = 1 if args.profile_copy else 0
     sess = D.Session(2, cfg)
+    if args.via_host_synced:
+        run_checked(sess, ops(args.warmup), mode=1)
+        run_checked(sess, ops(args.steps), mode=1)
+        sess.close()
+        return {"workload": f"send_recv_contiguous_{nbytes}B_2ranks", "via": "host-synced"}
     run_checked(sess, ops(args.warmup))
     sess.reset_stats()
     sec, _ = run_checked(sess, ops(args.steps))
@@ -421,7 +474,9 @@ def bench_copy(args):
         avg_us = 1000 * st.copy_ms / max(1, st.timed_copy)
         ach = 2 * nbytes / (avg_us * 1e-6) / 1e9
         line["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                            "frac": ach / HBM_PEAK_GBS,
+                            "traffic": measured_traffic("copy_contiguous_1GiB")
+                            if nbytes == 1 << 30 else None,
                             "kernel": "k_copy<16,CONTIG,CONTIG>", "bytes_per_launch": 2 * nbytes,
                             "avg_launch_us": avg_us, "launches_timed": int(st.timed_copy)}
     return line
@@ -433,7 +488,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="halo",
-                    choices=["halo", "pingpong", "allreduce", "copy"])
+                    choices=["halo", "pingpong", "allreduce", "copy", "vcopy"])
     ap.add_argument("--count", type=int, default=43690)
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")
     ap.add_argument("--bytes", type=int, default=None)
@@ -444,12 +499,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--profile-copy", action="store_true")
+    ap.add_argument("--via-host-synced", action="store_true",
+                    help="copy/allreduce: run only the host-synchronised path (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(ranks are host threads sharing one MI355X)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3)}
+    defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
+                "vcopy": (100, 10)}
     k, w = defaults[args.workload]
     args.steps = args.steps or k
     args.warmup = args.warmup if args.warmup is not None else w
@@ -457,9 +515,13 @@ def main():
         args.bytes = {"allreduce": 64 << 20, "copy": 1 << 30}.get(args.workload, 0)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    fn = {"halo": bench_halo, "allreduce": bench_allreduce, "pingpong": bench_pingpong,
-          "copy": bench_copy}[args.workload]
-    line = fn(args)
+    if args.workload == "vcopy":
+        line = {"workload": f"vector_copy_count{args.count}",
+                "roofline": vector_copy_roofline(args.count, args.steps)}
+    else:
+        fn = {"halo": bench_halo, "allreduce": bench_allreduce, "pingpong": bench_pingpong,
+              "copy": bench_copy}[args.workload]
+        line = fn(args)
     print(json.dumps(line), flush=True)
 
 

@@ -27,6 +27,18 @@ int mpixs_debug_copy_plan(uint64_t sbuf, int scount, mpixs_datatype stype, uint6
                           uint64_t *src_addr, uint64_t *dst_addr, int *unit_bytes,
                           int64_t *nunits);
 
+/* Time the copy kernel of one message at its real shape: plan the copy of
+ * (sbuf, scount, stype) into (rbuf, rcount, rtype) as the enqueue path
+ * would for a large message, launch its data kernel `reps` times back to
+ * back on the HIP stream `hip_stream` between one pair of HIP events, wait
+ * for the stream, and store the average per launch in *avg_us (and the unit
+ * size in *unit_bytes if not NULL).  Buffers must be device memory, types
+ * committed.  This call allocates a small scratch block and synchronises
+ * the stream; it is for benchmarks, not for the enqueue path. */
+int mpixs_debug_time_copy(void *hip_stream, const void *sbuf, int scount, mpixs_datatype stype,
+                          void *rbuf, int rcount, mpixs_datatype rtype, int reps, double *avg_us,
+                          int *unit_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1318,6 +1318,63 @@ int mpixs_debug_copy_plan(uint64_t sbuf, int scount, mpixs_datatype stype, uint6
     return MPIXS_SUCCESS;
 }
 
+// Time the data kernel of one message: launch it `reps` times back to back
+// on `hip_stream` between one pair of HIP events (no wait or signal kernels
+// in between), synchronise, and return the average per launch.
+int mpixs_debug_time_copy(void *hip_stream, const void *sbuf, int scount, mpixs_datatype stype,
+                          void *rbuf, int rcount, mpixs_datatype rtype, int reps, double *avg_us,
+                          int *unit_bytes) {
+    const TypeObj *ts = type_lookup(stype);
+    const TypeObj *tr = type_lookup(rtype);
+    if (!ts || !tr) return MPIXS_ERR_TYPE;
+    if (!avg_us || reps <= 0 || scount < 0 || rcount < 0) return MPIXS_ERR_ARG;
+    Side S, R;
+    S.buf = sbuf;
+    S.count = scount;
+    S.t = ts;
+    S.bytes = int64_t(scount) * ts->L.size;
+    R.buf = rbuf;
+    R.count = rcount;
+    R.t = tr;
+    R.bytes = int64_t(rcount) * tr->L.size;
+    const int64_t nbytes = std::min(S.bytes, R.bytes);
+    DMap ms, mr;
+    int wsz = 16;
+    uint64_t units = 0;
+    plan_copy(S, R, nbytes, &ms, &mr, &wsz, &units);
+    if (unit_bytes) *unit_bytes = wsz;
+    DevStream *scratch = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&scratch), sizeof(DevStream)) != hipSuccess)
+        return MPIXS_ERR_NOMEM;
+    hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+    int rc = MPIXS_SUCCESS;
+    if (hipMemsetAsync(scratch, 0, sizeof(DevStream), hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    CopyArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = ms;
+    a.dst = mr;
+    a.units = units;
+    a.me = scratch;
+    const uint64_t per_chunk = uint64_t(copy_block_units(false));
+    const uint64_t nwg = std::max<uint64_t>(1, (units + per_chunk - 1) / per_chunk);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = MPIXS_ERR_GPU;
+    if (!rc) rc = gpu_err(launch_copy(hs, a, wsz, int(nwg), false));   // warm
+    if (!rc && hipEventRecord(e0, hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    for (int i = 0; i < reps && !rc; ++i) rc = gpu_err(launch_copy(hs, a, wsz, int(nwg), false));
+    if (!rc && hipEventRecord(e1, hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    if (!rc && hipStreamSynchronize(hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    float ms_total = 0;
+    if (!rc && hipEventElapsedTime(&ms_total, e0, e1) != hipSuccess) rc = MPIXS_ERR_GPU;
+    if (!rc) *avg_us = 1000.0 * double(ms_total) / reps;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(hs);
+    (void)hipFree(scratch);
+    return rc;
+}
+
 const char *mpixs_error_string(int err) {
     switch (err) {
     case MPIXS_SUCCESS: return "SUCCESS";
