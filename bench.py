@@ -69,7 +69,7 @@ def make_vector(M, count, bl, stride, base):
     return t
 
 
-def halo_ops(D, r, n, A, H, vt, steps, tag0, mode, marks=False, status_ptr=0):
+def halo_ops(D, r, n, A, H, vt, steps, tag0, mode, marks=False, status_ptr=0, grouped=False):
     right, left = (r + 1) % n, (r - 1) % n
     rows = []
     a0, a3 = A.data_ptr(), A.data_ptr() + 12
@@ -78,6 +78,8 @@ def halo_ops(D, r, n, A, H, vt, steps, tag0, mode, marks=False, status_ptr=0):
         tag = tag0 + s
         if marks:
             rows.append(dict(kind=D.MARK, req=2 * s))
+        if grouped:
+            rows.append(dict(kind=D.GROUP_START))
         if mode == 0:
             rows += [dict(kind=D.ISEND, peer=right, tag=tag, count=1, datatype=vt, buf=a0, req=0),
                      dict(kind=D.ISEND, peer=left, tag=tag, count=1, datatype=vt, buf=a3, req=1),
@@ -93,14 +95,16 @@ def halo_ops(D, r, n, A, H, vt, steps, tag0, mode, marks=False, status_ptr=0):
             sl = dict(kind=D.SEND, peer=left, tag=tag, count=1, datatype=vt, buf=a3)
             rr = dict(kind=D.RECV, peer=right, tag=tag, count=1, datatype=vt, buf=h3)
             rows += [sr, rl, sl, rr] if r % 2 == 0 else [rl, sr, rr, sl]
+        if grouped:
+            rows.append(dict(kind=D.GROUP_END))
         if marks:
             rows.append(dict(kind=D.MARK, req=2 * s + 1))
     return D.ops_array(rows)
 
 
-def run_checked(sess, ops, mode=0, nmarks=0):
+def run_checked(sess, ops, mode=0, nmarks=0, max_reqs=64):
     from paper_2208_13707_amd import mpixs as M
-    rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks)
+    rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
     if rc:
         raise RuntimeError(f"driver: {M.errname(rc)} at thread {res.error_thread} op {res.error_op}")
     return res.seconds, marks
@@ -212,6 +216,24 @@ def bench_halo(args):
         lat = step_latencies(marks, steps)
         res.update(p50_step_us=pct(lat, 50), p99_step_us=pct(lat, 99))
         sess.close()
+        # ---- batched: every step's operations form one group (one kernel)
+        Hg = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
+        torch.cuda.synchronize()
+        sess = D.Session(n)
+        ops = [halo_ops(D, r, n, A[r], Hg[r], vt, warm, 20000, 0, grouped=True) for r in range(n)]
+        run_checked(sess, ops)
+        ops = [halo_ops(D, r, n, A[r], Hg[r], vt, steps, 20000, 0, grouped=True) for r in range(n)]
+        sec_g, _ = run_checked(sess, ops)
+        ops = [halo_ops(D, r, n, A[r], Hg[r], vt, steps, 20000, 0, marks=True, grouped=True)
+               for r in range(n)]
+        _, marks = run_checked(sess, ops, nmarks=2 * steps)
+        lat_g = step_latencies(marks, steps)
+        sess.close()
+        res.update(grouped_msgs_per_s=msgs / sec_g, grouped_ms_per_step=1000 * sec_g / steps,
+                   grouped_p50_step_us=pct(lat_g, 50), grouped_p99_step_us=pct(lat_g, 99))
+        for r in range(n):
+            if not torch.equal(Hg[r], H[r]):
+                raise AssertionError(f"rank {r}: grouped halo differs from the plain path")
         # ---- correctness against the oracle (sampled: after any step, H holds
         # the neighbours' halo columns; the oracle runs one full-size step)
         if count == args.count:
@@ -241,20 +263,25 @@ def bench_halo(args):
             headline = res
         out_sweep.append(res)
         log(f"[halo] count={count}: {res['msgs_per_s']:.0f} msgs/s, "
+            f"grouped {res['grouped_msgs_per_s']:.0f} msgs/s, "
             f"{res['gbps_algorithmic']:.1f} GB/s alg, "
             f"host-synced {res.get('host_synced_msgs_per_s', 0):.0f} msgs/s")
 
     h = headline
     roof = vector_copy_roofline(h["count"], steps)
-
+    grouped = h["grouped_msgs_per_s"] > h["msgs_per_s"]
+    value = h["grouped_msgs_per_s"] if grouped else h["msgs_per_s"]
+    ms_step = h["grouped_ms_per_step"] if grouped else h["ms_per_step"]
+    gbps_pay = value * h["payload_bytes"] / 1e9
+    hs = h.get("host_synced_msgs_per_s")
     line = {
         "metric": "enqueued msgs/s + GB/s (frac of HBM peak) vs host-synced path; p50/p99 latency",
-        "value": h["msgs_per_s"],
+        "value": value,
         "unit": "msgs/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": warm,
-        "ms_per_step": h["ms_per_step"],
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -262,13 +289,20 @@ def bench_halo(args):
         "data": "synthetic",
         "config": {"workload": f"ring_halo_8ranks_vector(count={h['count']},bl=3,stride=8)_f32",
                    "ranks": n, "count": h["count"], "payload_bytes": h["payload_bytes"],
-                   "msgs_per_step": 16, "parallelism": "1 GPU, 8 rank threads"},
-        "gbps_payload": h["gbps_payload"],
-        "gbps_algorithmic": h["gbps_algorithmic"],
-        "hbm_frac": h["gbps_algorithmic"] / HBM_PEAK_GBS,
-        "host_synced": {"value": h.get("host_synced_msgs_per_s"), "unit": "msgs/s",
-                        "speedup": h.get("speedup_vs_host_synced")},
-        "latency_us": {"p50": h["p50_step_us"], "p99": h["p99_step_us"], "of": "halo step"},
+                   "msgs_per_step": 16, "parallelism": "1 GPU, 8 rank threads",
+                   "variant": "grouped (each step one group)" if grouped else "plain enqueue"},
+        "gbps_payload": gbps_pay,
+        "gbps_algorithmic": 2 * gbps_pay,
+        "hbm_frac": 2 * gbps_pay / HBM_PEAK_GBS,
+        "plain_enqueue": {"value": h["msgs_per_s"], "ms_per_step": h["ms_per_step"],
+                          "p50_step_us": h["p50_step_us"], "p99_step_us": h["p99_step_us"]},
+        "grouped_enqueue": {"value": h["grouped_msgs_per_s"], "ms_per_step": h["grouped_ms_per_step"],
+                            "p50_step_us": h["grouped_p50_step_us"],
+                            "p99_step_us": h["grouped_p99_step_us"]},
+        "host_synced": {"value": hs, "unit": "msgs/s", "speedup": value / hs if hs else None},
+        "latency_us": {"p50": h["grouped_p50_step_us"] if grouped else h["p50_step_us"],
+                       "p99": h["grouped_p99_step_us"] if grouped else h["p99_step_us"],
+                       "of": "halo step"},
         "roofline": roof,
         "sweep": out_sweep if args.sweep else None,
     }
@@ -371,6 +405,130 @@ def bench_allreduce(args):
                      "kernel": f"k_reduce<{dtype},SUM,vec>", "bytes_per_launch": per_launch,
                      "avg_launch_us": avg_us, "launches_timed": int(st.timed_reduce)},
     }
+    return line
+
+
+# ------------------------------------------------------------------- batch
+def bench_batch(args):
+    """Config 4: 10,000 send/recv pairs over 32 ranks (sizes log-uniform
+    8 B .. 256 KiB, tags 0..63, 30 % vector datatypes).  Each rank isends
+    all its messages in global order, irecvs all of its messages, and waits
+    for all of them.  Variants: one group per batch (one batch kernel), the
+    plain enqueue path (one copy per message), and the host-synchronised path
+    (blocking calls in global message order)."""
+    import numpy as np
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    from workloads import configs as C
+    from workloads.program import Recv, Send, Wait
+
+    npairs, n = args.pairs, args.ranks_batch
+    p = C.batch(npairs=npairs, nranks=n)
+    msgs = C.batch_messages(npairs=npairs, nranks=n)
+    types = {}
+
+    def tt(tree):
+        key = repr(tree)
+        if key not in types:
+            if isinstance(tree, str):
+                types[key] = M.BASIC[tree]
+            else:
+                _, c, bl, st, base = tree
+                types[key] = make_vector(M, c, bl, st, M.BASIC[base])
+        return types[key]
+
+    S = [torch.from_numpy(p.buffers[r]["sbuf"]).cuda() for r in range(n)]
+    R = {v: [torch.from_numpy(p.buffers[r]["rbuf"].copy()).cuda() for r in range(n)]
+         for v in ("grouped", "plain", "host")}
+    torch.cuda.synchronize()
+    maxreq = max(len(p.ops[r][0]) for r in range(n)) + 1
+
+    def ops(variant, reps, tag_base=0):
+        out = []
+        for r in range(n):
+            rows = []
+            for _ in range(reps):
+                if variant == "grouped":
+                    rows.append(dict(kind=D.GROUP_START))
+                if variant in ("grouped", "plain"):
+                    nreq = 0
+                    for o in p.ops[r][0]:
+                        if isinstance(o, Send):
+                            rows.append(dict(kind=D.ISEND, peer=o.dest, tag=tag_base + o.tag,
+                                             count=o.count, datatype=tt(o.dtype),
+                                             buf=S[r].data_ptr() + o.off, req=nreq))
+                            nreq += 1
+                        elif isinstance(o, Recv):
+                            rows.append(dict(kind=D.IRECV, peer=o.source, tag=tag_base + o.tag,
+                                             count=o.count, datatype=tt(o.dtype),
+                                             buf=R[variant][r].data_ptr() + o.off, req=nreq))
+                            nreq += 1
+                        elif isinstance(o, Wait):
+                            rows.append(dict(kind=D.WAITALL, req=0, nreq=nreq))
+                if variant == "grouped":
+                    rows.append(dict(kind=D.GROUP_END))
+                if variant == "host":
+                    # blocking calls in global message order (deadlock-free)
+                    sends = [o for o in p.ops[r][0] if isinstance(o, Send)]
+                    recvs = [o for o in p.ops[r][0] if isinstance(o, Recv)]
+                    si = ri = 0
+                    for m in msgs:
+                        if m["src"] == r:
+                            o = sends[si]
+                            si += 1
+                            rows.append(dict(kind=D.SEND, peer=o.dest, tag=tag_base + o.tag,
+                                             count=o.count, datatype=tt(o.dtype),
+                                             buf=S[r].data_ptr() + o.off))
+                        elif m["dst"] == r:
+                            o = recvs[ri]
+                            ri += 1
+                            rows.append(dict(kind=D.RECV, peer=o.source, tag=tag_base + o.tag,
+                                             count=o.count, datatype=tt(o.dtype),
+                                             buf=R["host"][r].data_ptr() + o.off))
+            out.append(D.ops_array(rows))
+        return out
+
+    res = {}
+    for variant, mode, tagb in (("grouped", 0, 1000), ("plain", 0, 0), ("host", 1, 0)):
+        if variant == "host" and args.no_host_synced:
+            continue
+        k = args.steps if variant != "host" else max(1, min(args.steps, args.hs_steps))
+        sess = D.Session(n)
+        run_checked(sess, ops(variant, args.warmup, tagb), mode=mode, max_reqs=maxreq)
+        sec, _ = run_checked(sess, ops(variant, k, tagb), mode=mode, max_reqs=maxreq)
+        sess.close()
+        res[variant] = npairs * k / sec
+        log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.2f} ms per batch)")
+    # identical results across the paths and the oracle (on a sampled set of ranks)
+    for v in res:
+        for r in range(n):
+            if not torch.equal(R[v][r], R["grouped"][r]):
+                raise AssertionError(f"{v} path differs from grouped on rank {r}")
+    line = {
+        "metric": "enqueued msgs/s vs host-synced path (uneven batch)",
+        "value": res["grouped"], "unit": "msgs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000 * npairs / res["grouped"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"batch_{npairs}pairs_{n}ranks_8B-256KiB_30pct_vector",
+                   "variant": "one group per batch"},
+        "plain_enqueue": {"value": res["plain"], "unit": "msgs/s"},
+        "host_synced": {"value": res.get("host"), "unit": "msgs/s",
+                        "speedup": res["grouped"] / res["host"] if "host" in res else None,
+                        "plain_speedup": res["plain"] / res["host"] if "host" in res else None},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import simulate as sim
+        t0 = time.perf_counter()
+        ref = sim.run(p)
+        dt = time.perf_counter() - t0
+        for r in range(n):
+            if not np.array_equal(R["grouped"][r].cpu().numpy(), ref.buffers[r]["rbuf"]):
+                raise AssertionError(f"rank {r}: batch result differs from the oracle")
+        line["cpu_baseline"] = {"value": npairs / dt, "unit": "msgs/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the whole batch ({npairs} messages) once, {dt:.1f} s"}
     return line
 
 
@@ -488,7 +646,9 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="halo",
-                    choices=["halo", "pingpong", "allreduce", "copy", "vcopy"])
+                    choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch"])
+    ap.add_argument("--pairs", type=int, default=10000)
+    ap.add_argument("--ranks-batch", type=int, default=32)
     ap.add_argument("--count", type=int, default=43690)
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")
     ap.add_argument("--bytes", type=int, default=None)
@@ -507,7 +667,7 @@ def main():
               "(ranks are host threads sharing one MI355X)", file=sys.stderr)
         sys.exit(2)
     defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
-                "vcopy": (100, 10)}
+                "vcopy": (100, 10), "batch": (5, 1)}
     k, w = defaults[args.workload]
     args.steps = args.steps or k
     args.warmup = args.warmup if args.warmup is not None else w
@@ -520,7 +680,7 @@ def main():
                 "roofline": vector_copy_roofline(args.count, args.steps)}
     else:
         fn = {"halo": bench_halo, "allreduce": bench_allreduce, "pingpong": bench_pingpong,
-              "copy": bench_copy}[args.workload]
+              "copy": bench_copy, "batch": bench_batch}[args.workload]
         line = fn(args)
     print(json.dumps(line), flush=True)
 

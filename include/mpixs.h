@@ -118,15 +118,18 @@ typedef struct {
                                  as network endpoints are (§2.2, §3.1) */
     int32_t endpoint_policy;  /* 0: stream_create fails when the pool is empty;
                                  1: share endpoints round-robin (§3.1) [0] */
-    int32_t fuse_max_bytes;   /* messages up to this size wait and copy in one kernel
-                                 launch; larger ones use a one-wave wait kernel followed by
-                                 a full-grid copy [65536]; -1: never fuse */
+    int32_t fuse_max_bytes;   /* messages (and allreduces, counting all ranks' inputs) up
+                                 to this size wait and copy in one kernel of at most 32
+                                 workgroups; larger ones use a one-wave wait kernel, a
+                                 full-grid data kernel and a signal kernel [2097152];
+                                 -1: never fuse */
     int32_t timeout_ms;       /* host waits for a peer's enqueue, and device waits for a
                                  peer's stream, give up after this [30000] */
     int32_t max_channels;     /* device matching-table capacity in channels [1<<20] */
     int32_t profile;          /* 1: time copy and reduce kernels with HIP events */
     int32_t max_collectives;  /* device collective-slot capacity [4096] */
-    int32_t reserved[9];
+    int32_t batch_arena_mib;  /* host-pinned memory for batch descriptors, MiB [64] */
+    int32_t reserved[8];
 } mpixs_config;
 
 /* -------------------------------------------------------------- world (N ranks)
@@ -260,6 +263,36 @@ int mpixs_waitall_enqueue(int count, mpixs_request requests[], mpixs_status stat
  * At most 64 ranks per communicator. */
 int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
                             mpixs_datatype datatype, mpixs_op op, mpixs_comm comm);
+
+/* ---------------------------------------------------------------- batching
+ * Groups fuse many enqueued messages into one kernel.  The paper's enqueue
+ * semantics (§3.4) let an implementation move a nonblocking message at any
+ * point between its call and its wait; a group widens that window to the
+ * whole group: between mpixs_group_start(comm) and mpixs_group_end(comm) a
+ * rank's send / recv / isend / irecv / wait / waitall_enqueue calls on comm
+ * are recorded instead of enqueued (argument errors are still returned at
+ * once), and mpixs_group_end enqueues them all.
+ *
+ *  mpixs_group_end is collective over comm (every rank calls it, possibly
+ *  with an empty group; at most 64 ranks).  The rank that arrives last
+ *  matches the grouped operations of all ranks (the i-th grouped send of s
+ *  to d with tag t matches the i-th grouped receive of d from s with tag t)
+ *  and enqueues on its own stream one wait for all ranks' streams to reach
+ *  their group_end, one batch kernel that performs every copy of the group
+ *  (tiles of up to 1024 units scheduled over the whole grid) and writes the
+ *  receive statuses, and a completion signal; every other rank's stream
+ *  waits for that signal.  So later work on any rank's stream starts after
+ *  all copies of the group.  Blocking calls inside a group complete at
+ *  group_end; requests created inside a group complete at group_end too
+ *  (waiting on them inside or after the group only delivers the status).
+ *  Every grouped send must be matched inside the same group instance, else
+ *  group_end returns MPIXS_ERR_ARG on every rank and no copy of the group
+ *  runs.  A channel used inside groups must not also be used outside them.
+ *  allreduce_enqueue inside a group fails with MPIXS_ERR_ARG.
+ *  mpixs_group_end waits on the host until every rank has called it.
+ */
+int mpixs_group_start(mpixs_comm comm);
+int mpixs_group_end(mpixs_comm comm);
 
 /* ------------------------------------ conventional, host-synchronised calls
  * The comparison path of §2.4: MPI calls that run in the CPU context and

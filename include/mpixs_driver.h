@@ -28,7 +28,9 @@ enum {
                                 statuses at `status` (array) or none               */
     MPIXS_DRV_ALLREDUCE = 6, /* allreduce_enqueue(buf, buf2, ...) (host-synced:
                                 mpixs_allreduce); buf == 1 means in place          */
-    MPIXS_DRV_MARK = 7       /* record HIP event number `req` of this thread       */
+    MPIXS_DRV_MARK = 7,      /* record HIP event number `req` of this thread       */
+    MPIXS_DRV_GROUP_START = 8, /* mpixs_group_start(comm)                          */
+    MPIXS_DRV_GROUP_END = 9    /* mpixs_group_end(comm)                            */
 };
 
 typedef struct {

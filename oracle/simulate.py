@@ -20,6 +20,15 @@ What it states, and where the paper fixes it:
   ranks reached it; its result is the canonical-order fold (see reduce.py).
 * Enqueue calls on a communicator without a local GPU stream are an error
   (§3.4).
+* Groups (a batching extension): between GroupStart and GroupEnd on a
+  communicator a rank's sends and receives on it are posted but do not
+  block and do not move data; GroupEnd is collective (instance k = the k-th
+  GroupEnd of each rank on the communicator) and, once every rank reached
+  it, moves all of the instance's messages.  A grouped message whose peer
+  operation is not grouped in the same instance makes the whole instance
+  fail: no message of it moves and every rank's GroupEnd reports ERR_ARG.
+  A wait on a grouped request inside its group delivers the status at the
+  group's end.
 
 Readings where the paper is silent (each is listed in the design notes):
 
@@ -53,7 +62,9 @@ import numpy as np
 
 from . import reduce as red
 from . import typemap as tm
-from workloads.program import IN_PLACE, Allreduce, Program, Recv, Send, User, Wait
+from workloads.program import (
+    IN_PLACE, Allreduce, GroupEnd, GroupStart, Program, Recv, Send, User, Wait,
+)
 
 SUCCESS = "SUCCESS"
 
@@ -63,8 +74,10 @@ class _SendRec:
     rank: int
     tag: int
     basic: str
-    payload: np.ndarray
+    payload: Optional[np.ndarray]
     done: bool = False
+    group: Optional[Tuple[int, int]] = None     # (comm, instance) when grouped
+    src: Optional[Tuple[str, int, int, object]] = None   # (buf, off, count, typemap)
 
 
 @dataclass
@@ -76,6 +89,7 @@ class _RecvRec:
     t: tm.Typemap
     done: bool = False
     status: Optional[Tuple[int, int, str, int]] = None
+    group: Optional[Tuple[int, int]] = None
 
 
 @dataclass
@@ -167,6 +181,12 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
     coll_next: Dict[Tuple[int, int], int] = {}          # (comm, rank) -> next instance
     coll: Dict[Tuple[int, int], Dict[int, Allreduce]] = {}
     coll_done: Dict[Tuple[int, int], bool] = {}
+    group_open: Dict[Tuple[int, int], Tuple[int, int]] = {}    # (rank, comm) -> (comm, inst)
+    group_next: Dict[Tuple[int, int], int] = {}                # (rank, comm) -> next instance
+    group_arrived: Dict[Tuple[int, int], set] = {}
+    group_msgs: Dict[Tuple[int, int], list] = {}
+    group_ok: Dict[Tuple[int, int], bool] = {}
+    group_after: Dict[Tuple[int, int], list] = {}
 
     def chan(key):
         if key not in chans:
@@ -176,6 +196,9 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
     def transfer(key, k):
         s = chans[key].sends[k]
         r = chans[key].recvs[k]
+        if s.payload is None:
+            buf, off, count, t = s.src
+            s.payload = tm.pack(bufs[s.rank][buf], off, count, t)
         cap = r.count * r.t.size
         nbytes = int(s.payload.size)
         if nbytes > 0 and cap > 0 and s.basic != r.t.basic:
@@ -190,29 +213,55 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         s.done = r.done = True
         match_log.append((key[0], key[1], key[2], key[3], k))
 
-    def post_send(rank, op: Send) -> _SendRec:
+    def post_send(rank, op: Send, group=None) -> _SendRec:
         t = tm.build(op.dtype)
         key = (op.comm, rank, op.dest, op.tag)
         c = chan(key)
-        rec = _SendRec(rank, op.tag, t.basic, tm.pack(bufs[rank][op.buf], op.off, op.count, t))
+        if group is None:
+            rec = _SendRec(rank, op.tag, t.basic, tm.pack(bufs[rank][op.buf], op.off, op.count, t))
+        else:
+            rec = _SendRec(rank, op.tag, t.basic, None, group=group,
+                           src=(op.buf, op.off, op.count, t))
         k = c.nsend
         c.nsend += 1
         c.sends[k] = rec
-        if k in c.recvs:
+        if group is None and k in c.recvs and c.recvs[k].group is None:
             transfer(key, k)
+        elif group is not None:
+            group_msgs.setdefault(group, []).append((key, k))
         return rec
 
-    def post_recv(rank, op: Recv) -> _RecvRec:
+    def post_recv(rank, op: Recv, group=None) -> _RecvRec:
         t = tm.build(op.dtype)
         key = (op.comm, op.source, rank, op.tag)
         c = chan(key)
-        rec = _RecvRec(rank, op.buf, op.off, op.count, t)
+        rec = _RecvRec(rank, op.buf, op.off, op.count, t, group=group)
         k = c.nrecv
         c.nrecv += 1
         c.recvs[k] = rec
-        if k in c.sends:
+        if group is None and k in c.sends and c.sends[k].group is None:
             transfer(key, k)
+        elif group is not None:
+            group_msgs.setdefault(group, []).append((key, k))
         return rec
+
+    def end_group(comm, inst):
+        """All ranks reached GroupEnd instance ``inst`` of ``comm``: move its
+        messages, or fail the instance if one is unmatched inside it."""
+        msgs = group_msgs.get((comm, inst), [])
+        ok = True
+        for key, k in msgs:
+            c = chans[key]
+            s, r = c.sends.get(k), c.recvs.get(k)
+            if s is None or r is None or s.group != (comm, inst) or r.group != (comm, inst):
+                ok = False
+        if ok:
+            for key, k in sorted(set(msgs)):
+                if not chans[key].sends[k].done:
+                    transfer(key, k)
+        group_ok[(comm, inst)] = ok
+        for fn in group_after.pop((comm, inst), []):
+            fn(ok)
 
     def arrive(rank, op: Allreduce):
         k = coll_next.get((op.comm, rank), 0)
@@ -240,6 +289,14 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         op = ctx.ops[ctx.pc]
         if ctx.pending is not None:
             kind, obj = ctx.pending
+            if kind == "group":
+                if obj not in group_ok:
+                    return False
+                if not group_ok[obj]:
+                    sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_ARG"))
+                ctx.pending = None
+                ctx.pc += 1
+                return True
             if kind == "coll":
                 if not coll_done.get(obj, False):
                     return False
@@ -265,9 +322,18 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
                 sync_errors[rank].append((ctx.thread, ctx.pc, err))
                 ctx.pc += 1
                 return True
-            rec = post_send(rank, op) if isinstance(op, Send) else post_recv(rank, op)
+            grp = group_open.get((rank, op.comm))
+            rec = (post_send(rank, op, grp) if isinstance(op, Send) else post_recv(rank, op, grp))
             if op.req is not None:
                 requests[rank][op.req] = (rec, p.stream_of(rank, op.comm))
+                ctx.pc += 1
+                return True
+            if grp is not None:
+                if isinstance(op, Recv) and op.status is not None:
+                    name = op.status
+                    group_after.setdefault(grp, []).append(
+                        lambda ok, rec=rec, name=name, rank=rank:
+                        statuses[rank].__setitem__(name, rec.status) if ok else None)
                 ctx.pc += 1
                 return True
             ctx.pending = ("one", rec)
@@ -281,10 +347,24 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
                 sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_STREAM"))
                 ctx.pc += 1
                 return True
-            ctx.pending = ("waitall", [requests[rank][n][0] for n in op.reqs])
+            recs = [requests[rank][n][0] for n in op.reqs]
+            open_groups = [r.group for r in recs if r.group is not None and r.group not in group_ok]
+            if open_groups:
+                # inside its group: the statuses arrive at the group's end
+                for n, st_name in zip(op.reqs, op.statuses):
+                    r = requests[rank].pop(n)[0]
+                    if isinstance(r, _RecvRec) and st_name is not None:
+                        group_after.setdefault(r.group, []).append(
+                            lambda ok, r=r, st_name=st_name, rank=rank:
+                            statuses[rank].__setitem__(st_name, r.status) if ok else None)
+                ctx.pc += 1
+                return True
+            ctx.pending = ("waitall", recs)
             return step(ctx)
         if isinstance(op, Allreduce):
             err = _check_allreduce(p, rank, op)
+            if not err and (rank, op.comm) in group_open:
+                err = "ERR_ARG"          # collectives are not grouped
             if err:
                 sync_errors[rank].append((ctx.thread, ctx.pc, err))
                 ctx.pc += 1
@@ -295,6 +375,27 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
             _apply_user(bufs[rank], op.fn)
             ctx.pc += 1
             return True
+        if isinstance(op, GroupStart):
+            if (rank, op.comm) in group_open:
+                sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_ARG"))
+            else:
+                inst = group_next.get((rank, op.comm), 0)
+                group_open[(rank, op.comm)] = (op.comm, inst)
+            ctx.pc += 1
+            return True
+        if isinstance(op, GroupEnd):
+            grp = group_open.pop((rank, op.comm), None)
+            if grp is None:
+                sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_ARG"))
+                ctx.pc += 1
+                return True
+            group_next[(rank, op.comm)] = grp[1] + 1
+            arrived = group_arrived.setdefault(grp, set())
+            arrived.add(rank)
+            if len(arrived) == p.nranks:
+                end_group(*grp)
+            ctx.pending = ("group", grp)
+            return step(ctx)
         raise ValueError(f"unknown op {op!r}")
 
     def op_status_pairs(op: Wait):

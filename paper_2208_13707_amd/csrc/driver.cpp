@@ -63,6 +63,8 @@ int run_ops(const mpixs_drv_thread &t, int mode, std::vector<mpixs_request> &req
                                                 o.datatype, o.op, c);
             break;
         }
+        case MPIXS_DRV_GROUP_START: rc = mpixs_group_start(c); break;
+        case MPIXS_DRV_GROUP_END: rc = mpixs_group_end(c); break;
         case MPIXS_DRV_MARK:
             if (o.req >= 0 && size_t(o.req) < out.marks.size())
                 rc = hipEventRecord(out.marks[size_t(o.req)], hs) == hipSuccess ? 0 : MPIXS_ERR_GPU;

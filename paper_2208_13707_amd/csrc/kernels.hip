@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(64) k_signal(SignalArgs a) {
     if (a.status) write_status(a.status, a.st, fatal);
     if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
     if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+    if (a.host_flag) __hip_atomic_store(a.host_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ------------------------------------------------------------------ maps
@@ -302,7 +303,96 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
     }
 }
 
+// ----------------------------------------------------------------- batch
+// One kernel for every copy of a group.  Workgroup b runs a contiguous range
+// of tiles (balanced: base or base + 1), starting at the (message, tile)
+// the host computed for it, and walks the messages in order; the message's
+// descriptor is read from host-pinned memory into LDS when the workgroup
+// reaches it.  A tile is up to BATCH_TILE units of one message; the unit
+// size and map kinds of that message select the copy loop.
+template <int W, int SK, int DK>
+__device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint64_t u1) {
+    using T = typename Unit<W>::T;
+    constexpr int U = BATCH_TILE / COPY_THREADS;
+    T v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const uint64_t u = u0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
+        if (u < u1) v[k] = ld_unit<T, false>(map_addr<SK, W>(d.src, u));
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const uint64_t u = u0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
+        if (u < u1) st_unit<T, false>(map_addr<DK, W>(d.dst, u), v[k]);
+    }
+}
+
+template <int W, int SK>
+__device__ __forceinline__ void tile_copy_dk(const BatchDesc &d, uint64_t u0, uint64_t u1) {
+    switch (d.dst.kind) {
+    case MAP_CONTIG: tile_copy<W, SK, MAP_CONTIG>(d, u0, u1); break;
+    case MAP_VEC: tile_copy<W, SK, MAP_VEC>(d, u0, u1); break;
+    default: tile_copy<W, SK, MAP_SEG>(d, u0, u1); break;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void tile_copy_w(const BatchDesc &d, uint64_t u0, uint64_t u1) {
+    switch (d.src.kind) {
+    case MAP_CONTIG: tile_copy_dk<W, MAP_CONTIG>(d, u0, u1); break;
+    case MAP_VEC: tile_copy_dk<W, MAP_VEC>(d, u0, u1); break;
+    default: tile_copy_dk<W, MAP_SEG>(d, u0, u1); break;
+    }
+}
+
+__global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
+    __shared__ BatchDesc sd;
+    __shared__ uint32_t s_fatal;
+    const uint32_t b = blockIdx.x;
+    const uint64_t cnt = a.base + (b < a.extra ? 1 : 0);
+    uint32_t m = a.start[b].msg;
+    uint32_t tin = a.start[b].tile;
+    if (threadIdx.x == 0) {
+        s_fatal = ld_relaxed32(&a.me->fatal);
+        sd = a.desc[m];
+    }
+    __syncthreads();
+    for (uint64_t i = 0; i < cnt; ++i) {
+        if (tin >= sd.ntiles) {
+            ++m;
+            tin = 0;
+            __syncthreads();
+            if (threadIdx.x == 0) sd = a.desc[m];
+            __syncthreads();
+        }
+        if (!s_fatal) {
+            const uint64_t u0 = uint64_t(tin) * BATCH_TILE;
+            const uint64_t u1 = u0 + BATCH_TILE < sd.units ? u0 + BATCH_TILE : sd.units;
+            if (u0 < u1) {
+                switch (sd.w) {
+                case 16: tile_copy_w<16>(sd, u0, u1); break;
+                case 8: tile_copy_w<8>(sd, u0, u1); break;
+                case 4: tile_copy_w<4>(sd, u0, u1); break;
+                case 2: tile_copy_w<2>(sd, u0, u1); break;
+                default: tile_copy_w<1>(sd, u0, u1); break;
+                }
+            }
+        }
+        if (tin == 0 && threadIdx.x == 0) {
+            if (sd.status) write_status(sd.status, sd.st, s_fatal);
+            if (!s_fatal && sd.st.error && sd.rstream)
+                set_first_error(sd.rstream, uint32_t(sd.st.error));
+        }
+        ++tin;
+    }
+}
+
 // ------------------------------------------------------------- launchers
+hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg) {
+    hipLaunchKernelGGL(k_batch, dim3(nwg), dim3(COPY_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_post(hipStream_t s, uint64_t *p, uint64_t v) {
     hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();

@@ -171,7 +171,8 @@ struct CopyArgs {
 };
 
 // Completion of a message or collective after the stream's data kernel:
-// optional status and sticky error, then done = val.
+// optional status and sticky error, then done = val, then (optional) a
+// host-pinned word set to 1 so the host may recycle what the kernel read.
 struct SignalArgs {
     uint64_t *done_ptr;
     uint64_t done_val;
@@ -180,6 +181,39 @@ struct SignalArgs {
     StatusVal st;
     int32_t set_error;
     int32_t pad;
+    uint32_t *host_flag;
+};
+
+// ----------------------------------------------------------------- batches
+// One message of a batch, in host-pinned memory.  It is cut into tiles of
+// BATCH_TILE units; the workgroup that runs a message's tile 0 also writes
+// the message's receive status.
+constexpr uint32_t BATCH_TILE = 1024;
+
+struct alignas(16) BatchDesc {
+    DMap src;
+    DMap dst;
+    uint64_t units;
+    uint32_t w;             // unit bytes: 1, 2, 4, 8 or 16
+    uint32_t ntiles;        // max(1, ceil(units / BATCH_TILE))
+    void *status;           // receive status or nullptr
+    DevStream *rstream;     // receiver's stream block (sticky error)
+    StatusVal st;
+};
+
+// First tile of a workgroup: message index and tile within that message.
+struct BatchStart {
+    uint32_t msg;
+    uint32_t tile;
+};
+
+struct BatchArgs {
+    const BatchDesc *desc;
+    const BatchStart *start;
+    uint32_t nmsg;
+    uint32_t extra;         // workgroups b < extra run base + 1 tiles
+    uint64_t base;          // tiles per workgroup
+    DevStream *me;
 };
 
 enum RedOp : int32_t { OP_SUM = 1, OP_PROD = 2, OP_MIN = 3, OP_MAX = 4 };

@@ -12,6 +12,7 @@ hipError_t launch_signal(hipStream_t s, const SignalArgs &a);
 hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg, bool fused);
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg,
                          bool fused);
+hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg);
 int copy_block_units(bool fused);   // units in one copy chunk (one workgroup pass)
 int reduce_threads();
 

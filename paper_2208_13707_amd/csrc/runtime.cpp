@@ -36,7 +36,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "mpixs_launch.h"
@@ -383,6 +385,32 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
     if (rc) return rc;
     World *w = c->sh->w;
     StreamObj *st = c->stream;
+    if (c->in_group) {
+        // recorded; mpixs_group_end enqueues it
+        GOp g;
+        g.kind = side;
+        g.peer = peer;
+        g.tag = tag;
+        g.side.buf = buf;
+        g.side.count = count;
+        g.side.t = t;
+        g.side.bytes = int64_t(count) * t->L.size;
+        g.side.st = st;
+        g.side.rank = c->rank;
+        g.status = (side == 1 && !req) ? static_cast<void *>(status) : nullptr;
+        if (req) {
+            mpixs_request_s *r = new mpixs_request_s();
+            r->comm = c;
+            r->side = side;
+            r->grouped = true;
+            r->gop = c->gops.size();
+            g.req = r;
+            c->pending.fetch_add(1);
+            *req = r;
+        }
+        c->gops.push_back(g);
+        return MPIXS_SUCCESS;
+    }
     const int src = side == 0 ? c->rank : peer;
     const int dst = side == 0 ? peer : c->rank;
     Channel *ch = get_channel(c, src, dst, tag, false);
@@ -459,6 +487,25 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
     }
     World *w = reqs[0]->comm->sh->w;
     int rc = MPIXS_SUCCESS;
+    // grouped requests: inside their group the status pointer is recorded;
+    // after it the transfer is complete in stream order and only the status
+    // remains to be written
+    for (int i = 0; i < n && !rc; ++i) {
+        mpixs_request_s *r = reqs[i];
+        if (!r->grouped) continue;
+        mpixs_status *status = statuses ? (array_status ? &statuses[i] : statuses) : nullptr;
+        mpixs_comm_s *c = r->comm;
+        if (c->in_group && r->gop < c->gops.size() && c->gops[r->gop].req == r) {
+            c->gops[r->gop].req = nullptr;
+            if (r->side == 1) c->gops[r->gop].status = status;
+        } else if (r->side == 1 && status) {
+            WaitArgs s;
+            std::memset(&s, 0, sizeof(s));
+            s.status = status;
+            s.st = r->st;
+            rc = do_wait(w, st, s);
+        }
+    }
     // first-side requests: host-wait for each copy launch, then one wait
     // kernel per 64 of them; second-side receives only need their status.
     WaitArgs a;
@@ -476,6 +523,7 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
     for (int i = 0; i < n && !rc; ++i) {
         mpixs_request_s *r = reqs[i];
         mpixs_status *status = statuses ? (array_status ? &statuses[i] : statuses) : nullptr;
+        if (r->grouped) continue;
         if (r->second) {
             if (r->side == 1 && status) {
                 // the copy ran on this stream; only the status remains
@@ -632,6 +680,171 @@ void coll_collect(std::deque<CollRec *> &q, uint64_t &base) {
     }
 }
 
+// ------------------------------------------------------------- batches
+// Reserve `bytes` of the host-pinned descriptor arena and a completion flag.
+// Entries are recycled in order once their batch's signal kernel has set
+// the flag; if the arena is full the host waits for the oldest batch, which
+// was enqueued after everything it waits for and so always finishes.
+int arena_alloc(World *w, size_t bytes, size_t *off, int *flag) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes > w->arena_bytes) return MPIXS_ERR_NOMEM;
+    std::unique_lock<std::mutex> g(w->arena_mu);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        while (!w->arena_live.empty() &&
+               __atomic_load_n(&w->h_flags[w->arena_live.front().flag], __ATOMIC_ACQUIRE) == 1) {
+            w->free_flags.push_back(w->arena_live.front().flag);
+            w->arena_live.pop_front();
+        }
+        if (w->arena_live.empty()) w->arena_head = 0;
+        bool ok = false;
+        size_t at = 0;
+        if (!w->free_flags.empty()) {
+            if (w->arena_live.empty()) {
+                ok = true;
+                at = 0;
+            } else {
+                const size_t tail = w->arena_live.front().off;
+                if (w->arena_head >= tail) {
+                    if (w->arena_head + bytes <= w->arena_bytes) {
+                        ok = true;
+                        at = w->arena_head;
+                    } else if (bytes < tail) {
+                        ok = true;
+                        at = 0;
+                    }
+                } else if (w->arena_head + bytes < tail) {
+                    ok = true;
+                    at = w->arena_head;
+                }
+            }
+        }
+        if (ok) {
+            const int f = w->free_flags.back();
+            w->free_flags.pop_back();
+            __atomic_store_n(&w->h_flags[f], 0u, __ATOMIC_RELEASE);
+            w->arena_live.push_back(World::ArenaUse{at, bytes, f});
+            w->arena_head = at + bytes;
+            *off = at;
+            *flag = f;
+            return MPIXS_SUCCESS;
+        }
+        if (w->aborted.load()) return MPIXS_ERR_ABORTED;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(w->cfg.timeout_ms))
+            return MPIXS_ERR_TIMEOUT;
+        g.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        g.lock();
+    }
+}
+
+// Last rank of a group: match every rank's recorded operations, plan one
+// tile list, and enqueue wait(all arrivals) + batch kernel + signal.
+int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st, uint64_t g) {
+    const int n = sh->size;
+    struct Q {
+        std::vector<GOp *> s, r;
+    };
+    std::map<std::tuple<int, int, int>, Q> chans;
+    for (int q = 0; q < n; ++q)
+        for (GOp &op : rec->ops[size_t(q)]) {
+            if (op.kind == 0) chans[std::make_tuple(q, op.peer, op.tag)].s.push_back(&op);
+            else chans[std::make_tuple(op.peer, q, op.tag)].r.push_back(&op);
+        }
+    for (auto &kv : chans)
+        if (kv.second.s.size() != kv.second.r.size()) return MPIXS_ERR_ARG;
+    std::vector<BatchDesc> descs;
+    descs.reserve(64);
+    uint64_t total_tiles = 0;
+    for (auto &kv : chans) {
+        const int tag = std::get<2>(kv.first);
+        for (size_t i = 0; i < kv.second.s.size(); ++i) {
+            GOp *S = kv.second.s[i];
+            GOp *R = kv.second.r[i];
+            BatchDesc d;
+            std::memset(&d, 0, sizeof(d));
+            d.st = match_status(S->side, R->side, tag);
+            int wsz = 16;
+            uint64_t units = 0;
+            plan_copy(S->side, R->side, d.st.count_bytes, &d.src, &d.dst, &wsz, &units);
+            d.units = units;
+            d.w = uint32_t(wsz);
+            d.ntiles = uint32_t(std::max<uint64_t>(1, (units + BATCH_TILE - 1) / BATCH_TILE));
+            d.status = R->status;
+            d.rstream = R->side.st->dev;
+            if (R->req) R->req->st = d.st;
+            total_tiles += d.ntiles;
+            descs.push_back(d);
+        }
+    }
+    int rc = MPIXS_SUCCESS;
+    uint64_t *arrive = sh->d_grp;
+    uint64_t *done = sh->d_grp + 16 * n;
+    if (n > 1) {
+        WaitArgs wa;
+        std::memset(&wa, 0, sizeof(wa));
+        for (int q = 0; q < n; ++q) {
+            if (q == me) continue;
+            wa.ptr[wa.n] = arrive + 16 * q;
+            wa.target[wa.n] = g + 1;
+            wa.n++;
+        }
+        rc = do_wait(w, st, wa);
+        if (rc) return rc;
+    }
+    int flag = -1;
+    if (!descs.empty()) {
+        const uint64_t nwg = std::min<uint64_t>(total_tiles, 4096);
+        const size_t dbytes = descs.size() * sizeof(BatchDesc);
+        const size_t sbytes = size_t(nwg) * sizeof(BatchStart);
+        size_t off = 0;
+        rc = arena_alloc(w, dbytes + sbytes + 256, &off, &flag);
+        if (rc) return rc;
+        BatchDesc *hd = reinterpret_cast<BatchDesc *>(w->h_arena + off);
+        BatchStart *hs = reinterpret_cast<BatchStart *>(w->h_arena + off + ((dbytes + 255) & ~size_t(255)));
+        std::memcpy(hd, descs.data(), dbytes);
+        const uint64_t base = total_tiles / nwg;
+        const uint64_t extra = total_tiles % nwg;
+        uint32_t m = 0;
+        uint64_t first_of_m = 0;   // global index of message m's first tile
+        for (uint64_t b = 0; b < nwg; ++b) {
+            const uint64_t t = b * base + std::min(b, extra);
+            while (first_of_m + descs[m].ntiles <= t) {
+                first_of_m += descs[m].ntiles;
+                ++m;
+            }
+            hs[b].msg = m;
+            hs[b].tile = uint32_t(t - first_of_m);
+        }
+        BatchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.desc = hd;
+        a.start = hs;
+        a.nmsg = uint32_t(descs.size());
+        a.base = base;
+        a.extra = uint32_t(extra);
+        a.me = st->dev;
+        hipEvent_t e0 = nullptr;
+        if (profile_on(w)) prof_begin(w, st->hs, &e0);
+        rc = gpu_err(launch_batch(st->hs, a, int(nwg)));
+        if (profile_on(w)) prof_end(w, st->hs, e0, 0);
+        if (rc) return rc;
+        uint64_t bytes = 0;
+        for (auto &d : descs) bytes += uint64_t(d.st.count_bytes);
+        w->n_copy.fetch_add(1, std::memory_order_relaxed);
+        w->bytes_copied.fetch_add(bytes, std::memory_order_relaxed);
+    }
+    SignalArgs sg;
+    std::memset(&sg, 0, sizeof(sg));
+    sg.done_ptr = done;
+    sg.done_val = g + 1;
+    sg.me = st->dev;
+    sg.host_flag = flag >= 0 ? &w->h_flags[flag] : nullptr;
+    rc = gpu_err(launch_signal(st->hs, sg));
+    w->n_post.fetch_add(1, std::memory_order_relaxed);
+    return rc;
+}
+
 int parse_hex(const std::string &s, void *out, size_t n) {
     if (s.size() != 2 * n) return MPIXS_ERR_ARG;
     unsigned char *o = static_cast<unsigned char *>(out);
@@ -675,6 +888,7 @@ CommShared::~CommShared() {
     for (auto &kv : dir) delete kv.second;
     for (CollRec *r : colls) delete r;
     for (CollRec *r : hcolls) delete r;
+    for (GroupRec *r : groups) delete r;
 }
 
 }  // namespace mpixs
@@ -724,13 +938,26 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     w->d_streams = reinterpret_cast<DevStream *>(w->d_pool);
     w->d_chans = reinterpret_cast<DevChan *>(w->d_pool + s_bytes);
     w->d_coll = reinterpret_cast<uint64_t *>(w->d_pool + s_bytes + c_bytes);
-    if (hipHostMalloc(reinterpret_cast<void **>(&w->h_abort), 64, hipHostMallocDefault) !=
-        hipSuccess) {
+    if (c.batch_arena_mib <= 0) c.batch_arena_mib = 64;
+    w->arena_bytes = size_t(c.batch_arena_mib) << 20;
+    w->nflags = 4096;
+    // coherent host memory: the host writes these (or reads what the GPU
+    // wrote) while kernels run, and kernels must never see a cached copy
+    if (hipHostMalloc(reinterpret_cast<void **>(&w->h_abort), 64, hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w->h_arena), w->arena_bytes,
+                      hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w->h_flags), sizeof(uint32_t) * size_t(w->nflags),
+                      hipHostMallocCoherent) != hipSuccess) {
         (void)hipFree(w->d_pool);
+        if (w->h_abort) (void)hipHostFree(w->h_abort);
+        if (w->h_arena) (void)hipHostFree(w->h_arena);
         delete w;
         return MPIXS_ERR_NOMEM;
     }
     *w->h_abort = 0;
+    std::memset(w->h_flags, 0, sizeof(uint32_t) * size_t(w->nflags));
+    for (int i = w->nflags - 1; i >= 0; --i) w->free_flags.push_back(i);
     w->ep_users.assign(size_t(c.max_streams), 0);
 
     CommShared *sh = new CommShared();
@@ -775,6 +1002,8 @@ int mpixs_world_free(mpixs_world *pw) {
     (void)hipDeviceSynchronize();
     (void)hipFree(w->d_pool);
     (void)hipHostFree(w->h_abort);
+    (void)hipHostFree(w->h_arena);
+    (void)hipHostFree(w->h_flags);
     for (auto *h : w->world_handles) delete h;
     delete w->world_sh;
     delete w;
@@ -952,14 +1181,15 @@ int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm 
         CreateRec &cr = ps->creates[k];
         if (!cr.sh) {
             const size_t words = size_t(16) * size_t(ps->size + 1);
-            const size_t off = w->coll_next.fetch_add(words);
-            if (off + words > w->coll_words) return MPIXS_ERR_NOMEM;
+            const size_t off = w->coll_next.fetch_add(2 * words);
+            if (off + 2 * words > w->coll_words) return MPIXS_ERR_NOMEM;
             cr.sh = new CommShared();
             cr.sh->w = w;
             cr.sh->size = ps->size;
             cr.sh->id = w->next_comm_id.fetch_add(1);
             cr.sh->streams.assign(size_t(ps->size), nullptr);
             cr.sh->d_coll = w->d_coll + off;
+            cr.sh->d_grp = w->d_coll + off + words;
         }
         cr.sh->streams[size_t(parent->rank)] = s;
         cr.arrived++;
@@ -1049,6 +1279,7 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count, mpixs
                             mpixs_op op, mpixs_comm c) {
     int rc = check_allreduce(c, sendbuf, recvbuf, count, dt, op, true);
     if (rc) return rc;
+    if (c->in_group) return MPIXS_ERR_ARG;   // collectives are not grouped
     CommShared *sh = c->sh;
     World *w = sh->w;
     StreamObj *st = c->stream;
@@ -1083,6 +1314,66 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count, mpixs
     if (rec->refs.fetch_sub(1) == 1) {
         std::lock_guard<std::mutex> g(sh->coll_mu);
         coll_collect(sh->colls, sh->coll_base);
+    }
+    return rc;
+}
+
+// ================================================================ groups
+int mpixs_group_start(mpixs_comm c) {
+    if (!c || !c->sh) return MPIXS_ERR_COMM;
+    if (!c->stream || !c->stream->gpu) return MPIXS_ERR_COMM;
+    if (c->sh->size > 64) return MPIXS_ERR_COMM;
+    if (c->in_group) return MPIXS_ERR_ARG;
+    c->in_group = true;
+    c->gops.clear();
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_group_end(mpixs_comm c) {
+    if (!c || !c->sh) return MPIXS_ERR_COMM;
+    if (!c->in_group) return MPIXS_ERR_ARG;
+    c->in_group = false;
+    CommShared *sh = c->sh;
+    World *w = sh->w;
+    StreamObj *st = c->stream;
+    const int n = sh->size;
+    const uint64_t g = c->group_seq++;
+    sh->grp_mu.lock();
+    while (sh->group_base + sh->groups.size() <= g) {
+        GroupRec *r = new GroupRec();
+        r->ops.resize(size_t(n));
+        r->streams.assign(size_t(n), nullptr);
+        r->refs.store(n);
+        sh->groups.push_back(r);
+    }
+    GroupRec *rec = sh->groups[g - sh->group_base];
+    rec->ops[size_t(c->rank)] = std::move(c->gops);
+    c->gops.clear();
+    rec->streams[size_t(c->rank)] = st;
+    const bool last = ++rec->arrived == n;
+    int rc = MPIXS_SUCCESS;
+    if (last) {
+        sh->grp_mu.unlock();
+        rc = group_launch(w, sh, rec, c->rank, st, g);
+        rec->error = rc;
+        rec->launched.store(1, std::memory_order_release);
+    } else {
+        rc = do_post(w, st, sh->d_grp + 16 * c->rank, g + 1);
+        sh->grp_mu.unlock();
+        if (!rc) rc = host_wait(w, [&] { return rec->launched.load(std::memory_order_acquire) != 0; });
+        if (!rc) rc = rec->error;
+        if (!rc) {
+            WaitArgs a = wait_one(sh->d_grp + 16 * n, g + 1);
+            rc = do_wait(w, st, a);
+        }
+    }
+    if (rec->refs.fetch_sub(1) == 1) {
+        std::lock_guard<std::mutex> lk(sh->grp_mu);
+        while (!sh->groups.empty() && sh->groups.front()->refs.load() == 0) {
+            delete sh->groups.front();
+            sh->groups.pop_front();
+            ++sh->group_base;
+        }
     }
     return rc;
 }

@@ -113,6 +113,25 @@ struct CollRec {
     int count = 0, dtype = 0, op = 0;
 };
 
+// One operation recorded inside a group (see mpixs_group_start).
+struct GOp {
+    int kind = 0;                      // 0 send, 1 receive
+    int peer = -1;
+    int tag = 0;
+    Side side;
+    void *status = nullptr;            // receive status to write, or nullptr
+    mpixs_request_s *req = nullptr;    // request to receive the status values
+};
+
+struct GroupRec {
+    int arrived = 0;
+    std::vector<std::vector<GOp>> ops;  // per rank
+    std::vector<StreamObj *> streams;
+    std::atomic<int> launched{0};
+    int error = 0;
+    std::atomic<int> refs{0};
+};
+
 struct CreateRec {
     int arrived = 0;
     int left = 0;
@@ -132,6 +151,10 @@ struct CommShared {
     std::deque<CollRec *> hcolls;      // host-synchronised allreduce instances
     uint64_t hcoll_base = 0;
     uint64_t *d_coll = nullptr;        // arrive[q] at 16*q, done at 16*size
+    uint64_t *d_grp = nullptr;         // groups: arrive[q] at 16*q, done at 16*size
+    std::mutex grp_mu;
+    std::deque<GroupRec *> groups;
+    uint64_t group_base = 0;
     std::mutex create_mu;
     std::map<uint64_t, CreateRec> creates;
     std::atomic<int> handles{0};
@@ -151,9 +174,11 @@ struct mpixs_comm_s {
     int rank = -1;
     mpixs::StreamObj *stream = nullptr;
     std::unordered_map<uint64_t, mpixs::Channel *> cache;
-    uint64_t coll_seq = 0, hcoll_seq = 0, create_seq = 0;
+    uint64_t coll_seq = 0, hcoll_seq = 0, create_seq = 0, group_seq = 0;
     std::atomic<int> pending{0};
     bool world_handle = false;
+    bool in_group = false;
+    std::vector<mpixs::GOp> gops;
 };
 
 struct mpixs_request_s {
@@ -163,6 +188,8 @@ struct mpixs_request_s {
     uint64_t k = 0;
     int side = 0;                      // 0 send, 1 receive
     bool second = false;               // this side launched the copy itself
+    bool grouped = false;              // recorded in a group: complete at group_end
+    size_t gop = 0;                    // index in the comm's recorded operations
     mpixs::StatusVal st{};
 };
 
@@ -203,6 +230,20 @@ struct World {
     // statistics
     std::atomic<uint64_t> n_post{0}, n_wait{0}, n_copy{0}, n_reduce{0};
     std::atomic<uint64_t> bytes_copied{0}, bytes_reduced{0}, host_waits{0};
+    // host-pinned (coherent) ring of batch descriptor tables; an entry is
+    // recycled once the batch's signal kernel has set its flag
+    struct ArenaUse {
+        size_t off, bytes;
+        int flag;
+    };
+    std::mutex arena_mu;
+    char *h_arena = nullptr;
+    size_t arena_bytes = 0;
+    size_t arena_head = 0;
+    std::deque<ArenaUse> arena_live;
+    uint32_t *h_flags = nullptr;
+    int nflags = 0;
+    std::vector<int> free_flags;
     std::mutex prof_mu;
     std::vector<ProfPair> prof;
     uint64_t timed_copy = 0, timed_reduce = 0;

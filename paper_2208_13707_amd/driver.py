@@ -19,7 +19,7 @@ from . import mpixs as M
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DRIVER_PATH = os.path.join(_HERE, "libmpixs_driver.so")
 
-SEND, ISEND, RECV, IRECV, WAITALL, ALLREDUCE, MARK = 1, 2, 3, 4, 5, 6, 7
+SEND, ISEND, RECV, IRECV, WAITALL, ALLREDUCE, MARK, GROUP_START, GROUP_END = range(1, 10)
 
 OP_DTYPE = np.dtype([
     ("kind", "<i4"), ("comm", "<i4"), ("peer", "<i4"), ("tag", "<i4"), ("count", "<i4"),

@@ -39,7 +39,8 @@ class Config(ctypes.Structure):
     _fields_ = [("max_streams", ctypes.c_int32), ("endpoint_policy", ctypes.c_int32),
                 ("fuse_max_bytes", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
                 ("max_channels", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("max_collectives", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("max_collectives", ctypes.c_int32), ("batch_arena_mib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class Status(ctypes.Structure):
@@ -98,6 +99,8 @@ SIGNATURES = {
     "mpixs_wait_enqueue": [_pp, _vp],
     "mpixs_waitall_enqueue": [_i, _pp, _vp],
     "mpixs_allreduce_enqueue": [_vp, _vp, _i, ctypes.c_int32, ctypes.c_int32, _vp],
+    "mpixs_group_start": [_vp],
+    "mpixs_group_end": [_vp],
     "mpixs_send": [_vp, _i, ctypes.c_int32, _i, _i, _vp],
     "mpixs_recv": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _vp],
     "mpixs_allreduce": [_vp, _vp, _i, ctypes.c_int32, ctypes.c_int32, _vp],
@@ -312,6 +315,14 @@ def mpixs_waitall_enqueue(requests, statuses=None):
 
 def mpixs_allreduce_enqueue(sendbuf, recvbuf, count, dt, op, comm):
     return lib().mpixs_allreduce_enqueue(ptr(sendbuf), ptr(recvbuf), count, dt, op, comm)
+
+
+def mpixs_group_start(comm):
+    return lib().mpixs_group_start(comm)
+
+
+def mpixs_group_end(comm):
+    return lib().mpixs_group_end(comm)
 
 
 def mpixs_send(buf, count, dt, dest, tag, comm):

@@ -17,7 +17,9 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-from workloads.program import IN_PLACE, Allreduce, Program, Recv, Send, User, Wait
+from workloads.program import (
+    IN_PLACE, Allreduce, GroupEnd, GroupStart, Program, Recv, Send, User, Wait,
+)
 
 
 @dataclass
@@ -245,6 +247,10 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
                     record(r, t, i, rc)
                 elif isinstance(o, User):
                     user(r, o)
+                elif isinstance(o, GroupStart):
+                    record(r, t, i, M.mpixs_group_start(comm_of(r, o.comm)))
+                elif isinstance(o, GroupEnd):
+                    record(r, t, i, M.mpixs_group_end(comm_of(r, o.comm)))
                 else:
                     raise ValueError(o)
         except Exception:

@@ -183,3 +183,41 @@ def test_host_synced_vector_messages_match():
     ops = [[Send("A", 0, 1, vt, 1, 0), Send("A", 12, 1, vt, 1, 1)],
            [Recv("H", 0, 1, vt, 0, 0, status="a"), Recv("H", 12, 1, vt, 0, 1, status="b")]]
     check(single_stream(2, bufs, ops, name="host-synced vector"), host_synced=True)
+
+
+# ----------------------------------------------------------------- batching
+from workloads.program import GroupEnd, GroupStart  # noqa: E402
+
+
+@pytest.mark.parametrize("count,blocking", [(37, True), (2730, False), (43690, True)])
+def test_grouped_ring_halo(count, blocking):
+    check(C.ring_halo(count=count, steps=3, update=True, blocking_recv=blocking, grouped=True))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_grouped_random_programs(seed):
+    check(C.random_program(seed, nranks=5, nmsg=60, grouped=True))
+
+
+def test_grouped_batch_small():
+    check(C.batch(npairs=400, nranks=8, max_bytes=65536, grouped=True))
+
+
+def test_grouped_batch_config_size():
+    """10,000 messages over 32 ranks in one group, as the batching workload."""
+    check(C.batch(npairs=10000, nranks=32, grouped=True))
+
+
+def test_group_head_to_head_and_unmatched():
+    b = [{"s": as_bytes(np.array([10 + q, 20 + q], np.int32)), "r": np.full(8, 0xEE, np.uint8)}
+         for q in range(2)]
+    ops = [[GroupStart(), Send("s", 0, 1, "int32", 1 - q, 0),
+            Recv("r", 0, 1, "int32", 1 - q, 0, status="st"), GroupEnd(),
+            GroupStart(), Send("s", 4, 1, "int32", 1 - q, 5)] + ([GroupEnd()] if q else
+                                                                   [Send("s", 4, 1, "int32", 1, 6),
+                                                                    GroupEnd()])
+           for q in range(2)]
+    # rank 1 never receives tags 5/6 in its second group: that instance fails
+    ops[1].insert(-1, Recv("r", 4, 1, "int32", 0, 5))
+    g, _ = check(single_stream(2, b, ops, name="groups-h2h-unmatched"))
+    assert np.frombuffer(g.buffers[1]["r"][:4].tobytes(), np.int32)[0] == 10

@@ -254,3 +254,56 @@ def test_random_programs_complete_and_deliver(seed):
     # re-reading the send regions with numpy views of the vector/contiguous types
     assert len(r.match_log) == 40
     assert all(not e for e in r.sync_errors)
+
+
+# ------------------------------------------------------------------- groups
+from workloads.program import GroupEnd, GroupStart  # noqa: E402
+
+
+def test_group_head_to_head_blocking_sends_complete():
+    b = [{"s": as_bytes(np.array([10 + q], np.int32)), "r": np.zeros(4, np.uint8)}
+         for q in range(2)]
+    ops = [[GroupStart(), Send("s", 0, 1, "int32", 1 - q, 0), Recv("r", 0, 1, "int32", 1 - q, 0,
+                                                                    status="st"),
+            GroupEnd()] for q in range(2)]
+    r = sim.run(single_stream(2, b, ops))
+    assert not r.deadlock
+    assert [i32(r.buffers[q]["r"])[0] for q in range(2)] == [11, 10]
+    assert r.statuses[0]["st"] == (1, 0, "SUCCESS", 4)
+
+
+def test_group_unmatched_fails_whole_instance():
+    b = [{"s": as_bytes(np.array([1, 2], np.int32)), "r": np.full(8, 0xEE, np.uint8)}
+         for _ in range(2)]
+    ops = [[GroupStart(), Send("s", 0, 1, "int32", 1, 0), Send("s", 4, 1, "int32", 1, 1),
+            GroupEnd()],
+           [GroupStart(), Recv("r", 0, 1, "int32", 0, 0), GroupEnd()]]
+    r = sim.run(single_stream(2, b, ops))
+    assert not r.deadlock
+    assert [e for _, _, e in r.sync_errors[0]] == ["ERR_ARG"]
+    assert [e for _, _, e in r.sync_errors[1]] == ["ERR_ARG"]
+    assert r.buffers[1]["r"].tolist() == [0xEE] * 8
+
+
+@pytest.mark.parametrize("blocking", [True, False])
+def test_grouped_halo_equals_slicing(blocking):
+    count, steps = 29, 3
+    p = C.ring_halo(count=count, steps=steps, update=True, blocking_recv=blocking, grouped=True)
+    r = sim.run(p)
+    assert not r.deadlock
+    A, H = _halo_by_slicing(p, steps, count, True)
+    for q in range(p.nranks):
+        assert np.array_equal(f32(r.buffers[q]["A"]).reshape(count, 8), A[q])
+        assert r.statuses[q][f"st{steps - 1}b"] == ((q + 1) % p.nranks, steps - 1, "SUCCESS",
+                                                     12 * count)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_grouped_random_program_equals_ungrouped(seed):
+    a = sim.run(C.random_program(seed))
+    b = sim.run(C.random_program(seed, grouped=True))
+    assert not b.deadlock
+    for q in range(len(a.buffers)):
+        for k in a.buffers[q]:
+            assert np.array_equal(a.buffers[q][k], b.buffers[q][k])
+        assert a.statuses[q] == b.statuses[q]

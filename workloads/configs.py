@@ -26,8 +26,8 @@ from typing import List, Optional
 import numpy as np
 
 from .program import (
-    IN_PLACE, Allreduce, Program, Recv, Send, User, Wait, as_bytes, footprint_bound,
-    single_stream,
+    IN_PLACE, Allreduce, GroupEnd, GroupStart, Program, Recv, Send, User, Wait, as_bytes,
+    footprint_bound, single_stream,
 )
 
 SEED = 220813707
@@ -65,8 +65,9 @@ def halo_type(count: int):
 
 
 def ring_halo(count: int = 2730, steps: int = 100, nranks: int = 8,
-              update: bool = False, blocking_recv: bool = True) -> Program:
-    """Config 2: bidirectional ring halo exchange with a vector datatype."""
+              update: bool = False, blocking_recv: bool = True, grouped: bool = False) -> Program:
+    """Config 2: bidirectional ring halo exchange with a vector datatype.
+    ``grouped``: each step's operations form one group (one batch)."""
     vt = halo_type(count)
     bufs, ops = [], []
     for r in range(nranks):
@@ -77,6 +78,8 @@ def ring_halo(count: int = 2730, steps: int = 100, nranks: int = 8,
         right, left = (r + 1) % nranks, (r - 1) % nranks
         lst = []
         for s in range(steps):
+            if grouped:
+                lst.append(GroupStart())
             lst += [Send("A", 0, 1, vt, right, s, req=f"s{s}a"),
                     Send("A", 12, 1, vt, left, s, req=f"s{s}b")]
             if blocking_recv:
@@ -88,10 +91,13 @@ def ring_halo(count: int = 2730, steps: int = 100, nranks: int = 8,
                         Recv("H", 12, 1, vt, right, s, req=f"r{s}b")]
                 lst += [Wait([f"s{s}a", f"s{s}b", f"r{s}a", f"r{s}b"],
                              [None, None, f"st{s}a", f"st{s}b"])]
+            if grouped:
+                lst.append(GroupEnd())
             if update:
                 lst += [User(("add_rows_f32", "A", 0, "H", 0, count, 8, 0, 6))]
         ops.append(lst)
-    return single_stream(nranks, bufs, ops, name=f"ring_halo_{nranks}r_c{count}_s{steps}")
+    return single_stream(nranks, bufs, ops,
+                         name=f"ring_halo_{nranks}r_c{count}_s{steps}" + ("_grouped" if grouped else ""))
 
 
 # --------------------------------------------------------------------------- 3
@@ -150,9 +156,10 @@ def batch_messages(npairs: int = 10000, nranks: int = 32, max_bytes: int = 26214
 
 
 def batch(npairs: int = 10000, nranks: int = 32, max_bytes: int = 262144,
-          min_bytes: int = 8) -> Program:
+          min_bytes: int = 8, grouped: bool = False) -> Program:
     """Config 4: every rank isends all its messages in global order, then
-    irecvs all its messages in global order, then waits for all of them."""
+    irecvs all its messages in global order, then waits for all of them.
+    ``grouped``: all of it is one group (one batch)."""
     msgs = batch_messages(npairs, nranks, max_bytes, min_bytes)
     send_off = [0] * nranks
     recv_off = [0] * nranks
@@ -177,7 +184,10 @@ def batch(npairs: int = 10000, nranks: int = 32, max_bytes: int = 262144,
         ops[r] = ops[r] + recvs[r]
         if reqs:
             ops[r].append(Wait(reqs, stats))
-    return single_stream(nranks, bufs, ops, name=f"batch_{npairs}p_{nranks}r")
+        if grouped:
+            ops[r] = [GroupStart()] + ops[r] + [GroupEnd()]
+    return single_stream(nranks, bufs, ops,
+                         name=f"batch_{npairs}p_{nranks}r" + ("_grouped" if grouped else ""))
 
 
 # ------------------------------------------------------------------- examples
@@ -213,7 +223,7 @@ def threads_example(nthreads: int = 4, n: int = 100) -> Program:
 # --------------------------------------------------------------- random safe
 def random_program(seed: int, nranks: int = 4, nmsg: int = 40, max_elems: int = 300,
                    tags: int = 3, ncomms: int = 2, allreduces: int = 2,
-                   types: Optional[list] = None) -> Program:
+                   types: Optional[list] = None, grouped: bool = False) -> Program:
     """A random program that is safe under synchronous-send semantics.
 
     Messages are drawn as (src, dst, comm, tag, datatype); each rank issues
@@ -268,9 +278,12 @@ def random_program(seed: int, nranks: int = 4, nmsg: int = 40, max_elems: int = 
         lst = sends[r] + recvs[r]
         reqs = [o.req for o in lst]
         if reqs:
-            # waits of one communicator's stream at a time
             lst = list(lst)
             lst.append(Wait(reqs, [f"st_{q}" if q.startswith("r") else None for q in reqs]))
+        if grouped:
+            # one group per communicator (all on the rank's single stream)
+            lst = ([GroupStart(c) for c in range(ncomms)] + lst
+                   + [GroupEnd(c) for c in range(ncomms)])
         for a in range(allreduces):
             if a % 2 == 0:
                 lst.append(Allreduce("ared", 0, "aout", 0, red_n, "int64", "sum"))
@@ -279,4 +292,4 @@ def random_program(seed: int, nranks: int = 4, nmsg: int = 40, max_elems: int = 
         ops.append(lst)
     return Program(nranks=nranks, buffers=bufs, ops=[[o] for o in ops], streams_per_rank=1,
                    comm_streams=[[0] * nranks for _ in range(ncomms)],
-                   name=f"random_{seed}")
+                   name=f"random_{seed}" + ("_grouped" if grouped else ""))

@@ -119,7 +119,23 @@ class User:
     kind = "user"
 
 
-Op = Union[Send, Recv, Wait, Allreduce, User]
+@dataclass
+class GroupStart:
+    """Start recording this rank's operations on ``comm`` (a batch)."""
+    comm: int = 0
+
+    kind = "group_start"
+
+
+@dataclass
+class GroupEnd:
+    """Collective end of the rank's current group on ``comm``."""
+    comm: int = 0
+
+    kind = "group_end"
+
+
+Op = Union[Send, Recv, Wait, Allreduce, User, GroupStart, GroupEnd]
 
 
 @dataclass
@@ -224,7 +240,7 @@ def streams_of_thread(p: Program, rank: int, thread: int) -> List[int]:
 
 Tree = TypeTree
 __all__ = [
-    "Program", "Send", "Recv", "Wait", "Allreduce", "User", "IN_PLACE",
+    "Program", "Send", "Recv", "Wait", "Allreduce", "User", "GroupStart", "GroupEnd", "IN_PLACE",
     "ANY_SOURCE", "ANY_TAG", "BASIC_TYPES", "as_bytes", "count_messages", "Tree",
     "single_stream", "footprint_bound", "streams_of_thread",
 ]
