@@ -493,6 +493,8 @@ def bench_batch(args):
     for variant, mode, tagb in (("grouped", 0, 1000), ("plain", 0, 0), ("host", 1, 0)):
         if variant == "host" and args.no_host_synced:
             continue
+        if args.only_grouped and variant != "grouped":
+            continue
         k = args.steps if variant != "host" else max(1, min(args.steps, args.hs_steps))
         sess = D.Session(n)
         run_checked(sess, ops(variant, args.warmup, tagb), mode=mode, max_reqs=maxreq)
@@ -500,6 +502,8 @@ def bench_batch(args):
         sess.close()
         res[variant] = npairs * k / sec
         log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.2f} ms per batch)")
+    if args.only_grouped:
+        return {"workload": "batch", "grouped_msgs_per_s": res["grouped"]}
     # identical results across the paths and the oracle (on a sampled set of ranks)
     for v in res:
         for r in range(n):
@@ -530,6 +534,70 @@ def bench_batch(args):
                                 "kind": "oracle",
                                 "sample": f"the whole batch ({npairs} messages) once, {dt:.1f} s"}
     return line
+
+
+# ------------------------------------------------------------------- serve
+def bench_serve(args):
+    """Config 5: 64 rank threads serve an open-loop Poisson stream of
+    requests (60 % send/recv, 30 % isend+wait, 10 % allreduce-sum int32 over
+    all ranks; bytes log-uniform 64 B .. 4 MiB) admitted under an 8 GB device
+    budget; arrival rate swept 1e4 .. 1e6 per second."""
+    import numpy as np
+    from paper_2208_13707_amd import driver as D
+    from workloads import configs as C
+    from workloads import payload
+
+    n = args.serve_ranks
+    sess = D.Session(n)
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    rows = []
+    try:
+        rc, _, _ = sess.serve(C.serving_schedule(1e4, 64, nranks=n, seed=99), args.budget)
+        if rc:
+            raise RuntimeError(f"serve warm-up failed: {rc}")
+        for k, rate in enumerate(rates):
+            nreq = int(min(args.serve_max, max(200, rate * args.serve_seconds)))
+            sched = C.serving_schedule(rate, nreq, nranks=n, seed=k + 1)
+            rc, res, wall = sess.serve(sched, args.budget)
+            if rc:
+                raise RuntimeError(f"serve at rate {rate:g}: error {rc}")
+            arr = np.array([q["arrival_us"] for q in sched])
+            lat = res["done_us"] - arr
+            wait = res["admit_us"] - arr
+            # sampled check of results (point-to-point requests; payloads are
+            # regenerated on the host from their published definition)
+            for i in range(0, nreq, max(1, nreq // 50)):
+                q = sched[i]
+                if q["kind"] == 2:
+                    continue
+                b = payload.fill(q["seed"], q["bytes"])
+                j = np.arange(1, b.size + 1, dtype=np.uint64)
+                with np.errstate(over="ignore"):
+                    want = int((b.astype(np.uint64) * j).sum(dtype=np.uint64))
+                if int(res["checksum"][i]) != want:
+                    raise AssertionError(f"request {i}: checksum differs")
+            row = {"offered_per_s": rate, "requests": nreq,
+                   "served_per_s": nreq / wall if wall > 0 else None,
+                   "p50_latency_us": pct(lat, 50), "p99_latency_us": pct(lat, 99),
+                   "p99_admission_wait_us": pct(wait, 99),
+                   "gbps_payload": float(sum(q["bytes"] * (n if q["kind"] == 2 else 1)
+                                             for q in sched)) / wall / 1e9}
+            rows.append(row)
+            log(f"[serve] offered {rate:9.0f}/s: served {row['served_per_s']:9.0f}/s, "
+                f"p50 {row['p50_latency_us']:8.1f} us, p99 {row['p99_latency_us']:9.1f} us")
+    finally:
+        sess.close()
+    best = max(rows, key=lambda r: r["served_per_s"] or 0)
+    return {
+        "metric": "served requests/s with p50/p99 latency (open-loop Poisson arrivals)",
+        "value": best["served_per_s"], "unit": "requests/s", "n_gpus": 1,
+        "steps": sum(r["requests"] for r in rows), "warmup": 64,
+        "ms_per_step": 1000.0 / best["served_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"serving_{n}ranks_mix60-30-10_64B-4MiB",
+                   "budget_bytes": args.budget},
+        "sweep": rows,
+    }
 
 
 # ---------------------------------------------------------------- pingpong
@@ -646,8 +714,14 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="halo",
-                    choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch"])
+                    choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch", "serve"])
+    ap.add_argument("--serve-ranks", type=int, default=64)
+    ap.add_argument("--serve-rates", default="1e4,3e4,1e5,3e5,1e6")
+    ap.add_argument("--serve-seconds", type=float, default=0.5)
+    ap.add_argument("--serve-max", type=int, default=20000)
+    ap.add_argument("--budget", type=int, default=8 << 30)
     ap.add_argument("--pairs", type=int, default=10000)
+    ap.add_argument("--only-grouped", action="store_true", help="batch: grouped variant only")
     ap.add_argument("--ranks-batch", type=int, default=32)
     ap.add_argument("--count", type=int, default=43690)
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")
@@ -667,7 +741,7 @@ def main():
               "(ranks are host threads sharing one MI355X)", file=sys.stderr)
         sys.exit(2)
     defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
-                "vcopy": (100, 10), "batch": (5, 1)}
+                "vcopy": (100, 10), "batch": (5, 1), "serve": (1, 0)}
     k, w = defaults[args.workload]
     args.steps = args.steps or k
     args.warmup = args.warmup if args.warmup is not None else w
@@ -680,7 +754,7 @@ def main():
                 "roofline": vector_copy_roofline(args.count, args.steps)}
     else:
         fn = {"halo": bench_halo, "allreduce": bench_allreduce, "pingpong": bench_pingpong,
-              "copy": bench_copy, "batch": bench_batch}[args.workload]
+              "copy": bench_copy, "batch": bench_batch, "serve": bench_serve}[args.workload]
         line = fn(args)
     print(json.dumps(line), flush=True)
 

@@ -68,6 +68,62 @@ typedef struct {
     int64_t error_op;
 } mpixs_drv_result;
 
+/* ------------------------------------------------------------- serving
+ * An open-loop request server over the enqueue path.  Requests arrive at
+ * given times; the owner of a request (the sender of a point-to-point
+ * request, rank 0 of an allreduce) admits it when its buffers fit in a
+ * device arena of `budget_bytes` (waiting for earlier requests to finish if
+ * they do not), after which every participant enqueues its part on its
+ * stream: the sender fills its buffer with the request's payload and sends
+ * (send_enqueue, or isend_enqueue + wait_enqueue), the receiver receives and
+ * a checksum of the received bytes is written to host memory; for an
+ * allreduce every rank fills its input and calls allreduce_enqueue (int32
+ * SUM over all ranks) and rank 0 checksums its output.  A reaper thread
+ * watches the completion flags (written by the device), frees the buffers
+ * and timestamps the requests, so later arrivals are admitted as memory
+ * frees up while earlier requests are still on the GPU.
+ *
+ * Payload byte j of a buffer with seed s is byte (j mod 8) of
+ * splitmix64(s * 2^32 + floor(j / 8)) (Steele, Lea, Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014); the checksum of n bytes is
+ * the sum over j of byte_j * (j + 1) modulo 2^64.  An allreduce rank r uses
+ * seed s + r. */
+enum { MPIXS_DRV_REQ_SENDRECV = 0, MPIXS_DRV_REQ_ISEND_WAIT = 1, MPIXS_DRV_REQ_ALLREDUCE = 2 };
+
+typedef struct {
+    int32_t kind;
+    int32_t src;         /* point-to-point: sender */
+    int32_t dst;         /* point-to-point: receiver */
+    int32_t pad;
+    int64_t bytes;       /* message bytes; allreduce: bytes per rank (multiple of 4) */
+    double arrival_us;   /* arrival time after the start */
+    uint64_t seed;
+} mpixs_drv_req;
+
+typedef struct {
+    double admit_us;     /* when the owner admitted it (after the start) */
+    double done_us;      /* when the reaper saw its completion flag */
+    uint64_t checksum;   /* device checksum of the received / reduced bytes */
+    int32_t error;       /* first error of an enqueue call of the request */
+    int32_t pad;
+} mpixs_drv_req_result;
+
+/* Serve nreq requests (sorted by arrival) with one thread per rank of the
+ * communicators comms[0..nranks-1] (each with its GPU stream in streams[]).
+ * Requests are admitted first come, first served in arrival order, so a
+ * request never waits for memory held by requests that depend on it.
+ * Point-to-point requests need src != dst (a synchronous send to oneself on
+ * one stream cannot complete).  Returns MPIXS_ERR_ARG (nothing run) for an
+ * unsorted list, an unknown kind, out-of-range ranks or sizes, or an
+ * allreduce size that is not a multiple of 4; MPIXS_ERR_NOMEM if the budget
+ * cannot be allocated or a request does not fit it; otherwise the first
+ * error of an enqueue call (0 if none).  *wall_s receives the time from the
+ * start to the last completion.  The buffers live in one device allocation
+ * of budget_bytes made by this call and freed before it returns. */
+int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *comms,
+                    void *const *streams, const mpixs_drv_req *reqs, int64_t nreq,
+                    int64_t budget_bytes, mpixs_drv_req_result *results, double *wall_s);
+
 /* Run the threads; mode 0 = enqueue calls, 1 = host-synchronised calls.
  * marks_ms (optional, nthreads * max nmarks doubles, row-major by thread)
  * receives the time of every recorded mark relative to thread 0's mark 0.

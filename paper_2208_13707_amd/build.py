@@ -24,7 +24,7 @@ HIP_FLAGS = [
 
 LIBS = {
     "libmpixs.so": ["kernels.hip", "runtime.cpp", "types.cpp"],
-    "libmpixs_driver.so": ["driver.cpp"],
+    "libmpixs_driver.so": ["driver.cpp", "serve.hip"],
 }
 
 

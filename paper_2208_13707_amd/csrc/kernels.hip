@@ -348,21 +348,27 @@ __device__ __forceinline__ void tile_copy_w(const BatchDesc &d, uint64_t u0, uin
 __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
     __shared__ BatchDesc sd;
     __shared__ uint32_t s_fatal;
+    // descriptors live in host memory: lanes fetch one 16-byte word each so a
+    // descriptor costs one round trip over the fabric
+    constexpr int DW = sizeof(BatchDesc) / 16;
+    using W16 = __attribute__((ext_vector_type(4))) uint32_t;
     const uint32_t b = blockIdx.x;
     const uint64_t cnt = a.base + (b < a.extra ? 1 : 0);
     uint32_t m = a.start[b].msg;
     uint32_t tin = a.start[b].tile;
-    if (threadIdx.x == 0) {
-        s_fatal = ld_relaxed32(&a.me->fatal);
-        sd = a.desc[m];
-    }
+    if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
+    if (threadIdx.x < DW)
+        reinterpret_cast<W16 *>(&sd)[threadIdx.x] =
+            reinterpret_cast<const W16 *>(a.desc + m)[threadIdx.x];
     __syncthreads();
     for (uint64_t i = 0; i < cnt; ++i) {
         if (tin >= sd.ntiles) {
             ++m;
             tin = 0;
             __syncthreads();
-            if (threadIdx.x == 0) sd = a.desc[m];
+            if (threadIdx.x < DW)
+                reinterpret_cast<W16 *>(&sd)[threadIdx.x] =
+                    reinterpret_cast<const W16 *>(a.desc + m)[threadIdx.x];
             __syncthreads();
         }
         if (!s_fatal) {

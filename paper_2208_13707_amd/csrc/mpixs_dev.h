@@ -207,6 +207,8 @@ struct BatchStart {
     uint32_t tile;
 };
 
+static_assert(sizeof(BatchDesc) % 16 == 0, "descriptors are fetched in 16-byte words");
+
 struct BatchArgs {
     const BatchDesc *desc;
     const BatchStart *start;

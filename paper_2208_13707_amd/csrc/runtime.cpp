@@ -744,20 +744,25 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     const int n = sh->size;
     struct Q {
         std::vector<GOp *> s, r;
+        int tag = 0;
     };
-    std::map<std::tuple<int, int, int>, Q> chans;
+    std::unordered_map<uint64_t, Q> chans;
+    size_t nops = 0;
+    for (int q = 0; q < n; ++q) nops += rec->ops[size_t(q)].size();
+    chans.reserve(nops);
     for (int q = 0; q < n; ++q)
         for (GOp &op : rec->ops[size_t(q)]) {
-            if (op.kind == 0) chans[std::make_tuple(q, op.peer, op.tag)].s.push_back(&op);
-            else chans[std::make_tuple(op.peer, q, op.tag)].r.push_back(&op);
+            Q &e = chans[op.kind == 0 ? chan_key(q, op.peer, op.tag) : chan_key(op.peer, q, op.tag)];
+            e.tag = op.tag;
+            (op.kind == 0 ? e.s : e.r).push_back(&op);
         }
     for (auto &kv : chans)
         if (kv.second.s.size() != kv.second.r.size()) return MPIXS_ERR_ARG;
     std::vector<BatchDesc> descs;
-    descs.reserve(64);
+    descs.reserve(nops / 2 + 1);
     uint64_t total_tiles = 0;
     for (auto &kv : chans) {
-        const int tag = std::get<2>(kv.first);
+        const int tag = kv.second.tag;
         for (size_t i = 0; i < kv.second.s.size(); ++i) {
             GOp *S = kv.second.s[i];
             GOp *R = kv.second.r[i];

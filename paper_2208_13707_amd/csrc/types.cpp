@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <mutex>
 #include <numeric>
@@ -27,8 +28,12 @@ namespace {
 
 constexpr int64_t kMaxSegs = int64_t(1) << 24;
 
-std::mutex g_types_mu;
-std::vector<TypeObj *> g_types;   // index = handle
+// Handles index a fixed table that only grows; lookups take no lock (the
+// enqueue path looks a datatype up on every call, from every rank thread).
+constexpr int32_t kMaxTypes = 1 << 20;
+std::mutex g_types_mu;                       // serialises creation and free
+std::atomic<TypeObj *> *g_types = nullptr;   // kMaxTypes slots
+std::atomic<int32_t> g_ntypes{64};           // handles below 64 are reserved
 
 int64_t gcd64(int64_t a, int64_t b) {
     a = a < 0 ? -a : a;
@@ -173,11 +178,23 @@ int hrepeat(int64_t n, int64_t step, const Layout &T, Layout &R) {
     return MPIXS_SUCCESS;
 }
 
+std::atomic<TypeObj *> *types_table() {
+    static std::atomic<TypeObj *> *tab = [] {
+        auto *p = new std::atomic<TypeObj *>[kMaxTypes];
+        for (int32_t i = 0; i < kMaxTypes; ++i) p[i].store(nullptr, std::memory_order_relaxed);
+        return p;
+    }();
+    return tab;
+}
+
 int add_type(TypeObj *t, mpixs_datatype *out) {
     std::lock_guard<std::mutex> g(g_types_mu);
-    if (g_types.empty()) g_types.resize(64, nullptr);
-    g_types.push_back(t);
-    *out = mpixs_datatype(g_types.size() - 1);
+    g_types = types_table();
+    const int32_t id = g_ntypes.load(std::memory_order_relaxed);
+    if (id >= kMaxTypes) return MPIXS_ERR_NOMEM;
+    g_types[id].store(t, std::memory_order_release);
+    g_ntypes.store(id + 1, std::memory_order_release);
+    *out = mpixs_datatype(id);
     return MPIXS_SUCCESS;
 }
 
@@ -203,9 +220,8 @@ TypeObj *predefined(int basic) {
 
 TypeObj *any_type(mpixs_datatype dt) {
     if (dt >= 1 && dt <= 6) return predefined(dt);
-    std::lock_guard<std::mutex> g(g_types_mu);
-    if (dt < 64 || size_t(dt) >= g_types.size()) return nullptr;
-    return g_types[dt];
+    if (dt < 64 || dt >= g_ntypes.load(std::memory_order_acquire)) return nullptr;
+    return types_table()[dt].load(std::memory_order_acquire);
 }
 
 int make_derived(const Layout &L, mpixs_datatype *newtype) {
@@ -324,10 +340,10 @@ int mpixs_type_free(mpixs_datatype *type) {
     if (!type) return MPIXS_ERR_ARG;
     if (*type >= 1 && *type <= 6) return MPIXS_ERR_TYPE;
     std::lock_guard<std::mutex> g(g_types_mu);
-    if (*type < 64 || size_t(*type) >= g_types.size() || !g_types[*type]) return MPIXS_ERR_TYPE;
-    // Tables stay allocated: enqueued operations may still read them, and
-    // freeing pinned memory can synchronise the device.
-    g_types[*type] = nullptr;
+    if (*type < 64 || *type >= g_ntypes.load() || !types_table()[*type].load()) return MPIXS_ERR_TYPE;
+    // The object and its tables stay allocated: enqueued operations may still
+    // read them, and freeing pinned memory can synchronise the device.
+    types_table()[*type].store(nullptr, std::memory_order_release);
     *type = MPIXS_DATATYPE_NULL;
     return MPIXS_SUCCESS;
 }

@@ -117,6 +117,39 @@ def mpixs_drv_run(world, threads_ops: List[np.ndarray], comms: List[List[int]],
     return rc, res, marks[: n * nmarks].reshape(n, nmarks) if nmarks else None
 
 
+REQ_DTYPE = np.dtype([("kind", "<i4"), ("src", "<i4"), ("dst", "<i4"), ("pad", "<i4"),
+                      ("bytes", "<i8"), ("arrival_us", "<f8"), ("seed", "<u8")])
+RES_DTYPE = np.dtype([("admit_us", "<f8"), ("done_us", "<f8"), ("checksum", "<u8"),
+                      ("error", "<i4"), ("pad", "<i4")])
+
+
+def mpixs_drv_serve(world, comms, streams, reqs: np.ndarray, budget_bytes: int):
+    """Run the serving harness; returns (rc, results array, wall seconds)."""
+    L = dlib()
+    f = L.mpixs_drv_serve
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                  ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    f.restype = ctypes.c_int
+    n = len(comms)
+    ca = (ctypes.c_void_p * n)(*comms)
+    sa = (ctypes.c_void_p * n)(*streams)
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    res = np.zeros(max(1, len(reqs)), dtype=RES_DTYPE)
+    wall = ctypes.c_double()
+    rc = f(world, n, ca, sa, reqs.ctypes.data, len(reqs), budget_bytes, res.ctypes.data,
+           ctypes.byref(wall))
+    return rc, res[: len(reqs)], wall.value
+
+
+def requests_array(sched) -> np.ndarray:
+    a = np.zeros(len(sched), dtype=REQ_DTYPE)
+    for i, q in enumerate(sched):
+        for k in ("kind", "src", "dst", "bytes", "arrival_us", "seed"):
+            a[i][k] = q[k]
+    return a
+
+
 class Session:
     """A world of ``nranks`` ranks, each with its own torch stream, mpixs
     stream and stream communicator (created collectively from rank threads)."""
@@ -164,6 +197,10 @@ class Session:
     def run(self, threads_ops, mode=0, nmarks=0, max_reqs=64):
         return mpixs_drv_run(self.world, threads_ops, [[c] for c in self.comms],
                              self.hip_streams, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
+
+    def serve(self, sched, budget_bytes=8 << 30):
+        return mpixs_drv_serve(self.world, self.comms, self.hip_streams, requests_array(sched),
+                               budget_bytes)
 
     def stats(self):
         return M.mpixs_world_get_stats(self.world)[1]

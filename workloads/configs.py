@@ -190,6 +190,34 @@ def batch(npairs: int = 10000, nranks: int = 32, max_bytes: int = 262144,
                          name=f"batch_{npairs}p_{nranks}r" + ("_grouped" if grouped else ""))
 
 
+# --------------------------------------------------------------------- 5
+SERVE_KINDS = {"sendrecv": 0, "isend_wait": 1, "allreduce": 2}
+
+
+def serving_schedule(rate: float, nreq: int, nranks: int = 64, min_bytes: int = 64,
+                     max_bytes: int = 4 << 20, seed: int = 0):
+    """Config 5: an open-loop Poisson stream of ``nreq`` requests at ``rate``
+    per second: 60 % send/recv, 30 % isend+wait, 10 % allreduce-sum int32
+    (over all ranks), bytes log-uniform in [min_bytes, max_bytes] (allreduce:
+    per rank, a multiple of 4).  Returns a list of dicts sorted by arrival."""
+    g = rng(5, seed)
+    t = np.cumsum(g.exponential(1e6 / rate, size=nreq))
+    out = []
+    for i in range(nreq):
+        u = g.uniform()
+        kind = 0 if u < 0.6 else (1 if u < 0.9 else 2)
+        nbytes = int(math.floor(math.exp(g.uniform(math.log(min_bytes), math.log(max_bytes)))))
+        src = int(g.integers(nranks))
+        dst = int(g.integers(nranks - 1))
+        dst = dst + 1 if dst >= src else dst
+        if kind == 2:
+            nbytes = max(4, nbytes // 4 * 4)
+            src = dst = 0
+        out.append(dict(kind=kind, src=src, dst=dst, bytes=nbytes, arrival_us=float(t[i]),
+                        seed=(seed << 24) + i + 1))
+    return out
+
+
 # ------------------------------------------------------------------- examples
 def saxpy_example(n: int = 4096) -> Program:
     """The paper's GPU enqueue example (§6): rank 0 sends x (all 1.0) to rank
