@@ -440,7 +440,7 @@ def bench_batch(args):
 
     S = [torch.from_numpy(p.buffers[r]["sbuf"]).cuda() for r in range(n)]
     R = {v: [torch.from_numpy(p.buffers[r]["rbuf"].copy()).cuda() for r in range(n)]
-         for v in ("grouped", "plain", "host")}
+         for v in ("persistent", "grouped", "plain", "host", "tune")}
     torch.cuda.synchronize()
     maxreq = max(len(p.ops[r][0]) for r in range(n)) + 1
 
@@ -448,10 +448,14 @@ def bench_batch(args):
         out = []
         for r in range(n):
             rows = []
-            for _ in range(reps):
-                if variant == "grouped":
+            if variant in ("persistent", "tune") and reps > 0:
+                rows += [dict(kind=D.BATCH_START, req=0)] * reps
+                out.append(D.ops_array(rows))
+                continue
+            for _ in range(max(reps, 1)):
+                if variant in ("grouped", "persistent", "tune"):
                     rows.append(dict(kind=D.GROUP_START))
-                if variant in ("grouped", "plain"):
+                if variant in ("grouped", "plain", "persistent", "tune"):
                     nreq = 0
                     for o in p.ops[r][0]:
                         if isinstance(o, Send):
@@ -468,6 +472,8 @@ def bench_batch(args):
                             rows.append(dict(kind=D.WAITALL, req=0, nreq=nreq))
                 if variant == "grouped":
                     rows.append(dict(kind=D.GROUP_END))
+                if variant in ("persistent", "tune"):
+                    rows.append(dict(kind=D.GROUP_INIT, req=0))
                 if variant == "host":
                     # blocking calls in global message order (deadlock-free)
                     sends = [o for o in p.ops[r][0] if isinstance(o, Send)]
@@ -489,39 +495,65 @@ def bench_batch(args):
             out.append(D.ops_array(rows))
         return out
 
+    # schedule of the persistent batch: chosen by the autotuner, or given
+    sched = dict(tile=args.batch_tile, max_wg=args.batch_max_wg, graph=args.batch_graph)
+    tuned = None
+    if args.tune and not args.only_grouped:
+        from paper_2208_13707_amd import tune
+        best, rows = tune.tune_batch(n, lambda: ops("tune", 0), lambda k: ops("tune", k),
+                                     runs=max(3, args.steps), warm=1, max_reqs=maxreq, log=log)
+        sched = {k: best[k] for k in ("tile", "max_wg", "graph")}
+        tuned = {"chosen": best, "grid": rows}
+
     res = {}
-    for variant, mode, tagb in (("grouped", 0, 1000), ("plain", 0, 0), ("host", 1, 0)):
+    init_ms = None
+    for variant, mode, tagb in (("persistent", 0, 2000), ("grouped", 0, 1000), ("plain", 0, 0),
+                                ("host", 1, 0)):
         if variant == "host" and args.no_host_synced:
             continue
-        if args.only_grouped and variant != "grouped":
+        if args.only_grouped and variant not in ("grouped", "persistent"):
             continue
         k = args.steps if variant != "host" else max(1, min(args.steps, args.hs_steps))
-        sess = D.Session(n)
+        cfg = None
+        if variant == "persistent":
+            from paper_2208_13707_amd import tune
+            cfg = tune.config_for(sched["tile"], sched["max_wg"], sched["graph"])
+        sess = D.Session(n, cfg)
+        if variant == "persistent":
+            init_ms = 1000 * run_checked(sess, ops(variant, 0, tagb), max_reqs=maxreq)[0]
         run_checked(sess, ops(variant, args.warmup, tagb), mode=mode, max_reqs=maxreq)
         sec, _ = run_checked(sess, ops(variant, k, tagb), mode=mode, max_reqs=maxreq)
         sess.close()
         res[variant] = npairs * k / sec
-        log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.2f} ms per batch)")
+        log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.3f} ms per batch)")
     if args.only_grouped:
-        return {"workload": "batch", "grouped_msgs_per_s": res["grouped"]}
+        return {"workload": "batch", "grouped_msgs_per_s": res["grouped"],
+                "persistent_msgs_per_s": res["persistent"]}
     # identical results across the paths and the oracle (on a sampled set of ranks)
     for v in res:
         for r in range(n):
             if not torch.equal(R[v][r], R["grouped"][r]):
                 raise AssertionError(f"{v} path differs from grouped on rank {r}")
+    head = res["persistent"]
     line = {
         "metric": "enqueued msgs/s vs host-synced path (uneven batch)",
-        "value": res["grouped"], "unit": "msgs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1000 * npairs / res["grouped"],
+        "value": head, "unit": "msgs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000 * npairs / head,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"batch_{npairs}pairs_{n}ranks_8B-256KiB_30pct_vector",
-                   "variant": "one group per batch"},
+                   "variant": "persistent batch: planned once, one batch kernel per step",
+                   "schedule": sched},
+        "persistent_init_ms": init_ms,
+        "one_shot_group": {"value": res["grouped"], "unit": "msgs/s"},
         "plain_enqueue": {"value": res["plain"], "unit": "msgs/s"},
         "host_synced": {"value": res.get("host"), "unit": "msgs/s",
-                        "speedup": res["grouped"] / res["host"] if "host" in res else None,
+                        "speedup": head / res["host"] if "host" in res else None,
+                        "one_shot_group_speedup": res["grouped"] / res["host"] if "host" in res else None,
                         "plain_speedup": res["plain"] / res["host"] if "host" in res else None},
     }
+    if tuned:
+        line["autotune"] = tuned
     if not args.no_cpu_baseline:
         from oracle import simulate as sim
         t0 = time.perf_counter()
@@ -721,7 +753,13 @@ def main():
     ap.add_argument("--serve-max", type=int, default=20000)
     ap.add_argument("--budget", type=int, default=8 << 30)
     ap.add_argument("--pairs", type=int, default=10000)
-    ap.add_argument("--only-grouped", action="store_true", help="batch: grouped variant only")
+    ap.add_argument("--only-grouped", action="store_true",
+                    help="batch: persistent and one-shot group variants only")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch: pick the persistent batch schedule by a grid search first")
+    ap.add_argument("--batch-tile", type=int, default=1024)
+    ap.add_argument("--batch-max-wg", type=int, default=4096)
+    ap.add_argument("--batch-graph", type=int, default=0)
     ap.add_argument("--ranks-batch", type=int, default=32)
     ap.add_argument("--count", type=int, default=43690)
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")

@@ -77,6 +77,7 @@ typedef struct mpixs_info_s *mpixs_info;
 typedef struct mpixs_stream_s *mpixs_stream;
 typedef struct mpixs_comm_s *mpixs_comm;
 typedef struct mpixs_request_s *mpixs_request;
+typedef struct mpixs_batch_s *mpixs_batch;     /* a persistent group (one handle per rank) */
 typedef int32_t mpixs_datatype;
 typedef int32_t mpixs_op;
 
@@ -129,7 +130,13 @@ typedef struct {
     int32_t profile;          /* 1: time copy and reduce kernels with HIP events */
     int32_t max_collectives;  /* device collective-slot capacity [4096] */
     int32_t batch_arena_mib;  /* host-pinned memory for batch descriptors, MiB [64] */
-    int32_t reserved[8];
+    int32_t batch_tile;       /* units per tile of the batch kernel: 256, 512, 1024, 2048
+                                 or 4096 [1024]; other values: MPIXS_ERR_ARG */
+    int32_t batch_max_wg;     /* workgroups of one batch kernel, at most [4096] */
+    int32_t batch_graph;      /* persistent batches: 1 replays the launching rank's part
+                                 of a run (wait, batch kernel, signal) as one HIP graph,
+                                 0 launches the three kernels one by one [0] */
+    int32_t reserved[5];
 } mpixs_config;
 
 /* -------------------------------------------------------------- world (N ranks)
@@ -293,6 +300,46 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
  */
 int mpixs_group_start(mpixs_comm comm);
 int mpixs_group_end(mpixs_comm comm);
+
+/* ----------------------------------------------------- persistent batches
+ * A group that is run many times (a halo exchange or a batch of messages
+ * repeated every step) need not be matched and planned every time.  The
+ * model is MPI's persistent requests (init once, start many times) applied
+ * to an enqueued group:
+ *
+ *  mpixs_group_end_init(comm, &batch) ends the rank's current group like
+ *   mpixs_group_end -- collective, every rank of comm calls it for the same
+ *   group instance -- but moves no data and enqueues nothing.  The last rank
+ *   to arrive matches and plans the group once into device memory (one
+ *   descriptor per message, a tile schedule, and counters of its own);
+ *   every rank receives its handle in *batch (NULL on error).  Errors, the
+ *   same on every rank: MPIXS_ERR_ARG if a grouped send or receive is
+ *   unmatched, if a request created in the group is not waited for inside
+ *   it, or if some ranks ended the instance with mpixs_group_end instead;
+ *   MPIXS_ERR_NOMEM / MPIXS_ERR_GPU if the plan cannot be stored.  The
+ *   buffers, datatypes and statuses named by the group's calls must stay
+ *   valid until the batch is freed.
+ *  mpixs_batch_start_enqueue(batch) enqueues one run of the whole group on
+ *   the rank's stream: each run moves every message of the group again, from
+ *   the send buffers' contents when the run executes, and writes the
+ *   receive statuses.  Every rank starts its handle the same number of
+ *   times; run k of all ranks is one instance, and later work on any rank's
+ *   stream starts after all copies of that run.  One rank (the one that
+ *   planned it) launches a wait for the others' arrival, one batch kernel
+ *   and a signal; every other rank enqueues an arrival and a wait.  The
+ *   kernels keep their counters relative (they count runs on the device),
+ *   so their arguments are the same for every run and the launching rank's
+ *   part can be replayed as one HIP graph (mpixs_config.batch_graph).  Like
+ *   the other enqueue calls it may wait on the host until the peers have
+ *   enqueued their part of the run, never for GPU work.
+ *   MPIXS_ERR_REQUEST for a NULL handle; MPIXS_ERR_ARG inside an open group.
+ *  mpixs_batch_free(&batch): per rank; the last rank to free it waits for
+ *   the device to finish and releases the plan.  Handles keep their
+ *   communicator busy (mpixs_comm_free fails with MPIXS_ERR_PENDING).
+ */
+int mpixs_group_end_init(mpixs_comm comm, mpixs_batch *batch);
+int mpixs_batch_start_enqueue(mpixs_batch batch);
+int mpixs_batch_free(mpixs_batch *batch);
 
 /* ------------------------------------ conventional, host-synchronised calls
  * The comparison path of §2.4: MPI calls that run in the CPU context and

@@ -30,7 +30,10 @@ enum {
                                 mpixs_allreduce); buf == 1 means in place          */
     MPIXS_DRV_MARK = 7,      /* record HIP event number `req` of this thread       */
     MPIXS_DRV_GROUP_START = 8, /* mpixs_group_start(comm)                          */
-    MPIXS_DRV_GROUP_END = 9    /* mpixs_group_end(comm)                            */
+    MPIXS_DRV_GROUP_END = 9,   /* mpixs_group_end(comm)                            */
+    MPIXS_DRV_GROUP_INIT = 10, /* mpixs_group_end_init(comm, &batches[req])        */
+    MPIXS_DRV_BATCH_START = 11, /* mpixs_batch_start_enqueue(batches[req])         */
+    MPIXS_DRV_BATCH_FREE = 12  /* mpixs_batch_free(&batches[req])                  */
 };
 
 typedef struct {
@@ -57,7 +60,8 @@ typedef struct {
     const mpixs_drv_op *ops;
     int64_t nops;
     int32_t max_reqs;        /* request slots */
-    int32_t pad;
+    int32_t nbatches;        /* persistent batch slots at `batches` */
+    mpixs_batch *batches;    /* caller-owned, so batches outlive one run */
 } mpixs_drv_thread;
 
 typedef struct {

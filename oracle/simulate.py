@@ -29,6 +29,16 @@ What it states, and where the paper fixes it:
   fail: no message of it moves and every rank's GroupEnd reports ERR_ARG.
   A wait on a grouped request inside its group delivers the status at the
   group's end.
+* Persistent groups (the same extension, with MPI's persistent-request
+  model of init once, start many times): a group closed by GroupInit is
+  recorded, not run.  GroupInit is collective; it fails with ERR_ARG on
+  every rank when a recorded send or receive has no partner among all ranks'
+  recorded operations of that group or a request created in it is not
+  waited for inside it, and a Start of a failed (or unknown) batch is
+  ERR_REQUEST.  The j-th Start of every rank forms run j, which behaves
+  exactly as if each rank had issued GroupStart, its recorded operations and
+  GroupEnd at that point: payloads are the send buffers' contents when the
+  run happens.
 
 Readings where the paper is silent (each is listed in the design notes):
 
@@ -63,7 +73,7 @@ import numpy as np
 from . import reduce as red
 from . import typemap as tm
 from workloads.program import (
-    IN_PLACE, Allreduce, GroupEnd, GroupStart, Program, Recv, Send, User, Wait,
+    IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv, Send, Start, User, Wait,
 )
 
 SUCCESS = "SUCCESS"
@@ -187,6 +197,66 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
     group_msgs: Dict[Tuple[int, int], list] = {}
     group_ok: Dict[Tuple[int, int], bool] = {}
     group_after: Dict[Tuple[int, int], list] = {}
+    # persistent groups
+    persist_open: Dict[Tuple[int, int], str] = {}              # (rank, comm) -> batch name
+    batch_ops: Dict[Tuple[int, str], list] = {}                # (rank, batch) -> recorded ops
+    batch_arrived: Dict[str, set] = {}
+    batch_bad: Dict[str, bool] = {}
+    batch_ok: Dict[str, bool] = {}
+    batch_runs: Dict[Tuple[int, str], int] = {}
+
+    def terminators(ops):
+        """GroupStart index -> the op that closes that group (GroupEnd or
+        GroupInit on the same communicator), found by scanning ahead."""
+        out, open_ = {}, {}
+        for i, o in enumerate(ops):
+            if isinstance(o, GroupStart) and o.comm not in open_:
+                open_[o.comm] = i
+            elif isinstance(o, (GroupEnd, GroupInit)) and o.comm in open_:
+                out[open_.pop(o.comm)] = o
+        return out
+
+    def record_grouped(rank, op, grp):
+        """Post a send / receive / wait inside group ``grp`` (a one-shot
+        group instance, or a run of a persistent batch)."""
+        if isinstance(op, Wait):
+            # each request's status arrives at the end of its own group
+            for n, st_name in zip(op.reqs, op.statuses):
+                r = requests[rank].pop(n)[0]
+                if not isinstance(r, _RecvRec) or st_name is None:
+                    continue
+                if r.group in group_ok:
+                    if group_ok[r.group]:
+                        statuses[rank][st_name] = r.status
+                else:
+                    group_after.setdefault(r.group, []).append(
+                        lambda ok, r=r, st_name=st_name, rank=rank:
+                        statuses[rank].__setitem__(st_name, r.status) if ok else None)
+            return
+        rec = post_send(rank, op, grp) if isinstance(op, Send) else post_recv(rank, op, grp)
+        if op.req is not None:
+            requests[rank][op.req] = (rec, p.stream_of(rank, op.comm))
+        elif isinstance(op, Recv) and op.status is not None:
+            name = op.status
+            group_after.setdefault(grp, []).append(
+                lambda ok, rec=rec, name=name, rank=rank:
+                statuses[rank].__setitem__(name, rec.status) if ok else None)
+
+    def init_batch(name):
+        """Every rank reached GroupInit of ``name``: accept it if each
+        recorded send has a recorded partner (per channel, equal counts)."""
+        count: Dict[tuple, int] = {}
+        for (rank, b), ops in batch_ops.items():
+            if b != name:
+                continue
+            for o in ops:
+                if isinstance(o, Send):
+                    key = (o.comm, rank, o.dest, o.tag)
+                    count[key] = count.get(key, 0) + 1
+                elif isinstance(o, Recv):
+                    key = (o.comm, o.source, rank, o.tag)
+                    count[key] = count.get(key, 0) - 1
+        batch_ok[name] = not batch_bad.get(name, False) and all(v == 0 for v in count.values())
 
     def chan(key):
         if key not in chans:
@@ -289,6 +359,14 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         op = ctx.ops[ctx.pc]
         if ctx.pending is not None:
             kind, obj = ctx.pending
+            if kind == "init":
+                if obj not in batch_ok:
+                    return False
+                if not batch_ok[obj]:
+                    sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_ARG"))
+                ctx.pending = None
+                ctx.pc += 1
+                return True
             if kind == "group":
                 if obj not in group_ok:
                     return False
@@ -323,17 +401,20 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
                 ctx.pc += 1
                 return True
             grp = group_open.get((rank, op.comm))
-            rec = (post_send(rank, op, grp) if isinstance(op, Send) else post_recv(rank, op, grp))
-            if op.req is not None:
-                requests[rank][op.req] = (rec, p.stream_of(rank, op.comm))
+            bname = persist_open.get((rank, op.comm))
+            if bname is not None:
+                batch_ops.setdefault((rank, bname), []).append(op)
+                if op.req is not None:
+                    requests[rank][op.req] = (("batch", bname), p.stream_of(rank, op.comm))
                 ctx.pc += 1
                 return True
             if grp is not None:
-                if isinstance(op, Recv) and op.status is not None:
-                    name = op.status
-                    group_after.setdefault(grp, []).append(
-                        lambda ok, rec=rec, name=name, rank=rank:
-                        statuses[rank].__setitem__(name, rec.status) if ok else None)
+                record_grouped(rank, op, grp)
+                ctx.pc += 1
+                return True
+            rec = (post_send(rank, op, grp) if isinstance(op, Send) else post_recv(rank, op, grp))
+            if op.req is not None:
+                requests[rank][op.req] = (rec, p.stream_of(rank, op.comm))
                 ctx.pc += 1
                 return True
             ctx.pending = ("one", rec)
@@ -348,15 +429,24 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
                 ctx.pc += 1
                 return True
             recs = [requests[rank][n][0] for n in op.reqs]
+            recorded = [r for r in recs if isinstance(r, tuple)]
+            if recorded:
+                # waits on requests of an open persistent group are recorded too
+                names = {r[1] for r in recorded}
+                if len(recorded) != len(recs) or len(names) != 1:
+                    raise ValueError("a wait mixes requests of a persistent group with others")
+                bname = names.pop()
+                if any(k[0] == rank and v == bname for k, v in persist_open.items()):
+                    batch_ops.setdefault((rank, bname), []).append(op)
+                # (after a failed GroupInit the wait only releases the requests)
+                for n in op.reqs:
+                    requests[rank].pop(n)
+                ctx.pc += 1
+                return True
             open_groups = [r.group for r in recs if r.group is not None and r.group not in group_ok]
             if open_groups:
                 # inside its group: the statuses arrive at the group's end
-                for n, st_name in zip(op.reqs, op.statuses):
-                    r = requests[rank].pop(n)[0]
-                    if isinstance(r, _RecvRec) and st_name is not None:
-                        group_after.setdefault(r.group, []).append(
-                            lambda ok, r=r, st_name=st_name, rank=rank:
-                            statuses[rank].__setitem__(st_name, r.status) if ok else None)
+                record_grouped(rank, op, recs[0].group)
                 ctx.pc += 1
                 return True
             ctx.pending = ("waitall", recs)
@@ -381,8 +471,46 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
             else:
                 inst = group_next.get((rank, op.comm), 0)
                 group_open[(rank, op.comm)] = (op.comm, inst)
+                end = ctx.ends.get(ctx.pc)
+                if isinstance(end, GroupInit):
+                    persist_open[(rank, op.comm)] = end.batch
+                    batch_ops.setdefault((rank, end.batch), [])
             ctx.pc += 1
             return True
+        if isinstance(op, GroupInit):
+            grp = group_open.get((rank, op.comm))
+            if grp is None or persist_open.get((rank, op.comm)) != op.batch:
+                sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_ARG"))
+                ctx.pc += 1
+                return True
+            del group_open[(rank, op.comm)]
+            del persist_open[(rank, op.comm)]
+            group_next[(rank, op.comm)] = grp[1] + 1
+            if any(isinstance(v[0], tuple) and v[0] == ("batch", op.batch)
+                   for v in requests[rank].values()):
+                batch_bad[op.batch] = True     # a request of the group is never waited for
+            arrived = batch_arrived.setdefault(op.batch, set())
+            arrived.add(rank)
+            if len(arrived) == p.nranks:
+                init_batch(op.batch)
+            ctx.pending = ("init", op.batch)
+            return step(ctx)
+        if isinstance(op, Start):
+            if not batch_ok.get(op.batch, False):
+                sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_REQUEST"))
+                ctx.pc += 1
+                return True
+            j = batch_runs.get((rank, op.batch), 0)
+            batch_runs[(rank, op.batch)] = j + 1
+            grp = (("batch", op.batch), j)
+            for o in batch_ops[(rank, op.batch)]:
+                record_grouped(rank, o, grp)
+            arrived = group_arrived.setdefault(grp, set())
+            arrived.add(rank)
+            if len(arrived) == p.nranks:
+                end_group(*grp)
+            ctx.pending = ("group", grp)
+            return step(ctx)
         if isinstance(op, GroupEnd):
             grp = group_open.pop((rank, op.comm), None)
             if grp is None:
@@ -403,6 +531,8 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
 
     ctxs = [_Context(r, t, p.ops[r][t]) for r in range(p.nranks)
             for t in range(len(p.ops[r]))]
+    for c in ctxs:
+        c.ends = terminators(c.ops)
     deadlock = False
     for _ in range(max_rounds):
         progressed = False

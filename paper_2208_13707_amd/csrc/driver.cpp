@@ -65,6 +65,19 @@ int run_ops(const mpixs_drv_thread &t, int mode, std::vector<mpixs_request> &req
         }
         case MPIXS_DRV_GROUP_START: rc = mpixs_group_start(c); break;
         case MPIXS_DRV_GROUP_END: rc = mpixs_group_end(c); break;
+        case MPIXS_DRV_GROUP_INIT:
+        case MPIXS_DRV_BATCH_START:
+        case MPIXS_DRV_BATCH_FREE:
+            if (!t.batches || o.req < 0 || o.req >= t.nbatches) {
+                rc = MPIXS_ERR_ARG;
+            } else if (o.kind == MPIXS_DRV_GROUP_INIT) {
+                rc = mpixs_group_end_init(c, &t.batches[o.req]);
+            } else if (o.kind == MPIXS_DRV_BATCH_START) {
+                rc = mpixs_batch_start_enqueue(t.batches[o.req]);
+            } else {
+                rc = mpixs_batch_free(&t.batches[o.req]);
+            }
+            break;
         case MPIXS_DRV_MARK:
             if (o.req >= 0 && size_t(o.req) < out.marks.size())
                 rc = hipEventRecord(out.marks[size_t(o.req)], hs) == hipSuccess ? 0 : MPIXS_ERR_GPU;

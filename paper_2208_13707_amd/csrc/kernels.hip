@@ -14,6 +14,8 @@
 // but still publish completion, so every waiter downstream also finishes.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "../../include/mpixs.h"
 #include "mpixs_dev.h"
 #include "mpixs_launch.h"
@@ -101,8 +103,26 @@ __global__ void __launch_bounds__(64) k_signal(SignalArgs a) {
     const uint32_t fatal = ld_relaxed32(&a.me->fatal);
     if (a.status) write_status(a.status, a.st, fatal);
     if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
-    if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+    if (a.done_ptr) st_release(a.done_ptr, a.inc ? ld_acquire(a.done_ptr) + 1 : a.done_val);
     if (a.host_flag) __hip_atomic_store(a.host_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Persistent batches keep their counters relative: each run of a rank adds
+// one to its own arrive counter, and waits compare against counters read on
+// the device, so the launch arguments never change between runs.
+__global__ void __launch_bounds__(64) k_post_inc(uint64_t *p) {
+    if (threadIdx.x == 0) st_release(p, ld_acquire(p) + 1);
+}
+
+__global__ void __launch_bounds__(64) k_wait_rel(RelWaitArgs a) {
+    const uint32_t lane = threadIdx.x;
+    uint32_t err = 0;
+    const uint32_t fatal0 = ld_relaxed32(&a.me->fatal);
+    if (!fatal0 && lane < a.n && !((a.skip >> lane) & 1u)) {
+        const uint64_t target = ld_acquire(a.base) + a.delta;
+        err = spin_wait(a.ptr0 + uint64_t(lane) * a.stride, target, a.ctl);
+    }
+    if (err) set_fatal(a.me, err);
 }
 
 // ------------------------------------------------------------------ maps
@@ -310,10 +330,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
 // descriptor is read from host-pinned memory into LDS when the workgroup
 // reaches it.  A tile is up to BATCH_TILE units of one message; the unit
 // size and map kinds of that message select the copy loop.
-template <int W, int SK, int DK>
+template <int TILE, int W, int SK, int DK>
 __device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     using T = typename Unit<W>::T;
-    constexpr int U = BATCH_TILE / COPY_THREADS;
+    constexpr int U = TILE / COPY_THREADS;
     T v[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
@@ -327,24 +347,25 @@ __device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint6
     }
 }
 
-template <int W, int SK>
+template <int TILE, int W, int SK>
 __device__ __forceinline__ void tile_copy_dk(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     switch (d.dst.kind) {
-    case MAP_CONTIG: tile_copy<W, SK, MAP_CONTIG>(d, u0, u1); break;
-    case MAP_VEC: tile_copy<W, SK, MAP_VEC>(d, u0, u1); break;
-    default: tile_copy<W, SK, MAP_SEG>(d, u0, u1); break;
+    case MAP_CONTIG: tile_copy<TILE, W, SK, MAP_CONTIG>(d, u0, u1); break;
+    case MAP_VEC: tile_copy<TILE, W, SK, MAP_VEC>(d, u0, u1); break;
+    default: tile_copy<TILE, W, SK, MAP_SEG>(d, u0, u1); break;
     }
 }
 
-template <int W>
+template <int TILE, int W>
 __device__ __forceinline__ void tile_copy_w(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     switch (d.src.kind) {
-    case MAP_CONTIG: tile_copy_dk<W, MAP_CONTIG>(d, u0, u1); break;
-    case MAP_VEC: tile_copy_dk<W, MAP_VEC>(d, u0, u1); break;
-    default: tile_copy_dk<W, MAP_SEG>(d, u0, u1); break;
+    case MAP_CONTIG: tile_copy_dk<TILE, W, MAP_CONTIG>(d, u0, u1); break;
+    case MAP_VEC: tile_copy_dk<TILE, W, MAP_VEC>(d, u0, u1); break;
+    default: tile_copy_dk<TILE, W, MAP_SEG>(d, u0, u1); break;
     }
 }
 
+template <int TILE>
 __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
     __shared__ BatchDesc sd;
     __shared__ uint32_t s_fatal;
@@ -372,15 +393,15 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
             __syncthreads();
         }
         if (!s_fatal) {
-            const uint64_t u0 = uint64_t(tin) * BATCH_TILE;
-            const uint64_t u1 = u0 + BATCH_TILE < sd.units ? u0 + BATCH_TILE : sd.units;
+            const uint64_t u0 = uint64_t(tin) * TILE;
+            const uint64_t u1 = u0 + TILE < sd.units ? u0 + TILE : sd.units;
             if (u0 < u1) {
                 switch (sd.w) {
-                case 16: tile_copy_w<16>(sd, u0, u1); break;
-                case 8: tile_copy_w<8>(sd, u0, u1); break;
-                case 4: tile_copy_w<4>(sd, u0, u1); break;
-                case 2: tile_copy_w<2>(sd, u0, u1); break;
-                default: tile_copy_w<1>(sd, u0, u1); break;
+                case 16: tile_copy_w<TILE, 16>(sd, u0, u1); break;
+                case 8: tile_copy_w<TILE, 8>(sd, u0, u1); break;
+                case 4: tile_copy_w<TILE, 4>(sd, u0, u1); break;
+                case 2: tile_copy_w<TILE, 2>(sd, u0, u1); break;
+                default: tile_copy_w<TILE, 1>(sd, u0, u1); break;
                 }
             }
         }
@@ -394,9 +415,89 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
 }
 
 // ------------------------------------------------------------- launchers
+static const void *batch_kernel(uint32_t tile) {
+    switch (tile) {
+    case 256: return reinterpret_cast<const void *>(&k_batch<256>);
+    case 512: return reinterpret_cast<const void *>(&k_batch<512>);
+    case 1024: return reinterpret_cast<const void *>(&k_batch<1024>);
+    case 2048: return reinterpret_cast<const void *>(&k_batch<2048>);
+    case 4096: return reinterpret_cast<const void *>(&k_batch<4096>);
+    default: return nullptr;
+    }
+}
+
+bool batch_tile_ok(uint32_t tile) { return batch_kernel(tile) != nullptr; }
+
 hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg) {
-    hipLaunchKernelGGL(k_batch, dim3(nwg), dim3(COPY_THREADS), 0, s, a);
+    switch (a.tile) {
+    case 256: hipLaunchKernelGGL(k_batch<256>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 512: hipLaunchKernelGGL(k_batch<512>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 1024: hipLaunchKernelGGL(k_batch<1024>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 2048: hipLaunchKernelGGL(k_batch<2048>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 4096: hipLaunchKernelGGL(k_batch<4096>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_post_inc(hipStream_t s, uint64_t *p) {
+    hipLaunchKernelGGL(k_post_inc, dim3(1), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_wait_rel(hipStream_t s, const RelWaitArgs &a) {
+    hipLaunchKernelGGL(k_wait_rel, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+// The leader's part of one run of a persistent batch as a graph: [relative
+// wait for every other rank's arrival] -> batch kernel -> signal (done + 1).
+// Kernel node arguments are copied when the nodes are added.
+hipError_t build_batch_graph(hipGraph_t *out, const RelWaitArgs *w, const BatchArgs &a, int nwg,
+                             const SignalArgs &sg) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    hipGraphNode_t prev = nullptr, node = nullptr;
+    hipKernelNodeParams p;
+    if (w) {
+        RelWaitArgs wa = *w;
+        void *args[] = {&wa};
+        std::memset(&p, 0, sizeof(p));
+        p.func = const_cast<void *>(reinterpret_cast<const void *>(&k_wait_rel));
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(64);
+        p.kernelParams = args;
+        e = hipGraphAddKernelNode(&node, g, nullptr, 0, &p);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return e; }
+        prev = node;
+    }
+    if (nwg > 0) {
+        BatchArgs ba = a;
+        void *args[] = {&ba};
+        std::memset(&p, 0, sizeof(p));
+        p.func = const_cast<void *>(batch_kernel(a.tile));
+        if (!p.func) { (void)hipGraphDestroy(g); return hipErrorInvalidValue; }
+        p.gridDim = dim3(unsigned(nwg));
+        p.blockDim = dim3(COPY_THREADS);
+        p.kernelParams = args;
+        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return e; }
+        prev = node;
+    }
+    {
+        SignalArgs sa = sg;
+        void *args[] = {&sa};
+        std::memset(&p, 0, sizeof(p));
+        p.func = const_cast<void *>(reinterpret_cast<const void *>(&k_signal));
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(64);
+        p.kernelParams = args;
+        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return e; }
+    }
+    *out = g;
+    return hipSuccess;
 }
 
 hipError_t launch_post(hipStream_t s, uint64_t *p, uint64_t v) {

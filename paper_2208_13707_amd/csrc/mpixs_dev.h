@@ -180,22 +180,40 @@ struct SignalArgs {
     void *status;
     StatusVal st;
     int32_t set_error;
-    int32_t pad;
+    int32_t inc;            // nonzero: done = done + 1 (single writer), done_val unused
     uint32_t *host_flag;
 };
 
+// Relative wait of a persistent batch: lane q < n (bit q of skip clear)
+// waits until ptr0[q * stride] >= *base + delta.  Targets are read on the
+// device, so the same arguments serve every run of the batch.
+struct RelWaitArgs {
+    const uint64_t *ptr0;
+    const uint64_t *base;
+    uint64_t delta;
+    uint64_t skip;
+    uint32_t n;
+    uint32_t stride;        // in uint64_t words
+    WaitCtl ctl;
+    DevStream *me;
+};
+
 // ----------------------------------------------------------------- batches
-// One message of a batch, in host-pinned memory.  It is cut into tiles of
-// BATCH_TILE units; the workgroup that runs a message's tile 0 also writes
-// the message's receive status.
-constexpr uint32_t BATCH_TILE = 1024;
+// One message of a batch (in host-pinned memory for a one-shot group, in
+// device memory for a persistent batch).  It is cut into tiles of `tile`
+// units (a power of two from 256 to 4096, the same for the whole batch);
+// the workgroup that runs a message's tile 0 also writes the message's
+// receive status.
+constexpr uint32_t BATCH_TILE_DEFAULT = 1024;
+constexpr uint32_t BATCH_TILE_MIN = 256;
+constexpr uint32_t BATCH_TILE_MAX = 4096;
 
 struct alignas(16) BatchDesc {
     DMap src;
     DMap dst;
     uint64_t units;
     uint32_t w;             // unit bytes: 1, 2, 4, 8 or 16
-    uint32_t ntiles;        // max(1, ceil(units / BATCH_TILE))
+    uint32_t ntiles;        // max(1, ceil(units / tile))
     void *status;           // receive status or nullptr
     DevStream *rstream;     // receiver's stream block (sticky error)
     StatusVal st;
@@ -216,6 +234,8 @@ struct BatchArgs {
     uint32_t extra;         // workgroups b < extra run base + 1 tiles
     uint64_t base;          // tiles per workgroup
     DevStream *me;
+    uint32_t tile;          // units per tile
+    uint32_t pad;
 };
 
 enum RedOp : int32_t { OP_SUM = 1, OP_PROD = 2, OP_MIN = 3, OP_MAX = 4 };

@@ -13,6 +13,12 @@ hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg, bool fu
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg,
                          bool fused);
 hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg);
+bool batch_tile_ok(uint32_t tile);   // a tile size the batch kernel is built for
+hipError_t launch_post_inc(hipStream_t s, uint64_t *p);
+hipError_t launch_wait_rel(hipStream_t s, const RelWaitArgs &a);
+// leader's run of a persistent batch: [wait] -> batch -> signal (w may be null)
+hipError_t build_batch_graph(hipGraph_t *out, const RelWaitArgs *w, const BatchArgs &a, int nwg,
+                             const SignalArgs &sg);
 int copy_block_units(bool fused);   // units in one copy chunk (one workgroup pass)
 int reduce_threads();
 

@@ -738,10 +738,13 @@ int arena_alloc(World *w, size_t bytes, size_t *off, int *flag) {
     }
 }
 
-// Last rank of a group: match every rank's recorded operations, plan one
-// tile list, and enqueue wait(all arrivals) + batch kernel + signal.
-int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st, uint64_t g) {
-    const int n = sh->size;
+// Match every rank's recorded operations of a group (the i-th grouped send
+// of s to d with tag t pairs with the i-th grouped receive of d from s with
+// tag t), plan each copy, and cut the group into tiles: one descriptor per
+// message and, per workgroup, the (message, tile) it starts at.  Fills
+// everything of `a` except the descriptor / start pointers.
+int plan_group(World *w, GroupRec *rec, int n, std::vector<BatchDesc> &descs,
+               std::vector<BatchStart> &starts, BatchArgs &a, uint64_t *bytes) {
     struct Q {
         std::vector<GOp *> s, r;
         int tag = 0;
@@ -758,9 +761,11 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         }
     for (auto &kv : chans)
         if (kv.second.s.size() != kv.second.r.size()) return MPIXS_ERR_ARG;
-    std::vector<BatchDesc> descs;
+    const uint32_t tile = uint32_t(w->cfg.batch_tile);
+    descs.clear();
     descs.reserve(nops / 2 + 1);
     uint64_t total_tiles = 0;
+    *bytes = 0;
     for (auto &kv : chans) {
         const int tag = kv.second.tag;
         for (size_t i = 0; i < kv.second.s.size(); ++i) {
@@ -774,15 +779,51 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
             plan_copy(S->side, R->side, d.st.count_bytes, &d.src, &d.dst, &wsz, &units);
             d.units = units;
             d.w = uint32_t(wsz);
-            d.ntiles = uint32_t(std::max<uint64_t>(1, (units + BATCH_TILE - 1) / BATCH_TILE));
+            d.ntiles = uint32_t(std::max<uint64_t>(1, (units + tile - 1) / tile));
             d.status = R->status;
             d.rstream = R->side.st->dev;
             if (R->req) R->req->st = d.st;
             total_tiles += d.ntiles;
+            *bytes += uint64_t(d.st.count_bytes);
             descs.push_back(d);
         }
     }
-    int rc = MPIXS_SUCCESS;
+    std::memset(&a, 0, sizeof(a));
+    starts.clear();
+    if (descs.empty()) return MPIXS_SUCCESS;
+    const uint64_t nwg = std::min<uint64_t>(total_tiles, uint64_t(w->cfg.batch_max_wg));
+    const uint64_t base = total_tiles / nwg;
+    const uint64_t extra = total_tiles % nwg;
+    starts.resize(size_t(nwg));
+    uint32_t m = 0;
+    uint64_t first_of_m = 0;   // global index of message m's first tile
+    for (uint64_t b = 0; b < nwg; ++b) {
+        const uint64_t t = b * base + std::min(b, extra);
+        while (first_of_m + descs[m].ntiles <= t) {
+            first_of_m += descs[m].ntiles;
+            ++m;
+        }
+        starts[size_t(b)].msg = m;
+        starts[size_t(b)].tile = uint32_t(t - first_of_m);
+    }
+    a.nmsg = uint32_t(descs.size());
+    a.base = base;
+    a.extra = uint32_t(extra);
+    a.tile = tile;
+    return MPIXS_SUCCESS;
+}
+
+// Last rank of a group: plan it and enqueue wait(all arrivals) + batch
+// kernel + signal on its own stream.  Descriptors go to the host-pinned ring
+// arena, whose range the signal kernel hands back through a host flag.
+int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st, uint64_t g) {
+    const int n = sh->size;
+    std::vector<BatchDesc> descs;
+    std::vector<BatchStart> starts;
+    BatchArgs a;
+    uint64_t bytes = 0;
+    int rc = plan_group(w, rec, n, descs, starts, a, &bytes);
+    if (rc) return rc;
     uint64_t *arrive = sh->d_grp;
     uint64_t *done = sh->d_grp + 16 * n;
     if (n > 1) {
@@ -799,43 +840,23 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     }
     int flag = -1;
     if (!descs.empty()) {
-        const uint64_t nwg = std::min<uint64_t>(total_tiles, 4096);
         const size_t dbytes = descs.size() * sizeof(BatchDesc);
-        const size_t sbytes = size_t(nwg) * sizeof(BatchStart);
+        const size_t sbytes = starts.size() * sizeof(BatchStart);
         size_t off = 0;
         rc = arena_alloc(w, dbytes + sbytes + 256, &off, &flag);
         if (rc) return rc;
         BatchDesc *hd = reinterpret_cast<BatchDesc *>(w->h_arena + off);
         BatchStart *hs = reinterpret_cast<BatchStart *>(w->h_arena + off + ((dbytes + 255) & ~size_t(255)));
         std::memcpy(hd, descs.data(), dbytes);
-        const uint64_t base = total_tiles / nwg;
-        const uint64_t extra = total_tiles % nwg;
-        uint32_t m = 0;
-        uint64_t first_of_m = 0;   // global index of message m's first tile
-        for (uint64_t b = 0; b < nwg; ++b) {
-            const uint64_t t = b * base + std::min(b, extra);
-            while (first_of_m + descs[m].ntiles <= t) {
-                first_of_m += descs[m].ntiles;
-                ++m;
-            }
-            hs[b].msg = m;
-            hs[b].tile = uint32_t(t - first_of_m);
-        }
-        BatchArgs a;
-        std::memset(&a, 0, sizeof(a));
+        std::memcpy(hs, starts.data(), sbytes);
         a.desc = hd;
         a.start = hs;
-        a.nmsg = uint32_t(descs.size());
-        a.base = base;
-        a.extra = uint32_t(extra);
         a.me = st->dev;
         hipEvent_t e0 = nullptr;
         if (profile_on(w)) prof_begin(w, st->hs, &e0);
-        rc = gpu_err(launch_batch(st->hs, a, int(nwg)));
+        rc = gpu_err(launch_batch(st->hs, a, int(starts.size())));
         if (profile_on(w)) prof_end(w, st->hs, e0, 0);
         if (rc) return rc;
-        uint64_t bytes = 0;
-        for (auto &d : descs) bytes += uint64_t(d.st.count_bytes);
         w->n_copy.fetch_add(1, std::memory_order_relaxed);
         w->bytes_copied.fetch_add(bytes, std::memory_order_relaxed);
     }
@@ -848,6 +869,62 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     rc = gpu_err(launch_signal(st->hs, sg));
     w->n_post.fetch_add(1, std::memory_order_relaxed);
     return rc;
+}
+
+// Last rank of a persistent group: plan it once into device memory, with
+// its own relative counters (arrive[q] at word 16q, done at word 16n), and
+// optionally build the launching rank's part of a run as a graph.
+int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
+                 BatchPlan **out) {
+    const int n = sh->size;
+    std::unique_ptr<BatchPlan> P(new BatchPlan());
+    P->w = w;
+    P->n = n;
+    P->leader = me;
+    P->posted.reset(new std::atomic<uint64_t>[size_t(n)]);
+    for (int q = 0; q < n; ++q) P->posted[q].store(0);
+    std::vector<BatchDesc> descs;
+    std::vector<BatchStart> starts;
+    int rc = plan_group(w, rec, n, descs, starts, P->args, &P->bytes);
+    if (rc) return rc;
+    P->nmsg = descs.size();
+    P->nwg = int(starts.size());
+    const size_t cbytes = size_t(n + 1) * 16 * sizeof(uint64_t);
+    const size_t dbytes = (descs.size() * sizeof(BatchDesc) + 255) & ~size_t(255);
+    const size_t sbytes = starts.size() * sizeof(BatchStart);
+    if (hipMalloc(reinterpret_cast<void **>(&P->d_mem), cbytes + dbytes + sbytes) != hipSuccess)
+        return MPIXS_ERR_NOMEM;
+    std::vector<uint8_t> img(cbytes + dbytes + sbytes, 0);
+    if (!descs.empty()) std::memcpy(img.data() + cbytes, descs.data(), descs.size() * sizeof(BatchDesc));
+    if (!starts.empty()) std::memcpy(img.data() + cbytes + dbytes, starts.data(), sbytes);
+    if (hipMemcpy(P->d_mem, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return MPIXS_ERR_GPU;
+    P->d_ctr = reinterpret_cast<uint64_t *>(P->d_mem);
+    P->args.desc = reinterpret_cast<const BatchDesc *>(P->d_mem + cbytes);
+    P->args.start = reinterpret_cast<const BatchStart *>(P->d_mem + cbytes + dbytes);
+    P->args.me = st->dev;
+    std::memset(&P->lwait, 0, sizeof(P->lwait));
+    P->lwait.ptr0 = P->d_ctr;
+    P->lwait.stride = 16;
+    P->lwait.n = uint32_t(n);
+    P->lwait.skip = uint64_t(1) << me;
+    P->lwait.base = P->d_ctr + 16 * n;
+    P->lwait.delta = 1;
+    P->lwait.ctl = ctl_of(w);
+    P->lwait.me = st->dev;
+    std::memset(&P->sig, 0, sizeof(P->sig));
+    P->sig.done_ptr = P->d_ctr + 16 * n;
+    P->sig.inc = 1;
+    P->sig.me = st->dev;
+    if (w->cfg.batch_graph) {
+        if (build_batch_graph(&P->graph, n > 1 ? &P->lwait : nullptr, P->args, P->nwg, P->sig) !=
+                hipSuccess ||
+            hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess)
+            return MPIXS_ERR_GPU;
+    }
+    P->refs.store(n);
+    *out = P.release();
+    return MPIXS_SUCCESS;
 }
 
 int parse_hex(const std::string &s, void *out, size_t n) {
@@ -896,6 +973,12 @@ CommShared::~CommShared() {
     for (GroupRec *r : groups) delete r;
 }
 
+BatchPlan::~BatchPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (d_mem) (void)hipFree(d_mem);
+}
+
 }  // namespace mpixs
 
 using namespace mpixs;
@@ -914,6 +997,13 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     if (c.timeout_ms <= 0) c.timeout_ms = 30000;
     if (c.max_channels <= 0) c.max_channels = 1 << 20;
     if (c.max_collectives <= 0) c.max_collectives = 4096;
+    if (c.batch_tile == 0) c.batch_tile = int32_t(BATCH_TILE_DEFAULT);
+    if (c.batch_max_wg <= 0) c.batch_max_wg = 4096;
+    if (!batch_tile_ok(uint32_t(c.batch_tile)) || c.batch_max_wg > (1 << 20) ||
+        c.batch_graph < 0 || c.batch_graph > 1) {
+        delete w;
+        return MPIXS_ERR_ARG;
+    }
     if (hipGetDevice(&w->device) != hipSuccess) {
         delete w;
         return MPIXS_ERR_GPU;
@@ -1334,15 +1424,21 @@ int mpixs_group_start(mpixs_comm c) {
     return MPIXS_SUCCESS;
 }
 
-int mpixs_group_end(mpixs_comm c) {
-    if (!c || !c->sh) return MPIXS_ERR_COMM;
-    if (!c->in_group) return MPIXS_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Collective end of the rank's group; kind 1 runs it once, kind 2 makes it a
+// persistent batch (returned in *plan).
+int group_finish(mpixs_comm c, int kind, BatchPlan **plan) {
     c->in_group = false;
     CommShared *sh = c->sh;
     World *w = sh->w;
     StreamObj *st = c->stream;
     const int n = sh->size;
     const uint64_t g = c->group_seq++;
+    bool unwaited = false;
+    for (const GOp &op : c->gops) unwaited = unwaited || op.req != nullptr;
     sh->grp_mu.lock();
     while (sh->group_base + sh->groups.size() <= g) {
         GroupRec *r = new GroupRec();
@@ -1355,23 +1451,29 @@ int mpixs_group_end(mpixs_comm c) {
     rec->ops[size_t(c->rank)] = std::move(c->gops);
     c->gops.clear();
     rec->streams[size_t(c->rank)] = st;
+    if (rec->kind == 0) rec->kind = kind;
+    else if (rec->kind != kind) rec->mismatch = true;
+    if (kind == 2 && unwaited) rec->bad = true;
     const bool last = ++rec->arrived == n;
     int rc = MPIXS_SUCCESS;
     if (last) {
         sh->grp_mu.unlock();
-        rc = group_launch(w, sh, rec, c->rank, st, g);
+        if (rec->mismatch || rec->bad) rc = MPIXS_ERR_ARG;
+        else if (kind == 1) rc = group_launch(w, sh, rec, c->rank, st, g);
+        else rc = batch_create(w, sh, rec, c->rank, st, &rec->batch);
         rec->error = rc;
         rec->launched.store(1, std::memory_order_release);
     } else {
-        rc = do_post(w, st, sh->d_grp + 16 * c->rank, g + 1);
+        if (kind == 1) rc = do_post(w, st, sh->d_grp + 16 * c->rank, g + 1);
         sh->grp_mu.unlock();
         if (!rc) rc = host_wait(w, [&] { return rec->launched.load(std::memory_order_acquire) != 0; });
         if (!rc) rc = rec->error;
-        if (!rc) {
+        if (!rc && kind == 1) {
             WaitArgs a = wait_one(sh->d_grp + 16 * n, g + 1);
             rc = do_wait(w, st, a);
         }
     }
+    if (!rc && kind == 2) *plan = rec->batch;
     if (rec->refs.fetch_sub(1) == 1) {
         std::lock_guard<std::mutex> lk(sh->grp_mu);
         while (!sh->groups.empty() && sh->groups.front()->refs.load() == 0) {
@@ -1381,6 +1483,104 @@ int mpixs_group_end(mpixs_comm c) {
         }
     }
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpixs_group_end(mpixs_comm c) {
+    if (!c || !c->sh) return MPIXS_ERR_COMM;
+    if (!c->in_group) return MPIXS_ERR_ARG;
+    return group_finish(c, 1, nullptr);
+}
+
+int mpixs_group_end_init(mpixs_comm c, mpixs_batch *batch) {
+    if (!c || !c->sh) return MPIXS_ERR_COMM;
+    if (!c->in_group || !batch) return MPIXS_ERR_ARG;
+    *batch = nullptr;
+    BatchPlan *P = nullptr;
+    const int rc = group_finish(c, 2, &P);
+    if (rc) return rc;
+    mpixs_batch_s *b = new mpixs_batch_s();
+    b->p = P;
+    b->comm = c;
+    b->rank = c->rank;
+    c->pending.fetch_add(1);
+    *batch = b;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_batch_start_enqueue(mpixs_batch b) {
+    if (!b || !b->p) return MPIXS_ERR_REQUEST;
+    mpixs_comm_s *c = b->comm;
+    if (c->in_group) return MPIXS_ERR_ARG;
+    BatchPlan *P = b->p;
+    World *w = P->w;
+    StreamObj *st = c->stream;
+    if (w->aborted.load()) return MPIXS_ERR_ABORTED;
+    const uint64_t e = b->runs + 1;
+    int rc = MPIXS_SUCCESS;
+    if (b->rank == P->leader) {
+        // producer first: every other rank's arrival for run e is enqueued
+        for (int q = 0; q < P->n && !rc; ++q) {
+            if (q == P->leader) continue;
+            rc = host_wait(w, [&] { return P->posted[q].load(std::memory_order_acquire) >= e; });
+        }
+        if (!rc) {
+            if (P->exec) {
+                rc = gpu_err(hipGraphLaunch(P->exec, st->hs));
+            } else {
+                if (P->n > 1) rc = gpu_err(launch_wait_rel(st->hs, P->lwait));
+                if (!rc && P->nwg > 0) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
+                if (!rc) rc = gpu_err(launch_signal(st->hs, P->sig));
+            }
+        }
+        if (rc) {
+            int z = 0;
+            P->launch_err.compare_exchange_strong(z, rc);
+        }
+        P->launched.store(e, std::memory_order_release);
+        if (!rc) {
+            w->n_copy.fetch_add(P->nwg > 0 ? 1 : 0, std::memory_order_relaxed);
+            w->bytes_copied.fetch_add(P->bytes, std::memory_order_relaxed);
+        }
+    } else {
+        rc = gpu_err(launch_post_inc(st->hs, P->d_ctr + 16 * b->rank));
+        if (rc) return rc;
+        P->posted[b->rank].store(e, std::memory_order_release);
+        w->n_post.fetch_add(1, std::memory_order_relaxed);
+        rc = host_wait(w, [&] { return P->launched.load(std::memory_order_acquire) >= e; });
+        if (!rc) rc = P->launch_err.load();
+        if (!rc) {
+            RelWaitArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.ptr0 = P->d_ctr + 16 * P->n;
+            a.n = 1;
+            a.base = P->d_ctr + 16 * b->rank;
+            a.ctl = ctl_of(w);
+            a.me = st->dev;
+            rc = gpu_err(launch_wait_rel(st->hs, a));
+            w->n_wait.fetch_add(1, std::memory_order_relaxed);
+        }
+    }
+    b->runs = e;
+    return rc;
+}
+
+int mpixs_batch_free(mpixs_batch *batch) {
+    if (!batch || !*batch || !(*batch)->p) return MPIXS_ERR_REQUEST;
+    mpixs_batch_s *b = *batch;
+    BatchPlan *P = b->p;
+    b->comm->pending.fetch_sub(1);
+    delete b;
+    *batch = nullptr;
+    if (P->refs.fetch_sub(1) == 1) {
+        // no kernel of any run may still read the plan
+        (void)hipDeviceSynchronize();
+        delete P;
+    }
+    return MPIXS_SUCCESS;
 }
 
 // ========================================================= host-synchronised

@@ -123,13 +123,42 @@ struct GOp {
     mpixs_request_s *req = nullptr;    // request to receive the status values
 };
 
+struct BatchPlan;
+
 struct GroupRec {
     int arrived = 0;
+    int kind = 0;                       // 1: one-shot group_end, 2: persistent (group_end_init)
+    bool mismatch = false;              // ranks ended the instance with different calls
+    bool bad = false;                   // a persistent group left a request unwaited
+    BatchPlan *batch = nullptr;         // group_end_init: the plan made by the last rank
     std::vector<std::vector<GOp>> ops;  // per rank
     std::vector<StreamObj *> streams;
     std::atomic<int> launched{0};
     int error = 0;
     std::atomic<int> refs{0};
+};
+
+// A persistent batch: a group planned once, run by every start.  Device
+// memory holds the counters (arrive[q] at word 16q, done at word 16n, all
+// counting runs), the descriptors and the workgroup starts.
+struct BatchPlan {
+    World *w = nullptr;
+    int n = 0;
+    int leader = -1;                    // the rank whose stream launches the batch kernel
+    uint8_t *d_mem = nullptr;
+    uint64_t *d_ctr = nullptr;
+    BatchArgs args{};
+    RelWaitArgs lwait{};                // leader: every other rank arrived for this run
+    SignalArgs sig{};                   // leader: done + 1
+    int nwg = 0;
+    uint64_t nmsg = 0, bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::unique_ptr<std::atomic<uint64_t>[]> posted;   // runs whose arrival rank q has enqueued
+    std::atomic<uint64_t> launched{0};                  // runs the leader has enqueued
+    std::atomic<int> launch_err{0};
+    std::atomic<int> refs{0};
+    ~BatchPlan();
 };
 
 struct CreateRec {
@@ -191,6 +220,13 @@ struct mpixs_request_s {
     bool grouped = false;              // recorded in a group: complete at group_end
     size_t gop = 0;                    // index in the comm's recorded operations
     mpixs::StatusVal st{};
+};
+
+struct mpixs_batch_s {
+    mpixs::BatchPlan *p = nullptr;
+    mpixs_comm_s *comm = nullptr;
+    int rank = -1;
+    uint64_t runs = 0;                 // runs this rank has enqueued
 };
 
 namespace mpixs {

@@ -19,7 +19,9 @@ from . import mpixs as M
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DRIVER_PATH = os.path.join(_HERE, "libmpixs_driver.so")
 
-SEND, ISEND, RECV, IRECV, WAITALL, ALLREDUCE, MARK, GROUP_START, GROUP_END = range(1, 10)
+(SEND, ISEND, RECV, IRECV, WAITALL, ALLREDUCE, MARK, GROUP_START, GROUP_END, GROUP_INIT,
+ BATCH_START, BATCH_FREE) = range(1, 13)
+BATCH_SLOTS = 8
 
 OP_DTYPE = np.dtype([
     ("kind", "<i4"), ("comm", "<i4"), ("peer", "<i4"), ("tag", "<i4"), ("count", "<i4"),
@@ -33,7 +35,8 @@ class DrvThread(ctypes.Structure):
     _fields_ = [("comms", ctypes.c_void_p * 8), ("ncomms", ctypes.c_int32),
                 ("nmarks", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("ops", ctypes.c_void_p), ("nops", ctypes.c_int64),
-                ("max_reqs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("max_reqs", ctypes.c_int32), ("nbatches", ctypes.c_int32),
+                ("batches", ctypes.c_void_p)]
 
 
 class DrvResult(ctypes.Structure):
@@ -95,7 +98,10 @@ def ops_array(rows) -> np.ndarray:
 
 
 def mpixs_drv_run(world, threads_ops: List[np.ndarray], comms: List[List[int]],
-                  streams: List[int], mode: int = 0, nmarks: int = 0, max_reqs: int = 64):
+                  streams: List[int], mode: int = 0, nmarks: int = 0, max_reqs: int = 64,
+                  batches=None):
+    """batches: optional list (one per thread) of ctypes arrays of batch
+    handles, kept by the caller across runs."""
     n = len(threads_ops)
     arr = (DrvThread * n)()
     keep = []
@@ -110,6 +116,9 @@ def mpixs_drv_run(world, threads_ops: List[np.ndarray], comms: List[List[int]],
         arr[i].ops = ops.ctypes.data
         arr[i].nops = len(ops)
         arr[i].max_reqs = max_reqs
+        if batches is not None:
+            arr[i].nbatches = len(batches[i])
+            arr[i].batches = ctypes.addressof(batches[i])
     res = DrvResult()
     marks = np.full(max(1, n * nmarks), -1.0)
     rc = dlib().mpixs_drv_run(world, n, arr, mode, ctypes.byref(res),
@@ -159,6 +168,8 @@ class Session:
         torch.cuda.init()
         self.nranks = nranks
         self.hs = [hip_stream_create() for _ in range(nranks)]
+        # persistent batch handles per rank, kept across runs
+        self.batches = [(ctypes.c_void_p * BATCH_SLOTS)() for _ in range(nranks)]
         rc, self.world = M.mpixs_world_create(nranks, cfg)
         if rc:
             raise RuntimeError(f"world_create: {M.errname(rc)}")
@@ -196,7 +207,8 @@ class Session:
 
     def run(self, threads_ops, mode=0, nmarks=0, max_reqs=64):
         return mpixs_drv_run(self.world, threads_ops, [[c] for c in self.comms],
-                             self.hip_streams, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
+                             self.hip_streams, mode=mode, nmarks=nmarks, max_reqs=max_reqs,
+                             batches=self.batches)
 
     def serve(self, sched, budget_bytes=8 << 30):
         return mpixs_drv_serve(self.world, self.comms, self.hip_streams, requests_array(sched),
@@ -212,6 +224,9 @@ class Session:
         import torch
         torch.cuda.synchronize()
         for r in range(self.nranks):
+            for h in self.batches[r]:
+                if h:
+                    M.mpixs_batch_free(h)
             M.mpixs_comm_free(self.comms[r])
             M.mpixs_stream_free(self.streams[r])
         M.mpixs_world_free(self.world)

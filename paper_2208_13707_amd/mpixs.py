@@ -40,7 +40,8 @@ class Config(ctypes.Structure):
                 ("fuse_max_bytes", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
                 ("max_channels", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("max_collectives", ctypes.c_int32), ("batch_arena_mib", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("batch_tile", ctypes.c_int32), ("batch_max_wg", ctypes.c_int32),
+                ("batch_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Status(ctypes.Structure):
@@ -101,6 +102,9 @@ SIGNATURES = {
     "mpixs_allreduce_enqueue": [_vp, _vp, _i, ctypes.c_int32, ctypes.c_int32, _vp],
     "mpixs_group_start": [_vp],
     "mpixs_group_end": [_vp],
+    "mpixs_group_end_init": [_vp, _pp],
+    "mpixs_batch_start_enqueue": [_vp],
+    "mpixs_batch_free": [_pp],
     "mpixs_send": [_vp, _i, ctypes.c_int32, _i, _i, _vp],
     "mpixs_recv": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _vp],
     "mpixs_allreduce": [_vp, _vp, _i, ctypes.c_int32, ctypes.c_int32, _vp],
@@ -323,6 +327,23 @@ def mpixs_group_start(comm):
 
 def mpixs_group_end(comm):
     return lib().mpixs_group_end(comm)
+
+
+def mpixs_group_end_init(comm):
+    """Returns (rc, batch handle or None)."""
+    h = ctypes.c_void_p()
+    rc = lib().mpixs_group_end_init(comm, ctypes.byref(h))
+    return rc, h.value
+
+
+def mpixs_batch_start_enqueue(batch):
+    return lib().mpixs_batch_start_enqueue(batch)
+
+
+def mpixs_batch_free(batch):
+    h = ctypes.c_void_p(batch)
+    rc = lib().mpixs_batch_free(ctypes.byref(h))
+    return rc, h.value
 
 
 def mpixs_send(buf, count, dt, dest, tag, comm):

@@ -1,0 +1,81 @@
+"""Schedule autotuner for persistent batches.
+
+A persistent batch is planned once (descriptors, tile schedule) and then
+started every step, so the schedule is worth choosing by measurement: this
+module runs a grid search over the batch kernel's tile size (units per
+tile), its workgroup cap and whether the launching rank replays its part of
+a run as a HIP graph, timing real runs of the caller's batch through the
+native driver, and returns the fastest schedule.  It only chooses
+configuration values of the library (mpixs_config.batch_tile, batch_max_wg,
+batch_graph); every run goes through the C ABI.
+"""
+from __future__ import annotations
+
+import itertools
+from typing import Callable, Dict, List, Sequence, Tuple
+
+from . import driver as D
+from . import mpixs as M
+
+TILES = (256, 1024, 4096)
+MAX_WG = (1024, 4096, 16384)
+GRAPH = (0, 1)
+
+
+def schedules(tiles: Sequence[int] = TILES, max_wg: Sequence[int] = MAX_WG,
+              graph: Sequence[int] = GRAPH) -> List[Tuple[int, int, int]]:
+    return list(itertools.product(tiles, max_wg, graph))
+
+
+def config_for(tile: int, max_wg: int, graph: int, base: M.Config = None) -> M.Config:
+    c = M.Config()
+    if base is not None:
+        ctypes_copy(base, c)
+    c.batch_tile = tile
+    c.batch_max_wg = max_wg
+    c.batch_graph = graph
+    return c
+
+
+def ctypes_copy(src: M.Config, dst: M.Config) -> None:
+    for name, _ in M.Config._fields_:
+        setattr(dst, name, getattr(src, name))
+
+
+def time_schedule(nranks: int, cfg: M.Config, init_ops: Callable[[], list],
+                  start_ops: Callable[[int], list], runs: int, warm: int,
+                  max_reqs: int) -> float:
+    """Seconds per run of the batch under ``cfg`` (init and warm-up excluded)."""
+    sess = D.Session(nranks, cfg)
+    try:
+        for ops in (init_ops(), start_ops(warm)):
+            rc, res, _ = sess.run(ops, max_reqs=max_reqs)
+            if rc:
+                raise RuntimeError(f"tuning run failed: {M.errname(rc)} at thread "
+                                   f"{res.error_thread} op {res.error_op}")
+        rc, res, _ = sess.run(start_ops(runs), max_reqs=max_reqs)
+        if rc:
+            raise RuntimeError(f"tuning run failed: {M.errname(rc)}")
+        return res.seconds / runs
+    finally:
+        sess.close()
+
+
+def tune_batch(nranks: int, init_ops: Callable[[], list], start_ops: Callable[[int], list],
+               candidates: Sequence[Tuple[int, int, int]] = None, runs: int = 10,
+               warm: int = 2, max_reqs: int = 64, log=None) -> Tuple[Dict, List[Dict]]:
+    """Grid search; returns (best, all) as dicts with tile, max_wg, graph and
+    ms_per_run.  ``init_ops()`` gives each thread's driver ops that record
+    the group and end it with GROUP_INIT into batch slot 0;
+    ``start_ops(k)`` gives k BATCH_START ops per thread."""
+    out = []
+    for tile, max_wg, graph in (candidates or schedules()):
+        sec = time_schedule(nranks, config_for(tile, max_wg, graph), init_ops, start_ops,
+                            runs, warm, max_reqs)
+        row = dict(tile=tile, max_wg=max_wg, graph=graph, ms_per_run=1000.0 * sec)
+        out.append(row)
+        if log:
+            log(f"[tune] tile {tile:5d} max_wg {max_wg:6d} graph {graph}: "
+                f"{row['ms_per_run']:.3f} ms per run")
+    best = min(out, key=lambda r: r["ms_per_run"])
+    return best, out

@@ -18,7 +18,7 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 from workloads.program import (
-    IN_PLACE, Allreduce, GroupEnd, GroupStart, Program, Recv, Send, User, Wait,
+    IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv, Send, Start, User, Wait,
 )
 
 
@@ -148,6 +148,7 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
 
     sync_errors: List[List[Tuple[int, int, str]]] = [[] for _ in range(N)]
     requests: List[Dict[str, int]] = [dict() for _ in range(N)]
+    batches: List[Dict[str, Optional[int]]] = [dict() for _ in range(N)]
     err_lock = threading.Lock()
 
     def comm_of(r, c):
@@ -251,6 +252,12 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
                     record(r, t, i, M.mpixs_group_start(comm_of(r, o.comm)))
                 elif isinstance(o, GroupEnd):
                     record(r, t, i, M.mpixs_group_end(comm_of(r, o.comm)))
+                elif isinstance(o, GroupInit):
+                    rc, h = M.mpixs_group_end_init(comm_of(r, o.comm))
+                    batches[r][o.batch] = h
+                    record(r, t, i, rc)
+                elif isinstance(o, Start):
+                    record(r, t, i, M.mpixs_batch_start_enqueue(batches[r].get(o.batch)))
                 else:
                     raise ValueError(o)
         except Exception:
@@ -297,6 +304,9 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
     if stats:
         _, st = M.mpixs_world_get_stats(world)
     for r in range(N):
+        for h in batches[r].values():
+            if h:
+                assert M.mpixs_batch_free(h)[0] == 0
         for c in range(p.ncomms):
             assert M.mpixs_comm_free(comms[r][c]) == 0
         for s in range(p.streams_per_rank):

@@ -77,3 +77,15 @@ def test_info_hex_encoding(lib):
     assert M.mpixs_info_get(info, "type") == (0, "hipStream_t")
     assert M.mpixs_info_get(info, "nope") == (0, None)
     assert M.mpixs_info_free(info) == 0
+
+
+def test_bad_batch_schedule_is_rejected_before_any_gpu_call(lib):
+    """Invalid batch schedules fail with ERR_ARG while the world is validated,
+    before the library touches the device (so this runs without a GPU)."""
+    from paper_2208_13707_amd import mpixs as M
+    for field, value in (("batch_tile", 300), ("batch_tile", 8192), ("batch_graph", 2),
+                         ("batch_max_wg", 1 << 21)):
+        c = M.Config()
+        setattr(c, field, value)
+        rc, w = M.mpixs_world_create(2, c)
+        assert M.errname(rc) == "ERR_ARG" and not w, (field, value)

@@ -221,3 +221,41 @@ def test_group_head_to_head_and_unmatched():
     ops[1].insert(-1, Recv("r", 4, 1, "int32", 0, 5))
     g, _ = check(single_stream(2, b, ops, name="groups-h2h-unmatched"))
     assert np.frombuffer(g.buffers[1]["r"][:4].tobytes(), np.int32)[0] == 10
+
+
+# ------------------------------------------------------- persistent batches
+from workloads.program import GroupInit, Start  # noqa: E402
+
+
+@pytest.mark.parametrize("count,blocking,graph", [(37, True, 0), (2730, False, 1),
+                                                  (43690, True, 0)])
+def test_persistent_ring_halo(count, blocking, graph):
+    check(C.ring_halo(count=count, steps=4, update=True, blocking_recv=blocking, persistent=True),
+          cfg=cfg_with(batch_graph=graph), name=f"persistent halo c{count} graph={graph}")
+
+
+@pytest.mark.parametrize("tile,max_wg,graph", [(1024, 4096, 0), (256, 7, 1), (4096, 3, 0),
+                                               (512, 1 << 16, 1), (2048, 100, 0)])
+def test_persistent_batch_schedules(tile, max_wg, graph):
+    check(C.batch(npairs=400, nranks=8, max_bytes=65536, runs=3),
+          cfg=cfg_with(batch_tile=tile, batch_max_wg=max_wg, batch_graph=graph),
+          name=f"persistent batch tile={tile} max_wg={max_wg} graph={graph}")
+
+
+def test_persistent_batch_config_size():
+    """10,000 messages over 32 ranks, planned once, started 3 times."""
+    check(C.batch(npairs=10000, nranks=32, runs=3), cfg=cfg_with(batch_graph=1))
+
+
+def test_persistent_errors():
+    b = [{"s": as_bytes(np.array([5, 6], np.int32)), "r": np.full(8, 0xEE, np.uint8)}
+         for _ in range(2)]
+    ops = [[GroupStart(), Send("s", 0, 1, "int32", 1, 0), Send("s", 4, 1, "int32", 1, 0),
+            GroupInit("x"), Start("x")],
+           [GroupStart(), Recv("r", 0, 1, "int32", 0, 0), GroupInit("x"), Start("x")]]
+    check(single_stream(2, b, ops, name="persistent unmatched"))
+    # the request left unwaited is released by a wait after the failed init
+    ops = [[GroupStart(), Send("s", 0, 1, "int32", 1, 0, req="a"), GroupInit("y"), Start("y"),
+            Wait(["a"], [None])],
+           [GroupStart(), Recv("r", 0, 1, "int32", 0, 0), GroupInit("y"), Start("y")]]
+    check(single_stream(2, b, ops, name="persistent unwaited"))

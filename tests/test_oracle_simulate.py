@@ -307,3 +307,97 @@ def test_grouped_random_program_equals_ungrouped(seed):
         for k in a.buffers[q]:
             assert np.array_equal(a.buffers[q][k], b.buffers[q][k])
         assert a.statuses[q] == b.statuses[q]
+
+
+# ------------------------------------------------------------ persistent groups
+from workloads.program import GroupInit, Start, User  # noqa: E402
+
+
+@pytest.mark.parametrize("blocking", [True, False])
+def test_persistent_halo_equals_slicing(blocking):
+    """A halo step recorded once and started every step gives the exchange
+    written with numpy slicing."""
+    count, steps = 31, 4
+    p = C.ring_halo(count=count, steps=steps, update=True, blocking_recv=blocking,
+                    persistent=True)
+    r = sim.run(p)
+    assert not r.deadlock and not any(r.sync_errors)
+    A, H = _halo_by_slicing(p, steps, count, True)
+    for q in range(p.nranks):
+        assert np.array_equal(f32(r.buffers[q]["A"]).reshape(count, 8), A[q])
+        assert np.array_equal(f32(r.buffers[q]["H"]).reshape(count, 8), H[q])
+        assert r.statuses[q]["stb"] == ((q + 1) % p.nranks, 0, "SUCCESS", 12 * count)
+
+
+def test_persistent_batch_moves_the_last_contents():
+    """Each run re-reads the send buffers: after the last of 3 runs (the
+    senders add 1 to every int32 word between runs) every contiguous
+    message's receive bytes equal the sender's final bytes, computed with
+    numpy alone."""
+    runs = 3
+    p = C.batch(npairs=150, nranks=5, max_bytes=2048, runs=runs)
+    r = sim.run(p)
+    assert not r.deadlock and not any(r.sync_errors)
+    final = []
+    for q in range(p.nranks):
+        w = p.buffers[q]["sbuf"].view(np.int32).copy()
+        w += np.int32(runs - 1)
+        final.append(w.view(np.uint8))
+    sends, recvs = {}, {}
+    for q in range(p.nranks):
+        for o in p.ops[q][0]:
+            if isinstance(o, Send):
+                sends[o.req[1:]] = (q, o)
+            elif isinstance(o, Recv):
+                recvs[o.req[1:]] = (q, o)
+    checked = 0
+    for i, (s, so) in sends.items():
+        d, ro = recvs[i]
+        if isinstance(so.dtype, str):
+            n = so.count * {"uint8": 1, "int32": 4, "float32": 4}[so.dtype]
+            got = r.buffers[d]["rbuf"][ro.off: ro.off + n]
+            assert np.array_equal(got, final[s][so.off: so.off + n]), i
+            checked += 1
+    assert checked > 50
+
+
+def test_persistent_unmatched_or_unwaited_init_fails():
+    b = [{"s": as_bytes(np.array([5, 6], np.int32)), "r": np.full(8, 0xEE, np.uint8)}
+         for _ in range(2)]
+    # rank 0 records one send too many: init fails everywhere, starts are
+    # invalid and nothing moves
+    ops = [[GroupStart(), Send("s", 0, 1, "int32", 1, 0), Send("s", 4, 1, "int32", 1, 0),
+            GroupInit("x"), Start("x")],
+           [GroupStart(), Recv("r", 0, 1, "int32", 0, 0), GroupInit("x"), Start("x")]]
+    r = sim.run(single_stream(2, b, ops))
+    assert not r.deadlock
+    assert r.sync_errors[0] == [(0, 3, "ERR_ARG"), (0, 4, "ERR_REQUEST")]
+    assert r.sync_errors[1] == [(0, 2, "ERR_ARG"), (0, 3, "ERR_REQUEST")]
+    assert r.buffers[1]["r"].tolist() == [0xEE] * 8
+    # a request created in the group and never waited inside it
+    ops = [[GroupStart(), Send("s", 0, 1, "int32", 1, 0, req="a"), GroupInit("y"), Start("y"),
+            Wait(["a"], [None])],
+           [GroupStart(), Recv("r", 0, 1, "int32", 0, 0), GroupInit("y"), Start("y")]]
+    r = sim.run(single_stream(2, b, ops))
+    assert r.sync_errors[0] == [(0, 2, "ERR_ARG"), (0, 3, "ERR_REQUEST")]
+    assert r.sync_errors[1][0] == (0, 2, "ERR_ARG")
+    assert r.buffers[1]["r"].tolist() == [0xEE] * 8
+
+
+def test_persistent_runs_equal_repeated_groups():
+    """Start == GroupStart + the recorded operations + GroupEnd, run by run
+    (a planted mistake that snapshots payloads at init fails the batch test
+    above; this one checks statuses and buffers against one-shot groups)."""
+    p = C.batch(npairs=80, nranks=4, max_bytes=1024, runs=2)
+    q = C.batch(npairs=80, nranks=4, max_bytes=1024, grouped=True)
+    unrolled = []
+    for rank in range(q.nranks):
+        body = q.ops[rank][0]
+        sb = q.buffers[rank]["sbuf"]
+        unrolled.append(body + [User(("add_const_i32", "sbuf", 0, sb.size // 4, 1))] + body)
+    u = single_stream(q.nranks, q.buffers, unrolled)
+    a, b = sim.run(p), sim.run(u)
+    for rank in range(p.nranks):
+        for k in a.buffers[rank]:
+            assert np.array_equal(a.buffers[rank][k], b.buffers[rank][k])
+        assert a.statuses[rank] == b.statuses[rank]

@@ -26,8 +26,8 @@ from typing import List, Optional
 import numpy as np
 
 from .program import (
-    IN_PLACE, Allreduce, GroupEnd, GroupStart, Program, Recv, Send, User, Wait, as_bytes,
-    footprint_bound, single_stream,
+    IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv, Send, Start, User,
+    Wait, as_bytes, footprint_bound, single_stream,
 )
 
 SEED = 220813707
@@ -65,9 +65,14 @@ def halo_type(count: int):
 
 
 def ring_halo(count: int = 2730, steps: int = 100, nranks: int = 8,
-              update: bool = False, blocking_recv: bool = True, grouped: bool = False) -> Program:
+              update: bool = False, blocking_recv: bool = True, grouped: bool = False,
+              persistent: bool = False) -> Program:
     """Config 2: bidirectional ring halo exchange with a vector datatype.
-    ``grouped``: each step's operations form one group (one batch)."""
+    ``grouped``: each step's operations form one group (one batch).
+    ``persistent``: one step's operations (tag 0) are recorded once as the
+    persistent batch "halo", which every step starts."""
+    if persistent:
+        return _ring_halo_persistent(count, steps, nranks, update, blocking_recv)
     vt = halo_type(count)
     bufs, ops = [], []
     for r in range(nranks):
@@ -98,6 +103,35 @@ def ring_halo(count: int = 2730, steps: int = 100, nranks: int = 8,
         ops.append(lst)
     return single_stream(nranks, bufs, ops,
                          name=f"ring_halo_{nranks}r_c{count}_s{steps}" + ("_grouped" if grouped else ""))
+
+
+def _ring_halo_persistent(count, steps, nranks, update, blocking_recv) -> Program:
+    vt = halo_type(count)
+    bufs, ops = [], []
+    for r in range(nranks):
+        g = rng(2, r)
+        a = g.standard_normal(count * 8, dtype=np.float32)
+        h = g.standard_normal(count * 8, dtype=np.float32)
+        bufs.append({"A": as_bytes(a), "H": as_bytes(h)})
+        right, left = (r + 1) % nranks, (r - 1) % nranks
+        lst = [GroupStart(), Send("A", 0, 1, vt, right, 0, req="sa"),
+               Send("A", 12, 1, vt, left, 0, req="sb")]
+        if blocking_recv:
+            lst += [Recv("H", 0, 1, vt, left, 0, status="sta"),
+                    Recv("H", 12, 1, vt, right, 0, status="stb"),
+                    Wait(["sa", "sb"], [None, None])]
+        else:
+            lst += [Recv("H", 0, 1, vt, left, 0, req="ra"),
+                    Recv("H", 12, 1, vt, right, 0, req="rb"),
+                    Wait(["sa", "sb", "ra", "rb"], [None, None, "sta", "stb"])]
+        lst.append(GroupInit("halo"))
+        for _ in range(steps):
+            lst.append(Start("halo"))
+            if update:
+                lst.append(User(("add_rows_f32", "A", 0, "H", 0, count, 8, 0, 6)))
+        ops.append(lst)
+    return single_stream(nranks, bufs, ops,
+                         name=f"ring_halo_{nranks}r_c{count}_s{steps}_persistent")
 
 
 # --------------------------------------------------------------------------- 3
@@ -156,10 +190,13 @@ def batch_messages(npairs: int = 10000, nranks: int = 32, max_bytes: int = 26214
 
 
 def batch(npairs: int = 10000, nranks: int = 32, max_bytes: int = 262144,
-          min_bytes: int = 8, grouped: bool = False) -> Program:
+          min_bytes: int = 8, grouped: bool = False, runs: int = 0) -> Program:
     """Config 4: every rank isends all its messages in global order, then
     irecvs all its messages in global order, then waits for all of them.
-    ``grouped``: all of it is one group (one batch)."""
+    ``grouped``: all of it is one group (one batch).  ``runs`` > 0: the
+    group is recorded once as the persistent batch "batch" and started
+    ``runs`` times; before every run but the first, each rank adds 1 to
+    every int32 word of its send buffer, so each run moves new bytes."""
     msgs = batch_messages(npairs, nranks, max_bytes, min_bytes)
     send_off = [0] * nranks
     recv_off = [0] * nranks
@@ -184,10 +221,17 @@ def batch(npairs: int = 10000, nranks: int = 32, max_bytes: int = 262144,
         ops[r] = ops[r] + recvs[r]
         if reqs:
             ops[r].append(Wait(reqs, stats))
-        if grouped:
+        if runs > 0:
+            body = [GroupStart()] + ops[r] + [GroupInit("batch")]
+            for j in range(runs):
+                if j:
+                    body.append(User(("add_const_i32", "sbuf", 0, sb.size // 4, 1)))
+                body.append(Start("batch"))
+            ops[r] = body
+        elif grouped:
             ops[r] = [GroupStart()] + ops[r] + [GroupEnd()]
-    return single_stream(nranks, bufs, ops,
-                         name=f"batch_{npairs}p_{nranks}r" + ("_grouped" if grouped else ""))
+    suffix = f"_persistent{runs}" if runs > 0 else ("_grouped" if grouped else "")
+    return single_stream(nranks, bufs, ops, name=f"batch_{npairs}p_{nranks}r" + suffix)
 
 
 # --------------------------------------------------------------------- 5

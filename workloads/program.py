@@ -135,7 +135,26 @@ class GroupEnd:
     kind = "group_end"
 
 
-Op = Union[Send, Recv, Wait, Allreduce, User, GroupStart, GroupEnd]
+@dataclass
+class GroupInit:
+    """Collective end of the rank's current group on ``comm`` that keeps the
+    group as the persistent batch ``batch`` instead of running it."""
+    batch: str
+    comm: int = 0
+
+    kind = "group_init"
+
+
+@dataclass
+class Start:
+    """One run of the persistent batch ``batch`` (made on ``comm``)."""
+    batch: str
+    comm: int = 0
+
+    kind = "start"
+
+
+Op = Union[Send, Recv, Wait, Allreduce, User, GroupStart, GroupEnd, GroupInit, Start]
 
 
 @dataclass
@@ -240,7 +259,8 @@ def streams_of_thread(p: Program, rank: int, thread: int) -> List[int]:
 
 Tree = TypeTree
 __all__ = [
-    "Program", "Send", "Recv", "Wait", "Allreduce", "User", "GroupStart", "GroupEnd", "IN_PLACE",
+    "Program", "Send", "Recv", "Wait", "Allreduce", "User", "GroupStart", "GroupEnd",
+    "GroupInit", "Start", "IN_PLACE",
     "ANY_SOURCE", "ANY_TAG", "BASIC_TYPES", "as_bytes", "count_messages", "Tree",
     "single_stream", "footprint_bound", "streams_of_thread",
 ]
