@@ -501,7 +501,7 @@ def bench_batch(args):
     if args.tune and not args.only_grouped:
         from paper_2208_13707_amd import tune
         best, rows = tune.tune_batch(n, lambda: ops("tune", 0), lambda k: ops("tune", k),
-                                     runs=max(3, args.steps), warm=1, max_reqs=maxreq, log=log)
+                                     runs=max(20, args.steps), warm=3, max_reqs=maxreq, log=log)
         sched = {k: best[k] for k in ("tile", "max_wg", "graph")}
         tuned = {"chosen": best, "grid": rows}
 

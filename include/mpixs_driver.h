@@ -74,10 +74,10 @@ typedef struct {
 
 /* ------------------------------------------------------------- serving
  * An open-loop request server over the enqueue path.  Requests arrive at
- * given times; the owner of a request (the sender of a point-to-point
- * request, rank 0 of an allreduce) admits it when its buffers fit in a
- * device arena of `budget_bytes` (waiting for earlier requests to finish if
- * they do not), after which every participant enqueues its part on its
+ * given times; a scheduler thread admits them first come, first served, each
+ * once it has arrived and its buffers fit in a device arena of
+ * `budget_bytes` (waiting for earlier requests to finish if they do not),
+ * after which every participant's rank thread enqueues its part on its
  * stream: the sender fills its buffer with the request's payload and sends
  * (send_enqueue, or isend_enqueue + wait_enqueue), the receiver receives and
  * a checksum of the received bytes is written to host memory; for an
@@ -105,7 +105,7 @@ typedef struct {
 } mpixs_drv_req;
 
 typedef struct {
-    double admit_us;     /* when the owner admitted it (after the start) */
+    double admit_us;     /* when the scheduler admitted it (after the start) */
     double done_us;      /* when the reaper saw its completion flag */
     uint64_t checksum;   /* device checksum of the received / reduced bytes */
     int32_t error;       /* first error of an enqueue call of the request */
@@ -114,8 +114,9 @@ typedef struct {
 
 /* Serve nreq requests (sorted by arrival) with one thread per rank of the
  * communicators comms[0..nranks-1] (each with its GPU stream in streams[]).
- * Requests are admitted first come, first served in arrival order, so a
- * request never waits for memory held by requests that depend on it.
+ * Admission in arrival order keeps the admitted requests a prefix of the
+ * schedule, so a request never waits for memory held by requests that
+ * depend on it.
  * Point-to-point requests need src != dst (a synchronous send to oneself on
  * one stream cannot complete).  Returns MPIXS_ERR_ARG (nothing run) for an
  * unsorted list, an unknown kind, out-of-range ranks or sizes, or an

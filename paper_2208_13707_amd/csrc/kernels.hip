@@ -334,16 +334,19 @@ template <int TILE, int W, int SK, int DK>
 __device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     using T = typename Unit<W>::T;
     constexpr int U = TILE / COPY_THREADS;
-    T v[U];
+    // a tile of TILE * 16 bytes is 16 / W chunks of TILE units
+    for (uint64_t c0 = u0; c0 < u1; c0 += TILE) {
+        T v[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-        const uint64_t u = u0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
-        if (u < u1) v[k] = ld_unit<T, false>(map_addr<SK, W>(d.src, u));
-    }
+        for (int k = 0; k < U; ++k) {
+            const uint64_t u = c0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
+            if (u < u1) v[k] = ld_unit<T, false>(map_addr<SK, W>(d.src, u));
+        }
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-        const uint64_t u = u0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
-        if (u < u1) st_unit<T, false>(map_addr<DK, W>(d.dst, u), v[k]);
+        for (int k = 0; k < U; ++k) {
+            const uint64_t u = c0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
+            if (u < u1) st_unit<T, false>(map_addr<DK, W>(d.dst, u), v[k]);
+        }
     }
 }
 
@@ -393,8 +396,15 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
             __syncthreads();
         }
         if (!s_fatal) {
-            const uint64_t u0 = uint64_t(tin) * TILE;
-            const uint64_t u1 = u0 + TILE < sd.units ? u0 + TILE : sd.units;
+            const uint64_t tu = uint64_t(TILE) * (16u / sd.w);   // units per tile
+            const uint64_t u0 = uint64_t(tin) * tu;
+            const uint64_t u1 = u0 + tu < sd.units ? u0 + tu : sd.units;
+            if (tin + 1 == sd.ntiles && threadIdx.x < sd.tail) {
+                // byte tail of a copy dense on both sides
+                const uint64_t off = sd.units * sd.w + threadIdx.x;
+                reinterpret_cast<uint8_t *>(sd.dst.base)[off] =
+                    reinterpret_cast<const uint8_t *>(sd.src.base)[off];
+            }
             if (u0 < u1) {
                 switch (sd.w) {
                 case 16: tile_copy_w<TILE, 16>(sd, u0, u1); break;

@@ -200,10 +200,12 @@ struct RelWaitArgs {
 
 // ----------------------------------------------------------------- batches
 // One message of a batch (in host-pinned memory for a one-shot group, in
-// device memory for a persistent batch).  It is cut into tiles of `tile`
-// units (a power of two from 256 to 4096, the same for the whole batch);
-// the workgroup that runs a message's tile 0 also writes the message's
-// receive status.
+// device memory for a persistent batch).  It is cut into tiles of
+// tile * 16 bytes (tile = 256 .. 4096, the same for the whole batch), that
+// is tile * 16 / w units of w bytes, so tiles are balanced by bytes; a
+// message dense on both sides may end in a byte tail of fewer than w bytes,
+// copied with its last tile.  The workgroup that runs a message's tile 0
+// also writes the message's receive status.
 constexpr uint32_t BATCH_TILE_DEFAULT = 1024;
 constexpr uint32_t BATCH_TILE_MIN = 256;
 constexpr uint32_t BATCH_TILE_MAX = 4096;
@@ -213,10 +215,12 @@ struct alignas(16) BatchDesc {
     DMap dst;
     uint64_t units;
     uint32_t w;             // unit bytes: 1, 2, 4, 8 or 16
-    uint32_t ntiles;        // max(1, ceil(units / tile))
+    uint32_t ntiles;        // max(1, ceil(units / (tile * 16 / w)))
     void *status;           // receive status or nullptr
     DevStream *rstream;     // receiver's stream block (sticky error)
     StatusVal st;
+    uint32_t tail;          // bytes after the units (both maps dense), < w
+    uint32_t pad;
 };
 
 // First tile of a workgroup: message index and tile within that message.

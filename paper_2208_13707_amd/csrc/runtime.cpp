@@ -30,6 +30,11 @@
 #include <hip/hip_runtime.h>
 
 #include <immintrin.h>
+#include <linux/futex.h>
+#include <sys/syscall.h>
+#include <unistd.h>
+
+#include <climits>
 
 #include <algorithm>
 #include <chrono>
@@ -63,29 +68,77 @@ uint64_t chan_key(int src, int dst, int tag) {
     return (uint64_t(uint32_t(src)) << 44) ^ (uint64_t(uint32_t(dst)) << 24) ^ uint64_t(uint32_t(tag));
 }
 
-// Wait on the host until pred() holds.  Spins briefly, then yields, then
-// sleeps; gives up on abort or after the world's timeout (which aborts the
-// world so that every device wait ends too).
+// Host sleeping.  Rank threads often outnumber the host's cores, so a
+// thread that waits for another thread's enqueue must not hold a core for
+// long: it spins briefly, then yields its core for up to kYieldUs, then
+// sleeps on a futex word chosen by the address of the object it waits on (a
+// hashed table); whoever changes such an object bumps that word and wakes
+// its sleepers -- a system call only when someone sleeps there.  The waiter reads the word before testing its predicate and
+// the kernel compares it again before sleeping, so a change between the two
+// is never missed; sleeps are also bounded (1 ms), and abort wakes everyone.
+struct alignas(64) WakeSlot {
+    std::atomic<uint32_t> seq{0};
+    std::atomic<uint32_t> sleepers{0};
+};
+constexpr int kWakeSlots = 1024;
+WakeSlot g_wake[kWakeSlots];
+
+WakeSlot &wake_slot(const void *key) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(key);
+    return g_wake[((x >> 6) ^ (x >> 16)) & (kWakeSlots - 1)];
+}
+
+void futex_wake_all(std::atomic<uint32_t> *word) {
+    syscall(SYS_futex, reinterpret_cast<uint32_t *>(word), FUTEX_WAKE_PRIVATE, INT32_MAX, nullptr,
+            nullptr, 0);
+}
+
+void host_notify(const void *key) {
+    WakeSlot &s = wake_slot(key);
+    s.seq.fetch_add(1, std::memory_order_seq_cst);
+    if (s.sleepers.load(std::memory_order_seq_cst) != 0) futex_wake_all(&s.seq);
+}
+
+void host_notify_all() {
+    for (WakeSlot &s : g_wake) {
+        s.seq.fetch_add(1, std::memory_order_seq_cst);
+        if (s.sleepers.load(std::memory_order_seq_cst) != 0) futex_wake_all(&s.seq);
+    }
+}
+
+// Wait on the host until pred() holds; `key` is the address of the object
+// pred() reads (its writer calls host_notify(key)).  Gives up on abort or
+// after the world's timeout (which aborts the world so that every device
+// wait ends too).
 template <class Pred>
-int host_wait(World *w, Pred pred) {
+int host_wait(World *w, const void *key, Pred pred) {
     if (pred()) return MPIXS_SUCCESS;
     w->host_waits.fetch_add(1, std::memory_order_relaxed);
+    for (int i = 0; i < 128; ++i) {
+        _mm_pause();
+        if (pred()) return MPIXS_SUCCESS;
+    }
     const auto t0 = std::chrono::steady_clock::now();
+    constexpr auto kYieldUs = std::chrono::microseconds(50);
+    while (std::chrono::steady_clock::now() - t0 < kYieldUs) {
+        std::this_thread::yield();
+        if (pred()) return MPIXS_SUCCESS;
+    }
+    WakeSlot &s = wake_slot(key);
     const auto limit = std::chrono::milliseconds(w->cfg.timeout_ms);
-    for (uint64_t it = 1;; ++it) {
+    for (;;) {
+        const uint32_t seq = s.seq.load(std::memory_order_seq_cst);
         if (pred()) return MPIXS_SUCCESS;
         if (w->aborted.load(std::memory_order_acquire)) return MPIXS_ERR_ABORTED;
-        if (it < 4096) {
-            _mm_pause();
-        } else if (it < 8192) {
-            std::this_thread::yield();
-        } else {
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
-        }
-        if ((it & 255) == 0 && std::chrono::steady_clock::now() - t0 > limit) {
+        if (std::chrono::steady_clock::now() - t0 > limit) {
             mpixs_world_abort(reinterpret_cast<mpixs_world>(w));
             return MPIXS_ERR_TIMEOUT;
         }
+        s.sleepers.fetch_add(1, std::memory_order_seq_cst);
+        struct timespec ts = {0, 1000000};
+        syscall(SYS_futex, reinterpret_cast<uint32_t *>(&s.seq), FUTEX_WAIT_PRIVATE, seq, &ts,
+                nullptr, 0);
+        s.sleepers.fetch_sub(1, std::memory_order_seq_cst);
     }
 }
 
@@ -170,10 +223,11 @@ void finish_map(const Side &sd, MapPlan &p, int w, uint64_t units) {
 }  // namespace
 
 int plan_copy(const Side &S, const Side &R, int64_t nbytes, DMap *src, DMap *dst, int *wsz,
-              uint64_t *units) {
+              uint64_t *units, uint32_t *tail) {
     MapPlan ps, pr;
     *wsz = 16;
     *units = 0;
+    if (tail) *tail = 0;
     if (nbytes <= 0) {
         std::memset(src, 0, sizeof(*src));
         std::memset(dst, 0, sizeof(*dst));
@@ -181,6 +235,18 @@ int plan_copy(const Side &S, const Side &R, int64_t nbytes, DMap *src, DMap *dst
     }
     plan_map(S, ps);
     plan_map(R, pr);
+    if (tail && ps.m.kind == MAP_CONTIG && pr.m.kind == MAP_CONTIG) {
+        // dense on both sides: the unit follows the base addresses alone and
+        // the last nbytes mod W bytes form a byte tail
+        *wsz = int(std::min<int64_t>(16, lowbit(ps.g | pr.g)));
+        *units = uint64_t(nbytes / *wsz);
+        *tail = uint32_t(nbytes % *wsz);
+        finish_map(S, ps, *wsz, *units);
+        finish_map(R, pr, *wsz, *units);
+        *src = ps.m;
+        *dst = pr.m;
+        return MPIXS_SUCCESS;
+    }
     const int64_t g = nbytes | ps.g | pr.g;
     *wsz = int(std::min<int64_t>(16, lowbit(g)));
     *units = uint64_t(nbytes / *wsz);
@@ -366,7 +432,7 @@ int check_p2p(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, in
 // status and the sticky error.
 int complete_first(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, int side,
                    mpixs_status *status) {
-    int rc = host_wait(w, [&] { return rec->copy_enq.load(std::memory_order_acquire) != 0; });
+    int rc = host_wait(w, &rec->copy_enq, [&] { return rec->copy_enq.load(std::memory_order_acquire) != 0; });
     if (rc) return rc;
     WaitArgs a = wait_one(&ch->d->done, k + 1);
     if (side == 1) {
@@ -442,6 +508,7 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
                      (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
         rec->st = sv;
         rec->copy_enq.store(1, std::memory_order_release);
+        host_notify(&rec->copy_enq);
         rec_release(ch, rec);
         if (r) {
             r->comm = c;
@@ -456,6 +523,7 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
     }
     rc = do_post(w, st, &ch->d->ready[side], k + 1);
     rec->arrived.fetch_or(mine, std::memory_order_release);
+    host_notify(&rec->arrived);
     ch->mu.unlock();
     if (rc) {
         delete r;
@@ -536,7 +604,7 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
             }
             continue;
         }
-        rc = host_wait(w, [&] { return r->rec->copy_enq.load(std::memory_order_acquire) != 0; });
+        rc = host_wait(w, &r->rec->copy_enq, [&] { return r->rec->copy_enq.load(std::memory_order_acquire) != 0; });
         if (rc) break;
         if (r->side == 1 && status) {
             // one status per wait kernel
@@ -776,10 +844,11 @@ int plan_group(World *w, GroupRec *rec, int n, std::vector<BatchDesc> &descs,
             d.st = match_status(S->side, R->side, tag);
             int wsz = 16;
             uint64_t units = 0;
-            plan_copy(S->side, R->side, d.st.count_bytes, &d.src, &d.dst, &wsz, &units);
+            plan_copy(S->side, R->side, d.st.count_bytes, &d.src, &d.dst, &wsz, &units, &d.tail);
             d.units = units;
             d.w = uint32_t(wsz);
-            d.ntiles = uint32_t(std::max<uint64_t>(1, (units + tile - 1) / tile));
+            const uint64_t tu = uint64_t(tile) * uint64_t(16 / wsz);   // units per tile
+            d.ntiles = uint32_t(std::max<uint64_t>(1, (units + tu - 1) / tu));
             d.status = R->status;
             d.rstream = R->side.st->dev;
             if (R->req) R->req->st = d.st;
@@ -1132,6 +1201,7 @@ int mpixs_world_abort(mpixs_world w) {
     if (!w) return MPIXS_ERR_ARG;
     w->aborted.store(1, std::memory_order_release);
     __atomic_store_n(w->h_abort, 1u, __ATOMIC_RELEASE);
+    host_notify_all();
     return MPIXS_SUCCESS;
 }
 
@@ -1290,8 +1360,9 @@ int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm 
         cr.arrived++;
         sh = cr.sh;
     }
+    host_notify(&ps->creates);
     // all ranks of the parent must arrive (a collective call, §3.3)
-    int rc = host_wait(w, [&] {
+    int rc = host_wait(w, &ps->creates, [&] {
         std::lock_guard<std::mutex> g(ps->create_mu);
         return ps->creates[k].arrived == ps->size;
     });
@@ -1397,10 +1468,11 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count, mpixs
         sh->coll_mu.unlock();
         rc = do_reduce(w, st, rec, n, c->rank, arrive, k + 1, done, k + 1);
         rec->reduce_enq.store(1, std::memory_order_release);
+        host_notify(&rec->reduce_enq);
     } else {
         rc = do_post(w, st, arrive + 16 * c->rank, k + 1);
         sh->coll_mu.unlock();
-        if (!rc) rc = host_wait(w, [&] { return rec->reduce_enq.load(std::memory_order_acquire) != 0; });
+        if (!rc) rc = host_wait(w, &rec->reduce_enq, [&] { return rec->reduce_enq.load(std::memory_order_acquire) != 0; });
         if (!rc) {
             WaitArgs a = wait_one(done, k + 1);
             rc = do_wait(w, st, a);
@@ -1463,10 +1535,11 @@ int group_finish(mpixs_comm c, int kind, BatchPlan **plan) {
         else rc = batch_create(w, sh, rec, c->rank, st, &rec->batch);
         rec->error = rc;
         rec->launched.store(1, std::memory_order_release);
+        host_notify(&rec->launched);
     } else {
         if (kind == 1) rc = do_post(w, st, sh->d_grp + 16 * c->rank, g + 1);
         sh->grp_mu.unlock();
-        if (!rc) rc = host_wait(w, [&] { return rec->launched.load(std::memory_order_acquire) != 0; });
+        if (!rc) rc = host_wait(w, &rec->launched, [&] { return rec->launched.load(std::memory_order_acquire) != 0; });
         if (!rc) rc = rec->error;
         if (!rc && kind == 1) {
             WaitArgs a = wait_one(sh->d_grp + 16 * n, g + 1);
@@ -1525,7 +1598,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
         // producer first: every other rank's arrival for run e is enqueued
         for (int q = 0; q < P->n && !rc; ++q) {
             if (q == P->leader) continue;
-            rc = host_wait(w, [&] { return P->posted[q].load(std::memory_order_acquire) >= e; });
+            rc = host_wait(w, &P->posted[q], [&] { return P->posted[q].load(std::memory_order_acquire) >= e; });
         }
         if (!rc) {
             if (P->exec) {
@@ -1541,6 +1614,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
             P->launch_err.compare_exchange_strong(z, rc);
         }
         P->launched.store(e, std::memory_order_release);
+        host_notify(&P->launched);
         if (!rc) {
             w->n_copy.fetch_add(P->nwg > 0 ? 1 : 0, std::memory_order_relaxed);
             w->bytes_copied.fetch_add(P->bytes, std::memory_order_relaxed);
@@ -1549,8 +1623,9 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
         rc = gpu_err(launch_post_inc(st->hs, P->d_ctr + 16 * b->rank));
         if (rc) return rc;
         P->posted[b->rank].store(e, std::memory_order_release);
+        host_notify(&P->posted[b->rank]);
         w->n_post.fetch_add(1, std::memory_order_relaxed);
-        rc = host_wait(w, [&] { return P->launched.load(std::memory_order_acquire) >= e; });
+        rc = host_wait(w, &P->launched, [&] { return P->launched.load(std::memory_order_acquire) >= e; });
         if (!rc) rc = P->launch_err.load();
         if (!rc) {
             RelWaitArgs a;
@@ -1605,8 +1680,9 @@ int mpixs_send(const void *buf, int count, mpixs_datatype dt, int dest, int tag,
         rec->s.st = st;
         rec->s.rank = c->rank;
         rec->arrived.fetch_or(ARR_S, std::memory_order_release);
+        host_notify(&rec->arrived);
     }
-    rc = host_wait(w, [&] { return rec->done_host.load(std::memory_order_acquire) != 0; });
+    rc = host_wait(w, &rec->done_host, [&] { return rec->done_host.load(std::memory_order_acquire) != 0; });
     rec_release(ch, rec);
     return rc;
 }
@@ -1633,8 +1709,9 @@ int mpixs_recv(void *buf, int count, mpixs_datatype dt, int source, int tag, mpi
         rec->r.st = st;
         rec->r.rank = c->rank;
         rec->arrived.fetch_or(ARR_R, std::memory_order_release);
+        host_notify(&rec->arrived);
     }
-    rc = host_wait(w, [&] { return (rec->arrived.load(std::memory_order_acquire) & ARR_S) != 0; });
+    rc = host_wait(w, &rec->arrived, [&] { return (rec->arrived.load(std::memory_order_acquire) & ARR_S) != 0; });
     if (rc) {
         rec_release(ch, rec);
         return rc;
@@ -1649,6 +1726,7 @@ int mpixs_recv(void *buf, int count, mpixs_datatype dt, int source, int tag, mpi
     rc = do_copy(w, st, S, R, sv, nullptr, 0, nullptr, 0, status, true);
     if (!rc && hipStreamSynchronize(st->hs) != hipSuccess) rc = MPIXS_ERR_GPU;
     rec->done_host.store(1, std::memory_order_release);
+    host_notify(&rec->done_host);
     rec_release(ch, rec);
     return rc;
 }
@@ -1681,8 +1759,9 @@ int mpixs_allreduce(const void *sendbuf, void *recvbuf, int count, mpixs_datatyp
         rc = do_reduce(w, st, rec, n, c->rank, nullptr, 0, nullptr, 0);
         if (!rc && hipStreamSynchronize(st->hs) != hipSuccess) rc = MPIXS_ERR_GPU;
         rec->done_host.store(1, std::memory_order_release);
+        host_notify(&rec->done_host);
     } else {
-        rc = host_wait(w, [&] { return rec->done_host.load(std::memory_order_acquire) != 0; });
+        rc = host_wait(w, &rec->done_host, [&] { return rec->done_host.load(std::memory_order_acquire) != 0; });
     }
     if (rec->refs.fetch_sub(1) == 1) {
         std::lock_guard<std::mutex> g(sh->coll_mu);

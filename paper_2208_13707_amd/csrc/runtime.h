@@ -78,8 +78,10 @@ enum : uint32_t { ARR_S = 1, ARR_R = 2 };
 // Unit size and both address maps of a copy of `nbytes` packed bytes from
 // S's typemap into R's.  seg_s / seg_r override the SEG tables (host-side
 // planning of uncommitted types); nullptr uses the committed tables.
+// tail != nullptr: a copy dense on both sides may leave its last nbytes mod W
+// bytes to a byte tail (*tail), so that W follows the base addresses alone.
 int plan_copy(const Side &S, const Side &R, int64_t nbytes, DMap *src, DMap *dst, int *wsz,
-              uint64_t *units);
+              uint64_t *units, uint32_t *tail = nullptr);
 
 // Host record of message k of a channel: the first side to arrive stores
 // its descriptor, the second side reads it and launches the copy.

@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <immintrin.h>
+#include <linux/futex.h>
+#include <sys/syscall.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <atomic>
@@ -46,8 +49,11 @@ __global__ void __launch_bounds__(256) k_fill(uint8_t *p, int64_t n, uint64_t se
     }
 }
 
-// sum_j byte_j * (j + 1) mod 2^64, accumulated with device atomics
-__global__ void __launch_bounds__(256) k_checksum(const uint8_t *p, int64_t n, uint64_t *acc) {
+// sum_j byte_j * (j + 1) mod 2^64, accumulated with device atomics in
+// acc[0]; the last workgroup to finish (ticket in acc[1]) publishes the sum
+// and the completion flag to host memory.
+__global__ void __launch_bounds__(256) k_checksum(const uint8_t *p, int64_t n, uint64_t *acc,
+                                                   uint64_t *host_sum, uint32_t *host_flag) {
     uint64_t s = 0;
     for (int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x; j < n; j += int64_t(gridDim.x) * 256)
         s += uint64_t(p[j]) * uint64_t(j + 1);
@@ -58,14 +64,12 @@ __global__ void __launch_bounds__(256) k_checksum(const uint8_t *p, int64_t n, u
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long *>(acc),
-                                    static_cast<unsigned long long>(red[0]));
-}
-
-// after the checksum kernel (kernel boundary): publish to host memory
-__global__ void k_complete(const uint64_t *acc, uint64_t *host_sum, uint32_t *host_flag) {
     if (threadIdx.x != 0) return;
-    *host_sum = *acc;
+    __hip_atomic_fetch_add(&acc[0], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t = __hip_atomic_fetch_add(&acc[1], uint64_t(1), __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    if (t + 1 != gridDim.x) return;
+    *host_sum = __hip_atomic_load(&acc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(host_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -79,12 +83,15 @@ int grid_for(int64_t n, int64_t per_thread) {
 class Arena {
   public:
     explicit Arena(size_t cap) : cap_(cap) { free_[0] = cap; }
-    // blocks until `n` bytes fit; false on timeout or if n exceeds the budget
-    bool alloc(size_t n, size_t *off, std::chrono::milliseconds timeout) {
+    // blocks until `n` bytes fit; false on timeout, once `stop` is set, or if
+    // n exceeds the budget
+    bool alloc(size_t n, size_t *off, std::chrono::milliseconds timeout,
+               const std::atomic<int> &stop) {
         std::unique_lock<std::mutex> g(mu_);
         if (n > cap_) return false;
         const auto until = clk::now() + timeout;
         for (;;) {
+            if (stop.load()) return false;
             for (auto it = free_.begin(); it != free_.end(); ++it) {
                 if (it->second >= n) {
                     *off = it->first;
@@ -95,7 +102,8 @@ class Arena {
                     return true;
                 }
             }
-            if (cv_.wait_until(g, until) == std::cv_status::timeout) return false;
+            if (clk::now() >= until) return false;
+            cv_.wait_for(g, std::chrono::milliseconds(10));
         }
     }
     void release(size_t off, size_t n) {
@@ -126,9 +134,22 @@ class Arena {
 };
 
 struct Slot {
-    std::atomic<int> admitted{0};
+    std::atomic<uint32_t> admitted{0};
     size_t off = 0, bytes = 0;
 };
+
+// 64 rank threads share the host's cores, so threads that wait for another
+// thread sleep on a futex word (bounded to 1 ms, so a failure elsewhere is
+// always noticed) instead of spinning.
+void futex_wait(std::atomic<uint32_t> &w, uint32_t seen) {
+    struct timespec ts = {0, 1000000};
+    syscall(SYS_futex, reinterpret_cast<uint32_t *>(&w), FUTEX_WAIT_PRIVATE, seen, &ts, nullptr, 0);
+}
+
+void futex_wake(std::atomic<uint32_t> &w) {
+    syscall(SYS_futex, reinterpret_cast<uint32_t *>(&w), FUTEX_WAKE_PRIVATE, INT32_MAX, nullptr,
+            nullptr, 0);
+}
 
 size_t round256(int64_t n) { return size_t((n + 255) / 256 * 256); }
 
@@ -138,7 +159,8 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                                void *const *streams, const mpixs_drv_req *reqs, int64_t nreq,
                                int64_t budget_bytes, mpixs_drv_req_result *results,
                                double *wall_s) {
-    if (!world || nranks <= 0 || !comms || !streams || (nreq > 0 && (!reqs || !results)) ||
+    if (!world || nranks <= 0 || !comms || !streams || nreq < 0 || nreq >= INT32_MAX ||
+        (nreq > 0 && (!reqs || !results)) ||
         budget_bytes <= 0)
         return MPIXS_ERR_ARG;
     char *arena_mem = nullptr;
@@ -148,7 +170,7 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
     const size_t nslot = size_t(std::max<int64_t>(nreq, 1));
     if (hipMalloc(reinterpret_cast<void **>(&arena_mem), size_t(budget_bytes)) != hipSuccess)
         return MPIXS_ERR_NOMEM;
-    if (hipMalloc(reinterpret_cast<void **>(&dsum), nslot * 8) != hipSuccess ||
+    if (hipMalloc(reinterpret_cast<void **>(&dsum), nslot * 16) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&hsum), nslot * 8, hipHostMallocCoherent) !=
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&hflag), nslot * 4, hipHostMallocCoherent) !=
@@ -158,7 +180,7 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
         if (hsum) (void)hipHostFree(hsum);
         return MPIXS_ERR_NOMEM;
     }
-    (void)hipMemset(dsum, 0, nslot * 8);
+    (void)hipMemset(dsum, 0, nslot * 16);
     (void)hipDeviceSynchronize();
     std::memset(hsum, 0, nslot * 8);
     std::memset(hflag, 0, nslot * 4);
@@ -194,12 +216,6 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
     std::mutex admit_mu;
     std::deque<int64_t> admitted;          // admission order, for the reaper
     std::atomic<int64_t> completed{0};
-    // Admission is first come, first served in arrival order: request i is
-    // admitted only after every earlier request.  The admitted requests are
-    // then always a prefix of the schedule, whose participants never wait for
-    // a later request, so the arena can never fill up with requests that
-    // depend on one still waiting for memory.
-    std::atomic<int64_t> next_admit{0};
     std::atomic<int> first_error{0};
     std::atomic<int> go{0};
     clk::time_point t0;
@@ -212,6 +228,43 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
         mpixs_world_abort(world);
     };
 
+    // Admission (one thread): first come, first served in arrival order,
+    // each request as soon as it has arrived and its buffers fit into the
+    // arena.  The admitted requests are then always a prefix of the
+    // schedule, and a rank thread only ever waits for an earlier request, so
+    // memory can never fill up with requests that depend on one still
+    // waiting for memory; and admission never waits for a busy rank thread.
+    auto admitter = [&]() {
+        while (!go.load(std::memory_order_acquire)) _mm_pause();
+        for (int64_t i = 0; i < nreq && !first_error.load(); ++i) {
+            const mpixs_drv_req &q = reqs[i];
+            const auto arrive = t0 + std::chrono::duration_cast<clk::duration>(
+                                         std::chrono::duration<double, std::micro>(q.arrival_us));
+            if (arrive - clk::now() > std::chrono::microseconds(200))
+                std::this_thread::sleep_until(arrive - std::chrono::microseconds(100));
+            while (clk::now() < arrive) _mm_pause();
+            const size_t each = round256(q.bytes);
+            const size_t need = q.kind == MPIXS_DRV_REQ_ALLREDUCE ? 2 * each * size_t(nranks)
+                                                                  : 2 * each;
+            size_t off = 0;
+            if (!arena.alloc(need, &off, std::chrono::milliseconds(60000), first_error)) {
+                results[i].error = MPIXS_ERR_NOMEM;
+                fail(MPIXS_ERR_NOMEM);
+                break;
+            }
+            Slot &sl = slots[size_t(i)];
+            sl.off = off;
+            sl.bytes = need;
+            results[i].admit_us = us_since(clk::now());
+            {
+                std::lock_guard<std::mutex> g(admit_mu);
+                admitted.push_back(i);
+            }
+            sl.admitted.store(1, std::memory_order_release);
+            futex_wake(sl.admitted);
+        }
+    };
+
     auto worker = [&](int r) {
         hipStream_t hs = static_cast<hipStream_t>(streams[r]);
         mpixs_comm c = comms[r];
@@ -219,45 +272,11 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
         for (int64_t i : mine[size_t(r)]) {
             if (first_error.load()) break;
             const mpixs_drv_req &q = reqs[i];
-            const auto arrive = t0 + std::chrono::duration_cast<clk::duration>(
-                                         std::chrono::duration<double, std::micro>(q.arrival_us));
-            // 64 rank threads share the host's cores: sleep until shortly
-            // before the arrival, then yield
-            if (arrive - clk::now() > std::chrono::microseconds(300))
-                std::this_thread::sleep_until(arrive - std::chrono::microseconds(150));
-            while (clk::now() < arrive) std::this_thread::yield();
-            const int owner = q.kind == MPIXS_DRV_REQ_ALLREDUCE ? 0 : q.src;
             Slot &sl = slots[size_t(i)];
-            if (r == owner) {
-                for (int spin = 0; next_admit.load(std::memory_order_acquire) != i; ++spin) {
-                    if (first_error.load()) return;
-                    if (spin < 256) _mm_pause();
-                    else std::this_thread::yield();
-                }
-                const size_t each = round256(q.bytes);
-                const size_t need = q.kind == MPIXS_DRV_REQ_ALLREDUCE ? 2 * each * size_t(nranks)
-                                                                      : 2 * each;
-                size_t off = 0;
-                if (!arena.alloc(need, &off, std::chrono::milliseconds(60000))) {
-                    results[i].error = MPIXS_ERR_NOMEM;
-                    fail(MPIXS_ERR_NOMEM);
-                    break;
-                }
-                sl.off = off;
-                sl.bytes = need;
-                results[i].admit_us = us_since(clk::now());
-                {
-                    std::lock_guard<std::mutex> g(admit_mu);
-                    admitted.push_back(i);
-                }
-                sl.admitted.store(1, std::memory_order_release);
-                next_admit.store(i + 1, std::memory_order_release);
-            } else {
-                for (int spin = 0; !sl.admitted.load(std::memory_order_acquire); ++spin) {
-                    if (first_error.load()) return;
-                    if (spin < 256) _mm_pause();
-                    else std::this_thread::yield();
-                }
+            for (int spin = 0; !sl.admitted.load(std::memory_order_acquire); ++spin) {
+                if (first_error.load()) return;
+                if (spin < 64) _mm_pause();
+                else futex_wait(sl.admitted, 0);
             }
             const size_t each = round256(q.bytes);
             char *base = arena_mem + sl.off;
@@ -270,9 +289,7 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                 rc = mpixs_allreduce_enqueue(in, out, int(q.bytes / 4), MPIXS_INT32, MPIXS_SUM, c);
                 if (!rc && r == 0) {
                     hipLaunchKernelGGL(k_checksum, dim3(grid_for(q.bytes, 64)), dim3(256), 0, hs,
-                                       out, q.bytes, dsum + i);
-                    hipLaunchKernelGGL(k_complete, dim3(1), dim3(64), 0, hs, dsum + i, hsum + i,
-                                       hflag + i);
+                                       out, q.bytes, dsum + 2 * i, hsum + i, hflag + i);
                 }
             } else {
                 uint8_t *sb = reinterpret_cast<uint8_t *>(base);
@@ -300,9 +317,7 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                     }
                     if (!rc) {
                         hipLaunchKernelGGL(k_checksum, dim3(grid_for(q.bytes, 64)), dim3(256), 0,
-                                           hs, rb, q.bytes, dsum + i);
-                        hipLaunchKernelGGL(k_complete, dim3(1), dim3(64), 0, hs, dsum + i,
-                                           hsum + i, hflag + i);
+                                           hs, rb, q.bytes, dsum + 2 * i, hsum + i, hflag + i);
                     }
                 }
             }
@@ -348,9 +363,11 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
 
     std::vector<std::thread> th;
     for (int r = 0; r < nranks; ++r) th.emplace_back(worker, r);
+    std::thread ad(admitter);
     t0 = clk::now();
     go.store(1, std::memory_order_release);
     std::thread rp(reaper);
+    ad.join();
     for (auto &x : th) x.join();
     // requests that failed before completing will never set their flag
     if (first_error.load()) {
