@@ -102,6 +102,50 @@ def halo_ops(D, r, n, A, H, vt, steps, tag0, mode, marks=False, status_ptr=0, gr
     return D.ops_array(rows)
 
 
+def halo_persistent_ops(D, r, n, A, H, vt, steps, init=False, marks=False):
+    """init: record one halo step (tag 0) as persistent batch slot 0;
+    else: start it ``steps`` times."""
+    if init:
+        right, left = (r + 1) % n, (r - 1) % n
+        a0, a3 = A.data_ptr(), A.data_ptr() + 12
+        h0, h3 = H.data_ptr(), H.data_ptr() + 12
+        rows = [dict(kind=D.GROUP_START),
+                dict(kind=D.ISEND, peer=right, tag=0, count=1, datatype=vt, buf=a0, req=0),
+                dict(kind=D.ISEND, peer=left, tag=0, count=1, datatype=vt, buf=a3, req=1),
+                dict(kind=D.RECV, peer=left, tag=0, count=1, datatype=vt, buf=h0),
+                dict(kind=D.RECV, peer=right, tag=0, count=1, datatype=vt, buf=h3),
+                dict(kind=D.WAITALL, req=0, nreq=2),
+                dict(kind=D.GROUP_INIT, req=0)]
+        return D.ops_array(rows)
+    rows = []
+    for s in range(steps):
+        if marks:
+            rows.append(dict(kind=D.MARK, req=2 * s))
+        rows.append(dict(kind=D.BATCH_START, req=0))
+        if marks:
+            rows.append(dict(kind=D.MARK, req=2 * s + 1))
+    return D.ops_array(rows)
+
+
+def time_batch_kernel(sess, reps):
+    """Average duration of a persistent batch's kernel (slot 0 of rank 0's
+    handles), launched back to back between one pair of HIP events."""
+    import ctypes
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    f = M.lib().mpixs_debug_time_batch
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]
+    f.restype = ctypes.c_int
+    hs = D.hip_stream_create()
+    avg, nbytes, nwg = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int()
+    rc = f(sess.batches[0][0], hs, reps, ctypes.byref(avg), ctypes.byref(nbytes), ctypes.byref(nwg))
+    D.hip_stream_destroy(hs)
+    if rc:
+        raise RuntimeError(f"mpixs_debug_time_batch: {M.errname(rc)}")
+    return avg.value, nbytes.value, nwg.value
+
+
 def run_checked(sess, ops, mode=0, nmarks=0, max_reqs=64):
     from paper_2208_13707_amd import mpixs as M
     rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
@@ -185,6 +229,21 @@ def bench_halo(args):
     from workloads import configs as C
 
     n, steps, warm = 8, args.steps, args.warmup
+    if args.kernel_only:
+        # counter runs: plan one persistent halo step (no GPU waits) and launch
+        # its batch kernel only
+        p = C.ring_halo(count=args.count, steps=1)
+        A = [torch.from_numpy(p.buffers[r]["A"].copy()).cuda() for r in range(n)]
+        H = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
+        vt = make_vector(M, args.count, 3, 8, M.FLOAT32)
+        torch.cuda.synchronize()
+        sess = D.Session(n)
+        run_checked(sess, [halo_persistent_ops(D, r, n, A[r], H[r], vt, 0, init=True)
+                           for r in range(n)])
+        us, payload, nwg = time_batch_kernel(sess, steps)
+        sess.close()
+        return {"workload": "halo batch kernel only", "avg_launch_us": us,
+                "payload_bytes": payload, "workgroups": nwg, "launches": steps + 1}
     counts = [args.count] + ([c for c in C.HALO_COUNTS if c != args.count] if args.sweep else [])
     out_sweep = []
     headline = None
@@ -234,6 +293,29 @@ def bench_halo(args):
         for r in range(n):
             if not torch.equal(Hg[r], H[r]):
                 raise AssertionError(f"rank {r}: grouped halo differs from the plain path")
+        # ---- persistent: one step recorded once, started every step
+        Hp = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
+        torch.cuda.synchronize()
+        sess = D.Session(n)
+        run_checked(sess, [halo_persistent_ops(D, r, n, A[r], Hp[r], vt, 0, init=True)
+                           for r in range(n)])
+        run_checked(sess, [halo_persistent_ops(D, r, n, A[r], Hp[r], vt, warm) for r in range(n)])
+        sec_p, _ = run_checked(sess, [halo_persistent_ops(D, r, n, A[r], Hp[r], vt, steps)
+                                      for r in range(n)])
+        _, marks = run_checked(sess, [halo_persistent_ops(D, r, n, A[r], Hp[r], vt, steps,
+                                                          marks=True) for r in range(n)],
+                               nmarks=2 * steps)
+        lat_p = step_latencies(marks, steps)
+        if count == args.count:
+            bk_us, bk_payload, bk_wg = time_batch_kernel(sess, max(20, steps))
+            res["batch_kernel"] = {"avg_launch_us": bk_us, "payload_bytes": bk_payload,
+                                   "workgroups": bk_wg}
+        sess.close()
+        res.update(persistent_msgs_per_s=msgs / sec_p, persistent_ms_per_step=1000 * sec_p / steps,
+                   persistent_p50_step_us=pct(lat_p, 50), persistent_p99_step_us=pct(lat_p, 99))
+        for r in range(n):
+            if not torch.equal(Hp[r], H[r]):
+                raise AssertionError(f"rank {r}: persistent halo differs from the plain path")
         # ---- correctness against the oracle (sampled: after any step, H holds
         # the neighbours' halo columns; the oracle runs one full-size step)
         if count == args.count:
@@ -264,14 +346,35 @@ def bench_halo(args):
         out_sweep.append(res)
         log(f"[halo] count={count}: {res['msgs_per_s']:.0f} msgs/s, "
             f"grouped {res['grouped_msgs_per_s']:.0f} msgs/s, "
+            f"persistent {res['persistent_msgs_per_s']:.0f} msgs/s, "
             f"{res['gbps_algorithmic']:.1f} GB/s alg, "
             f"host-synced {res.get('host_synced_msgs_per_s', 0):.0f} msgs/s")
 
     h = headline
-    roof = vector_copy_roofline(h["count"], steps)
-    grouped = h["grouped_msgs_per_s"] > h["msgs_per_s"]
-    value = h["grouped_msgs_per_s"] if grouped else h["msgs_per_s"]
-    ms_step = h["grouped_ms_per_step"] if grouped else h["ms_per_step"]
+    variants = {"plain": ("msgs_per_s", "ms_per_step", "p50_step_us", "p99_step_us",
+                          "plain enqueue (one copy per message)"),
+                "grouped": ("grouped_msgs_per_s", "grouped_ms_per_step", "grouped_p50_step_us",
+                            "grouped_p99_step_us", "grouped (each step one group)"),
+                "persistent": ("persistent_msgs_per_s", "persistent_ms_per_step",
+                               "persistent_p50_step_us", "persistent_p99_step_us",
+                               "persistent batch (one step recorded once, started every step)")}
+    best = max(variants, key=lambda v: h[variants[v][0]])
+    kv, km, k50, k99, vname = variants[best]
+    value, ms_step = h[kv], h[km]
+    if best == "persistent":
+        bk = h["batch_kernel"]
+        per_launch = 2 * bk["payload_bytes"]
+        ach = per_launch / (bk["avg_launch_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS,
+                "traffic": measured_traffic(f"halo_batch_count{h['count']}"),
+                "kernel": "mpixs::k_batch<1024>", "bytes_per_launch": per_launch,
+                "avg_launch_us": bk["avg_launch_us"], "launches_timed": max(20, steps),
+                "workgroups": bk["workgroups"],
+                "note": "batch kernel of one halo step (16 messages), launched back to back "
+                        "between one event pair"}
+    else:
+        roof = vector_copy_roofline(h["count"], steps)
     gbps_pay = value * h["payload_bytes"] / 1e9
     hs = h.get("host_synced_msgs_per_s")
     line = {
@@ -290,7 +393,7 @@ def bench_halo(args):
         "config": {"workload": f"ring_halo_8ranks_vector(count={h['count']},bl=3,stride=8)_f32",
                    "ranks": n, "count": h["count"], "payload_bytes": h["payload_bytes"],
                    "msgs_per_step": 16, "parallelism": "1 GPU, 8 rank threads",
-                   "variant": "grouped (each step one group)" if grouped else "plain enqueue"},
+                   "variant": vname},
         "gbps_payload": gbps_pay,
         "gbps_algorithmic": 2 * gbps_pay,
         "hbm_frac": 2 * gbps_pay / HBM_PEAK_GBS,
@@ -299,10 +402,13 @@ def bench_halo(args):
         "grouped_enqueue": {"value": h["grouped_msgs_per_s"], "ms_per_step": h["grouped_ms_per_step"],
                             "p50_step_us": h["grouped_p50_step_us"],
                             "p99_step_us": h["grouped_p99_step_us"]},
-        "host_synced": {"value": hs, "unit": "msgs/s", "speedup": value / hs if hs else None},
-        "latency_us": {"p50": h["grouped_p50_step_us"] if grouped else h["p50_step_us"],
-                       "p99": h["grouped_p99_step_us"] if grouped else h["p99_step_us"],
-                       "of": "halo step"},
+        "persistent_enqueue": {"value": h["persistent_msgs_per_s"],
+                               "ms_per_step": h["persistent_ms_per_step"],
+                               "p50_step_us": h["persistent_p50_step_us"],
+                               "p99_step_us": h["persistent_p99_step_us"]},
+        "host_synced": {"value": hs, "unit": "msgs/s", "speedup": value / hs if hs else None,
+                        "plain_speedup": h["msgs_per_s"] / hs if hs else None},
+        "latency_us": {"p50": h[k50], "p99": h[k99], "of": "halo step"},
         "roofline": roof,
         "sweep": out_sweep if args.sweep else None,
     }
@@ -497,6 +603,15 @@ def bench_batch(args):
 
     # schedule of the persistent batch: chosen by the autotuner, or given
     sched = dict(tile=args.batch_tile, max_wg=args.batch_max_wg, graph=args.batch_graph)
+    if args.kernel_only:
+        # counter runs: plan the batch (no GPU waits) and launch its kernel only
+        from paper_2208_13707_amd import tune
+        sess = D.Session(n, tune.config_for(sched["tile"], sched["max_wg"], sched["graph"]))
+        run_checked(sess, ops("persistent", 0), max_reqs=maxreq)
+        us, payload, nwg = time_batch_kernel(sess, args.steps)
+        sess.close()
+        return {"workload": "batch kernel only", "avg_launch_us": us, "payload_bytes": payload,
+                "workgroups": nwg, "launches": args.steps + 1}
     tuned = None
     if args.tune and not args.only_grouped:
         from paper_2208_13707_amd import tune
@@ -522,7 +637,17 @@ def bench_batch(args):
         if variant == "persistent":
             init_ms = 1000 * run_checked(sess, ops(variant, 0, tagb), max_reqs=maxreq)[0]
         run_checked(sess, ops(variant, args.warmup, tagb), mode=mode, max_reqs=maxreq)
-        sec, _ = run_checked(sess, ops(variant, k, tagb), mode=mode, max_reqs=maxreq)
+        sess.reset_stats()
+        # median of three timings for the fast variants
+        reps = 3 if variant in ("persistent", "grouped") else 1
+        secs = sorted(run_checked(sess, ops(variant, k, tagb), mode=mode, max_reqs=maxreq)[0]
+                      for _ in range(reps))
+        sec = secs[len(secs) // 2]
+        st = sess.stats()
+        log(f"[batch] {variant}: host waits {st.host_waits}, sleeps {st.host_sleeps}, "
+            f"sleep timeouts {st.host_sleep_timeouts} over {reps * k} batches")
+        if variant == "persistent":
+            bk = time_batch_kernel(sess, 20)
         sess.close()
         res[variant] = npairs * k / sec
         log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.3f} ms per batch)")
@@ -552,6 +677,16 @@ def bench_batch(args):
                         "one_shot_group_speedup": res["grouped"] / res["host"] if "host" in res else None,
                         "plain_speedup": res["plain"] / res["host"] if "host" in res else None},
     }
+    bk_us, bk_payload, bk_wg = bk
+    per_launch = 2 * bk_payload
+    ach = per_launch / (bk_us * 1e-6) / 1e9
+    line["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("batch_10000"),
+                        "kernel": f"mpixs::k_batch<{sched['tile']}>",
+                        "bytes_per_launch": per_launch, "avg_launch_us": bk_us,
+                        "launches_timed": 20, "workgroups": bk_wg,
+                        "note": "batch kernel of the whole 10,000-message group, launched back "
+                                "to back between one event pair"}
     if tuned:
         line["autotune"] = tuned
     if not args.no_cpu_baseline:
@@ -755,6 +890,9 @@ def main():
     ap.add_argument("--pairs", type=int, default=10000)
     ap.add_argument("--only-grouped", action="store_true",
                     help="batch: persistent and one-shot group variants only")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="halo / batch: plan the persistent batch and time its kernel only "
+                         "(no device waits: for counter runs)")
     ap.add_argument("--tune", action="store_true",
                     help="batch: pick the persistent batch schedule by a grid search first")
     ap.add_argument("--batch-tile", type=int, default=1024)

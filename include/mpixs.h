@@ -370,6 +370,8 @@ typedef struct {
     double copy_ms;             /* profile=1: sum of their event durations */
     uint64_t timed_reduce;
     double reduce_ms;
+    uint64_t host_sleeps;       /* host waits that went to sleep (futex) at least once */
+    uint64_t host_sleep_timeouts; /* sleeps that ended by their 1 ms bound, not a wake-up */
 } mpixs_stats;
 
 /* Counters of the world since creation (or the last reset).  With

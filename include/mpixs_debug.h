@@ -1,7 +1,8 @@
 /*
  * mpixs_debug.h -- host-side introspection of libmpixs for tests.
  *
- * Not part of the enqueue interface; nothing here touches the GPU.
+ * Not part of the enqueue interface: plan introspection (no GPU work) and
+ * kernel timing for benchmarks.
  */
 #ifndef MPIXS_DEBUG_H
 #define MPIXS_DEBUG_H
@@ -38,6 +39,19 @@ int mpixs_debug_copy_plan(uint64_t sbuf, int scount, mpixs_datatype stype, uint6
 int mpixs_debug_time_copy(void *hip_stream, const void *sbuf, int scount, mpixs_datatype stype,
                           void *rbuf, int rcount, mpixs_datatype rtype, int reps, double *avg_us,
                           int *unit_bytes);
+
+/* Time the batch kernel of a persistent batch at its real shape: launch it
+ * `reps` times back to back (after one untimed launch) on the HIP stream
+ * `hip_stream` between one pair of HIP events, without the waits and the
+ * signal of a run, wait for the stream, and store the average per launch in
+ * *avg_us, the group's payload bytes (sum over its messages) in
+ * *payload_bytes and the launch's workgroups in *workgroups (either may be
+ * NULL).  Each launch performs every copy of the group again, so the
+ * buffers hold the same bytes afterwards.  No run of the batch may be in
+ * flight.  MPIXS_ERR_REQUEST for a NULL handle, MPIXS_ERR_ARG for reps < 1
+ * or avg_us NULL. */
+int mpixs_debug_time_batch(mpixs_batch batch, void *hip_stream, int reps, double *avg_us,
+                           int64_t *payload_bytes, int *workgroups);
 
 #ifdef __cplusplus
 }

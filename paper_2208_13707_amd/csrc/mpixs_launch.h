@@ -12,6 +12,10 @@ hipError_t launch_signal(hipStream_t s, const SignalArgs &a);
 hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg, bool fused);
 hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg,
                          bool fused);
+// large reductions over 8, 16, 32 or 64 ranks with 16-byte aligned buffers
+bool reduce_fixed_ok(int n);
+int reduce_fixed_units();            // vectors per lane of launch_reduce_fixed
+hipError_t launch_reduce_fixed(hipStream_t s, const ReduceArgs &a, int basic, int op, int nwg);
 hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg);
 bool batch_tile_ok(uint32_t tile);   // a tile size the batch kernel is built for
 hipError_t launch_post_inc(hipStream_t s, uint64_t *p);

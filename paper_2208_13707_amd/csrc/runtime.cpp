@@ -34,6 +34,7 @@
 #include <sys/syscall.h>
 #include <unistd.h>
 
+#include <cerrno>
 #include <climits>
 
 #include <algorithm>
@@ -126,6 +127,7 @@ int host_wait(World *w, const void *key, Pred pred) {
     }
     WakeSlot &s = wake_slot(key);
     const auto limit = std::chrono::milliseconds(w->cfg.timeout_ms);
+    w->host_sleeps.fetch_add(1, std::memory_order_relaxed);
     for (;;) {
         const uint32_t seq = s.seq.load(std::memory_order_seq_cst);
         if (pred()) return MPIXS_SUCCESS;
@@ -136,8 +138,10 @@ int host_wait(World *w, const void *key, Pred pred) {
         }
         s.sleepers.fetch_add(1, std::memory_order_seq_cst);
         struct timespec ts = {0, 1000000};
-        syscall(SYS_futex, reinterpret_cast<uint32_t *>(&s.seq), FUTEX_WAIT_PRIVATE, seq, &ts,
-                nullptr, 0);
+        const long r = syscall(SYS_futex, reinterpret_cast<uint32_t *>(&s.seq), FUTEX_WAIT_PRIVATE,
+                               seq, &ts, nullptr, 0);
+        if (r != 0 && errno == ETIMEDOUT)
+            w->host_sleep_timeouts.fetch_add(1, std::memory_order_relaxed);
         s.sleepers.fetch_sub(1, std::memory_order_seq_cst);
     }
 }
@@ -710,9 +714,12 @@ int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64
             rc = do_wait(w, on, wa);
             if (rc) return rc;
         }
-        const uint64_t nwg = std::min<uint64_t>(nchunks, uint64_t(1) << 22);
+        const bool fixed = vec && reduce_fixed_ok(n);
+        const uint64_t per_wg = fixed ? uint64_t(reduce_fixed_units()) : 1;
+        const uint64_t nwg = std::min<uint64_t>((nchunks + per_wg - 1) / per_wg, uint64_t(1) << 22);
         if (profile_on(w)) prof_begin(w, on->hs, &e0);
-        rc = gpu_err(launch_reduce(on->hs, a, rec->dtype, rec->op, vec, int(nwg), false));
+        rc = gpu_err(fixed ? launch_reduce_fixed(on->hs, a, rec->dtype, rec->op, int(nwg))
+                           : launch_reduce(on->hs, a, rec->dtype, rec->op, vec, int(nwg), false));
         if (profile_on(w)) prof_end(w, on->hs, e0, 1);
         if (rc) return rc;
         if (done_ptr) {
@@ -858,6 +865,7 @@ int plan_group(World *w, GroupRec *rec, int n, std::vector<BatchDesc> &descs,
         }
     }
     std::memset(&a, 0, sizeof(a));
+    a.tile = tile;
     starts.clear();
     if (descs.empty()) return MPIXS_SUCCESS;
     const uint64_t nwg = std::min<uint64_t>(total_tiles, uint64_t(w->cfg.batch_max_wg));
@@ -957,7 +965,9 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     int rc = plan_group(w, rec, n, descs, starts, P->args, &P->bytes);
     if (rc) return rc;
     P->nmsg = descs.size();
-    P->nwg = int(starts.size());
+    // an empty group still runs one workgroup, which publishes the run
+    P->nwg = std::max(1, int(starts.size()));
+    // counters: arrive[q] at word 16q, done at 16n
     const size_t cbytes = size_t(n + 1) * 16 * sizeof(uint64_t);
     const size_t dbytes = (descs.size() * sizeof(BatchDesc) + 255) & ~size_t(255);
     const size_t sbytes = starts.size() * sizeof(BatchStart);
@@ -981,6 +991,10 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     P->lwait.delta = 1;
     P->lwait.ctl = ctl_of(w);
     P->lwait.me = st->dev;
+    // done + 1 after the batch kernel: the kernel boundary makes its stores
+    // visible, so one release store publishes the run (a release in every
+    // workgroup instead costs an L2 writeback each and was measured several
+    // times slower)
     std::memset(&P->sig, 0, sizeof(P->sig));
     P->sig.done_ptr = P->d_ctr + 16 * n;
     P->sig.inc = 1;
@@ -1605,7 +1619,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
                 rc = gpu_err(hipGraphLaunch(P->exec, st->hs));
             } else {
                 if (P->n > 1) rc = gpu_err(launch_wait_rel(st->hs, P->lwait));
-                if (!rc && P->nwg > 0) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
+                if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
                 if (!rc) rc = gpu_err(launch_signal(st->hs, P->sig));
             }
         }
@@ -1616,7 +1630,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
         P->launched.store(e, std::memory_order_release);
         host_notify(&P->launched);
         if (!rc) {
-            w->n_copy.fetch_add(P->nwg > 0 ? 1 : 0, std::memory_order_relaxed);
+            w->n_copy.fetch_add(P->nmsg > 0 ? 1 : 0, std::memory_order_relaxed);
             w->bytes_copied.fetch_add(P->bytes, std::memory_order_relaxed);
         }
     } else {
@@ -1804,6 +1818,8 @@ int mpixs_world_get_stats(mpixs_world w, mpixs_stats *s) {
     s->bytes_copied = w->bytes_copied.load();
     s->bytes_reduced = w->bytes_reduced.load();
     s->host_waits = w->host_waits.load();
+    s->host_sleeps = w->host_sleeps.load();
+    s->host_sleep_timeouts = w->host_sleep_timeouts.load();
     s->timed_copy = w->timed_copy;
     s->copy_ms = w->copy_ms;
     s->timed_reduce = w->timed_reduce;
@@ -1817,6 +1833,8 @@ int mpixs_world_reset_stats(mpixs_world w) {
     mpixs_world_get_stats(w, &tmp);
     w->n_post = 0;
     w->n_wait = 0;
+    w->host_sleeps = 0;
+    w->host_sleep_timeouts = 0;
     w->n_copy = 0;
     w->n_reduce = 0;
     w->bytes_copied = 0;
@@ -1947,6 +1965,33 @@ int mpixs_debug_time_copy(void *hip_stream, const void *sbuf, int scount, mpixs_
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(hs);
     (void)hipFree(scratch);
+    return rc;
+}
+
+int mpixs_debug_time_batch(mpixs_batch b, void *hip_stream, int reps, double *avg_us,
+                           int64_t *payload_bytes, int *workgroups) {
+    if (!b || !b->p) return MPIXS_ERR_REQUEST;
+    if (reps < 1 || !avg_us) return MPIXS_ERR_ARG;
+    BatchPlan *P = b->p;
+    if (payload_bytes) *payload_bytes = int64_t(P->bytes);
+    if (workgroups) *workgroups = P->nwg;
+    *avg_us = 0;
+    const BatchArgs a = P->args;
+    hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = MPIXS_SUCCESS;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MPIXS_ERR_GPU;
+    if (!rc) rc = gpu_err(launch_batch(hs, a, P->nwg));   // warm
+    if (!rc && hipEventRecord(e0, hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    for (int i = 0; i < reps && !rc; ++i) rc = gpu_err(launch_batch(hs, a, P->nwg));
+    if (!rc && hipEventRecord(e1, hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    if (!rc && hipStreamSynchronize(hs) != hipSuccess) rc = MPIXS_ERR_GPU;
+    float ms_total = 0;
+    if (!rc && hipEventElapsedTime(&ms_total, e0, e1) != hipSuccess) rc = MPIXS_ERR_GPU;
+    if (!rc) *avg_us = 1000.0 * double(ms_total) / reps;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(hs);
     return rc;
 }
 

@@ -151,7 +151,7 @@ struct BatchPlan {
     uint64_t *d_ctr = nullptr;
     BatchArgs args{};
     RelWaitArgs lwait{};                // leader: every other rank arrived for this run
-    SignalArgs sig{};                   // leader: done + 1
+    SignalArgs sig{};                   // leader, after the batch kernel: done + 1
     int nwg = 0;
     uint64_t nmsg = 0, bytes = 0;
     hipGraph_t graph = nullptr;
@@ -268,6 +268,7 @@ struct World {
     // statistics
     std::atomic<uint64_t> n_post{0}, n_wait{0}, n_copy{0}, n_reduce{0};
     std::atomic<uint64_t> bytes_copied{0}, bytes_reduced{0}, host_waits{0};
+    std::atomic<uint64_t> host_sleeps{0}, host_sleep_timeouts{0};
     // host-pinned (coherent) ring of batch descriptor tables; an entry is
     // recycled once the batch's signal kernel has set its flag
     struct ArenaUse {

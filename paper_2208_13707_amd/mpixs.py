@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("bytes_copied", ctypes.c_uint64), ("bytes_reduced", ctypes.c_uint64),
                 ("host_waits", ctypes.c_uint64), ("timed_copy", ctypes.c_uint64),
                 ("copy_ms", ctypes.c_double), ("timed_reduce", ctypes.c_uint64),
-                ("reduce_ms", ctypes.c_double)]
+                ("reduce_ms", ctypes.c_double), ("host_sleeps", ctypes.c_uint64),
+                ("host_sleep_timeouts", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p

@@ -44,8 +44,9 @@ def ctypes_copy(src: M.Config, dst: M.Config) -> None:
 
 def time_schedule(nranks: int, cfg: M.Config, init_ops: Callable[[], list],
                   start_ops: Callable[[int], list], runs: int, warm: int,
-                  max_reqs: int) -> float:
-    """Seconds per run of the batch under ``cfg`` (init and warm-up excluded)."""
+                  max_reqs: int, repeats: int = 3) -> float:
+    """Seconds per run of the batch under ``cfg`` (init and warm-up excluded):
+    the median of ``repeats`` timings of ``runs`` back-to-back runs."""
     sess = D.Session(nranks, cfg)
     try:
         for ops in (init_ops(), start_ops(warm)):
@@ -53,10 +54,13 @@ def time_schedule(nranks: int, cfg: M.Config, init_ops: Callable[[], list],
             if rc:
                 raise RuntimeError(f"tuning run failed: {M.errname(rc)} at thread "
                                    f"{res.error_thread} op {res.error_op}")
-        rc, res, _ = sess.run(start_ops(runs), max_reqs=max_reqs)
-        if rc:
-            raise RuntimeError(f"tuning run failed: {M.errname(rc)}")
-        return res.seconds / runs
+        times = []
+        for _ in range(repeats):
+            rc, res, _ = sess.run(start_ops(runs), max_reqs=max_reqs)
+            if rc:
+                raise RuntimeError(f"tuning run failed: {M.errname(rc)}")
+            times.append(res.seconds / runs)
+        return sorted(times)[len(times) // 2]
     finally:
         sess.close()
 

@@ -99,6 +99,16 @@ def test_allreduce_other_ops(op, dtype):
     check(C.allreduce(12345 * 8, dtype, nranks=5, calls=1, op=op))
 
 
+@pytest.mark.parametrize("nranks,dtype,op", [(8, "float32", "sum"), (32, "int64", "max"),
+                                             (64, "int32", "sum"), (16, "float64", "prod")])
+def test_allreduce_fixed_rank_count_kernels(nranks, dtype, op):
+    """Split-path reductions over 8/16/32/64 ranks use the kernels unrolled
+    over the rank count; odd element counts exercise the vector tail."""
+    es = {"int32": 4, "int64": 8, "float32": 4, "float64": 8}[dtype]
+    count = (4 << 20) // (es * nranks) * 2 + 3
+    check(C.allreduce(count * es, dtype, nranks=nranks, calls=2, op=op))
+
+
 def test_allreduce_in_place_and_ragged():
     check(C.allreduce(4 * 1001, "float32", nranks=7, calls=3, in_place=True))
     check(C.allreduce(8 * 3, "int64", nranks=3, calls=1))
