@@ -127,6 +127,22 @@ def halo_persistent_ops(D, r, n, A, H, vt, steps, init=False, marks=False):
     return D.ops_array(rows)
 
 
+def batch_nt_used(flag, payload):
+    """Whether the batch kernel uses nontemporal accesses (the library's rule
+    for mpixs_config.batch_nontemporal)."""
+    return flag == 1 or (flag == 0 and payload >= 64 << 20)
+
+
+def halo_batch_cfg(M, args):
+    """World configuration of the persistent halo (batch schedule flags)."""
+    c = M.Config()
+    c.batch_tile = args.batch_tile
+    c.batch_max_wg = args.batch_max_wg
+    c.batch_graph = args.batch_graph
+    c.batch_nontemporal = args.batch_nt
+    return c
+
+
 def time_batch_kernel(sess, reps):
     """Average duration of a persistent batch's kernel (slot 0 of rank 0's
     handles), launched back to back between one pair of HIP events."""
@@ -237,7 +253,7 @@ def bench_halo(args):
         H = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
         vt = make_vector(M, args.count, 3, 8, M.FLOAT32)
         torch.cuda.synchronize()
-        sess = D.Session(n)
+        sess = D.Session(n, halo_batch_cfg(M, args))
         run_checked(sess, [halo_persistent_ops(D, r, n, A[r], H[r], vt, 0, init=True)
                            for r in range(n)])
         us, payload, nwg = time_batch_kernel(sess, steps)
@@ -296,7 +312,7 @@ def bench_halo(args):
         # ---- persistent: one step recorded once, started every step
         Hp = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
         torch.cuda.synchronize()
-        sess = D.Session(n)
+        sess = D.Session(n, halo_batch_cfg(M, args))
         run_checked(sess, [halo_persistent_ops(D, r, n, A[r], Hp[r], vt, 0, init=True)
                            for r in range(n)])
         run_checked(sess, [halo_persistent_ops(D, r, n, A[r], Hp[r], vt, warm) for r in range(n)])
@@ -368,7 +384,9 @@ def bench_halo(args):
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS,
                 "traffic": measured_traffic(f"halo_batch_count{h['count']}"),
-                "kernel": "mpixs::k_batch<1024>", "bytes_per_launch": per_launch,
+                "kernel": f"mpixs::k_batch<{args.batch_tile}, "
+                          f"{'true' if batch_nt_used(args.batch_nt, bk['payload_bytes']) else 'false'}>",
+                "bytes_per_launch": per_launch,
                 "avg_launch_us": bk["avg_launch_us"], "launches_timed": max(20, steps),
                 "workgroups": bk["workgroups"],
                 "note": "batch kernel of one halo step (16 messages), launched back to back "
@@ -606,7 +624,8 @@ def bench_batch(args):
     if args.kernel_only:
         # counter runs: plan the batch (no GPU waits) and launch its kernel only
         from paper_2208_13707_amd import tune
-        sess = D.Session(n, tune.config_for(sched["tile"], sched["max_wg"], sched["graph"]))
+        sess = D.Session(n, tune.config_for(sched["tile"], sched["max_wg"], sched["graph"],
+                                   nontemporal=args.batch_nt))
         run_checked(sess, ops("persistent", 0), max_reqs=maxreq)
         us, payload, nwg = time_batch_kernel(sess, args.steps)
         sess.close()
@@ -632,7 +651,8 @@ def bench_batch(args):
         cfg = None
         if variant == "persistent":
             from paper_2208_13707_amd import tune
-            cfg = tune.config_for(sched["tile"], sched["max_wg"], sched["graph"])
+            cfg = tune.config_for(sched["tile"], sched["max_wg"], sched["graph"],
+                                   nontemporal=args.batch_nt)
         sess = D.Session(n, cfg)
         if variant == "persistent":
             init_ms = 1000 * run_checked(sess, ops(variant, 0, tagb), max_reqs=maxreq)[0]
@@ -682,7 +702,8 @@ def bench_batch(args):
     ach = per_launch / (bk_us * 1e-6) / 1e9
     line["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("batch_10000"),
-                        "kernel": f"mpixs::k_batch<{sched['tile']}>",
+                        "kernel": f"mpixs::k_batch<{sched['tile']}, "
+                                  f"{'true' if batch_nt_used(args.batch_nt, bk_payload) else 'false'}>",
                         "bytes_per_launch": per_launch, "avg_launch_us": bk_us,
                         "launches_timed": 20, "workgroups": bk_wg,
                         "note": "batch kernel of the whole 10,000-message group, launched back "
@@ -895,9 +916,11 @@ def main():
                          "(no device waits: for counter runs)")
     ap.add_argument("--tune", action="store_true",
                     help="batch: pick the persistent batch schedule by a grid search first")
-    ap.add_argument("--batch-tile", type=int, default=1024)
-    ap.add_argument("--batch-max-wg", type=int, default=4096)
+    ap.add_argument("--batch-tile", type=int, default=256)
+    ap.add_argument("--batch-max-wg", type=int, default=16384)
     ap.add_argument("--batch-graph", type=int, default=0)
+    ap.add_argument("--batch-nt", type=int, default=0,
+                    help="batch kernel nontemporal accesses: 0 auto, 1 on, 2 off")
     ap.add_argument("--ranks-batch", type=int, default=32)
     ap.add_argument("--count", type=int, default=43690)
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")

@@ -130,13 +130,15 @@ typedef struct {
     int32_t profile;          /* 1: time copy and reduce kernels with HIP events */
     int32_t max_collectives;  /* device collective-slot capacity [4096] */
     int32_t batch_arena_mib;  /* host-pinned memory for batch descriptors, MiB [64] */
-    int32_t batch_tile;       /* units per tile of the batch kernel: 256, 512, 1024, 2048
-                                 or 4096 [1024]; other values: MPIXS_ERR_ARG */
-    int32_t batch_max_wg;     /* workgroups of one batch kernel, at most [4096] */
+    int32_t batch_tile;       /* tile of the batch kernel in 16-byte units: 256, 512, 1024,
+                                 2048 or 4096 [256]; other values: MPIXS_ERR_ARG */
+    int32_t batch_max_wg;     /* workgroups of one batch kernel, at most [16384] */
     int32_t batch_graph;      /* persistent batches: 1 replays the launching rank's part
                                  of a run (wait, batch kernel, signal) as one HIP graph,
                                  0 launches the three kernels one by one [0] */
-    int32_t reserved[5];
+    int32_t batch_nontemporal; /* batch kernel loads and stores: 0 nontemporal for groups
+                                 of at least 64 MiB of payload, 1 always, 2 never [0] */
+    int32_t reserved[4];
 } mpixs_config;
 
 /* -------------------------------------------------------------- world (N ranks)

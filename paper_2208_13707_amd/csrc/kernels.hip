@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_n(ReduceArgs a) {
 // descriptor is read from host-pinned memory into LDS when the workgroup
 // reaches it.  A tile is up to BATCH_TILE units of one message; the unit
 // size and map kinds of that message select the copy loop.
-template <int TILE, int W, int SK, int DK>
+template <int TILE, bool NT, int W, int SK, int DK>
 __device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     using T = typename Unit<W>::T;
     constexpr int U = TILE / COPY_THREADS;
@@ -414,35 +414,36 @@ __device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint6
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const uint64_t u = c0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
-            if (u < u1) v[k] = ld_unit<T, false>(map_addr<SK, W>(d.src, u));
+            if (u < u1) v[k] = ld_unit<T, NT>(map_addr<SK, W>(d.src, u));
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const uint64_t u = c0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
-            if (u < u1) st_unit<T, false>(map_addr<DK, W>(d.dst, u), v[k]);
+            if (u < u1) st_unit<T, NT>(map_addr<DK, W>(d.dst, u), v[k]);
         }
     }
 }
 
-template <int TILE, int W, int SK>
+template <int TILE, bool NT, int W, int SK>
 __device__ __forceinline__ void tile_copy_dk(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     switch (d.dst.kind) {
-    case MAP_CONTIG: tile_copy<TILE, W, SK, MAP_CONTIG>(d, u0, u1); break;
-    case MAP_VEC: tile_copy<TILE, W, SK, MAP_VEC>(d, u0, u1); break;
-    default: tile_copy<TILE, W, SK, MAP_SEG>(d, u0, u1); break;
+    case MAP_CONTIG: tile_copy<TILE, NT, W, SK, MAP_CONTIG>(d, u0, u1); break;
+    case MAP_VEC: tile_copy<TILE, NT, W, SK, MAP_VEC>(d, u0, u1); break;
+    default: tile_copy<TILE, NT, W, SK, MAP_SEG>(d, u0, u1); break;
     }
 }
 
-template <int TILE, int W>
+template <int TILE, bool NT, int W>
 __device__ __forceinline__ void tile_copy_w(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     switch (d.src.kind) {
-    case MAP_CONTIG: tile_copy_dk<TILE, W, MAP_CONTIG>(d, u0, u1); break;
-    case MAP_VEC: tile_copy_dk<TILE, W, MAP_VEC>(d, u0, u1); break;
-    default: tile_copy_dk<TILE, W, MAP_SEG>(d, u0, u1); break;
+    case MAP_CONTIG: tile_copy_dk<TILE, NT, W, MAP_CONTIG>(d, u0, u1); break;
+    case MAP_VEC: tile_copy_dk<TILE, NT, W, MAP_VEC>(d, u0, u1); break;
+    default: tile_copy_dk<TILE, NT, W, MAP_SEG>(d, u0, u1); break;
     }
 }
 
-template <int TILE>
+// NT: nontemporal loads and stores (groups much larger than the caches)
+template <int TILE, bool NT>
 __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
     __shared__ BatchDesc sd;
     __shared__ uint32_t s_fatal;
@@ -481,11 +482,11 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
             }
             if (u0 < u1) {
                 switch (sd.w) {
-                case 16: tile_copy_w<TILE, 16>(sd, u0, u1); break;
-                case 8: tile_copy_w<TILE, 8>(sd, u0, u1); break;
-                case 4: tile_copy_w<TILE, 4>(sd, u0, u1); break;
-                case 2: tile_copy_w<TILE, 2>(sd, u0, u1); break;
-                default: tile_copy_w<TILE, 1>(sd, u0, u1); break;
+                case 16: tile_copy_w<TILE, NT, 16>(sd, u0, u1); break;
+                case 8: tile_copy_w<TILE, NT, 8>(sd, u0, u1); break;
+                case 4: tile_copy_w<TILE, NT, 4>(sd, u0, u1); break;
+                case 2: tile_copy_w<TILE, NT, 2>(sd, u0, u1); break;
+                default: tile_copy_w<TILE, NT, 1>(sd, u0, u1); break;
                 }
             }
         }
@@ -499,29 +500,39 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
 }
 
 // ------------------------------------------------------------- launchers
-static const void *batch_kernel(uint32_t tile) {
+template <bool NT>
+static const void *batch_kernel_nt(uint32_t tile) {
     switch (tile) {
-    case 256: return reinterpret_cast<const void *>(&k_batch<256>);
-    case 512: return reinterpret_cast<const void *>(&k_batch<512>);
-    case 1024: return reinterpret_cast<const void *>(&k_batch<1024>);
-    case 2048: return reinterpret_cast<const void *>(&k_batch<2048>);
-    case 4096: return reinterpret_cast<const void *>(&k_batch<4096>);
+    case 256: return reinterpret_cast<const void *>(&k_batch<256, NT>);
+    case 512: return reinterpret_cast<const void *>(&k_batch<512, NT>);
+    case 1024: return reinterpret_cast<const void *>(&k_batch<1024, NT>);
+    case 2048: return reinterpret_cast<const void *>(&k_batch<2048, NT>);
+    case 4096: return reinterpret_cast<const void *>(&k_batch<4096, NT>);
     default: return nullptr;
     }
 }
 
-bool batch_tile_ok(uint32_t tile) { return batch_kernel(tile) != nullptr; }
+static const void *batch_kernel(uint32_t tile, bool nt) {
+    return nt ? batch_kernel_nt<true>(tile) : batch_kernel_nt<false>(tile);
+}
 
-hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg) {
+bool batch_tile_ok(uint32_t tile) { return batch_kernel(tile, false) != nullptr; }
+
+template <bool NT>
+static hipError_t launch_batch_nt(hipStream_t s, const BatchArgs &a, int nwg) {
     switch (a.tile) {
-    case 256: hipLaunchKernelGGL(k_batch<256>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
-    case 512: hipLaunchKernelGGL(k_batch<512>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
-    case 1024: hipLaunchKernelGGL(k_batch<1024>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
-    case 2048: hipLaunchKernelGGL(k_batch<2048>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
-    case 4096: hipLaunchKernelGGL(k_batch<4096>, dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_batch<256, NT>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 512: hipLaunchKernelGGL((k_batch<512, NT>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 1024: hipLaunchKernelGGL((k_batch<1024, NT>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 2048: hipLaunchKernelGGL((k_batch<2048, NT>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
+    case 4096: hipLaunchKernelGGL((k_batch<4096, NT>), dim3(nwg), dim3(COPY_THREADS), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg) {
+    return a.nt ? launch_batch_nt<true>(s, a, nwg) : launch_batch_nt<false>(s, a, nwg);
 }
 
 hipError_t launch_post_inc(hipStream_t s, uint64_t *p) {
@@ -559,7 +570,7 @@ hipError_t build_batch_graph(hipGraph_t *out, const RelWaitArgs *w, const BatchA
     BatchArgs ba = a;
     void *args[] = {&ba};
     std::memset(&p, 0, sizeof(p));
-    p.func = const_cast<void *>(batch_kernel(a.tile));
+    p.func = const_cast<void *>(batch_kernel(a.tile, a.nt != 0));
     if (!p.func || nwg < 1) { (void)hipGraphDestroy(g); return hipErrorInvalidValue; }
     p.gridDim = dim3(unsigned(nwg));
     p.blockDim = dim3(COPY_THREADS);

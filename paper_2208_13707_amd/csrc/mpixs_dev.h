@@ -206,7 +206,7 @@ struct RelWaitArgs {
 // message dense on both sides may end in a byte tail of fewer than w bytes,
 // copied with its last tile.  The workgroup that runs a message's tile 0
 // also writes the message's receive status.
-constexpr uint32_t BATCH_TILE_DEFAULT = 1024;
+constexpr uint32_t BATCH_TILE_DEFAULT = 256;
 constexpr uint32_t BATCH_TILE_MIN = 256;
 constexpr uint32_t BATCH_TILE_MAX = 4096;
 
@@ -239,7 +239,7 @@ struct BatchArgs {
     uint64_t base;          // tiles per workgroup
     DevStream *me;
     uint32_t tile;          // units per tile
-    uint32_t pad;
+    uint32_t nt;            // nonzero: nontemporal loads and stores
 };
 
 enum RedOp : int32_t { OP_SUM = 1, OP_PROD = 2, OP_MIN = 3, OP_MAX = 4 };

@@ -887,6 +887,8 @@ int plan_group(World *w, GroupRec *rec, int n, std::vector<BatchDesc> &descs,
     a.base = base;
     a.extra = uint32_t(extra);
     a.tile = tile;
+    const int ntc = w->cfg.batch_nontemporal;
+    a.nt = (ntc == 1 || (ntc == 0 && *bytes >= (uint64_t(64) << 20))) ? 1u : 0u;
     return MPIXS_SUCCESS;
 }
 
@@ -1081,9 +1083,10 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     if (c.max_channels <= 0) c.max_channels = 1 << 20;
     if (c.max_collectives <= 0) c.max_collectives = 4096;
     if (c.batch_tile == 0) c.batch_tile = int32_t(BATCH_TILE_DEFAULT);
-    if (c.batch_max_wg <= 0) c.batch_max_wg = 4096;
+    if (c.batch_max_wg <= 0) c.batch_max_wg = 16384;
     if (!batch_tile_ok(uint32_t(c.batch_tile)) || c.batch_max_wg > (1 << 20) ||
-        c.batch_graph < 0 || c.batch_graph > 1) {
+        c.batch_graph < 0 || c.batch_graph > 1 || c.batch_nontemporal < 0 ||
+        c.batch_nontemporal > 2) {
         delete w;
         return MPIXS_ERR_ARG;
     }

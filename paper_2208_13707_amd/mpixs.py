@@ -41,7 +41,8 @@ class Config(ctypes.Structure):
                 ("max_channels", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("max_collectives", ctypes.c_int32), ("batch_arena_mib", ctypes.c_int32),
                 ("batch_tile", ctypes.c_int32), ("batch_max_wg", ctypes.c_int32),
-                ("batch_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("batch_graph", ctypes.c_int32), ("batch_nontemporal", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Status(ctypes.Structure):

@@ -27,13 +27,15 @@ def schedules(tiles: Sequence[int] = TILES, max_wg: Sequence[int] = MAX_WG,
     return list(itertools.product(tiles, max_wg, graph))
 
 
-def config_for(tile: int, max_wg: int, graph: int, base: M.Config = None) -> M.Config:
+def config_for(tile: int, max_wg: int, graph: int, base: M.Config = None,
+               nontemporal: int = 0) -> M.Config:
     c = M.Config()
     if base is not None:
         ctypes_copy(base, c)
     c.batch_tile = tile
     c.batch_max_wg = max_wg
     c.batch_graph = graph
+    c.batch_nontemporal = nontemporal
     return c
 
 
