@@ -940,7 +940,7 @@ def main():
               "(ranks are host threads sharing one MI355X)", file=sys.stderr)
         sys.exit(2)
     defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
-                "vcopy": (100, 10), "batch": (5, 1), "serve": (1, 0)}
+                "vcopy": (100, 10), "batch": (20, 5), "serve": (1, 0)}
     k, w = defaults[args.workload]
     args.steps = args.steps or k
     args.warmup = args.warmup if args.warmup is not None else w
