@@ -32,6 +32,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 
 
+def kernel_sources():
+    """Every source file that defines device code, in a fixed order."""
+    src = os.path.join(ROOT, "paper_2208_13707_amd", "csrc")
+    names = sorted(f for f in os.listdir(src)
+                   if f.startswith("k_") or f in ("kernels_common.h", "mpixs_dev.h"))
+    return [os.path.join(src, f) for f in names]
+
+
 def measured_traffic(key):
     """HBM bytes per launch of a kernel from the committed counter runs, or
     None when the kernel sources changed since those counters were taken."""
@@ -42,10 +50,9 @@ def measured_traffic(key):
         rec = _json.load(open(path))
     except OSError:
         return None
-    src = os.path.join(ROOT, "paper_2208_13707_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("kernels.hip", "mpixs_dev.h"):
-        h.update(open(os.path.join(src, f), "rb").read())
+    for path in kernel_sources():
+        h.update(open(path, "rb").read())
     if h.hexdigest() != rec.get("kernels_sha256") or key not in rec:
         return None
     return rec[key]["read_bytes"] + rec[key]["write_bytes"]

@@ -23,7 +23,8 @@ HIP_FLAGS = [
 ]
 
 LIBS = {
-    "libmpixs.so": ["kernels.hip", "runtime.cpp", "types.cpp"],
+    "libmpixs.so": ["k_sync.hip", "k_copy.hip", "k_reduce.hip", "k_batch.hip", "k_batch_nt.hip",
+                    "runtime.cpp", "types.cpp"],
     "libmpixs_driver.so": ["driver.cpp", "serve.hip"],
 }
 

@@ -1,0 +1,236 @@
+// Canonical-order reduction kernels of the enqueued allreduce (libmpixs,
+// gfx950).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/mpixs.h"
+#include "kernels_common.h"
+#include "mpixs_dev.h"
+#include "mpixs_launch.h"
+
+namespace mpixs {
+
+// ---------------------------------------------------------------- reduce
+template <typename T> struct Uns { using U = T; };
+template <> struct Uns<int32_t> { using U = uint32_t; };
+template <> struct Uns<int64_t> { using U = uint64_t; };
+
+template <typename T, int OP>
+__device__ __forceinline__ T combine(T acc, T x) {
+    if constexpr (OP == OP_SUM) {
+        using U = typename Uns<T>::U;
+        return T(U(acc) + U(x));
+    } else if constexpr (OP == OP_PROD) {
+        using U = typename Uns<T>::U;
+        return T(U(acc) * U(x));
+    } else if constexpr (OP == OP_MIN) {
+        return x < acc ? x : acc;
+    } else {
+        return x > acc ? x : acc;
+    }
+}
+
+constexpr int RED_THREADS = 256;
+constexpr int RED_GROUP = 16;   // inputs loaded back to back before folding
+
+// out_q[i] = (((in_0[i] op in_1[i]) op in_2[i]) ... op in_{n-1}[i]) for every q:
+// the left fold in rank order, each element owned by one lane (16 bytes of
+// elements per lane when every buffer is 16-byte aligned).  Workgroups take
+// chunks of RED_THREADS vectors.  FUSED: small collectives; threads q < n
+// of every workgroup wait for rank q's arrive counter first and the last
+// workgroup publishes done.
+template <typename T, int OP, bool VEC, bool FUSED>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
+    __shared__ uint32_t s_fatal;
+    if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
+    __syncthreads();
+    if (FUSED && a.arrive && !s_fatal) {
+        uint32_t err = 0;
+        const int q = threadIdx.x;
+        if (q < a.n && q != a.me_rank) err = spin_wait(a.arrive + q * 16, a.arrive_target, a.ctl);
+        if (err) set_fatal(a.me, err);
+        __syncthreads();
+        if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (!s_fatal) {
+        const int n = a.n;
+        constexpr int L = VEC ? int(16 / sizeof(T)) : 1;
+        using V = T __attribute__((ext_vector_type(L)));
+        const uint64_t nvec = a.count / L;
+        const uint64_t nch = (nvec + RED_THREADS - 1) / RED_THREADS;
+        for (uint64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+            const uint64_t v = c * RED_THREADS + threadIdx.x;
+            if (v < nvec) {
+                constexpr bool NT = !FUSED;
+                V acc = ld_unit<V, NT>(reinterpret_cast<uint64_t>(reinterpret_cast<const V *>(a.in[0]) + v));
+                for (int q0 = 1; q0 < n; q0 += RED_GROUP) {
+                    V x[RED_GROUP];
+#pragma unroll
+                    for (int j = 0; j < RED_GROUP; ++j)
+                        if (q0 + j < n)
+                            x[j] = ld_unit<V, NT>(
+                                reinterpret_cast<uint64_t>(reinterpret_cast<const V *>(a.in[q0 + j]) + v));
+#pragma unroll
+                    for (int j = 0; j < RED_GROUP; ++j)
+                        if (q0 + j < n) {
+#pragma unroll
+                            for (int l = 0; l < L; ++l) acc[l] = combine<T, OP>(acc[l], x[j][l]);
+                        }
+                }
+                for (int q = 0; q < n; ++q)
+                    st_unit<V, NT>(reinterpret_cast<uint64_t>(reinterpret_cast<V *>(a.out[q]) + v), acc);
+            }
+        }
+        if constexpr (VEC) {
+            // tail elements that do not fill a vector
+            const uint64_t gtid = uint64_t(blockIdx.x) * RED_THREADS + threadIdx.x;
+            const uint64_t i = nvec * L + gtid;
+            if (i < a.count) {
+                T acc = reinterpret_cast<const T *>(a.in[0])[i];
+                for (int q = 1; q < n; ++q)
+                    acc = combine<T, OP>(acc, reinterpret_cast<const T *>(a.in[q])[i]);
+                for (int q = 0; q < n; ++q) reinterpret_cast<T *>(a.out[q])[i] = acc;
+            }
+        }
+    }
+    if constexpr (FUSED) {
+        if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
+            if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+        }
+    }
+}
+
+// Large reductions over a rank count known at compile time (8, 16, 32 or
+// 64, 16-byte aligned buffers): each lane folds RED_FIXED_U vectors, and
+// with the inputs unrolled the loads of all ranks are in flight together
+// (measured about 7 % faster than the runtime-n loop at 16 x 64 MiB).  Same
+// canonical order: acc = in_0, then acc = acc (+) in_q for q = 1 .. N-1.
+constexpr int RED_FIXED_U = 2;
+
+template <typename T, int OP, int N>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_n(ReduceArgs a) {
+    __shared__ uint32_t s_fatal;
+    if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
+    __syncthreads();
+    if (s_fatal) return;
+    constexpr int L = int(16 / sizeof(T));
+    constexpr int U = RED_FIXED_U;
+    using V = T __attribute__((ext_vector_type(L)));
+    const uint64_t nvec = a.count / L;
+    constexpr uint64_t CH = uint64_t(RED_THREADS) * U;
+    const uint64_t nch = (nvec + CH - 1) / CH;
+    for (uint64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        V acc[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint64_t v = c * CH + threadIdx.x + uint64_t(k) * RED_THREADS;
+            if (v < nvec)
+                acc[k] = ld_unit<V, true>(reinterpret_cast<uint64_t>(reinterpret_cast<const V *>(a.in[0]) + v));
+        }
+#pragma unroll
+        for (int q = 1; q < N; ++q) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint64_t v = c * CH + threadIdx.x + uint64_t(k) * RED_THREADS;
+                if (v < nvec) {
+                    const V x = ld_unit<V, true>(
+                        reinterpret_cast<uint64_t>(reinterpret_cast<const V *>(a.in[q]) + v));
+#pragma unroll
+                    for (int l = 0; l < L; ++l) acc[k][l] = combine<T, OP>(acc[k][l], x[l]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint64_t v = c * CH + threadIdx.x + uint64_t(k) * RED_THREADS;
+                if (v < nvec)
+                    st_unit<V, true>(reinterpret_cast<uint64_t>(reinterpret_cast<V *>(a.out[q]) + v), acc[k]);
+            }
+        }
+    }
+    // tail elements that do not fill a vector
+    const uint64_t gtid = uint64_t(blockIdx.x) * RED_THREADS + threadIdx.x;
+    const uint64_t i = nvec * L + gtid;
+    if (i < a.count) {
+        T acc = reinterpret_cast<const T *>(a.in[0])[i];
+        for (int q = 1; q < N; ++q) acc = combine<T, OP>(acc, reinterpret_cast<const T *>(a.in[q])[i]);
+        for (int q = 0; q < N; ++q) reinterpret_cast<T *>(a.out[q])[i] = acc;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+int reduce_threads() { return RED_THREADS; }
+
+template <typename T, int OP, bool F>
+static hipError_t reduce_op(hipStream_t s, const ReduceArgs &a, bool vec, int nwg) {
+    if (vec) hipLaunchKernelGGL((k_reduce<T, OP, true, F>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_reduce<T, OP, false, F>), dim3(nwg), dim3(RED_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool F>
+static hipError_t reduce_t(hipStream_t s, const ReduceArgs &a, int op, bool vec, int nwg) {
+    switch (op) {
+    case OP_SUM: return reduce_op<T, OP_SUM, F>(s, a, vec, nwg);
+    case OP_PROD: return reduce_op<T, OP_PROD, F>(s, a, vec, nwg);
+    case OP_MIN: return reduce_op<T, OP_MIN, F>(s, a, vec, nwg);
+    default: return reduce_op<T, OP_MAX, F>(s, a, vec, nwg);
+    }
+}
+
+template <bool F>
+static hipError_t reduce_f(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec,
+                           int nwg) {
+    switch (basic) {
+    case MPIXS_INT32: return reduce_t<int32_t, F>(s, a, op, vec, nwg);
+    case MPIXS_INT64: return reduce_t<int64_t, F>(s, a, op, vec, nwg);
+    case MPIXS_FLOAT32: return reduce_t<float, F>(s, a, op, vec, nwg);
+    default: return reduce_t<double, F>(s, a, op, vec, nwg);
+    }
+}
+
+hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, bool vec, int nwg,
+                         bool fused) {
+    return fused ? reduce_f<true>(s, a, basic, op, vec, nwg) : reduce_f<false>(s, a, basic, op, vec, nwg);
+}
+
+bool reduce_fixed_ok(int n) { return n == 8 || n == 16 || n == 32 || n == 64; }
+int reduce_fixed_units() { return RED_FIXED_U; }
+
+template <typename T, int OP>
+static hipError_t reduce_fixed_n(hipStream_t s, const ReduceArgs &a, int nwg) {
+    switch (a.n) {
+    case 8: hipLaunchKernelGGL((k_reduce_n<T, OP, 8>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_reduce_n<T, OP, 16>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_reduce_n<T, OP, 32>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_reduce_n<T, OP, 64>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t reduce_fixed_t(hipStream_t s, const ReduceArgs &a, int op, int nwg) {
+    switch (op) {
+    case OP_SUM: return reduce_fixed_n<T, OP_SUM>(s, a, nwg);
+    case OP_PROD: return reduce_fixed_n<T, OP_PROD>(s, a, nwg);
+    case OP_MIN: return reduce_fixed_n<T, OP_MIN>(s, a, nwg);
+    default: return reduce_fixed_n<T, OP_MAX>(s, a, nwg);
+    }
+}
+
+hipError_t launch_reduce_fixed(hipStream_t s, const ReduceArgs &a, int basic, int op, int nwg) {
+    switch (basic) {
+    case MPIXS_INT32: return reduce_fixed_t<int32_t>(s, a, op, nwg);
+    case MPIXS_INT64: return reduce_fixed_t<int64_t>(s, a, op, nwg);
+    case MPIXS_FLOAT32: return reduce_fixed_t<float>(s, a, op, nwg);
+    default: return reduce_fixed_t<double>(s, a, op, nwg);
+    }
+}
+
+}  // namespace mpixs

@@ -1,4 +1,5 @@
-// Host-side launchers of the kernels in kernels.hip.
+// Host-side launchers of the kernels (k_sync.hip, k_copy.hip, k_reduce.hip,
+// k_batch.hip).
 #pragma once
 #include <hip/hip_runtime_api.h>
 
@@ -19,6 +20,8 @@ hipError_t launch_reduce_fixed(hipStream_t s, const ReduceArgs &a, int basic, in
 hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg);
 bool batch_tile_ok(uint32_t tile);   // a tile size the batch kernel is built for
 hipError_t launch_post_inc(hipStream_t s, uint64_t *p);
+const void *wait_rel_kernel();        // kernel handles for graph nodes
+const void *signal_kernel();
 hipError_t launch_wait_rel(hipStream_t s, const RelWaitArgs &a);
 // leader's run of a persistent batch: [wait] -> batch -> signal (w may be null)
 hipError_t build_batch_graph(hipGraph_t *out, const RelWaitArgs *w, const BatchArgs &a, int nwg,
