@@ -54,8 +54,8 @@ enum {
     MPIXS_ERR_COUNT = 2,        /* negative count */
     MPIXS_ERR_TYPE = 3,         /* bad or uncommitted datatype; overlapping receive type;
                                    signature mismatch (asynchronous) */
-    MPIXS_ERR_RANK = 4,         /* peer rank out of range, or MPIXS_ANY_SOURCE */
-    MPIXS_ERR_TAG = 5,          /* negative tag, or MPIXS_ANY_TAG */
+    MPIXS_ERR_RANK = 4,         /* peer rank out of range, or a wildcard where none is allowed */
+    MPIXS_ERR_TAG = 5,          /* negative tag, or a wildcard where none is allowed */
     MPIXS_ERR_COMM = 6,         /* communicator has no local GPU stream (§3.4) */
     MPIXS_ERR_STREAM = 7,       /* waitall over requests of different streams (§3.4) */
     MPIXS_ERR_REQUEST = 8,      /* NULL or foreign request */
@@ -138,7 +138,11 @@ typedef struct {
                                  0 launches the three kernels one by one [0] */
     int32_t batch_nontemporal; /* batch kernel loads and stores: 0 nontemporal for groups
                                  of at least 64 MiB of payload, 1 always, 2 never [0] */
-    int32_t reserved[4];
+    int32_t matching;         /* point-to-point matching (§2.1): 0 sequence pairing per
+                                 (comm, source, destination, tag) channel, wildcards
+                                 rejected; 1 ordered queues per destination, receives may
+                                 use MPIXS_ANY_SOURCE / MPIXS_ANY_TAG [0] */
+    int32_t reserved[3];
 } mpixs_config;
 
 /* -------------------------------------------------------------- world (N ranks)
@@ -228,9 +232,24 @@ int mpixs_type_get_extent(mpixs_datatype type, int64_t *lb, int64_t *extent);
  * All take a stream communicator whose local stream is a GPU stream
  * (else MPIXS_ERR_COMM, §3.4).  Each returns once the operation is
  * registered; the operation runs on the stream after the operations enqueued
- * before it (§3.4).  Matching: the k-th send from rank s to rank d with tag
- * t on a communicator matches the k-th receive of rank d from s with tag t
- * on it (MPI's non-overtaking order without wildcards, §2.1).
+ * before it (§3.4).  Matching (§2.1), by mpixs_config.matching:
+ *  0 (default): the k-th send from rank s to rank d with tag t on a
+ *    communicator matches the k-th receive of rank d from s with tag t on it
+ *    (MPI's non-overtaking order without wildcards); wildcards are rejected
+ *    (MPIXS_ERR_RANK / MPIXS_ERR_TAG).
+ *  1: ordered queues per destination.  A send matches the earliest posted,
+ *    unmatched receive of its destination that accepts its (source, tag);
+ *    a receive -- source may be MPIXS_ANY_SOURCE, tag MPIXS_ANY_TAG --
+ *    matches the earliest enqueued, unmatched send to it that it accepts;
+ *    otherwise the operation waits in the queue.  "Earliest" is the order in
+ *    which the enqueue calls reach the library, so messages of one sender
+ *    never overtake each other; which of several senders a wildcard receive
+ *    meets depends on the threads' timing, as in MPI.  The status reports
+ *    the matched source, tag and count.  Each message takes one block of
+ *    the device matching table (cfg.max_channels in total; MPIXS_ERR_NOMEM
+ *    once exhausted).  Wildcards are not allowed inside groups, and the
+ *    host-synchronised calls (mpixs_send / mpixs_recv) return
+ *    MPIXS_ERR_COMM in this mode.
  *
  *  send_enqueue:  later work on the stream starts once buf may be reused
  *                 (the data has been copied into the matched receive buffer).
@@ -249,8 +268,7 @@ int mpixs_type_get_extent(mpixs_datatype type, int64_t *lb, int64_t *extent);
  * request whose peer has not arrived yet, allreduce of a rank that is not
  * the last to arrive), so that a device wait is never queued ahead of what
  * it waits for.  That host wait gives up after cfg.timeout_ms with
- * MPIXS_ERR_TIMEOUT.  Wildcards are not supported (MPIXS_ERR_RANK /
- * MPIXS_ERR_TAG).
+ * MPIXS_ERR_TIMEOUT.
  */
 int mpixs_send_enqueue(const void *buf, int count, mpixs_datatype datatype, int dest, int tag,
                        mpixs_comm comm);

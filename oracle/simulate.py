@@ -20,6 +20,16 @@ What it states, and where the paper fixes it:
   ranks reached it; its result is the canonical-order fold (see reduce.py).
 * Enqueue calls on a communicator without a local GPU stream are an error
   (§3.4).
+* Matching with wildcards (programs with matching = "queue"): MPI's rule
+  with posted and unexpected queues per destination -- a send meets the
+  earliest posted receive that accepts its (source, tag), a receive (source
+  may be ANY_SOURCE, tag ANY_TAG) meets the earliest unmatched send to it
+  that it accepts, else the operation waits in its queue.  "Earliest" is the
+  order in which the operations are issued; messages of one sender keep
+  their order.  When several senders compete for a wildcard receive the
+  result depends on that order (in MPI and on the GPU alike), so such
+  programs are compared by invariants, not byte for byte.  Wildcards are not
+  allowed inside groups.
 * Groups (a batching extension): between GroupStart and GroupEnd on a
   communicator a rank's sends and receives on it are posted but do not
   block and do not move data; GroupEnd is collective (instance k = the k-th
@@ -73,7 +83,8 @@ import numpy as np
 from . import reduce as red
 from . import typemap as tm
 from workloads.program import (
-    IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv, Send, Start, User, Wait,
+    ANY_SOURCE, ANY_TAG, IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv, Send,
+    Start, User, Wait,
 )
 
 SUCCESS = "SUCCESS"
@@ -100,6 +111,7 @@ class _RecvRec:
     done: bool = False
     status: Optional[Tuple[int, int, str, int]] = None
     group: Optional[Tuple[int, int]] = None
+    want: Tuple[int, int] = (0, 0)               # queue matching: (source, tag) accepted
 
 
 @dataclass
@@ -139,9 +151,10 @@ def _check_p2p(p: Program, rank: int, op) -> Optional[str]:
     except tm.TypeError_:
         return "ERR_TYPE"
     peer = op.dest if isinstance(op, Send) else op.source
-    if not (0 <= peer < p.nranks):
+    wild = isinstance(op, Recv) and p.matching == "queue"
+    if not (0 <= peer < p.nranks) and not (wild and peer == ANY_SOURCE):
         return "ERR_RANK"
-    if op.tag < 0:
+    if op.tag < 0 and not (wild and op.tag == ANY_TAG):
         return "ERR_TAG"
     if isinstance(op, Recv) and tm.overlaps(t, op.count):
         return "ERR_TYPE"
@@ -264,8 +277,11 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         return chans[key]
 
     def transfer(key, k):
-        s = chans[key].sends[k]
-        r = chans[key].recvs[k]
+        move(chans[key].sends[k], chans[key].recvs[k], key, k)
+
+    def move(s, r, key, k):
+        """Unpack send s into receive r (the receive checks of the module
+        docstring) and log the match."""
         if s.payload is None:
             buf, off, count, t = s.src
             s.payload = tm.pack(bufs[s.rank][buf], off, count, t)
@@ -282,6 +298,43 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         r.status = (s.rank, s.tag, err, written)
         s.done = r.done = True
         match_log.append((key[0], key[1], key[2], key[3], k))
+
+    queues: Dict[Tuple[int, int], Tuple[list, list]] = {}   # (comm, dst) -> (unexpected, posted)
+    qcount: Dict[Tuple[int, int, int, int], int] = {}
+
+    def queue_match(s, r, comm):
+        key = (comm, s.rank, r.rank, s.tag)
+        k = qcount.get(key, 0)
+        qcount[key] = k + 1
+        move(s, r, key, k)
+
+    def accepts(r, s):
+        src, tag = r.want
+        return src in (ANY_SOURCE, s.rank) and tag in (ANY_TAG, s.tag)
+
+    def post_send_q(rank, op: Send) -> _SendRec:
+        t = tm.build(op.dtype)
+        rec = _SendRec(rank, op.tag, t.basic, tm.pack(bufs[rank][op.buf], op.off, op.count, t))
+        unexpected, posted = queues.setdefault((op.comm, op.dest), ([], []))
+        for i, r in enumerate(posted):
+            if accepts(r, rec):
+                del posted[i]
+                queue_match(rec, r, op.comm)
+                return rec
+        unexpected.append(rec)
+        return rec
+
+    def post_recv_q(rank, op: Recv) -> _RecvRec:
+        t = tm.build(op.dtype)
+        rec = _RecvRec(rank, op.buf, op.off, op.count, t, want=(op.source, op.tag))
+        unexpected, posted = queues.setdefault((op.comm, rank), ([], []))
+        for i, s in enumerate(unexpected):
+            if accepts(rec, s):
+                del unexpected[i]
+                queue_match(s, rec, op.comm)
+                return rec
+        posted.append(rec)
+        return rec
 
     def post_send(rank, op: Send, group=None) -> _SendRec:
         t = tm.build(op.dtype)
@@ -401,6 +454,20 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
                 ctx.pc += 1
                 return True
             grp = group_open.get((rank, op.comm))
+            if grp is not None and isinstance(op, Recv) and (op.source == ANY_SOURCE
+                                                             or op.tag == ANY_TAG):
+                err = "ERR_RANK" if op.source == ANY_SOURCE else "ERR_TAG"
+                sync_errors[rank].append((ctx.thread, ctx.pc, err))
+                ctx.pc += 1
+                return True
+            if grp is None and p.matching == "queue":
+                rec = post_send_q(rank, op) if isinstance(op, Send) else post_recv_q(rank, op)
+                if op.req is not None:
+                    requests[rank][op.req] = (rec, p.stream_of(rank, op.comm))
+                    ctx.pc += 1
+                    return True
+                ctx.pending = ("one", rec)
+                return step(ctx)
             bname = persist_open.get((rank, op.comm))
             if bname is not None:
                 batch_ops.setdefault((rank, bname), []).append(op)

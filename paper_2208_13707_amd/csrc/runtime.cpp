@@ -403,6 +403,10 @@ Channel *get_channel(mpixs_comm_s *c, int src, int dst, int tag, bool host_mode)
 
 void rec_release(Channel *ch, Rec *r) {
     if (r->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+        if (ch->priv) {
+            delete ch;   // a one-message channel dies with its message
+            return;
+        }
         std::lock_guard<std::mutex> g(ch->mu);
         ch->collect();
     }
@@ -421,8 +425,10 @@ int check_p2p(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, in
     if (!c->stream || !c->stream->gpu) return MPIXS_ERR_COMM;
     if (count < 0) return MPIXS_ERR_COUNT;
     if (!type_ok(dt, t)) return MPIXS_ERR_TYPE;
-    if (peer < 0 || peer >= c->sh->size) return MPIXS_ERR_RANK;
-    if (tag < 0) return MPIXS_ERR_TAG;
+    const bool wild = recv && c->sh->w->cfg.matching == 1;
+    if (!(wild && peer == MPIXS_ANY_SOURCE) && (peer < 0 || peer >= c->sh->size))
+        return MPIXS_ERR_RANK;
+    if (!(wild && tag == MPIXS_ANY_TAG) && tag < 0) return MPIXS_ERR_TAG;
     if (recv && count > 0 && (*t)->L.overlap) return MPIXS_ERR_TYPE;
     const int64_t bytes = int64_t(count) * (*t)->L.size;
     if (bytes > 0 && !buf) return MPIXS_ERR_BUFFER;
@@ -448,6 +454,122 @@ int complete_first(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, i
     return rc;
 }
 
+// Ordered-queue matching (§2.1 with wildcards): a send meets the earliest
+// posted receive of its destination that accepts (source, tag); a receive
+// meets the earliest enqueued send that it accepts; otherwise the operation
+// waits in its destination's queue.  "Earliest" is host enqueue order, the
+// order in which the enqueue calls reach the library, which keeps MPI's
+// non-overtaking rule for each sender and makes a wildcard receive take the
+// first matching message enqueued.  Every message gets its own one-message
+// channel; the first of the pair posts ready on it and the second copies,
+// exactly as on a sequence channel with k = 0.
+int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeObj *t, int peer,
+              int tag, mpixs_status *status, mpixs_request *req) {
+    World *w = c->sh->w;
+    StreamObj *st = c->stream;
+    const int me = c->rank;
+    const int dst = side == 0 ? peer : me;
+    MatchQueue &q = c->sh->mq[size_t(dst)];
+    Side mine;
+    mine.buf = buf;
+    mine.count = count;
+    mine.t = t;
+    mine.bytes = int64_t(count) * t->L.size;
+    mine.st = st;
+    mine.rank = me;
+    mpixs_request_s *r = req ? new mpixs_request_s() : nullptr;
+    std::unique_lock<std::mutex> lk(q.mu);
+    QOp partner;
+    bool found = false;
+    if (side == 0) {
+        for (auto it = q.posted.begin(); it != q.posted.end(); ++it) {
+            if ((it->src == MPIXS_ANY_SOURCE || it->src == me) &&
+                (it->tag == MPIXS_ANY_TAG || it->tag == tag)) {
+                partner = *it;
+                q.posted.erase(it);
+                found = true;
+                break;
+            }
+        }
+    } else {
+        for (auto it = q.unexpected.begin(); it != q.unexpected.end(); ++it) {
+            if ((peer == MPIXS_ANY_SOURCE || it->src == peer) &&
+                (tag == MPIXS_ANY_TAG || it->tag == tag)) {
+                partner = *it;
+                q.unexpected.erase(it);
+                found = true;
+                break;
+            }
+        }
+    }
+    int rc = MPIXS_SUCCESS;
+    if (found) {
+        lk.unlock();
+        // second of the pair: the partner's ready post is already enqueued
+        Channel *ch = partner.ch;
+        Rec *rec = partner.rec;
+        {
+            std::lock_guard<std::mutex> g(ch->mu);
+            (side == 0 ? rec->s : rec->r) = mine;
+        }
+        const int mtag = side == 0 ? tag : partner.tag;
+        const StatusVal sv = match_status(rec->s, rec->r, mtag);
+        const bool recv_here = side == 1;
+        rc = do_copy(w, st, rec->s, rec->r, sv, &ch->d->ready[1 - side], 1, &ch->d->done, 1,
+                     (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
+        rec->st = sv;
+        rec->copy_enq.store(1, std::memory_order_release);
+        host_notify(&rec->copy_enq);
+        rec_release(ch, rec);
+        if (r) {
+            r->comm = c;
+            r->side = side;
+            r->second = true;
+            r->st = sv;
+            r->k = 0;
+            c->pending.fetch_add(1);
+            *req = r;
+        }
+        return rc;
+    }
+    // first of the pair: a fresh one-message channel, posted while the queue
+    // is locked so that no partner can enqueue its wait before this post
+    const uint32_t idx = w->chan_next.fetch_add(1);
+    if (idx >= w->chan_cap) {
+        delete r;
+        return MPIXS_ERR_NOMEM;
+    }
+    Channel *ch = new Channel();
+    ch->priv = true;
+    ch->d = w->d_chans + idx;
+    Rec *rec = ch->at(0);
+    (side == 0 ? rec->s : rec->r) = mine;
+    rc = do_post(w, st, &ch->d->ready[side], 1);
+    if (rc) {
+        delete ch;
+        delete r;
+        return rc;
+    }
+    rec->arrived.fetch_or(side == 0 ? ARR_S : ARR_R, std::memory_order_release);
+    QOp op;
+    op.ch = ch;
+    op.rec = rec;
+    op.src = side == 0 ? me : peer;
+    op.tag = tag;
+    (side == 0 ? q.unexpected : q.posted).push_back(op);
+    lk.unlock();
+    if (!r) return complete_first(w, st, ch, rec, 0, side, status);
+    r->comm = c;
+    r->ch = ch;
+    r->rec = rec;
+    r->k = 0;
+    r->side = side;
+    r->second = false;
+    c->pending.fetch_add(1);
+    *req = r;
+    return MPIXS_SUCCESS;
+}
+
 int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt, int peer,
         int tag, mpixs_status *status, mpixs_request *req) {
     const TypeObj *t = nullptr;
@@ -455,6 +577,10 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
     if (rc) return rc;
     World *w = c->sh->w;
     StreamObj *st = c->stream;
+    if (c->in_group && side == 1 && peer == MPIXS_ANY_SOURCE) return MPIXS_ERR_RANK;
+    if (c->in_group && side == 1 && tag == MPIXS_ANY_TAG) return MPIXS_ERR_TAG;
+    if (!c->in_group && w->cfg.matching == 1)
+        return p2p_queue(c, side, buf, count, t, peer, tag, status, req);
     if (c->in_group) {
         // recorded; mpixs_group_end enqueues it
         GOp g;
@@ -1086,7 +1212,7 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     if (c.batch_max_wg <= 0) c.batch_max_wg = 16384;
     if (!batch_tile_ok(uint32_t(c.batch_tile)) || c.batch_max_wg > (1 << 20) ||
         c.batch_graph < 0 || c.batch_graph > 1 || c.batch_nontemporal < 0 ||
-        c.batch_nontemporal > 2) {
+        c.batch_nontemporal > 2 || c.matching < 0 || c.matching > 1) {
         delete w;
         return MPIXS_ERR_ARG;
     }
@@ -1146,6 +1272,7 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     sh->size = nranks;
     sh->id = 0;
     sh->streams.assign(size_t(nranks), nullptr);
+    sh->mq.reset(new MatchQueue[size_t(nranks)]);
     sh->handles.store(nranks);
     w->world_sh = sh;
     for (int r = 0; r < nranks; ++r) {
@@ -1370,6 +1497,7 @@ int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm 
             cr.sh->size = ps->size;
             cr.sh->id = w->next_comm_id.fetch_add(1);
             cr.sh->streams.assign(size_t(ps->size), nullptr);
+            cr.sh->mq.reset(new MatchQueue[size_t(ps->size)]);
             cr.sh->d_coll = w->d_coll + off;
             cr.sh->d_grp = w->d_coll + off + words;
         }
@@ -1680,6 +1808,7 @@ int mpixs_send(const void *buf, int count, mpixs_datatype dt, int dest, int tag,
     const TypeObj *t = nullptr;
     int rc = check_p2p(c, buf, count, dt, dest, tag, false, &t);
     if (rc) return rc;
+    if (c->sh->w->cfg.matching == 1) return MPIXS_ERR_COMM;   // sequence channels only
     World *w = c->sh->w;
     StreamObj *st = c->stream;
     if (hipStreamSynchronize(st->hs) != hipSuccess) return MPIXS_ERR_GPU;
@@ -1709,6 +1838,7 @@ int mpixs_recv(void *buf, int count, mpixs_datatype dt, int source, int tag, mpi
     const TypeObj *t = nullptr;
     int rc = check_p2p(c, buf, count, dt, source, tag, true, &t);
     if (rc) return rc;
+    if (c->sh->w->cfg.matching == 1) return MPIXS_ERR_COMM;   // sequence channels only
     World *w = c->sh->w;
     StreamObj *st = c->stream;
     if (hipStreamSynchronize(st->hs) != hipSuccess) return MPIXS_ERR_GPU;

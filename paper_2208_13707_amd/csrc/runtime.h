@@ -96,6 +96,7 @@ struct Rec {
 
 struct Channel {
     DevChan *d = nullptr;
+    bool priv = false;                 // one message's channel (ordered-queue matching)
     uint64_t seq[2] = {0, 0};          // [0] touched by the source thread, [1] by the destination
     std::mutex mu;
     std::deque<Rec *> recs;
@@ -169,6 +170,22 @@ struct CreateRec {
     CommShared *sh = nullptr;
 };
 
+// Ordered-queue matching (mpixs_config.matching = 1): per destination rank,
+// the receives posted and the sends enqueued that have not met a partner
+// yet, each with its own one-message channel.
+struct QOp {
+    Channel *ch = nullptr;
+    Rec *rec = nullptr;
+    int src = 0;                       // a send's source; a receive's source or ANY_SOURCE
+    int tag = 0;                       // a send's tag; a receive's tag or ANY_TAG
+};
+
+struct MatchQueue {
+    std::mutex mu;
+    std::deque<QOp> unexpected;        // sends, in enqueue order
+    std::deque<QOp> posted;            // receives, in post order
+};
+
 struct CommShared {
     World *w = nullptr;
     int size = 0;
@@ -189,6 +206,7 @@ struct CommShared {
     std::mutex create_mu;
     std::map<uint64_t, CreateRec> creates;
     std::atomic<int> handles{0};
+    std::unique_ptr<MatchQueue[]> mq;  // ordered-queue matching, one per rank
     ~CommShared();
 };
 

@@ -42,7 +42,7 @@ class Config(ctypes.Structure):
                 ("max_collectives", ctypes.c_int32), ("batch_arena_mib", ctypes.c_int32),
                 ("batch_tile", ctypes.c_int32), ("batch_max_wg", ctypes.c_int32),
                 ("batch_graph", ctypes.c_int32), ("batch_nontemporal", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("matching", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Status(ctypes.Structure):

@@ -109,6 +109,14 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
     tstreams = [[torch.cuda.ExternalStream(h, device=dev) for h in row] for row in hip_streams]
     torch.cuda.synchronize()
 
+    if p.matching == "queue":
+        # ordered-queue matching (wildcards allowed)
+        base = cfg
+        cfg = M.Config()
+        if base is not None:
+            for name, _ in M.Config._fields_:
+                setattr(cfg, name, getattr(base, name))
+        cfg.matching = 1
     rc, world = M.mpixs_world_create(N, cfg)
     assert rc == 0, M.errname(rc)
     types = _Types(M)

@@ -269,3 +269,41 @@ def test_persistent_errors():
             Wait(["a"], [None])],
            [GroupStart(), Recv("r", 0, 1, "int32", 0, 0), GroupInit("y"), Start("y")]]
     check(single_stream(2, b, ops, name="persistent unwaited"))
+
+
+# -------------------------------------------------- ordered-queue matching
+from tests.checks import check_competing  # noqa: E402
+
+
+def queue_mode(p):
+    p.matching = "queue"
+    return p
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_wildcard_programs(k):
+    """Wildcard receives whose match is the same in every interleaving."""
+    check(C.wildcard_programs()[k])
+
+
+def test_wildcard_competing_senders():
+    """Three senders race for ANY_SOURCE / ANY_TAG receives: every message
+    arrives exactly once, in order per sender, with a matching status."""
+    p = C.competing_senders()
+    _say(p.name)
+    for _ in range(3):
+        g = run_program(p)
+        vals = np.frombuffer(g.buffers[0]["r"].tobytes(), np.int32).tolist()
+        check_competing(vals, [g.statuses[0][f"s{j}"] for j in range(12)])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_queue_matching_random_programs(seed):
+    """Without wildcards the queue engine must give sequence pairing's results."""
+    check(queue_mode(C.random_program(seed, nranks=4, nmsg=40)), name=f"queue random {seed}")
+
+
+def test_queue_matching_halo_and_batch():
+    check(queue_mode(C.ring_halo(count=2730, steps=3, update=True, blocking_recv=False)),
+          name="queue halo")
+    check(queue_mode(C.batch(npairs=1000, nranks=8, max_bytes=65536)), name="queue batch")

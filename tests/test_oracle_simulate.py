@@ -401,3 +401,66 @@ def test_persistent_runs_equal_repeated_groups():
         for k in a.buffers[rank]:
             assert np.array_equal(a.buffers[rank][k], b.buffers[rank][k])
         assert a.statuses[rank] == b.statuses[rank]
+
+
+# ------------------------------------------------------------------ wildcards
+from tests.checks import check_competing  # noqa: E402
+
+
+def i32(a):
+    return np.frombuffer(a.tobytes(), np.int32)
+
+
+def _queue(nranks, bufs, ops, name="wild"):
+    p = single_stream(nranks, bufs, ops, name=name)
+    p.matching = "queue"
+    return p
+
+def test_wildcard_matches_in_order():
+    p1, p2, p3 = C.wildcard_programs()
+    r = sim.run(p1)
+    assert not r.deadlock and not any(r.sync_errors)
+    assert i32(r.buffers[1]["r"]).tolist() == [50, 30, 70]
+    assert [r.statuses[1][f"st{i}"][:2] for i in range(3)] == [(0, 5), (0, 3), (0, 7)]
+    r = sim.run(p2)
+    assert i32(r.buffers[1]["r"]).tolist() == [102, 100]
+    assert r.statuses[1]["a"] == (2, 20, "SUCCESS", 4) and r.statuses[1]["b"] == (0, 10, "SUCCESS", 4)
+    r = sim.run(p3)
+    assert i32(r.buffers[1]["r"]).tolist() == [1, 2]
+    assert r.statuses[1]["sw"] == (0, 4, "SUCCESS", 4)
+
+
+def test_wildcard_competing_senders_are_valid():
+    p = C.competing_senders()
+    r = sim.run(p)
+    assert not r.deadlock
+    vals = i32(r.buffers[0]["r"]).tolist()
+    check_competing(vals, [r.statuses[0][f"s{j}"] for j in range(12)])
+
+
+def test_wildcards_rejected_in_sequence_mode_and_in_groups():
+    b = [{"s": as_bytes(np.array([1], np.int32))}, {"r": np.zeros(4, np.uint8)}]
+    ops = [[Send("s", 0, 1, "int32", 1, 0)],
+           [Recv("r", 0, 1, "int32", ANY_SOURCE, 0), Recv("r", 0, 1, "int32", 0, 0)]]
+    r = sim.run(single_stream(2, b, ops))
+    assert r.sync_errors[1] == [(0, 0, "ERR_RANK")]
+    ops = [[GroupStart(), GroupEnd(), Send("s", 0, 1, "int32", 1, 0)],
+           [GroupStart(), Recv("r", 0, 1, "int32", 0, ANY_TAG), GroupEnd(),
+            Recv("r", 0, 1, "int32", 0, 0)]]
+    r = sim.run(_queue(2, b, ops))
+    assert not r.deadlock
+    assert r.sync_errors[1] == [(0, 1, "ERR_TAG")]
+    assert i32(r.buffers[1]["r"]).tolist() == [1]
+
+
+def test_queue_matching_without_wildcards_equals_sequence_pairing():
+    """Without wildcards both matching modes are MPI's non-overtaking rule."""
+    for seed in range(4):
+        a = sim.run(C.random_program(seed))
+        q = C.random_program(seed)
+        q.matching = "queue"
+        b = sim.run(q)
+        for rank in range(len(a.buffers)):
+            for k in a.buffers[rank]:
+                assert np.array_equal(a.buffers[rank][k], b.buffers[rank][k])
+            assert a.statuses[rank] == b.statuses[rank]

@@ -26,8 +26,8 @@ from typing import List, Optional
 import numpy as np
 
 from .program import (
-    IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv, Send, Start, User,
-    Wait, as_bytes, footprint_bound, single_stream,
+    ANY_SOURCE, ANY_TAG, IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv,
+    Send, Start, User, Wait, as_bytes, footprint_bound, single_stream,
 )
 
 SEED = 220813707
@@ -365,3 +365,49 @@ def random_program(seed: int, nranks: int = 4, nmsg: int = 40, max_elems: int = 
     return Program(nranks=nranks, buffers=bufs, ops=[[o] for o in ops], streams_per_rank=1,
                    comm_streams=[[0] * nranks for _ in range(ncomms)],
                    name=f"random_{seed}" + ("_grouped" if grouped else ""))
+
+
+# ------------------------------------------------------------------ wildcards
+def _queue(nranks, bufs, ops, name="wild") -> Program:
+    p = single_stream(nranks, bufs, ops, name=name)
+    p.matching = "queue"
+    return p
+
+
+def wildcard_programs():
+    """Programs whose wildcard matches are the same in every interleaving."""
+    out = []
+    # ANY_TAG from one sender: messages arrive in send order (non-overtaking)
+    b = [{"s": as_bytes(np.array([50, 30, 70], np.int32))}, {"r": np.zeros(12, np.uint8)}]
+    ops = [[Send("s", 4 * i, 1, "int32", 1, t) for i, t in enumerate((5, 3, 7))],
+           [Recv("r", 4 * i, 1, "int32", 0, ANY_TAG, status=f"st{i}") for i in range(3)]]
+    out.append(_queue(2, b, ops, "any-tag-in-order"))
+    # ANY_SOURCE told apart by tags
+    b = [{"s": as_bytes(np.array([100 + q], np.int32)), "r": np.zeros(8, np.uint8)}
+         for q in range(3)]
+    ops = [[Send("s", 0, 1, "int32", 1, 10)],
+           [Recv("r", 0, 1, "int32", ANY_SOURCE, 20, status="a"),
+            Recv("r", 4, 1, "int32", ANY_SOURCE, 10, status="b")],
+           [Send("s", 0, 1, "int32", 1, 20)]]
+    out.append(_queue(3, b, ops, "any-source-by-tag"))
+    # a wildcard receive posted before a specific one takes the first message
+    b = [{"s": as_bytes(np.array([1, 2], np.int32))}, {"r": np.zeros(8, np.uint8)}]
+    ops = [[Send("s", 0, 1, "int32", 1, 4, req="x"), Send("s", 4, 1, "int32", 1, 4, req="y"),
+            Wait(["x", "y"], [None, None])],
+           [Recv("r", 0, 1, "int32", ANY_SOURCE, ANY_TAG, req="w", status=None),
+            Recv("r", 4, 1, "int32", 0, 4, req="v"), Wait(["w", "v"], ["sw", "sv"])]]
+    out.append(_queue(2, b, ops, "posted-order"))
+    return out
+
+
+def competing_senders(nsend=3, per=4):
+    """Ranks 1..nsend each send `per` messages (value 1000 * src + i) to rank
+    0, which receives them all with ANY_SOURCE / ANY_TAG."""
+    n = nsend + 1
+    bufs = [{"r": np.zeros(4 * nsend * per, np.uint8)}]
+    ops = [[Recv("r", 4 * j, 1, "int32", ANY_SOURCE, ANY_TAG, status=f"s{j}")
+            for j in range(nsend * per)]]
+    for q in range(1, n):
+        bufs.append({"s": as_bytes(np.array([1000 * q + i for i in range(per)], np.int32))})
+        ops.append([Send("s", 4 * i, 1, "int32", 0, 7 + i) for i in range(per)])
+    return _queue(n, bufs, ops, "competing")

@@ -165,6 +165,10 @@ class Program:
     streams_per_rank: int = 1
     comm_streams: List[List[Optional[int]]] = field(default_factory=list)
     name: str = ""
+    # "sequence": k-th send meets k-th receive per (comm, src, dst, tag), no
+    # wildcards; "queue": ordered posted / unexpected queues per destination,
+    # receives may use ANY_SOURCE / ANY_TAG
+    matching: str = "sequence"
 
     def __post_init__(self):
         if not self.comm_streams:
