@@ -87,6 +87,7 @@ typedef int32_t mpixs_op;
 #define MPIXS_DATATYPE_NULL ((mpixs_datatype)0)
 #define MPIXS_ANY_SOURCE (-2)
 #define MPIXS_ANY_TAG (-1)
+#define MPIXS_ANY_INDEX (-3)    /* any stream index (multiplex communicators, §3.5) */
 #define MPIXS_IN_PLACE ((const void *)1)
 
 /* basic datatypes (homogeneous; derived types are built from one of them) */
@@ -109,7 +110,7 @@ typedef struct {
     int32_t source;
     int32_t tag;
     int32_t error;
-    int32_t reserved;
+    int32_t source_index;       /* sender's stream index on a multiplex communicator, else 0 */
     int64_t count_bytes;
 } mpixs_status;
 
@@ -318,6 +319,41 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
  *  allreduce_enqueue inside a group fails with MPIXS_ERR_ARG.
  *  mpixs_group_end waits on the host until every rank has called it.
  */
+/* --------------------------------------- multiplex stream communicators (§3.5)
+ * mpixs_comm_create_multiplex (the paper's MPIX_Stream_comm_create_multiple):
+ *   collective over parent; every rank attaches `count` (0..64) of its GPU
+ *   streams, which become its stream indices 0..count-1 (an index is a rank
+ *   for threads).  Errors: MPIXS_ERR_STREAM for a NULL or non-GPU stream or
+ *   one of another world, MPIXS_ERR_ARG for a bad count.  The ordinary
+ *   enqueue calls and allreduce fail on such a communicator with
+ *   MPIXS_ERR_COMM (it has no single local stream).
+ * mpixs_stream_{send,recv,isend,irecv}_enqueue (the paper's MPIX_Stream_send
+ *   family, enqueued): the operation is enqueued on the local stream of the
+ *   local index (src_idx for a send, dst_idx for a receive) and addresses
+ *   the remote stream of the other index; a receive may use
+ *   MPIXS_ANY_SOURCE, MPIXS_ANY_TAG and MPIXS_ANY_INDEX (src_idx).  Matching
+ *   is ordered-queue matching per destination endpoint (rank, stream index)
+ *   -- the rule documented for mpixs_config.matching = 1, whatever that
+ *   setting -- and the status reports the sender's rank, stream index
+ *   (source_index), tag and count.  Semantics of completion, requests and
+ *   host blocking are those of the enqueue calls above; requests belong to
+ *   the stream they were enqueued on (waitall across streams:
+ *   MPIXS_ERR_STREAM).  Argument errors: MPIXS_ERR_RANK for a peer or index
+ *   out of range, MPIXS_ERR_TAG, MPIXS_ERR_COUNT, MPIXS_ERR_TYPE,
+ *   MPIXS_ERR_BUFFER, MPIXS_ERR_COMM on a communicator that is not
+ *   multiplex; an erroneous call has no side effect. */
+int mpixs_comm_create_multiplex(mpixs_comm parent, int count, const mpixs_stream streams[],
+                                mpixs_comm *comm);
+int mpixs_stream_send_enqueue(const void *buf, int count, mpixs_datatype datatype, int dest,
+                              int tag, mpixs_comm comm, int src_idx, int dst_idx);
+int mpixs_stream_recv_enqueue(void *buf, int count, mpixs_datatype datatype, int source, int tag,
+                              mpixs_comm comm, int src_idx, int dst_idx, mpixs_status *status);
+int mpixs_stream_isend_enqueue(const void *buf, int count, mpixs_datatype datatype, int dest,
+                               int tag, mpixs_comm comm, int src_idx, int dst_idx,
+                               mpixs_request *request);
+int mpixs_stream_irecv_enqueue(void *buf, int count, mpixs_datatype datatype, int source, int tag,
+                               mpixs_comm comm, int src_idx, int dst_idx, mpixs_request *request);
+
 int mpixs_group_start(mpixs_comm comm);
 int mpixs_group_end(mpixs_comm comm);
 

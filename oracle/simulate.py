@@ -30,6 +30,12 @@ What it states, and where the paper fixes it:
   result depends on that order (in MPI and on the GPU alike), so such
   programs are compared by invariants, not byte for byte.  Wildcards are not
   allowed inside groups.
+* Multiplex stream communicators (§3.5): every rank attaches several
+  streams, addressed by index; a send names its own index and the
+  receiver's, a receive its own index and the sender's (or ANY_INDEX).
+  Matching is the queue matching above, per destination (rank, index).
+  Ordinary calls, allreduce and groups on such a communicator are ERR_COMM
+  (it has no single stream), and index calls on other communicators too.
 * Groups (a batching extension): between GroupStart and GroupEnd on a
   communicator a rank's sends and receives on it are posted but do not
   block and do not move data; GroupEnd is collective (instance k = the k-th
@@ -66,7 +72,8 @@ Readings where the paper is silent (each is listed in the design notes):
 * Invalid arguments are reported when the op is issued and the op then has
   no effect at all.  Checks run in this order: communicator (ERR_COMM),
   count (ERR_COUNT), datatype (ERR_TYPE), peer rank (ERR_RANK, also for the
-  any-source wildcard), tag (ERR_TAG, also for the any-tag wildcard),
+  any-source wildcard where wildcards are not allowed), tag (ERR_TAG,
+  likewise), stream indices of a multiplex communicator (ERR_RANK),
   overlapping receive typemap (ERR_TYPE); for allreduce: communicator, count,
   datatype (basic types only), operation (ERR_OP); for wait / waitall:
   unknown request (ERR_REQUEST), requests of different streams (ERR_STREAM).
@@ -83,7 +90,8 @@ import numpy as np
 from . import reduce as red
 from . import typemap as tm
 from workloads.program import (
-    ANY_SOURCE, ANY_TAG, IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program, Recv, Send,
+    ANY_INDEX, ANY_SOURCE, ANY_TAG, IN_PLACE, Allreduce, GroupEnd, GroupInit, GroupStart, Program,
+    Recv, Send,
     Start, User, Wait,
 )
 
@@ -99,6 +107,7 @@ class _SendRec:
     done: bool = False
     group: Optional[Tuple[int, int]] = None     # (comm, instance) when grouped
     src: Optional[Tuple[str, int, int, object]] = None   # (buf, off, count, typemap)
+    idx: int = 0                                # sender's stream index (multiplex)
 
 
 @dataclass
@@ -111,7 +120,7 @@ class _RecvRec:
     done: bool = False
     status: Optional[Tuple[int, int, str, int]] = None
     group: Optional[Tuple[int, int]] = None
-    want: Tuple[int, int] = (0, 0)               # queue matching: (source, tag) accepted
+    want: Tuple[int, int, int] = (0, 0, 0)       # queue matching: (source, index, tag) accepted
 
 
 @dataclass
@@ -142,7 +151,12 @@ class _Context:
 
 
 def _check_p2p(p: Program, rank: int, op) -> Optional[str]:
-    if not (0 <= op.comm < p.ncomms) or p.stream_of(rank, op.comm) is None:
+    if not (0 <= op.comm < p.ncomms):
+        return "ERR_COMM"
+    mp = p.multiplex(op.comm)
+    if mp != (op.src_idx is not None or op.dst_idx is not None):
+        return "ERR_COMM"        # an ordinary call on a multiplex communicator, or vice versa
+    if not mp and p.stream_of(rank, op.comm) is None:
         return "ERR_COMM"
     if op.count < 0:
         return "ERR_COUNT"
@@ -150,12 +164,26 @@ def _check_p2p(p: Program, rank: int, op) -> Optional[str]:
         t = tm.build(op.dtype)
     except tm.TypeError_:
         return "ERR_TYPE"
+    recv = isinstance(op, Recv)
     peer = op.dest if isinstance(op, Send) else op.source
-    wild = isinstance(op, Recv) and p.matching == "queue"
+    wild = recv and (p.matching == "queue" or mp)
     if not (0 <= peer < p.nranks) and not (wild and peer == ANY_SOURCE):
         return "ERR_RANK"
     if op.tag < 0 and not (wild and op.tag == ANY_TAG):
         return "ERR_TAG"
+    if mp:
+        streams = p.comm_streams[op.comm]
+        local = op.dst_idx if recv else op.src_idx
+        remote = op.src_idx if recv else op.dst_idx
+        if local is None or not (0 <= local < len(streams[rank])):
+            return "ERR_RANK"
+        if recv and remote == ANY_INDEX:
+            pass
+        elif recv and peer == ANY_SOURCE:
+            if remote is None or remote < 0:
+                return "ERR_RANK"
+        elif remote is None or not (0 <= remote < len(streams[peer])):
+            return "ERR_RANK"
     if isinstance(op, Recv) and tm.overlaps(t, op.count):
         return "ERR_TYPE"
     return None
@@ -299,7 +327,8 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         s.done = r.done = True
         match_log.append((key[0], key[1], key[2], key[3], k))
 
-    queues: Dict[Tuple[int, int], Tuple[list, list]] = {}   # (comm, dst) -> (unexpected, posted)
+    # (comm, dst, dst stream index) -> (unexpected, posted)
+    queues: Dict[Tuple[int, int, int], Tuple[list, list]] = {}
     qcount: Dict[Tuple[int, int, int, int], int] = {}
 
     def queue_match(s, r, comm):
@@ -309,13 +338,14 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         move(s, r, key, k)
 
     def accepts(r, s):
-        src, tag = r.want
-        return src in (ANY_SOURCE, s.rank) and tag in (ANY_TAG, s.tag)
+        src, idx, tag = r.want
+        return src in (ANY_SOURCE, s.rank) and idx in (ANY_INDEX, s.idx) and tag in (ANY_TAG, s.tag)
 
     def post_send_q(rank, op: Send) -> _SendRec:
         t = tm.build(op.dtype)
-        rec = _SendRec(rank, op.tag, t.basic, tm.pack(bufs[rank][op.buf], op.off, op.count, t))
-        unexpected, posted = queues.setdefault((op.comm, op.dest), ([], []))
+        rec = _SendRec(rank, op.tag, t.basic, tm.pack(bufs[rank][op.buf], op.off, op.count, t),
+                       idx=op.src_idx or 0)
+        unexpected, posted = queues.setdefault((op.comm, op.dest, op.dst_idx or 0), ([], []))
         for i, r in enumerate(posted):
             if accepts(r, rec):
                 del posted[i]
@@ -326,8 +356,9 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
 
     def post_recv_q(rank, op: Recv) -> _RecvRec:
         t = tm.build(op.dtype)
-        rec = _RecvRec(rank, op.buf, op.off, op.count, t, want=(op.source, op.tag))
-        unexpected, posted = queues.setdefault((op.comm, rank), ([], []))
+        rec = _RecvRec(rank, op.buf, op.off, op.count, t,
+                       want=(op.source, op.src_idx if op.src_idx is not None else 0, op.tag))
+        unexpected, posted = queues.setdefault((op.comm, rank, op.dst_idx or 0), ([], []))
         for i, s in enumerate(unexpected):
             if accepts(rec, s):
                 del unexpected[i]
@@ -460,10 +491,10 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
                 sync_errors[rank].append((ctx.thread, ctx.pc, err))
                 ctx.pc += 1
                 return True
-            if grp is None and p.matching == "queue":
+            if grp is None and (p.matching == "queue" or p.multiplex(op.comm)):
                 rec = post_send_q(rank, op) if isinstance(op, Send) else post_recv_q(rank, op)
                 if op.req is not None:
-                    requests[rank][op.req] = (rec, p.stream_of(rank, op.comm))
+                    requests[rank][op.req] = (rec, p.stream_of_op(rank, op))
                     ctx.pc += 1
                     return True
                 ctx.pending = ("one", rec)
@@ -533,7 +564,9 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
             ctx.pc += 1
             return True
         if isinstance(op, GroupStart):
-            if (rank, op.comm) in group_open:
+            if not (0 <= op.comm < p.ncomms) or p.stream_of(rank, op.comm) is None:
+                sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_COMM"))
+            elif (rank, op.comm) in group_open:
                 sync_errors[rank].append((ctx.thread, ctx.pc, "ERR_ARG"))
             else:
                 inst = group_next.get((rank, op.comm), 0)

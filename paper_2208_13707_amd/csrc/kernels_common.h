@@ -83,7 +83,7 @@ __device__ __forceinline__ void write_status(void *dst, const StatusVal &v, uint
     s->source = v.source;
     s->tag = v.tag;
     s->error = fatal ? int32_t(fatal) : v.error;
-    s->reserved = 0;
+    s->source_index = v.source_index;
     s->count_bytes = fatal ? 0 : v.count_bytes;
 }
 

@@ -130,7 +130,7 @@ struct StatusVal {
     int32_t source;
     int32_t tag;
     int32_t error;
-    int32_t reserved;
+    int32_t source_index;   // sender's stream index (multiplex communicators), else 0
     int64_t count_bytes;
 };
 

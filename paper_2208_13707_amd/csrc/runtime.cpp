@@ -267,6 +267,7 @@ StatusVal match_status(const Side &s, const Side &r, int tag) {
     StatusVal st{};
     st.source = s.rank;
     st.tag = tag;
+    st.source_index = s.idx;   // the sender's stream index (multiplex communicators)
     const int64_t cap = r.bytes;
     if (s.bytes > 0 && cap > 0 && s.t->L.basic != r.t->L.basic) {
         st.error = MPIXS_ERR_TYPE;
@@ -464,12 +465,15 @@ int complete_first(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, i
 // channel; the first of the pair posts ready on it and the second copies,
 // exactly as on a sequence channel with k = 0.
 int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeObj *t, int peer,
-              int tag, mpixs_status *status, mpixs_request *req) {
+              int tag, mpixs_status *status, mpixs_request *req, StreamObj *st, int my_idx,
+              int peer_idx) {
     World *w = c->sh->w;
-    StreamObj *st = c->stream;
+    CommShared *sh = c->sh;
     const int me = c->rank;
-    const int dst = side == 0 ? peer : me;
-    MatchQueue &q = c->sh->mq[size_t(dst)];
+    // the destination endpoint's queue
+    const int ep = side == 0 ? (sh->multiplex ? sh->ep_base[size_t(peer)] + peer_idx : peer)
+                             : (sh->multiplex ? sh->ep_base[size_t(me)] + my_idx : me);
+    MatchQueue &q = sh->mq[size_t(ep)];
     Side mine;
     mine.buf = buf;
     mine.count = count;
@@ -477,13 +481,16 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     mine.bytes = int64_t(count) * t->L.size;
     mine.st = st;
     mine.rank = me;
+    mine.idx = my_idx;
     mpixs_request_s *r = req ? new mpixs_request_s() : nullptr;
+    if (r) r->stream = st;
     std::unique_lock<std::mutex> lk(q.mu);
     QOp partner;
     bool found = false;
     if (side == 0) {
         for (auto it = q.posted.begin(); it != q.posted.end(); ++it) {
             if ((it->src == MPIXS_ANY_SOURCE || it->src == me) &&
+                (it->src_idx == MPIXS_ANY_INDEX || it->src_idx == my_idx) &&
                 (it->tag == MPIXS_ANY_TAG || it->tag == tag)) {
                 partner = *it;
                 q.posted.erase(it);
@@ -494,6 +501,7 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     } else {
         for (auto it = q.unexpected.begin(); it != q.unexpected.end(); ++it) {
             if ((peer == MPIXS_ANY_SOURCE || it->src == peer) &&
+                (peer_idx == MPIXS_ANY_INDEX || it->src_idx == peer_idx) &&
                 (tag == MPIXS_ANY_TAG || it->tag == tag)) {
                 partner = *it;
                 q.unexpected.erase(it);
@@ -555,6 +563,7 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     op.ch = ch;
     op.rec = rec;
     op.src = side == 0 ? me : peer;
+    op.src_idx = side == 0 ? my_idx : peer_idx;
     op.tag = tag;
     (side == 0 ? q.unexpected : q.posted).push_back(op);
     lk.unlock();
@@ -580,7 +589,7 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
     if (c->in_group && side == 1 && peer == MPIXS_ANY_SOURCE) return MPIXS_ERR_RANK;
     if (c->in_group && side == 1 && tag == MPIXS_ANY_TAG) return MPIXS_ERR_TAG;
     if (!c->in_group && w->cfg.matching == 1)
-        return p2p_queue(c, side, buf, count, t, peer, tag, status, req);
+        return p2p_queue(c, side, buf, count, t, peer, tag, status, req, st, 0, 0);
     if (c->in_group) {
         // recorded; mpixs_group_end enqueues it
         GOp g;
@@ -612,7 +621,10 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
     Channel *ch = get_channel(c, src, dst, tag, false);
     if (!ch) return MPIXS_ERR_NOMEM;
     mpixs_request_s *r = nullptr;
-    if (req) r = new mpixs_request_s();
+    if (req) {
+        r = new mpixs_request_s();
+        r->stream = st;
+    }
     const uint64_t k = ch->seq[side]++;
     Side me;
     me.buf = buf;
@@ -680,8 +692,9 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
     for (int i = 0; i < n; ++i) {
         mpixs_request_s *r = reqs[i];
         if (!r || !r->comm) return MPIXS_ERR_REQUEST;
-        if (st && r->comm->stream != st) return MPIXS_ERR_STREAM;
-        st = r->comm->stream;
+        StreamObj *rs = r->stream ? r->stream : r->comm->stream;
+        if (st && rs != st) return MPIXS_ERR_STREAM;
+        st = rs;
     }
     World *w = reqs[0]->comm->sh->w;
     int rc = MPIXS_SUCCESS;
@@ -1535,6 +1548,7 @@ int mpixs_comm_free(mpixs_comm *pc) {
     if (c->pending.load() > 0) return MPIXS_ERR_PENDING;
     World *w = c->sh->w;
     if (c->stream) c->stream->comm_refs.fetch_sub(1);
+    for (StreamObj *s : c->mstreams) s->comm_refs.fetch_sub(1);
     if (c->sh->handles.fetch_sub(1) == 1) delete c->sh;
     w->live_comms.fetch_sub(1);
     delete c;
@@ -1575,6 +1589,134 @@ int mpixs_irecv_enqueue(void *buf, int count, mpixs_datatype dt, int source, int
                         mpixs_comm comm, mpixs_request *request) {
     if (!request) return MPIXS_ERR_ARG;
     return p2p(comm, 1, buf, count, dt, source, tag, nullptr, request);
+}
+
+// ------------------------------------------- multiplex communicators (§3.5)
+}  // extern "C"
+
+namespace {
+
+// Argument checks of the index-addressed calls, in the order of check_p2p
+// (communicator, count, datatype, peer, tag, stream indices, overlap,
+// buffer).  The local index names the stream the operation is enqueued on.
+int check_mp(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, int peer, int tag,
+             bool recv, int src_idx, int dst_idx, const TypeObj **t, StreamObj **st) {
+    if (!c || !c->sh || !c->sh->multiplex) return MPIXS_ERR_COMM;
+    CommShared *sh = c->sh;
+    if (count < 0) return MPIXS_ERR_COUNT;
+    if (!type_ok(dt, t)) return MPIXS_ERR_TYPE;
+    if (!(recv && peer == MPIXS_ANY_SOURCE) && (peer < 0 || peer >= sh->size)) return MPIXS_ERR_RANK;
+    if (!(recv && tag == MPIXS_ANY_TAG) && tag < 0) return MPIXS_ERR_TAG;
+    const int local = recv ? dst_idx : src_idx;
+    const int remote = recv ? src_idx : dst_idx;
+    if (local < 0 || local >= int(c->mstreams.size())) return MPIXS_ERR_RANK;
+    if (recv && remote == MPIXS_ANY_INDEX) {
+    } else if (recv && peer == MPIXS_ANY_SOURCE) {
+        if (remote < 0) return MPIXS_ERR_RANK;
+    } else if (remote < 0 || remote >= int(sh->mst[size_t(peer)].size())) {
+        return MPIXS_ERR_RANK;
+    }
+    if (recv && count > 0 && (*t)->L.overlap) return MPIXS_ERR_TYPE;
+    const int64_t bytes = int64_t(count) * (*t)->L.size;
+    if (bytes > 0 && !buf) return MPIXS_ERR_BUFFER;
+    if (!(*t)->L.dense() && bytes >= (int64_t(1) << 32)) return MPIXS_ERR_COUNT;
+    if (sh->w->aborted.load()) return MPIXS_ERR_ABORTED;
+    *st = c->mstreams[size_t(local)];
+    return MPIXS_SUCCESS;
+}
+
+int mp_p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt, int peer,
+           int tag, int src_idx, int dst_idx, mpixs_status *status, mpixs_request *req) {
+    const TypeObj *t = nullptr;
+    StreamObj *st = nullptr;
+    const int rc = check_mp(c, buf, count, dt, peer, tag, side == 1, src_idx, dst_idx, &t, &st);
+    if (rc) return rc;
+    return side == 0 ? p2p_queue(c, 0, buf, count, t, peer, tag, status, req, st, src_idx, dst_idx)
+                     : p2p_queue(c, 1, buf, count, t, peer, tag, status, req, st, dst_idx, src_idx);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpixs_stream_send_enqueue(const void *buf, int count, mpixs_datatype dt, int dest, int tag,
+                              mpixs_comm comm, int src_idx, int dst_idx) {
+    return mp_p2p(comm, 0, buf, count, dt, dest, tag, src_idx, dst_idx, nullptr, nullptr);
+}
+
+int mpixs_stream_recv_enqueue(void *buf, int count, mpixs_datatype dt, int source, int tag,
+                              mpixs_comm comm, int src_idx, int dst_idx, mpixs_status *status) {
+    return mp_p2p(comm, 1, buf, count, dt, source, tag, src_idx, dst_idx, status, nullptr);
+}
+
+int mpixs_stream_isend_enqueue(const void *buf, int count, mpixs_datatype dt, int dest, int tag,
+                               mpixs_comm comm, int src_idx, int dst_idx, mpixs_request *request) {
+    if (!request) return MPIXS_ERR_ARG;
+    return mp_p2p(comm, 0, buf, count, dt, dest, tag, src_idx, dst_idx, nullptr, request);
+}
+
+int mpixs_stream_irecv_enqueue(void *buf, int count, mpixs_datatype dt, int source, int tag,
+                               mpixs_comm comm, int src_idx, int dst_idx, mpixs_request *request) {
+    if (!request) return MPIXS_ERR_ARG;
+    return mp_p2p(comm, 1, buf, count, dt, source, tag, src_idx, dst_idx, nullptr, request);
+}
+
+int mpixs_comm_create_multiplex(mpixs_comm parent, int count, const mpixs_stream *streams,
+                                mpixs_comm *newcomm) {
+    if (!parent || !parent->sh || !newcomm) return MPIXS_ERR_COMM;
+    if (count < 0 || count > 64 || (count > 0 && !streams)) return MPIXS_ERR_ARG;
+    CommShared *ps = parent->sh;
+    World *w = ps->w;
+    for (int i = 0; i < count; ++i)
+        if (!streams[i] || streams[i]->w != w || !streams[i]->gpu) return MPIXS_ERR_STREAM;
+    const uint64_t k = parent->create_seq++;
+    CommShared *sh = nullptr;
+    {
+        std::unique_lock<std::mutex> g(ps->create_mu);
+        CreateRec &cr = ps->creates[k];
+        if (!cr.sh) {
+            cr.sh = new CommShared();
+            cr.sh->w = w;
+            cr.sh->size = ps->size;
+            cr.sh->id = w->next_comm_id.fetch_add(1);
+            cr.sh->streams.assign(size_t(ps->size), nullptr);
+            cr.sh->multiplex = true;
+            cr.sh->mst.resize(size_t(ps->size));
+        }
+        cr.sh->mst[size_t(parent->rank)].assign(streams, streams + count);
+        cr.arrived++;
+        sh = cr.sh;
+    }
+    host_notify(&ps->creates);
+    // all ranks of the parent must arrive (a collective call, §3.3 / §3.5)
+    int rc = host_wait(w, &ps->creates, [&] {
+        std::lock_guard<std::mutex> g(ps->create_mu);
+        return ps->creates[k].arrived == ps->size;
+    });
+    {
+        std::lock_guard<std::mutex> g(ps->create_mu);
+        if (!rc && !sh->ep_ready) {
+            // the first rank past the barrier lays out the endpoints
+            sh->ep_base.assign(size_t(ps->size) + 1, 0);
+            for (int q = 0; q < ps->size; ++q)
+                sh->ep_base[size_t(q) + 1] = sh->ep_base[size_t(q)] + int(sh->mst[size_t(q)].size());
+            sh->mq.reset(new MatchQueue[size_t(std::max(1, sh->ep_base[size_t(ps->size)]))]);
+            sh->ep_ready = true;
+        }
+        CreateRec &cr = ps->creates[k];
+        if (++cr.left == ps->size) ps->creates.erase(k);
+    }
+    if (rc) return rc;
+    mpixs_comm_s *c = new mpixs_comm_s();
+    c->sh = sh;
+    c->rank = parent->rank;
+    c->stream = nullptr;   // the ordinary calls need a single stream: MPIXS_ERR_COMM
+    c->mstreams.assign(streams, streams + count);
+    for (StreamObj *s : c->mstreams) s->comm_refs.fetch_add(1);
+    sh->handles.fetch_add(1);
+    w->live_comms.fetch_add(1);
+    *newcomm = c;
+    return MPIXS_SUCCESS;
 }
 
 int mpixs_wait_enqueue(mpixs_request *request, mpixs_status *status) {

@@ -71,6 +71,7 @@ struct Side {
     int64_t bytes = 0;
     StreamObj *st = nullptr;
     int rank = -1;
+    int idx = 0;                       // stream index (multiplex communicators)
 };
 
 enum : uint32_t { ARR_S = 1, ARR_R = 2 };
@@ -177,6 +178,7 @@ struct QOp {
     Channel *ch = nullptr;
     Rec *rec = nullptr;
     int src = 0;                       // a send's source; a receive's source or ANY_SOURCE
+    int src_idx = 0;                   // a send's stream index; a receive's or ANY_INDEX
     int tag = 0;                       // a send's tag; a receive's tag or ANY_TAG
 };
 
@@ -206,7 +208,13 @@ struct CommShared {
     std::mutex create_mu;
     std::map<uint64_t, CreateRec> creates;
     std::atomic<int> handles{0};
-    std::unique_ptr<MatchQueue[]> mq;  // ordered-queue matching, one per rank
+    std::unique_ptr<MatchQueue[]> mq;  // ordered-queue matching, one per endpoint
+    // multiplex communicators (§3.5): every rank attaches several streams;
+    // endpoint (rank, index) has queue ep_base[rank] + index
+    bool multiplex = false;
+    std::vector<std::vector<StreamObj *>> mst;
+    std::vector<int> ep_base;
+    bool ep_ready = false;             // under create_mu of the parent
     ~CommShared();
 };
 
@@ -228,6 +236,7 @@ struct mpixs_comm_s {
     bool world_handle = false;
     bool in_group = false;
     std::vector<mpixs::GOp> gops;
+    std::vector<mpixs::StreamObj *> mstreams;   // multiplex: local streams by index
 };
 
 struct mpixs_request_s {
@@ -240,6 +249,7 @@ struct mpixs_request_s {
     bool grouped = false;              // recorded in a group: complete at group_end
     size_t gop = 0;                    // index in the comm's recorded operations
     mpixs::StatusVal st{};
+    mpixs::StreamObj *stream = nullptr; // the stream the request was enqueued on
 };
 
 struct mpixs_batch_s {

@@ -26,6 +26,7 @@ ERR_NAMES = {
 }
 ANY_SOURCE = -2
 ANY_TAG = -1
+ANY_INDEX = -3
 IN_PLACE = 1
 
 UINT8, INT8, INT32, FLOAT32, INT64, FLOAT64 = 1, 2, 3, 4, 5, 6
@@ -47,7 +48,7 @@ class Config(ctypes.Structure):
 
 class Status(ctypes.Structure):
     _fields_ = [("source", ctypes.c_int32), ("tag", ctypes.c_int32), ("error", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("count_bytes", ctypes.c_int64)]
+                ("source_index", ctypes.c_int32), ("count_bytes", ctypes.c_int64)]
 
 
 STATUS_BYTES = ctypes.sizeof(Status)
@@ -105,6 +106,11 @@ SIGNATURES = {
     "mpixs_group_start": [_vp],
     "mpixs_group_end": [_vp],
     "mpixs_group_end_init": [_vp, _pp],
+    "mpixs_comm_create_multiplex": [_vp, _i, _pp, _pp],
+    "mpixs_stream_send_enqueue": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _i, _i],
+    "mpixs_stream_recv_enqueue": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _i, _i, _vp],
+    "mpixs_stream_isend_enqueue": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _i, _i, _pp],
+    "mpixs_stream_irecv_enqueue": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _i, _i, _pp],
     "mpixs_batch_start_enqueue": [_vp],
     "mpixs_batch_free": [_pp],
     "mpixs_send": [_vp, _i, ctypes.c_int32, _i, _i, _vp],
@@ -329,6 +335,37 @@ def mpixs_group_start(comm):
 
 def mpixs_group_end(comm):
     return lib().mpixs_group_end(comm)
+
+
+def mpixs_comm_create_multiplex(parent, streams):
+    """Returns (rc, communicator or None)."""
+    arr = (ctypes.c_void_p * max(len(streams), 1))(*streams)
+    h = ctypes.c_void_p()
+    rc = lib().mpixs_comm_create_multiplex(parent, len(streams), arr, ctypes.byref(h))
+    return rc, h.value
+
+
+def mpixs_stream_send_enqueue(buf, count, dt, dest, tag, comm, src_idx, dst_idx):
+    return lib().mpixs_stream_send_enqueue(ptr(buf), count, dt, dest, tag, comm, src_idx, dst_idx)
+
+
+def mpixs_stream_recv_enqueue(buf, count, dt, source, tag, comm, src_idx, dst_idx, status=None):
+    return lib().mpixs_stream_recv_enqueue(ptr(buf), count, dt, source, tag, comm, src_idx,
+                                           dst_idx, ptr(status))
+
+
+def mpixs_stream_isend_enqueue(buf, count, dt, dest, tag, comm, src_idx, dst_idx):
+    h = ctypes.c_void_p()
+    rc = lib().mpixs_stream_isend_enqueue(ptr(buf), count, dt, dest, tag, comm, src_idx, dst_idx,
+                                          ctypes.byref(h))
+    return rc, h.value
+
+
+def mpixs_stream_irecv_enqueue(buf, count, dt, source, tag, comm, src_idx, dst_idx):
+    h = ctypes.c_void_p()
+    rc = lib().mpixs_stream_irecv_enqueue(ptr(buf), count, dt, source, tag, comm, src_idx,
+                                          dst_idx, ctypes.byref(h))
+    return rc, h.value
 
 
 def mpixs_group_end_init(comm):

@@ -29,6 +29,7 @@ class GpuResult:
     sync_errors: List[List[Tuple[int, int, str]]]
     stream_errors: List[List[str]]
     stats: object
+    status_index: object = None      # per rank: status name -> sender's stream index
 
 
 def _log(msg):
@@ -140,7 +141,11 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
                 mstreams[r][s] = h
             for c in range(p.ncomms):
                 st = p.comm_streams[c][r]
-                rc, h = M.mpixs_comm_create_with_stream(wc, mstreams[r][st] if st is not None else None)
+                if isinstance(st, list):
+                    rc, h = M.mpixs_comm_create_multiplex(wc, [mstreams[r][s] for s in st])
+                else:
+                    rc, h = M.mpixs_comm_create_with_stream(
+                        wc, mstreams[r][st] if st is not None else None)
                 assert rc == 0, M.errname(rc)
                 comms[r][c] = h
         except Exception:
@@ -201,7 +206,31 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
     def worker(r, t):
         try:
             for i, o in enumerate(p.ops[r][t]):
-                if isinstance(o, Send):
+                if isinstance(o, (Send, Recv)) and (o.src_idx is not None or o.dst_idx is not None):
+                    # index-addressed call of a multiplex communicator
+                    dt = types.get(o.dtype)
+                    c = comm_of(r, o.comm)
+                    si = o.src_idx if o.src_idx is not None else -99
+                    di = o.dst_idx if o.dst_idx is not None else -99
+                    if isinstance(o, Send) and o.req is None:
+                        rc = M.mpixs_stream_send_enqueue(bufptr(r, o.buf, o.off), o.count, dt,
+                                                         o.dest, o.tag, c, si, di)
+                    elif isinstance(o, Send):
+                        rc, h = M.mpixs_stream_isend_enqueue(bufptr(r, o.buf, o.off), o.count, dt,
+                                                             o.dest, o.tag, c, si, di)
+                        if rc == 0:
+                            requests[r][o.req] = h
+                    elif o.req is None:
+                        rc = M.mpixs_stream_recv_enqueue(bufptr(r, o.buf, o.off), o.count, dt,
+                                                         o.source, o.tag, c, si, di,
+                                                         status_ptr(r, o.status))
+                    else:
+                        rc, h = M.mpixs_stream_irecv_enqueue(bufptr(r, o.buf, o.off), o.count, dt,
+                                                             o.source, o.tag, c, si, di)
+                        if rc == 0:
+                            requests[r][o.req] = h
+                    record(r, t, i, rc)
+                elif isinstance(o, Send):
                     dt = types.get(o.dtype)
                     c = comm_of(r, o.comm)
                     if host_synced:
@@ -293,14 +322,16 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
         raise RuntimeError("\n".join(failures))
 
     out_bufs = [{k: v.cpu().numpy().copy() for k, v in b.items()} for b in dbufs]
-    statuses = []
+    statuses, status_index = [], []
     for r in range(N):
         raw = dstat[r].cpu().numpy().tobytes()
-        d = {}
+        d, di = {}, {}
         for name, idx in layout[r][0].items():
-            src, tag, err, _, cnt = struct.unpack_from("<iiiiq", raw, idx * M.STATUS_BYTES)
+            src, tag, err, sidx, cnt = struct.unpack_from("<iiiiq", raw, idx * M.STATUS_BYTES)
             d[name] = (src, tag, M.errname(err), cnt)
+            di[name] = sidx
         statuses.append(d)
+        status_index.append(di)
     stream_errors = []
     for r in range(N):
         errs = []
@@ -324,7 +355,8 @@ def run_program(p: Program, cfg=None, host_synced: bool = False, timeout_s: floa
     for row in hip_streams:
         for h in row:
             D.hip_stream_destroy(h)
-    return GpuResult(out_bufs, statuses, [sorted(e) for e in sync_errors], stream_errors, st)
+    return GpuResult(out_bufs, statuses, [sorted(e) for e in sync_errors], stream_errors, st,
+                     status_index)
 
 
 def compare(p: Program, gpu: GpuResult, ref, check_statuses: bool = True) -> List[str]:

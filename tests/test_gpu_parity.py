@@ -307,3 +307,44 @@ def test_queue_matching_halo_and_batch():
     check(queue_mode(C.ring_halo(count=2730, steps=3, update=True, blocking_recv=False)),
           name="queue halo")
     check(queue_mode(C.batch(npairs=1000, nranks=8, max_bytes=65536)), name="queue batch")
+
+
+# ------------------------------------------------------------ multiplex (§3.5)
+from tests.checks import check_n_to_1_racing  # noqa: E402
+from workloads.program import ANY_INDEX, GroupStart as _GroupStart  # noqa: E402
+
+
+@pytest.mark.parametrize("nthreads", [2, 4, 8])
+def test_multiplex_n_to_1_by_tag(nthreads):
+    g, _ = check(C.multiplex_n_to_1(nthreads=nthreads, per=3))
+    for k in range(3 * nthreads):
+        v = int(np.frombuffer(g.buffers[1]["r"][4 * k: 4 * k + 4].tobytes(), np.int32)[0])
+        assert g.status_index[1][f"s{k}"] == v // 100
+
+
+def test_multiplex_n_to_1_racing():
+    p = C.multiplex_n_to_1(nthreads=4, per=3, racing=True)
+    _say(p.name)
+    for _ in range(3):
+        g = run_program(p)
+        assert not any(g.sync_errors)
+        vals = np.frombuffer(g.buffers[1]["r"].tobytes(), np.int32).tolist()
+        check_n_to_1_racing(vals, [g.statuses[1][f"s{k}"] for k in range(12)],
+                            indices=[g.status_index[1][f"s{k}"] for k in range(12)])
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_multiplex_all_pairs(n):
+    check(C.multiplex_all_pairs(n))
+
+
+def test_multiplex_argument_errors():
+    b = [{"s": as_bytes(np.array([1, 2], np.int32)), "r": np.zeros(8, np.uint8)} for _ in range(2)]
+    ops = [[[Send("s", 0, 1, "int32", 1, 0),
+             Send("s", 0, 1, "int32", 1, 0, src_idx=2, dst_idx=0),
+             Send("s", 0, 1, "int32", 1, 0, src_idx=0, dst_idx=1),
+             Allreduce("s", 0, "r", 0, 1, "int32", "sum"),
+             _GroupStart(),
+             Send("s", 4, 1, "int32", 1, 3, src_idx=1, dst_idx=0)]],
+           [[Recv("r", 0, 1, "int32", 0, ANY_TAG, src_idx=ANY_INDEX, dst_idx=0, status="x")]]]
+    check(Program(2, b, ops, 2, [[[0, 1], [0]]], name="multiplex-errors"))

@@ -464,3 +464,52 @@ def test_queue_matching_without_wildcards_equals_sequence_pairing():
             for k in a.buffers[rank]:
                 assert np.array_equal(a.buffers[rank][k], b.buffers[rank][k])
             assert a.statuses[rank] == b.statuses[rank]
+
+
+# ------------------------------------------------------------ multiplex (§3.5)
+from tests.checks import check_n_to_1_racing  # noqa: E402
+from workloads.program import ANY_INDEX  # noqa: E402
+
+
+def test_multiplex_n_to_1_by_tag():
+    p = C.multiplex_n_to_1(nthreads=4, per=3)
+    r = sim.run(p)
+    assert not r.deadlock and not any(r.sync_errors)
+    want = [100 * i + j for i in range(4) for j in range(3)][::-1]
+    assert i32(r.buffers[1]["r"]).tolist() == want
+    assert r.statuses[1]["s0"] == (0, 32, "SUCCESS", 4)
+
+
+def test_multiplex_n_to_1_racing_is_valid():
+    p = C.multiplex_n_to_1(nthreads=4, per=3, racing=True)
+    r = sim.run(p)
+    assert not r.deadlock
+    check_n_to_1_racing(i32(r.buffers[1]["r"]).tolist(), [r.statuses[1][f"s{k}"] for k in range(12)])
+
+
+def test_multiplex_all_pairs_closed_form():
+    n = 3
+    r = sim.run(C.multiplex_all_pairs(n))
+    assert not r.deadlock and not any(r.sync_errors)
+    for rank in range(2):
+        got = i32(r.buffers[rank]["r"]).tolist()
+        # thread i received from thread j of the other rank: 1000 * (1 - rank) + 10 * j + i
+        assert got == [1000 * (1 - rank) + 10 * j + i for i in range(n) for j in range(n)]
+
+
+def test_multiplex_argument_errors():
+    b = [{"s": as_bytes(np.array([1, 2], np.int32)), "r": np.zeros(8, np.uint8)} for _ in range(2)]
+    ops = [[[Send("s", 0, 1, "int32", 1, 0),                                  # ordinary: ERR_COMM
+             Send("s", 0, 1, "int32", 1, 0, src_idx=2, dst_idx=0),            # local index: ERR_RANK
+             Send("s", 0, 1, "int32", 1, 0, src_idx=0, dst_idx=1),            # remote index: ERR_RANK
+             Allreduce("s", 0, "r", 0, 1, "int32", "sum"),                    # ERR_COMM
+             GroupStart(),                                                    # ERR_COMM
+             Send("s", 4, 1, "int32", 1, 3, src_idx=1, dst_idx=0)]],
+           [[Recv("r", 0, 1, "int32", 0, ANY_TAG, src_idx=ANY_INDEX, dst_idx=0, status="x")]]]
+    p = Program(2, b, ops, 2, [[[0, 1], [0]]], name="mp-errors")
+    r = sim.run(p)
+    assert not r.deadlock
+    assert r.sync_errors[0] == [(0, 0, "ERR_COMM"), (0, 1, "ERR_RANK"), (0, 2, "ERR_RANK"),
+                                (0, 3, "ERR_COMM"), (0, 4, "ERR_COMM")]
+    assert i32(r.buffers[1]["r"]).tolist()[0] == 2
+    assert r.statuses[1]["x"] == (0, 3, "SUCCESS", 4)

@@ -411,3 +411,57 @@ def competing_senders(nsend=3, per=4):
         bufs.append({"s": as_bytes(np.array([1000 * q + i for i in range(per)], np.int32))})
         ops.append([Send("s", 4 * i, 1, "int32", 0, 7 + i) for i in range(per)])
     return _queue(n, bufs, ops, "competing")
+
+
+# ------------------------------------------------------------ multiplex (§3.5)
+def multiplex_n_to_1(nthreads: int = 4, per: int = 3, racing: bool = False) -> Program:
+    """The paper's N-to-1 use of a multiplex stream communicator: rank 0 runs
+    ``nthreads`` threads, each on its own stream (index i), isending ``per``
+    messages (value 100 * i + j, tag 10 * i + j) to the single polling
+    thread of rank 1 (index 0), which receives them all on one communicator
+    with ANY_INDEX -- by tag, in reverse order (each match unique), or with
+    ANY_TAG as well (``racing``: the senders race)."""
+    from .program import ANY_INDEX
+    bufs = [{"s": as_bytes(np.array([100 * i + j for i in range(nthreads) for j in range(per)],
+                                    np.int32))},
+            {"r": np.zeros(4 * nthreads * per, np.uint8)}]
+    # request names are per rank: each thread uses its own
+    senders = [[Send("s", 4 * (i * per + j), 1, "int32", 1, 10 * i + j, req=f"m{i}_{j}",
+                     src_idx=i, dst_idx=0) for j in range(per)]
+               + [Wait([f"m{i}_{j}" for j in range(per)], [None] * per)] for i in range(nthreads)]
+    order = [(i, j) for i in range(nthreads) for j in range(per)]
+    if racing:
+        recv = [Recv("r", 4 * k, 1, "int32", 0, ANY_TAG, status=f"s{k}", src_idx=ANY_INDEX,
+                     dst_idx=0) for k in range(len(order))]
+    else:
+        recv = [Recv("r", 4 * k, 1, "int32", 0, 10 * i + j, status=f"s{k}", src_idx=ANY_INDEX,
+                     dst_idx=0) for k, (i, j) in enumerate(reversed(order))]
+    return Program(nranks=2, buffers=bufs, ops=[senders, [recv]], streams_per_rank=nthreads,
+                   comm_streams=[[list(range(nthreads)), [0]]],
+                   name=f"multiplex_{nthreads}to1" + ("_racing" if racing else ""))
+
+
+def multiplex_all_pairs(nthreads: int = 2) -> Program:
+    """Two ranks with ``nthreads`` streams each on one multiplex communicator:
+    thread i of each rank sends one message to every thread j of the other
+    rank (indices i -> j, value 1000 * rank + 10 * i + j) and receives one
+    from every thread of the other rank, addressed by index."""
+    bufs, ops = [], []
+    for r in range(2):
+        vals = [1000 * r + 10 * i + j for i in range(nthreads) for j in range(nthreads)]
+        bufs.append({"s": as_bytes(np.array(vals, np.int32)),
+                     "r": np.zeros(4 * nthreads * nthreads, np.uint8)})
+        threads = []
+        for i in range(nthreads):
+            lst = [Send("s", 4 * (i * nthreads + j), 1, "int32", 1 - r, 5, req=f"x{i}_{j}",
+                        src_idx=i, dst_idx=j) for j in range(nthreads)]
+            lst += [Recv("r", 4 * (i * nthreads + j), 1, "int32", 1 - r, 5, req=f"y{i}_{j}",
+                         src_idx=j, dst_idx=i) for j in range(nthreads)]
+            lst.append(Wait([f"x{i}_{j}" for j in range(nthreads)]
+                            + [f"y{i}_{j}" for j in range(nthreads)],
+                            [None] * nthreads + [f"st{i}_{j}" for j in range(nthreads)]))
+            threads.append(lst)
+        ops.append(threads)
+    return Program(nranks=2, buffers=bufs, ops=ops, streams_per_rank=nthreads,
+                   comm_streams=[[list(range(nthreads)), list(range(nthreads))]],
+                   name=f"multiplex_pairs_{nthreads}")

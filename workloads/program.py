@@ -36,6 +36,7 @@ BASIC_TYPES = {
 
 #: special argument values (as in MPI, wildcards are negative)
 ANY_SOURCE = -2
+ANY_INDEX = -3
 ANY_TAG = -1
 IN_PLACE = "__in_place__"
 
@@ -53,6 +54,9 @@ class Send:
     tag: int
     comm: int = 0
     req: Optional[str] = None        # set => isend
+    # multiplex communicators: stream indices (src_idx is this rank's)
+    src_idx: Optional[int] = None
+    dst_idx: Optional[int] = None
 
     @property
     def kind(self):
@@ -71,6 +75,10 @@ class Recv:
     comm: int = 0
     req: Optional[str] = None        # set => irecv
     status: Optional[str] = None
+    # multiplex communicators: stream indices (dst_idx is this rank's;
+    # src_idx may be ANY_INDEX)
+    src_idx: Optional[int] = None
+    dst_idx: Optional[int] = None
 
     @property
     def kind(self):
@@ -177,15 +185,13 @@ class Program:
             raise ValueError("one op table and one buffer set per rank")
         for r in range(self.nranks):
             owner = {}
+            req_thread = {}
             for t, lst in enumerate(self.ops[r]):
                 for o in lst:
-                    c = getattr(o, "comm", None)
-                    if isinstance(o, User):
-                        st = o.stream
-                    elif c is not None and 0 <= c < len(self.comm_streams):
-                        st = self.comm_streams[c][r]
-                    else:
-                        st = None
+                    name = getattr(o, "req", None)
+                    if name is not None and req_thread.setdefault(name, t) != t:
+                        raise ValueError(f"rank {r}: request {name!r} used by two threads")
+                    st = self.stream_of_op(r, o)
                     if st is None:
                         continue
                     if not 0 <= st < self.streams_per_rank:
@@ -201,8 +207,28 @@ class Program:
     def ncomms(self):
         return len(self.comm_streams)
 
+    def multiplex(self, comm: int) -> bool:
+        """A multiplex communicator lists several streams per rank."""
+        return any(isinstance(x, list) for x in self.comm_streams[comm])
+
     def stream_of(self, rank: int, comm: int) -> Optional[int]:
-        return self.comm_streams[comm][rank]
+        """The rank's single stream of a communicator (None for none, and for
+        multiplex communicators, which have no single stream)."""
+        x = self.comm_streams[comm][rank]
+        return None if isinstance(x, list) else x
+
+    def stream_of_op(self, rank: int, o) -> Optional[int]:
+        """The stream an operation of ``rank`` runs on, if any."""
+        if isinstance(o, User):
+            return o.stream
+        c = getattr(o, "comm", None)
+        if c is None or not (0 <= c < len(self.comm_streams)):
+            return None
+        x = self.comm_streams[c][rank]
+        if isinstance(x, list):
+            local = getattr(o, "src_idx" if isinstance(o, Send) else "dst_idx", None)
+            return x[local] if isinstance(local, int) and 0 <= local < len(x) else None
+        return x
 
     def copy_buffers(self) -> List[Dict[str, np.ndarray]]:
         return [{k: v.copy() for k, v in b.items()} for b in self.buffers]
@@ -250,12 +276,7 @@ def streams_of_thread(p: Program, rank: int, thread: int) -> List[int]:
     """Streams that thread ``thread`` of ``rank`` drives (in first-use order)."""
     out = []
     for o in p.ops[rank][thread]:
-        if isinstance(o, User):
-            st = o.stream
-        elif getattr(o, "comm", None) is not None and 0 <= o.comm < p.ncomms:
-            st = p.comm_streams[o.comm][rank]
-        else:
-            st = None
+        st = p.stream_of_op(rank, o)
         if st is not None and st not in out:
             out.append(st)
     return out
@@ -265,6 +286,6 @@ Tree = TypeTree
 __all__ = [
     "Program", "Send", "Recv", "Wait", "Allreduce", "User", "GroupStart", "GroupEnd",
     "GroupInit", "Start", "IN_PLACE",
-    "ANY_SOURCE", "ANY_TAG", "BASIC_TYPES", "as_bytes", "count_messages", "Tree",
+    "ANY_SOURCE", "ANY_TAG", "ANY_INDEX", "BASIC_TYPES", "as_bytes", "count_messages", "Tree",
     "single_stream", "footprint_bound", "streams_of_thread",
 ]
