@@ -795,6 +795,113 @@ def bench_serve(args):
     }
 
 
+# ------------------------------------------------------------------ N-to-1
+def bench_nto1(args):
+    """N-to-1 through a multiplex stream communicator (§3.5): rank 0 runs
+    N sender threads, each on its own stream, that isend M 8-byte messages
+    per step to the single polling thread of rank 1, which receives them all
+    on one communicator with ANY_INDEX / ANY_TAG.  Compared with N separate
+    stream communicators (the polling thread addresses each in turn) and
+    with the host-synchronised calls on those."""
+    import numpy as np
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+
+    n, per, steps, warm = args.nto1_senders, args.nto1_per_step, args.steps, args.warmup
+    S = [torch.arange(2 * per, dtype=torch.int32, device="cuda") + 1000 * (i + 1)
+         for i in range(n)]
+    R = {v: torch.zeros(2 * n * per, dtype=torch.int32, device="cuda")
+         for v in ("mux", "pairs", "host")}
+    torch.cuda.synchronize()
+    dt = M.BASIC["int32"]
+
+    def ops(variant, k):
+        senders, recv = [], []
+        for i in range(n):
+            rows = []
+            for _ in range(k):
+                for j in range(per):
+                    a = S[i].data_ptr() + 8 * j
+                    if variant == "mux":
+                        rows.append(dict(kind=D.STREAM_ISEND, comm=0, peer=1, tag=j, count=2,
+                                         datatype=dt, buf=a, req=j, op=i, pad=0))
+                    elif variant == "pairs":
+                        rows.append(dict(kind=D.ISEND, comm=1, peer=1, tag=j, count=2,
+                                         datatype=dt, buf=a, req=j))
+                    else:
+                        rows.append(dict(kind=D.SEND, comm=1, peer=1, tag=j, count=2,
+                                         datatype=dt, buf=a))
+                if variant != "host":
+                    rows.append(dict(kind=D.WAITALL, req=0, nreq=per))
+            senders.append(D.ops_array(rows))
+        rows = []
+        for _ in range(k):
+            slot = 0
+            for j in range(per):
+                for i in range(n):
+                    a = R[variant].data_ptr() + 8 * (j * n + i)
+                    if variant == "mux":
+                        rows.append(dict(kind=D.STREAM_IRECV, comm=0, peer=M.ANY_SOURCE,
+                                         tag=M.ANY_TAG, count=2, datatype=dt, buf=a, req=slot,
+                                         op=M.ANY_INDEX, pad=0))
+                    elif variant == "pairs":
+                        rows.append(dict(kind=D.IRECV, comm=1 + i, peer=0, tag=j, count=2,
+                                         datatype=dt, buf=a, req=slot))
+                    else:
+                        rows.append(dict(kind=D.RECV, comm=1 + i, peer=0, tag=j, count=2,
+                                         datatype=dt, buf=a))
+                    slot += 1
+            if variant != "host":
+                rows.append(dict(kind=D.WAITALL, req=0, nreq=slot))
+        return senders, D.ops_array(rows)
+
+    res = {}
+    for variant, mode in (("mux", 0), ("pairs", 0), ("host", 1)):
+        if variant == "host" and args.no_host_synced:
+            continue
+        sess = D.NTo1Session(n)
+        k = steps if variant != "host" else max(1, min(steps, args.hs_steps))
+        s_ops, r_ops = ops(variant, warm)
+        rc, r, _ = sess.run(s_ops, r_ops, mode=mode, max_reqs=n * per)
+        if rc:
+            raise RuntimeError(f"nto1 {variant}: {M.errname(rc)}")
+        s_ops, r_ops = ops(variant, k)
+        rc, r, _ = sess.run(s_ops, r_ops, mode=mode, max_reqs=n * per)
+        if rc:
+            raise RuntimeError(f"nto1 {variant}: {M.errname(rc)}")
+        if variant == "mux":
+            # one more step into a cleared buffer: across steps a wildcard
+            # receive may take a fast sender's next-step message, so the
+            # exact check is made on a single step, where every message
+            # meets exactly one of the step's receives
+            R["mux"].zero_()
+            torch.cuda.synchronize()
+            s_ops, r_ops = ops(variant, 1)
+            rc, _, _ = sess.run(s_ops, r_ops, mode=mode, max_reqs=n * per)
+            if rc:
+                raise RuntimeError(f"nto1 {variant}: {M.errname(rc)}")
+            torch.cuda.synchronize()
+            want = np.sort(np.concatenate([s.cpu().numpy() for s in S]))
+            if not np.array_equal(np.sort(R["mux"].cpu().numpy()), want):
+                raise AssertionError("multiplex N-to-1 lost or duplicated a message")
+        sess.close()
+        res[variant] = n * per * k / r.seconds
+        log(f"[nto1] {variant}: {res[variant]:.0f} msgs/s")
+    if "host" in res and not torch.equal(R["pairs"], R["host"]):
+        raise AssertionError("N-to-1 over pairs differs from the host-synchronised path")
+    return {
+        "metric": "enqueued msgs/s, N-to-1 over one multiplex communicator (8-byte messages)",
+        "value": res["mux"], "unit": "msgs/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": 1000.0 * n * per / res["mux"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": f"n_to_1_{n}senders_{per}msgs_per_step_8B"},
+        "separate_stream_comms": {"value": res["pairs"], "unit": "msgs/s"},
+        "host_synced": {"value": res.get("host"), "unit": "msgs/s",
+                        "speedup": res["mux"] / res["host"] if "host" in res else None},
+    }
+
+
 # ---------------------------------------------------------------- pingpong
 def bench_pingpong(args):
     import numpy as np
@@ -909,7 +1016,10 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="halo",
-                    choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch", "serve"])
+                    choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch", "serve",
+                             "nto1"])
+    ap.add_argument("--nto1-senders", type=int, default=8)
+    ap.add_argument("--nto1-per-step", type=int, default=16)
     ap.add_argument("--serve-ranks", type=int, default=64)
     ap.add_argument("--serve-rates", default="1e4,3e4,1e5,3e5,1e6")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
@@ -947,7 +1057,8 @@ def main():
               "(ranks are host threads sharing one MI355X)", file=sys.stderr)
         sys.exit(2)
     defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
-                "vcopy": (100, 10), "batch": (20, 5), "serve": (1, 0)}
+                "vcopy": (100, 10), "batch": (20, 5), "serve": (1, 0),
+                "nto1": (200, 20)}
     k, w = defaults[args.workload]
     args.steps = args.steps or k
     args.warmup = args.warmup if args.warmup is not None else w
@@ -960,7 +1071,8 @@ def main():
                 "roofline": vector_copy_roofline(args.count, args.steps)}
     else:
         fn = {"halo": bench_halo, "allreduce": bench_allreduce, "pingpong": bench_pingpong,
-              "copy": bench_copy, "batch": bench_batch, "serve": bench_serve}[args.workload]
+              "copy": bench_copy, "batch": bench_batch, "serve": bench_serve,
+              "nto1": bench_nto1}[args.workload]
         line = fn(args)
     print(json.dumps(line), flush=True)
 

@@ -33,7 +33,12 @@ enum {
     MPIXS_DRV_GROUP_END = 9,   /* mpixs_group_end(comm)                            */
     MPIXS_DRV_GROUP_INIT = 10, /* mpixs_group_end_init(comm, &batches[req])        */
     MPIXS_DRV_BATCH_START = 11, /* mpixs_batch_start_enqueue(batches[req])         */
-    MPIXS_DRV_BATCH_FREE = 12  /* mpixs_batch_free(&batches[req])                  */
+    MPIXS_DRV_BATCH_FREE = 12, /* mpixs_batch_free(&batches[req])                  */
+    /* multiplex communicators: src_idx in `op`, dst_idx in `pad` */
+    MPIXS_DRV_STREAM_SEND = 13,  /* mpixs_stream_send_enqueue                      */
+    MPIXS_DRV_STREAM_ISEND = 14, /* mpixs_stream_isend_enqueue into slot `req`     */
+    MPIXS_DRV_STREAM_RECV = 15,  /* mpixs_stream_recv_enqueue                      */
+    MPIXS_DRV_STREAM_IRECV = 16  /* mpixs_stream_irecv_enqueue into slot `req`     */
 };
 
 typedef struct {
@@ -53,7 +58,7 @@ typedef struct {
 } mpixs_drv_op;
 
 typedef struct {
-    mpixs_comm comms[8];     /* this thread's communicators */
+    mpixs_comm comms[16];    /* this thread's communicators */
     int32_t ncomms;
     int32_t nmarks;          /* HIP events this thread may record (MPIXS_DRV_MARK) */
     void *hip_stream;        /* the thread's hipStream_t, synchronised at the end */

@@ -65,6 +65,24 @@ int run_ops(const mpixs_drv_thread &t, int mode, std::vector<mpixs_request> &req
         }
         case MPIXS_DRV_GROUP_START: rc = mpixs_group_start(c); break;
         case MPIXS_DRV_GROUP_END: rc = mpixs_group_end(c); break;
+        case MPIXS_DRV_STREAM_SEND:
+            rc = mpixs_stream_send_enqueue(reinterpret_cast<const void *>(o.buf), o.count,
+                                           o.datatype, o.peer, o.tag, c, o.op, o.pad);
+            break;
+        case MPIXS_DRV_STREAM_ISEND:
+            rc = mpixs_stream_isend_enqueue(reinterpret_cast<const void *>(o.buf), o.count,
+                                            o.datatype, o.peer, o.tag, c, o.op, o.pad,
+                                            &reqs[size_t(o.req)]);
+            break;
+        case MPIXS_DRV_STREAM_RECV:
+            rc = mpixs_stream_recv_enqueue(reinterpret_cast<void *>(o.buf), o.count, o.datatype,
+                                           o.peer, o.tag, c, o.op, o.pad,
+                                           reinterpret_cast<mpixs_status *>(o.status));
+            break;
+        case MPIXS_DRV_STREAM_IRECV:
+            rc = mpixs_stream_irecv_enqueue(reinterpret_cast<void *>(o.buf), o.count, o.datatype,
+                                            o.peer, o.tag, c, o.op, o.pad, &reqs[size_t(o.req)]);
+            break;
         case MPIXS_DRV_GROUP_INIT:
         case MPIXS_DRV_BATCH_START:
         case MPIXS_DRV_BATCH_FREE:
@@ -98,6 +116,8 @@ int run_ops(const mpixs_drv_thread &t, int mode, std::vector<mpixs_request> &req
 extern "C" int mpixs_drv_run(mpixs_world world, int nthreads, const mpixs_drv_thread *threads,
                              int mode, mpixs_drv_result *result, double *marks_ms) {
     if (!world || nthreads <= 0 || !threads || !result) return MPIXS_ERR_ARG;
+    for (int i = 0; i < nthreads; ++i)
+        if (threads[i].ncomms < 0 || threads[i].ncomms > 16) return MPIXS_ERR_ARG;
     std::vector<ThreadOut> outs(static_cast<size_t>(nthreads));
     int max_marks = 0;
     for (int i = 0; i < nthreads; ++i) {

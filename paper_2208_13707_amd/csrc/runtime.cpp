@@ -513,9 +513,20 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     int rc = MPIXS_SUCCESS;
     if (found) {
         lk.unlock();
-        // second of the pair: the partner's ready post is already enqueued
+        // second of the pair: the partner publishes its operation in the
+        // queue before it enqueues its ready post (so that launches happen
+        // outside the queue lock); wait for that post to be enqueued, so the
+        // device wait below never precedes its producer
         Channel *ch = partner.ch;
         Rec *rec = partner.rec;
+        const uint32_t other = side == 0 ? ARR_R : ARR_S;
+        rc = host_wait(w, &rec->arrived, [&] {
+            return (rec->arrived.load(std::memory_order_acquire) & other) != 0;
+        });
+        if (rc) {
+            delete r;
+            return rc;
+        }
         {
             std::lock_guard<std::mutex> g(ch->mu);
             (side == 0 ? rec->s : rec->r) = mine;
@@ -540,8 +551,9 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
         }
         return rc;
     }
-    // first of the pair: a fresh one-message channel, posted while the queue
-    // is locked so that no partner can enqueue its wait before this post
+    // first of the pair: a fresh one-message channel, published in the queue
+    // and then posted outside the lock (a partner waits on the host until
+    // the post is enqueued)
     const uint32_t idx = w->chan_next.fetch_add(1);
     if (idx >= w->chan_cap) {
         delete r;
@@ -552,13 +564,6 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     ch->d = w->d_chans + idx;
     Rec *rec = ch->at(0);
     (side == 0 ? rec->s : rec->r) = mine;
-    rc = do_post(w, st, &ch->d->ready[side], 1);
-    if (rc) {
-        delete ch;
-        delete r;
-        return rc;
-    }
-    rec->arrived.fetch_or(side == 0 ? ARR_S : ARR_R, std::memory_order_release);
     QOp op;
     op.ch = ch;
     op.rec = rec;
@@ -567,6 +572,16 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     op.tag = tag;
     (side == 0 ? q.unexpected : q.posted).push_back(op);
     lk.unlock();
+    rc = do_post(w, st, &ch->d->ready[side], 1);
+    rec->arrived.fetch_or(side == 0 ? ARR_S : ARR_R, std::memory_order_release);
+    host_notify(&rec->arrived);
+    if (rc) {
+        // the operation is already visible to partners: stop the world
+        // rather than leave one waiting for a post that never comes
+        mpixs_world_abort(reinterpret_cast<mpixs_world>(w));
+        delete r;
+        return rc;
+    }
     if (!r) return complete_first(w, st, ch, rec, 0, side, status);
     r->comm = c;
     r->ch = ch;

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 DRIVER_PATH = os.path.join(_HERE, "libmpixs_driver.so")
 
 (SEND, ISEND, RECV, IRECV, WAITALL, ALLREDUCE, MARK, GROUP_START, GROUP_END, GROUP_INIT,
- BATCH_START, BATCH_FREE) = range(1, 13)
+ BATCH_START, BATCH_FREE, STREAM_SEND, STREAM_ISEND, STREAM_RECV, STREAM_IRECV) = range(1, 17)
 BATCH_SLOTS = 8
 
 OP_DTYPE = np.dtype([
@@ -32,7 +32,7 @@ assert OP_DTYPE.itemsize == 64
 
 
 class DrvThread(ctypes.Structure):
-    _fields_ = [("comms", ctypes.c_void_p * 8), ("ncomms", ctypes.c_int32),
+    _fields_ = [("comms", ctypes.c_void_p * 16), ("ncomms", ctypes.c_int32),
                 ("nmarks", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("ops", ctypes.c_void_p), ("nops", ctypes.c_int64),
                 ("max_reqs", ctypes.c_int32), ("nbatches", ctypes.c_int32),
@@ -232,3 +232,82 @@ class Session:
         M.mpixs_world_free(self.world)
         for s in self.hs:
             hip_stream_destroy(s)
+
+
+class NTo1Session:
+    """Two ranks for an N-to-1 pattern (§3.5): rank 0 has ``nsend`` threads,
+    each with its own stream; rank 1 has one polling thread with one stream.
+    Communicators: ``mux`` (one multiplex communicator over all of them, per
+    rank) and, for comparison, ``pair[i]`` (one stream communicator joining
+    sender stream i and the polling stream)."""
+
+    def __init__(self, nsend: int, cfg: Optional[M.Config] = None):
+        import torch
+        torch.cuda.init()
+        self.nsend = nsend
+        self.hs0 = [hip_stream_create() for _ in range(nsend)]
+        self.hs1 = hip_stream_create()
+        rc, self.world = M.mpixs_world_create(2, cfg)
+        if rc:
+            raise RuntimeError(f"world_create: {M.errname(rc)}")
+        self.s0, self.s1 = [], None
+        self.mux = [None, None]
+        self.pair = [[None, None] for _ in range(nsend)]
+        errs = []
+
+        def mk(h):
+            rc, info = M.mpixs_info_create()
+            M.mpixs_info_set(info, "type", "hipStream_t")
+            M.mpixs_info_set_hex(info, "value", struct.pack("<Q", h))
+            rc, s = M.mpixs_stream_create(self.world, info)
+            assert rc == 0, M.errname(rc)
+            M.mpixs_info_free(info)
+            return s
+
+        def setup(r):
+            try:
+                rc, wc = M.mpixs_world_comm(self.world, r)
+                if r == 0:
+                    self.s0 = [mk(h) for h in self.hs0]
+                    mine = self.s0
+                else:
+                    self.s1 = mk(self.hs1)
+                    mine = [self.s1]
+                rc, c = M.mpixs_comm_create_multiplex(wc, mine)
+                assert rc == 0, M.errname(rc)
+                self.mux[r] = c
+                for i in range(nsend):
+                    rc, c = M.mpixs_comm_create_with_stream(wc, self.s0[i] if r == 0 else self.s1)
+                    assert rc == 0, M.errname(rc)
+                    self.pair[i][r] = c
+            except Exception as e:  # pragma: no cover - reported below
+                errs.append(repr(e))
+
+        th = [threading.Thread(target=setup, args=(r,)) for r in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if errs:
+            raise RuntimeError("; ".join(errs))
+
+    def run(self, sender_ops, receiver_ops, mode=0, max_reqs=64):
+        """sender_ops[i]: thread i of rank 0 (communicators [mux, pair[i]]);
+        receiver_ops: the polling thread (communicators [mux, pair[0..n-1]])."""
+        comms = [[self.mux[0], self.pair[i][0]] for i in range(self.nsend)]
+        comms.append([self.mux[1]] + [self.pair[i][1] for i in range(self.nsend)])
+        return mpixs_drv_run(self.world, list(sender_ops) + [receiver_ops], comms,
+                             list(self.hs0) + [self.hs1], mode=mode, max_reqs=max_reqs)
+
+    def close(self):
+        import torch
+        torch.cuda.synchronize()
+        for r in range(2):
+            M.mpixs_comm_free(self.mux[r])
+            for i in range(self.nsend):
+                M.mpixs_comm_free(self.pair[i][r])
+        for s in self.s0 + [self.s1]:
+            M.mpixs_stream_free(s)
+        M.mpixs_world_free(self.world)
+        for h in self.hs0 + [self.hs1]:
+            hip_stream_destroy(h)
