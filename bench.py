@@ -16,7 +16,8 @@ oracle timed on a bounded sample of the same workload.
 
 Other workloads (--workload): pingpong (2 ranks, 1000 x 4 KiB int32),
 allreduce (16 ranks, SUM, --bytes per rank, --dtype), copy (one contiguous
-message of --bytes between two ranks).
+message of --bytes between two ranks), batch, serve, nto1, and hostrate (CPU
+only: the host message-rate model of three engine locking policies).
 """
 from __future__ import annotations
 
@@ -902,6 +903,43 @@ def bench_nto1(args):
     }
 
 
+# ---------------------------------------------------------------- hostrate
+def bench_hostrate(args):
+    """CPU only: the host message-rate model under the three engine policies
+    (global critical section, per-context critical sections, stream contexts),
+    8-byte isend / irecv in windows of 64, 1..P thread pairs; best of 3."""
+    from paper_2208_13707_amd import driver as D
+    cpus = len(os.sched_getaffinity(0))
+    pairs = [p for p in (1, 2, 4, 8, 16) if 2 * p <= cpus] or [1]
+    per = args.hostrate_msgs
+    want = {}
+    curves = {}
+    for pol in ("global", "per_context", "stream"):
+        curves[pol] = []
+        for p in pairs:
+            best = 0.0
+            for _ in range(3):
+                rc, rate, ck = D.mpixs_drv_host_msgrate(p, pol, per, 64)
+                if rc:
+                    raise RuntimeError(f"host_msgrate({p}, {pol}): rc {rc}")
+                if want.setdefault(p, ck) != ck:
+                    raise AssertionError(f"host_msgrate checksum differs ({p} pairs, {pol})")
+                best = max(best, rate)
+            curves[pol].append(best)
+            log(f"[hostrate] {pol} {p} pairs: {best / 1e6:.2f} M msgs/s")
+    top = curves["stream"][-1]
+    return {
+        "metric": "host message rate, 8-byte isend/irecv (CPU model, no GPU)",
+        "value": top, "unit": "msgs/s", "n_gpus": 0, "steps": per, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"host_msgrate_{pairs[-1]}pairs_window64_{per}msgs_per_pair",
+                   "thread_pairs": pairs, "cpus": cpus},
+        "curves_msgs_per_s": curves,
+        "stream_vs_per_context": [s / v for s, v in zip(curves["stream"], curves["per_context"])],
+    }
+
+
 # ---------------------------------------------------------------- pingpong
 def bench_pingpong(args):
     import numpy as np
@@ -1017,7 +1055,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="halo",
                     choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch", "serve",
-                             "nto1"])
+                             "nto1", "hostrate"])
+    ap.add_argument("--hostrate-msgs", type=int, default=1000000,
+                    help="hostrate: messages per thread pair")
     ap.add_argument("--nto1-senders", type=int, default=8)
     ap.add_argument("--nto1-per-step", type=int, default=16)
     ap.add_argument("--serve-ranks", type=int, default=64)
@@ -1058,12 +1098,15 @@ def main():
         sys.exit(2)
     defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
                 "vcopy": (100, 10), "batch": (20, 5), "serve": (1, 0),
-                "nto1": (200, 20)}
+                "nto1": (200, 20), "hostrate": (1, 0)}
     k, w = defaults[args.workload]
     args.steps = args.steps or k
     args.warmup = args.warmup if args.warmup is not None else w
     if args.bytes is None:
         args.bytes = {"allreduce": 64 << 20, "copy": 1 << 30}.get(args.workload, 0)
+    if args.workload == "hostrate":
+        print(json.dumps(bench_hostrate(args)), flush=True)
+        return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "vcopy":

@@ -134,6 +134,27 @@ int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *comms,
                     void *const *streams, const mpixs_drv_req *reqs, int64_t nreq,
                     int64_t budget_bytes, mpixs_drv_req_result *results, double *wall_s);
 
+/* ------------------------------------------------ host message-rate model
+ * A CPU-only analog of the paper's multithreaded message-rate measurement
+ * (§5.3, Fig. 3).  Thread i of a simulated sender process sends
+ * msgs_per_pair 8-byte messages to thread i of a simulated receiver process
+ * (npairs pairs, 2 * npairs threads), each thread on its own context, in
+ * windows of `window` isends (irecvs) closed by a waitall; at most two
+ * windows are in flight.  The message engine (request objects, posted and
+ * unexpected queues, progress) is synchronised by policy 0 (one critical
+ * section per process, held for each call and yielded between progress
+ * passes), 1 (one mutex per context, taken separately on the send path, the
+ * receive path, each progress pass and each request release) or 2 (stream
+ * contexts: no locks).  Completion flags and request reference counts are
+ * atomic in every policy.  *msgs_per_s receives the total message rate;
+ * *checksum (may be NULL) the sum over pairs i and messages n of
+ * (i * 2^40 + n) * (n + 1) modulo 2^64 as received, which holds only if
+ * every message arrived once and in order.  Returns 0, or 1 for bad
+ * arguments (npairs 1..256, policy 0..2, msgs_per_pair >= 1, window
+ * 1..1024).  Does not touch the GPU. */
+int mpixs_drv_host_msgrate(int npairs, int policy, int64_t msgs_per_pair, int window,
+                           double *msgs_per_s, uint64_t *checksum);
+
 /* Run the threads; mode 0 = enqueue calls, 1 = host-synchronised calls.
  * marks_ms (optional, nthreads * max nmarks doubles, row-major by thread)
  * receives the time of every recorded mark relative to thread 0's mark 0.

@@ -151,6 +151,23 @@ def mpixs_drv_serve(world, comms, streams, reqs: np.ndarray, budget_bytes: int):
     return rc, res[: len(reqs)], wall.value
 
 
+HOST_POLICIES = {"global": 0, "per_context": 1, "stream": 2}
+
+
+def mpixs_drv_host_msgrate(npairs: int, policy: str, msgs_per_pair: int, window: int = 64):
+    """CPU-only message-rate model (no GPU): returns (rc, msgs/s, checksum)."""
+    L = dlib()
+    f = L.mpixs_drv_host_msgrate
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]
+    f.restype = ctypes.c_int
+    rate = ctypes.c_double()
+    ck = ctypes.c_uint64()
+    rc = f(npairs, HOST_POLICIES.get(policy, -1) if isinstance(policy, str) else policy,
+           msgs_per_pair, window, ctypes.byref(rate), ctypes.byref(ck))
+    return rc, rate.value, ck.value
+
+
 def requests_array(sched) -> np.ndarray:
     a = np.zeros(len(sched), dtype=REQ_DTYPE)
     for i, q in enumerate(sched):
