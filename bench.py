@@ -148,6 +148,7 @@ def halo_batch_cfg(M, args):
     c.batch_max_wg = args.batch_max_wg
     c.batch_graph = args.batch_graph
     c.batch_nontemporal = args.batch_nt
+    c.batch_sync = args.batch_sync
     return c
 
 
@@ -628,12 +629,13 @@ def bench_batch(args):
         return out
 
     # schedule of the persistent batch: chosen by the autotuner, or given
-    sched = dict(tile=args.batch_tile, max_wg=args.batch_max_wg, graph=args.batch_graph)
+    sched = dict(tile=args.batch_tile, max_wg=args.batch_max_wg, graph=args.batch_graph,
+                 sync=args.batch_sync)
     if args.kernel_only:
         # counter runs: plan the batch (no GPU waits) and launch its kernel only
         from paper_2208_13707_amd import tune
         sess = D.Session(n, tune.config_for(sched["tile"], sched["max_wg"], sched["graph"],
-                                   nontemporal=args.batch_nt))
+                                            nontemporal=args.batch_nt, sync=sched["sync"]))
         run_checked(sess, ops("persistent", 0), max_reqs=maxreq)
         us, payload, nwg = time_batch_kernel(sess, args.steps)
         sess.close()
@@ -644,7 +646,7 @@ def bench_batch(args):
         from paper_2208_13707_amd import tune
         best, rows = tune.tune_batch(n, lambda: ops("tune", 0), lambda k: ops("tune", k),
                                      runs=max(20, args.steps), warm=3, max_reqs=maxreq, log=log)
-        sched = {k: best[k] for k in ("tile", "max_wg", "graph")}
+        sched = {k: best[k] for k in ("tile", "max_wg", "graph", "sync")}
         tuned = {"chosen": best, "grid": rows}
 
     res = {}
@@ -660,7 +662,7 @@ def bench_batch(args):
         if variant == "persistent":
             from paper_2208_13707_amd import tune
             cfg = tune.config_for(sched["tile"], sched["max_wg"], sched["graph"],
-                                   nontemporal=args.batch_nt)
+                                  nontemporal=args.batch_nt, sync=sched["sync"])
         sess = D.Session(n, cfg)
         if variant == "persistent":
             init_ms = 1000 * run_checked(sess, ops(variant, 0, tagb), max_reqs=maxreq)[0]
@@ -676,6 +678,7 @@ def bench_batch(args):
             f"sleep timeouts {st.host_sleep_timeouts} over {reps * k} batches")
         if variant == "persistent":
             bk = time_batch_kernel(sess, 20)
+            log(f"[batch] persistent: batch kernel alone {bk[0]:.1f} us")
         sess.close()
         res[variant] = npairs * k / sec
         log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.3f} ms per batch)")
@@ -1078,6 +1081,8 @@ def main():
     ap.add_argument("--batch-graph", type=int, default=0)
     ap.add_argument("--batch-nt", type=int, default=0,
                     help="batch kernel nontemporal accesses: 0 auto, 1 on, 2 off")
+    ap.add_argument("--batch-sync", type=int, default=0,
+                    help="persistent batches: 0 device counters, 1 HIP events")
     ap.add_argument("--ranks-batch", type=int, default=32)
     ap.add_argument("--count", type=int, default=43690)
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")

@@ -143,7 +143,13 @@ typedef struct {
                                  (comm, source, destination, tag) channel, wildcards
                                  rejected; 1 ordered queues per destination, receives may
                                  use MPIXS_ANY_SOURCE / MPIXS_ANY_TAG [0] */
-    int32_t reserved[3];
+    int32_t batch_sync;       /* persistent batches: how a run's arrivals and completion
+                                 are ordered across the ranks' streams: 0 device counters
+                                 (an arrival kernel on every rank, a wait kernel and a
+                                 signal kernel around the batch kernel), 1 HIP events
+                                 (hipEventRecord / hipStreamWaitEvent, no extra kernels;
+                                 not with batch_graph = 1) [0] */
+    int32_t reserved[2];
 } mpixs_config;
 
 /* -------------------------------------------------------------- world (N ranks)
@@ -385,7 +391,11 @@ int mpixs_group_end(mpixs_comm comm);
  *   and a signal; every other rank enqueues an arrival and a wait.  The
  *   kernels keep their counters relative (they count runs on the device),
  *   so their arguments are the same for every run and the launching rank's
- *   part can be replayed as one HIP graph (mpixs_config.batch_graph).  Like
+ *   part can be replayed as one HIP graph (mpixs_config.batch_graph).  With
+ *   mpixs_config.batch_sync = 1 the arrivals and the completion are HIP
+ *   events instead (each other rank records one, the launching rank's
+ *   stream waits for them, runs the batch kernel and records one that the
+ *   other streams wait for): no arrival, wait or signal kernel.  Like
  *   the other enqueue calls it may wait on the host until the peers have
  *   enqueued their part of the run, never for GPU work.
  *   MPIXS_ERR_REQUEST for a NULL handle; MPIXS_ERR_ARG inside an open group.

@@ -21,17 +21,21 @@ namespace mpixs {
 template <int TILE, bool NT, int W, int SK, int DK>
 __device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     using T = typename Unit<W>::T;
-    constexpr int U = TILE / COPY_THREADS;
-    // a tile of TILE * 16 bytes is 16 / W chunks of TILE units
-    for (uint64_t c0 = u0; c0 < u1; c0 += TILE) {
-        T v[U];
+    // a tile holds TILE * 16 / W units, K per lane; a lane issues up to 8
+    // loads before its first store, so a tile of narrow units costs one
+    // memory round trip instead of one per chunk (the stores could alias
+    // later loads, so the compiler cannot hoist them by itself)
+    constexpr int K = TILE / COPY_THREADS * (16 / W);
+    constexpr int B = K < 8 ? K : 8;
+    for (uint64_t c0 = u0; c0 < u1; c0 += uint64_t(B) * COPY_THREADS) {
+        T v[B];
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
+        for (int k = 0; k < B; ++k) {
             const uint64_t u = c0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
             if (u < u1) v[k] = ld_unit<T, NT>(map_addr<SK, W>(d.src, u));
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
+        for (int k = 0; k < B; ++k) {
             const uint64_t u = c0 + threadIdx.x + uint64_t(k) * COPY_THREADS;
             if (u < u1) st_unit<T, NT>(map_addr<DK, W>(d.dst, u), v[k]);
         }

@@ -1155,6 +1155,18 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     P->sig.done_ptr = P->d_ctr + 16 * n;
     P->sig.inc = 1;
     P->sig.me = st->dev;
+    if (w->cfg.batch_sync == 1) {
+        // event dependencies instead of counters: rank q records post_ev[q]
+        // after its prior work, the leader's stream waits for those, runs the
+        // batch kernel and records done_ev, every other stream waits for it
+        P->post_ev.assign(size_t(n), nullptr);
+        for (int q = 0; q < n; ++q)
+            if (q != me && hipEventCreateWithFlags(&P->post_ev[size_t(q)], hipEventDisableTiming) !=
+                               hipSuccess)
+                return MPIXS_ERR_GPU;
+        if (hipEventCreateWithFlags(&P->done_ev, hipEventDisableTiming) != hipSuccess)
+            return MPIXS_ERR_GPU;
+    }
     if (w->cfg.batch_graph) {
         if (build_batch_graph(&P->graph, n > 1 ? &P->lwait : nullptr, P->args, P->nwg, P->sig) !=
                 hipSuccess ||
@@ -1213,6 +1225,9 @@ CommShared::~CommShared() {
 }
 
 BatchPlan::~BatchPlan() {
+    for (hipEvent_t e : post_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (done_ev) (void)hipEventDestroy(done_ev);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (d_mem) (void)hipFree(d_mem);
@@ -1240,7 +1255,8 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     if (c.batch_max_wg <= 0) c.batch_max_wg = 16384;
     if (!batch_tile_ok(uint32_t(c.batch_tile)) || c.batch_max_wg > (1 << 20) ||
         c.batch_graph < 0 || c.batch_graph > 1 || c.batch_nontemporal < 0 ||
-        c.batch_nontemporal > 2 || c.matching < 0 || c.matching > 1) {
+        c.batch_nontemporal > 2 || c.matching < 0 || c.matching > 1 || c.batch_sync < 0 ||
+        c.batch_sync > 1 || (c.batch_sync == 1 && c.batch_graph == 1)) {
         delete w;
         return MPIXS_ERR_ARG;
     }
@@ -1903,7 +1919,16 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
             rc = host_wait(w, &P->posted[q], [&] { return P->posted[q].load(std::memory_order_acquire) >= e; });
         }
         if (!rc) {
-            if (P->exec) {
+            if (P->done_ev) {
+                // each follower recorded its event for run e before posting
+                // e, and records it again only after its wait for this run,
+                // which comes after this launch (followers wait for
+                // `launched`), so every wait here sees run e's record
+                for (int q = 0; q < P->n && !rc; ++q)
+                    if (q != P->leader) rc = gpu_err(hipStreamWaitEvent(st->hs, P->post_ev[size_t(q)], 0));
+                if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
+                if (!rc) rc = gpu_err(hipEventRecord(P->done_ev, st->hs));
+            } else if (P->exec) {
                 rc = gpu_err(hipGraphLaunch(P->exec, st->hs));
             } else {
                 if (P->n > 1) rc = gpu_err(launch_wait_rel(st->hs, P->lwait));
@@ -1922,14 +1947,20 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
             w->bytes_copied.fetch_add(P->bytes, std::memory_order_relaxed);
         }
     } else {
-        rc = gpu_err(launch_post_inc(st->hs, P->d_ctr + 16 * b->rank));
+        if (P->done_ev) rc = gpu_err(hipEventRecord(P->post_ev[size_t(b->rank)], st->hs));
+        else rc = gpu_err(launch_post_inc(st->hs, P->d_ctr + 16 * b->rank));
         if (rc) return rc;
         P->posted[b->rank].store(e, std::memory_order_release);
         host_notify(&P->posted[b->rank]);
         w->n_post.fetch_add(1, std::memory_order_relaxed);
         rc = host_wait(w, &P->launched, [&] { return P->launched.load(std::memory_order_acquire) >= e; });
         if (!rc) rc = P->launch_err.load();
-        if (!rc) {
+        if (!rc && P->done_ev) {
+            // the leader recorded run e's completion before publishing e,
+            // and records run e + 1 only after this rank posted e + 1
+            rc = gpu_err(hipStreamWaitEvent(st->hs, P->done_ev, 0));
+            w->n_wait.fetch_add(1, std::memory_order_relaxed);
+        } else if (!rc) {
             RelWaitArgs a;
             std::memset(&a, 0, sizeof(a));
             a.ptr0 = P->d_ctr + 16 * P->n;

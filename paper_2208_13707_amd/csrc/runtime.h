@@ -158,6 +158,8 @@ struct BatchPlan {
     uint64_t nmsg = 0, bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> post_ev;    // batch_sync = 1: per rank, recorded at its arrival
+    hipEvent_t done_ev = nullptr;       // batch_sync = 1: recorded after the batch kernel
     std::unique_ptr<std::atomic<uint64_t>[]> posted;   // runs whose arrival rank q has enqueued
     std::atomic<uint64_t> launched{0};                  // runs the leader has enqueued
     std::atomic<int> launch_err{0};

@@ -43,7 +43,8 @@ class Config(ctypes.Structure):
                 ("max_collectives", ctypes.c_int32), ("batch_arena_mib", ctypes.c_int32),
                 ("batch_tile", ctypes.c_int32), ("batch_max_wg", ctypes.c_int32),
                 ("batch_graph", ctypes.c_int32), ("batch_nontemporal", ctypes.c_int32),
-                ("matching", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("matching", ctypes.c_int32), ("batch_sync", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Status(ctypes.Structure):

@@ -83,9 +83,11 @@ def test_bad_batch_schedule_is_rejected_before_any_gpu_call(lib):
     """Invalid batch schedules fail with ERR_ARG while the world is validated,
     before the library touches the device (so this runs without a GPU)."""
     from paper_2208_13707_amd import mpixs as M
-    for field, value in (("batch_tile", 300), ("batch_tile", 8192), ("batch_graph", 2),
-                         ("batch_max_wg", 1 << 21)):
+    for fields in ({"batch_tile": 300}, {"batch_tile": 8192}, {"batch_graph": 2},
+                   {"batch_max_wg": 1 << 21}, {"batch_sync": 2}, {"batch_sync": -1},
+                   {"batch_sync": 1, "batch_graph": 1}):
         c = M.Config()
-        setattr(c, field, value)
+        for field, value in fields.items():
+            setattr(c, field, value)
         rc, w = M.mpixs_world_create(2, c)
-        assert M.errname(rc) == "ERR_ARG" and not w, (field, value)
+        assert M.errname(rc) == "ERR_ARG" and not w, fields

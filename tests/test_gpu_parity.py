@@ -237,24 +237,29 @@ def test_group_head_to_head_and_unmatched():
 from workloads.program import GroupInit, Start  # noqa: E402
 
 
-@pytest.mark.parametrize("count,blocking,graph", [(37, True, 0), (2730, False, 1),
-                                                  (43690, True, 0)])
-def test_persistent_ring_halo(count, blocking, graph):
+@pytest.mark.parametrize("count,blocking,graph,sync", [(37, True, 0, 0), (2730, False, 1, 0),
+                                                       (43690, True, 0, 0), (37, False, 0, 1),
+                                                       (43690, True, 0, 1)])
+def test_persistent_ring_halo(count, blocking, graph, sync):
     check(C.ring_halo(count=count, steps=4, update=True, blocking_recv=blocking, persistent=True),
-          cfg=cfg_with(batch_graph=graph), name=f"persistent halo c{count} graph={graph}")
+          cfg=cfg_with(batch_graph=graph, batch_sync=sync),
+          name=f"persistent halo c{count} graph={graph} sync={sync}")
 
 
-@pytest.mark.parametrize("tile,max_wg,graph", [(1024, 4096, 0), (256, 7, 1), (4096, 3, 0),
-                                               (512, 1 << 16, 1), (2048, 100, 0)])
-def test_persistent_batch_schedules(tile, max_wg, graph):
+@pytest.mark.parametrize("tile,max_wg,graph,sync", [(1024, 4096, 0, 0), (256, 7, 1, 0),
+                                                    (4096, 3, 0, 1), (512, 1 << 16, 1, 0),
+                                                    (2048, 100, 0, 1)])
+def test_persistent_batch_schedules(tile, max_wg, graph, sync):
     check(C.batch(npairs=400, nranks=8, max_bytes=65536, runs=3),
-          cfg=cfg_with(batch_tile=tile, batch_max_wg=max_wg, batch_graph=graph),
-          name=f"persistent batch tile={tile} max_wg={max_wg} graph={graph}")
+          cfg=cfg_with(batch_tile=tile, batch_max_wg=max_wg, batch_graph=graph, batch_sync=sync),
+          name=f"persistent batch tile={tile} max_wg={max_wg} graph={graph} sync={sync}")
 
 
-def test_persistent_batch_config_size():
+@pytest.mark.parametrize("graph,sync", [(1, 0), (0, 1)])
+def test_persistent_batch_config_size(graph, sync):
     """10,000 messages over 32 ranks, planned once, started 3 times."""
-    check(C.batch(npairs=10000, nranks=32, runs=3), cfg=cfg_with(batch_graph=1))
+    check(C.batch(npairs=10000, nranks=32, runs=3), cfg=cfg_with(batch_graph=graph, batch_sync=sync),
+          name=f"persistent batch 10000 msgs graph={graph} sync={sync}")
 
 
 def test_persistent_errors():
