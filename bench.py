@@ -171,6 +171,15 @@ def time_batch_kernel(sess, reps):
     return avg.value, nbytes.value, nwg.value
 
 
+def close_checked(sess):
+    """Close a session after checking that no rank's stream recorded an
+    asynchronous error (a copy or wait that failed on the device)."""
+    errs = sess.stream_errors()
+    sess.close()
+    if any(errs):
+        raise RuntimeError(f"asynchronous stream errors: {errs}")
+
+
 def run_checked(sess, ops, mode=0, nmarks=0, max_reqs=64):
     from paper_2208_13707_amd import mpixs as M
     rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
@@ -266,7 +275,7 @@ def bench_halo(args):
         run_checked(sess, [halo_persistent_ops(D, r, n, A[r], H[r], vt, 0, init=True)
                            for r in range(n)])
         us, payload, nwg = time_batch_kernel(sess, steps)
-        sess.close()
+        close_checked(sess)
         return {"workload": "halo batch kernel only", "avg_launch_us": us,
                 "payload_bytes": payload, "workgroups": nwg, "launches": steps + 1}
     counts = [args.count] + ([c for c in C.HALO_COUNTS if c != args.count] if args.sweep else [])
@@ -299,7 +308,7 @@ def bench_halo(args):
         _, marks = run_checked(sess, ops, nmarks=2 * steps)
         lat = step_latencies(marks, steps)
         res.update(p50_step_us=pct(lat, 50), p99_step_us=pct(lat, 99))
-        sess.close()
+        close_checked(sess)
         # ---- batched: every step's operations form one group (one kernel)
         Hg = [torch.from_numpy(p.buffers[r]["H"].copy()).cuda() for r in range(n)]
         torch.cuda.synchronize()
@@ -312,7 +321,7 @@ def bench_halo(args):
                for r in range(n)]
         _, marks = run_checked(sess, ops, nmarks=2 * steps)
         lat_g = step_latencies(marks, steps)
-        sess.close()
+        close_checked(sess)
         res.update(grouped_msgs_per_s=msgs / sec_g, grouped_ms_per_step=1000 * sec_g / steps,
                    grouped_p50_step_us=pct(lat_g, 50), grouped_p99_step_us=pct(lat_g, 99))
         for r in range(n):
@@ -335,7 +344,7 @@ def bench_halo(args):
             bk_us, bk_payload, bk_wg = time_batch_kernel(sess, max(20, steps))
             res["batch_kernel"] = {"avg_launch_us": bk_us, "payload_bytes": bk_payload,
                                    "workgroups": bk_wg}
-        sess.close()
+        close_checked(sess)
         res.update(persistent_msgs_per_s=msgs / sec_p, persistent_ms_per_step=1000 * sec_p / steps,
                    persistent_p50_step_us=pct(lat_p, 50), persistent_p99_step_us=pct(lat_p, 99))
         for r in range(n):
@@ -360,7 +369,7 @@ def bench_halo(args):
             run_checked(sess, ops, mode=1)
             ops = [halo_ops(D, r, n, A[r], H2[r], vt, hs_steps, 10000, 1) for r in range(n)]
             sec_hs, _ = run_checked(sess, ops, mode=1)
-            sess.close()
+            close_checked(sess)
             res["host_synced_msgs_per_s"] = 16 * hs_steps / sec_hs
             res["speedup_vs_host_synced"] = res["msgs_per_s"] / res["host_synced_msgs_per_s"]
             for r in range(n):
@@ -483,13 +492,13 @@ def bench_allreduce(args):
         # path runs the same reduce kernel without them
         run_checked(sess, ops(args.warmup), mode=1)
         run_checked(sess, ops(args.steps), mode=1)
-        sess.close()
+        close_checked(sess)
         return {"workload": f"allreduce_{n}r_{dtype}_{nbytes}B", "via": "host-synced"}
     run_checked(sess, ops(args.warmup))
     sec, _ = run_checked(sess, ops(args.steps))
     _, marks = run_checked(sess, ops(args.steps, True), nmarks=2 * args.steps)
     lat = step_latencies(marks, args.steps)
-    sess.close()
+    close_checked(sess)
     # sampled check against the oracle's fold (every 4097th element)
     from oracle import reduce as red
     idx = np.arange(0, count, 4097)
@@ -504,7 +513,7 @@ def bench_allreduce(args):
         run_checked(sess, ops(min(args.warmup, 3)), mode=1)
         k = max(1, min(args.steps, args.hs_steps))
         sec_hs, _ = run_checked(sess, ops(k), mode=1)
-        sess.close()
+        close_checked(sess)
         hs = k / sec_hs
     cfg = M.Config()
     cfg.profile = 1
@@ -512,7 +521,7 @@ def bench_allreduce(args):
     run_checked(sess, ops(args.steps))
     torch.cuda.synchronize()
     st = sess.stats()
-    sess.close()
+    close_checked(sess)
     avg_us = 1000 * st.reduce_ms / max(1, st.timed_reduce)
     per_launch = 2 * n * nbytes
     achieved = per_launch / (avg_us * 1e-6) / 1e9
@@ -638,7 +647,7 @@ def bench_batch(args):
                                             nontemporal=args.batch_nt, sync=sched["sync"]))
         run_checked(sess, ops("persistent", 0), max_reqs=maxreq)
         us, payload, nwg = time_batch_kernel(sess, args.steps)
-        sess.close()
+        close_checked(sess)
         return {"workload": "batch kernel only", "avg_launch_us": us, "payload_bytes": payload,
                 "workgroups": nwg, "launches": args.steps + 1}
     tuned = None
@@ -679,7 +688,7 @@ def bench_batch(args):
         if variant == "persistent":
             bk = time_batch_kernel(sess, 20)
             log(f"[batch] persistent: batch kernel alone {bk[0]:.1f} us")
-        sess.close()
+        close_checked(sess)
         res[variant] = npairs * k / sec
         log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.3f} ms per batch)")
     if args.only_grouped:
@@ -785,7 +794,7 @@ def bench_serve(args):
             log(f"[serve] offered {rate:9.0f}/s: served {row['served_per_s']:9.0f}/s, "
                 f"p50 {row['p50_latency_us']:8.1f} us, p99 {row['p99_latency_us']:9.1f} us")
     finally:
-        sess.close()
+        close_checked(sess)
     best = max(rows, key=lambda r: r["served_per_s"] or 0)
     return {
         "metric": "served requests/s with p50/p99 latency (open-loop Poisson arrivals)",
@@ -889,7 +898,7 @@ def bench_nto1(args):
             want = np.sort(np.concatenate([s.cpu().numpy() for s in S]))
             if not np.array_equal(np.sort(R["mux"].cpu().numpy()), want):
                 raise AssertionError("multiplex N-to-1 lost or duplicated a message")
-        sess.close()
+        close_checked(sess)
         res[variant] = n * per * k / r.seconds
         log(f"[nto1] {variant}: {res[variant]:.0f} msgs/s")
     if "host" in res and not torch.equal(R["pairs"], R["host"]):
@@ -981,7 +990,7 @@ def bench_pingpong(args):
             rtt = [(marks[0, 2 * s + 1] - marks[0, 2 * s]) * 1000 for s in range(nmsg // 2)]
             out["one_way_p50_us"] = pct(rtt, 50) / 2
             out["one_way_p99_us"] = pct(rtt, 99) / 2
-        sess.close()
+        close_checked(sess)
         out[mode] = nmsg / sec
     assert np.array_equal(X[0].cpu().numpy(), p.buffers[0]["x"]), "echo changed the data"
     return {
@@ -1021,14 +1030,14 @@ def bench_copy(args):
     if args.via_host_synced:
         run_checked(sess, ops(args.warmup), mode=1)
         run_checked(sess, ops(args.steps), mode=1)
-        sess.close()
+        close_checked(sess)
         return {"workload": f"send_recv_contiguous_{nbytes}B_2ranks", "via": "host-synced"}
     run_checked(sess, ops(args.warmup))
     sess.reset_stats()
     sec, _ = run_checked(sess, ops(args.steps))
     torch.cuda.synchronize()
     st = sess.stats()
-    sess.close()
+    close_checked(sess)
     assert torch.equal(src, dst)
     gbps = 2 * nbytes * args.steps / sec / 1e9
     line = {

@@ -234,6 +234,15 @@ class Session:
     def stats(self):
         return M.mpixs_world_get_stats(self.world)[1]
 
+    def stream_errors(self):
+        """First asynchronous error of every rank's stream (0: none); read
+        after the streams are idle."""
+        out = []
+        for s in self.streams:
+            rc, e = M.mpixs_stream_get_error(s)
+            out.append(e if rc == 0 else rc)
+        return out
+
     def reset_stats(self):
         M.mpixs_world_reset_stats(self.world)
 
@@ -315,6 +324,14 @@ class NTo1Session:
         comms.append([self.mux[1]] + [self.pair[i][1] for i in range(self.nsend)])
         return mpixs_drv_run(self.world, list(sender_ops) + [receiver_ops], comms,
                              list(self.hs0) + [self.hs1], mode=mode, max_reqs=max_reqs)
+
+    def stream_errors(self):
+        """First asynchronous error of every stream (0: none)."""
+        out = []
+        for s in list(self.s0) + [self.s1]:
+            rc, e = M.mpixs_stream_get_error(s)
+            out.append(e if rc == 0 else rc)
+        return out
 
     def close(self):
         import torch
