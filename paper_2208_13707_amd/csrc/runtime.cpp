@@ -155,7 +155,7 @@ WaitCtl ctl_of(World *w) {
 
 bool profile_on(World *w) { return w->cfg.profile != 0; }
 
-void prof_begin(World *w, hipStream_t s, hipEvent_t *e0) {
+void prof_begin(World *, hipStream_t s, hipEvent_t *e0) {
     (void)hipEventCreate(e0);
     (void)hipEventRecord(*e0, s);
 }

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256) k_checksum(const uint8_t *p, int64_t n, u
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if (threadIdx.x < unsigned(o)) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
