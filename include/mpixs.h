@@ -51,7 +51,8 @@ extern "C" {
 enum {
     MPIXS_SUCCESS = 0,
     MPIXS_ERR_ARG = 1,          /* invalid argument (NULL handle, size out of range) */
-    MPIXS_ERR_COUNT = 2,        /* negative count */
+    MPIXS_ERR_COUNT = 2,        /* negative count; a message of 2^32 bytes or more whose
+                                   datatype is not dense (its device unit index is 32-bit) */
     MPIXS_ERR_TYPE = 3,         /* bad or uncommitted datatype; overlapping receive type;
                                    signature mismatch (asynchronous) */
     MPIXS_ERR_RANK = 4,         /* peer rank out of range, or a wildcard where none is allowed */
@@ -268,6 +269,10 @@ int mpixs_type_get_extent(mpixs_datatype type, int64_t *lb, int64_t *extent);
  *                 transfer; *req is consumed and set to NULL at this call.
  *  waitall_enqueue: requests must all belong to one stream (§3.4), else
  *                 MPIXS_ERR_STREAM; statuses may be NULL.
+ *  Sizes: a message whose datatype is dense (its element is one contiguous
+ *  block: a basic type, a contiguous type, a vector or indexed type that
+ *  reduces to one block) may have any byte count; any other message must
+ *  stay below 2^32 bytes (else MPIXS_ERR_COUNT, with no side effect).
  *
  * Host blocking: a call never waits for the GPU.  A call whose stream must
  * wait for the peer's stream may wait, on the host, until the peer thread
