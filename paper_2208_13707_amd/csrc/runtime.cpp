@@ -1053,7 +1053,7 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     const int n = sh->size;
     std::vector<BatchDesc> descs;
     std::vector<BatchStart> starts;
-    BatchArgs a;
+    BatchArgs a{};
     uint64_t bytes = 0;
     int rc = plan_group(w, rec, n, descs, starts, a, &bytes);
     if (rc) return rc;

@@ -356,3 +356,11 @@ def test_multiplex_argument_errors():
              Send("s", 4, 1, "int32", 1, 3, src_idx=1, dst_idx=0)]],
            [[Recv("r", 0, 1, "int32", 0, ANY_TAG, src_idx=ANY_INDEX, dst_idx=0, status="x")]]]
     check(Program(2, b, ops, 2, [[[0, 1], [0]]], name="multiplex-errors"))
+
+
+# -------------------------------------------------------------- degenerate
+@pytest.mark.parametrize("k", range(2))
+def test_degenerate_programs(k):
+    """A one-rank world (self messages, one-rank and zero-count allreduce);
+    empty one-shot and persistent groups, zero-count allreduce."""
+    check(C.degenerate_programs()[k])

@@ -515,3 +515,20 @@ def test_multiplex_argument_errors():
                                 (0, 3, "ERR_COMM"), (0, 4, "ERR_COMM")]
     assert i32(r.buffers[1]["r"]).tolist()[0] == 2
     assert r.statuses[1]["x"] == (0, 3, "SUCCESS", 4)
+
+
+def test_degenerate_programs():
+    """One rank: a message to itself is delivered, an allreduce over one rank
+    is the identity, a zero-count allreduce writes nothing; empty groups,
+    one-shot and persistent, move nothing."""
+    one, two = C.degenerate_programs()
+    r = sim.run(one)
+    assert not r.deadlock and not any(r.sync_errors)
+    assert i32(r.buffers[0]["b"]).tolist() == [1, 2, 3, 4, 5]
+    assert i32(r.buffers[0]["c"]).tolist() == [1, 2, 3, 4, 5]
+    assert r.statuses[0]["st"] == (0, 7, "SUCCESS", 20)
+    r = sim.run(two)
+    assert not r.deadlock and not any(r.sync_errors)
+    for q in range(2):
+        assert i32(r.buffers[q]["y"]).tolist() == [2, -2, 7]
+        assert i32(r.buffers[q]["x"]).tolist() == [q + 1, -(q + 2), 7 * q]

@@ -465,3 +465,25 @@ def multiplex_all_pairs(nthreads: int = 2) -> Program:
     return Program(nranks=2, buffers=bufs, ops=ops, streams_per_rank=nthreads,
                    comm_streams=[[list(range(nthreads)), list(range(nthreads))]],
                    name=f"multiplex_pairs_{nthreads}")
+
+
+# ------------------------------------------------------------- degenerate
+def degenerate_programs():
+    """Degenerate cases: a one-rank world (messages to itself, an allreduce
+    over one rank, a zero-count allreduce), and two ranks with an empty
+    one-shot group, a zero-count allreduce, and an empty persistent group
+    started twice."""
+    out = []
+    b = [{"a": as_bytes(np.arange(1, 6, dtype=np.int32)), "b": np.zeros(20, np.uint8),
+          "c": np.zeros(20, np.uint8)}]
+    ops = [[Send("a", 0, 5, "int32", 0, 7, req="s"), Recv("b", 0, 5, "int32", 0, 7, status="st"),
+            Wait(["s"], [None]), Allreduce("a", 0, "c", 0, 5, "int32", "sum"),
+            Allreduce("a", 0, "c", 0, 0, "int32", "sum")]]
+    out.append(single_stream(1, b, ops, name="one-rank"))
+    b = [{"x": as_bytes(np.array([r + 1, -(r + 2), 7 * r], np.int32)), "y": np.zeros(12, np.uint8)}
+         for r in range(2)]
+    ops = [[GroupStart(), GroupEnd(), Allreduce("x", 0, "y", 0, 0, "int32", "sum"),
+            Allreduce("x", 0, "y", 0, 3, "int32", "max"), GroupStart(), GroupInit("e"),
+            Start("e"), Start("e")] for _ in range(2)]
+    out.append(single_stream(2, b, ops, name="empty-groups"))
+    return out
