@@ -687,7 +687,8 @@ def bench_batch(args):
         sec = secs[len(secs) // 2]
         st = sess.stats()
         log(f"[batch] {variant}: host waits {st.host_waits}, sleeps {st.host_sleeps}, "
-            f"sleep timeouts {st.host_sleep_timeouts} over {reps * k} batches")
+            f"sleep timeouts {st.host_sleep_timeouts} over {reps * k} batches, "
+            f"{st.groups_planned} plans in {st.plan_ms:.1f} ms")
         if variant == "persistent":
             bk = time_batch_kernel(sess, 20)
             log(f"[batch] persistent: batch kernel alone {bk[0]:.1f} us")

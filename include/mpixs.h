@@ -443,6 +443,8 @@ typedef struct {
     double reduce_ms;
     uint64_t host_sleeps;       /* host waits that went to sleep (futex) at least once */
     uint64_t host_sleep_timeouts; /* sleeps that ended by their 1 ms bound, not a wake-up */
+    uint64_t groups_planned;    /* group instances matched and planned (one-shot or init) */
+    double plan_ms;             /* host time the planning ranks spent on them */
 } mpixs_stats;
 
 /* Counters of the world since creation (or the last reset).  With

@@ -65,8 +65,11 @@ constexpr uint64_t kFusedMaxWG = 32;
 
 int gpu_err(hipError_t e) { return e == hipSuccess ? MPIXS_SUCCESS : MPIXS_ERR_GPU; }
 
+// Distinct (source, destination, tag) give distinct keys: ranks are below
+// 4096 (12 bits each, bits 44..55 and 32..43), tags below 2^31 (bits
+// 0..30); bit 63 is left for the host-synchronised mode.
 uint64_t chan_key(int src, int dst, int tag) {
-    return (uint64_t(uint32_t(src)) << 44) ^ (uint64_t(uint32_t(dst)) << 24) ^ uint64_t(uint32_t(tag));
+    return (uint64_t(uint32_t(src)) << 44) | (uint64_t(uint32_t(dst)) << 32) | uint64_t(uint32_t(tag));
 }
 
 // Host sleeping.  Rank threads often outnumber the host's cores, so a
@@ -972,35 +975,81 @@ int arena_alloc(World *w, size_t bytes, size_t *off, int *flag) {
 // tag t), plan each copy, and cut the group into tiles: one descriptor per
 // message and, per workgroup, the (message, tile) it starts at.  Fills
 // everything of `a` except the descriptor / start pointers.
-int plan_group(World *w, GroupRec *rec, int n, std::vector<BatchDesc> &descs,
-               std::vector<BatchStart> &starts, BatchArgs &a, uint64_t *bytes) {
-    struct Q {
-        std::vector<GOp *> s, r;
-        int tag = 0;
-    };
-    std::unordered_map<uint64_t, Q> chans;
+int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, BatchArgs &a, uint64_t *bytes) {
+    struct PlanTimer {   // host time of this plan, for the diagnostics counters
+        World *w;
+        std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+        ~PlanTimer() {
+            const auto ns = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                std::chrono::steady_clock::now() - t0).count();
+            w->plan_ns.fetch_add(uint64_t(ns), std::memory_order_relaxed);
+            w->groups_planned.fetch_add(1, std::memory_order_relaxed);
+        }
+    } timer{w};
+    // Matching in two linear passes over flat arrays (no per-channel
+    // containers): an open-addressing table numbers the channels in order of
+    // first appearance and counts each channel's sends and receives; the
+    // second pass lays the sends and the receives out channel by channel in
+    // program order, so the i-th send of a channel sits beside its i-th
+    // receive.  The arrays belong to the communicator and keep their memory
+    // from one instance to the next (instances of a communicator are planned
+    // one at a time, under plan_mu).
+    PlanScratch &z = sh->plan;
     size_t nops = 0;
     for (int q = 0; q < n; ++q) nops += rec->ops[size_t(q)].size();
-    chans.reserve(nops);
+    size_t cap = 16;
+    while (cap < 2 * nops) cap <<= 1;
+    constexpr uint64_t kEmpty = ~uint64_t(0);   // no channel key has bit 63 set
+    z.table.assign(cap, PlanScratch::Slot{kEmpty, 0});
+    z.chan_of.resize(nops);
+    z.nsend.clear();
+    z.nrecv.clear();
+    z.ctag.clear();
+    size_t k = 0;
     for (int q = 0; q < n; ++q)
         for (GOp &op : rec->ops[size_t(q)]) {
-            Q &e = chans[op.kind == 0 ? chan_key(q, op.peer, op.tag) : chan_key(op.peer, q, op.tag)];
-            e.tag = op.tag;
-            (op.kind == 0 ? e.s : e.r).push_back(&op);
+            const uint64_t key = op.kind == 0 ? chan_key(q, op.peer, op.tag) : chan_key(op.peer, q, op.tag);
+            size_t h = size_t((key * 0x9E3779B97F4A7C15ull) >> 17) & (cap - 1);
+            while (z.table[h].key != kEmpty && z.table[h].key != key) h = (h + 1) & (cap - 1);
+            if (z.table[h].key == kEmpty) {
+                z.table[h] = PlanScratch::Slot{key, uint32_t(z.nsend.size())};
+                z.nsend.push_back(0);
+                z.nrecv.push_back(0);
+                z.ctag.push_back(op.tag);
+            }
+            const uint32_t c = z.table[h].chan;
+            z.chan_of[k++] = c;
+            ++(op.kind == 0 ? z.nsend : z.nrecv)[c];
         }
-    for (auto &kv : chans)
-        if (kv.second.s.size() != kv.second.r.size()) return MPIXS_ERR_ARG;
+    const size_t nch = z.nsend.size();
+    z.first.assign(nch + 1, 0);   // first pair of each channel
+    for (size_t c = 0; c < nch; ++c) {
+        if (z.nsend[c] != z.nrecv[c]) return MPIXS_ERR_ARG;
+        z.first[c + 1] = z.first[c] + z.nsend[c];
+    }
+    const size_t npairs = z.first[nch];
+    z.s_of.resize(npairs);
+    z.r_of.resize(npairs);
+    z.fill_s.assign(z.first.begin(), z.first.end() - 1);
+    z.fill_r = z.fill_s;
+    k = 0;
+    for (int q = 0; q < n; ++q)
+        for (GOp &op : rec->ops[size_t(q)]) {
+            const uint32_t c = z.chan_of[k++];
+            if (op.kind == 0) z.s_of[z.fill_s[c]++] = &op;
+            else z.r_of[z.fill_r[c]++] = &op;
+        }
     const uint32_t tile = uint32_t(w->cfg.batch_tile);
-    descs.clear();
-    descs.reserve(nops / 2 + 1);
+    std::vector<BatchDesc> &descs = z.descs;
+    descs.resize(npairs);
     uint64_t total_tiles = 0;
     *bytes = 0;
-    for (auto &kv : chans) {
-        const int tag = kv.second.tag;
-        for (size_t i = 0; i < kv.second.s.size(); ++i) {
-            GOp *S = kv.second.s[i];
-            GOp *R = kv.second.r[i];
-            BatchDesc d;
+    for (size_t c = 0; c < nch; ++c) {
+        const int tag = z.ctag[c];
+        for (size_t i = z.first[c]; i < z.first[c + 1]; ++i) {
+            GOp *S = z.s_of[i];
+            GOp *R = z.r_of[i];
+            BatchDesc &d = descs[i];
             std::memset(&d, 0, sizeof(d));
             d.st = match_status(S->side, R->side, tag);
             int wsz = 16;
@@ -1015,9 +1064,9 @@ int plan_group(World *w, GroupRec *rec, int n, std::vector<BatchDesc> &descs,
             if (R->req) R->req->st = d.st;
             total_tiles += d.ntiles;
             *bytes += uint64_t(d.st.count_bytes);
-            descs.push_back(d);
         }
     }
+    std::vector<BatchStart> &starts = z.starts;
     std::memset(&a, 0, sizeof(a));
     a.tile = tile;
     starts.clear();
@@ -1051,11 +1100,12 @@ int plan_group(World *w, GroupRec *rec, int n, std::vector<BatchDesc> &descs,
 // arena, whose range the signal kernel hands back through a host flag.
 int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st, uint64_t g) {
     const int n = sh->size;
-    std::vector<BatchDesc> descs;
-    std::vector<BatchStart> starts;
+    std::lock_guard<std::mutex> plan_lock(sh->plan_mu);
+    const std::vector<BatchDesc> &descs = sh->plan.descs;
+    const std::vector<BatchStart> &starts = sh->plan.starts;
     BatchArgs a{};
     uint64_t bytes = 0;
-    int rc = plan_group(w, rec, n, descs, starts, a, &bytes);
+    int rc = plan_group(w, sh, rec, n, a, &bytes);
     if (rc) return rc;
     uint64_t *arrive = sh->d_grp;
     uint64_t *done = sh->d_grp + 16 * n;
@@ -1116,9 +1166,10 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     P->leader = me;
     P->posted.reset(new std::atomic<uint64_t>[size_t(n)]);
     for (int q = 0; q < n; ++q) P->posted[q].store(0);
-    std::vector<BatchDesc> descs;
-    std::vector<BatchStart> starts;
-    int rc = plan_group(w, rec, n, descs, starts, P->args, &P->bytes);
+    std::lock_guard<std::mutex> plan_lock(sh->plan_mu);
+    const std::vector<BatchDesc> &descs = sh->plan.descs;
+    const std::vector<BatchStart> &starts = sh->plan.starts;
+    int rc = plan_group(w, sh, rec, n, P->args, &P->bytes);
     if (rc) return rc;
     P->nmsg = descs.size();
     // an empty group still runs one workgroup, which publishes the run
@@ -2141,6 +2192,8 @@ int mpixs_world_get_stats(mpixs_world w, mpixs_stats *s) {
     s->host_waits = w->host_waits.load();
     s->host_sleeps = w->host_sleeps.load();
     s->host_sleep_timeouts = w->host_sleep_timeouts.load();
+    s->groups_planned = w->groups_planned.load();
+    s->plan_ms = double(w->plan_ns.load()) * 1e-6;
     s->timed_copy = w->timed_copy;
     s->copy_ms = w->copy_ms;
     s->timed_reduce = w->timed_reduce;
@@ -2156,6 +2209,8 @@ int mpixs_world_reset_stats(mpixs_world w) {
     w->n_wait = 0;
     w->host_sleeps = 0;
     w->host_sleep_timeouts = 0;
+    w->groups_planned = 0;
+    w->plan_ns = 0;
     w->n_copy = 0;
     w->n_reduce = 0;
     w->bytes_copied = 0;

@@ -190,6 +190,22 @@ struct MatchQueue {
     std::deque<QOp> posted;            // receives, in post order
 };
 
+// Working arrays of group planning, kept by a communicator so that their
+// memory is reused from one group instance to the next.
+struct PlanScratch {
+    struct Slot {
+        uint64_t key;
+        uint32_t chan;
+    };
+    std::vector<Slot> table;            // open addressing: channel key -> channel
+    std::vector<uint32_t> chan_of;      // channel of every grouped operation
+    std::vector<uint32_t> nsend, nrecv, first, fill_s, fill_r;
+    std::vector<int> ctag;
+    std::vector<GOp *> s_of, r_of;      // pair i: its send and its receive
+    std::vector<BatchDesc> descs;
+    std::vector<BatchStart> starts;
+};
+
 struct CommShared {
     World *w = nullptr;
     int size = 0;
@@ -206,6 +222,8 @@ struct CommShared {
     uint64_t *d_grp = nullptr;         // groups: arrive[q] at 16*q, done at 16*size
     std::mutex grp_mu;
     std::deque<GroupRec *> groups;
+    std::mutex plan_mu;                // one group plan at a time uses `plan`
+    PlanScratch plan;
     uint64_t group_base = 0;
     std::mutex create_mu;
     std::map<uint64_t, CreateRec> creates;
@@ -299,6 +317,7 @@ struct World {
     std::atomic<uint64_t> n_post{0}, n_wait{0}, n_copy{0}, n_reduce{0};
     std::atomic<uint64_t> bytes_copied{0}, bytes_reduced{0}, host_waits{0};
     std::atomic<uint64_t> host_sleeps{0}, host_sleep_timeouts{0};
+    std::atomic<uint64_t> groups_planned{0}, plan_ns{0};
     // host-pinned (coherent) ring of batch descriptor tables; an entry is
     // recycled once the batch's signal kernel has set its flag
     struct ArenaUse {

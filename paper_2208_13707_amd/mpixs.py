@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("host_waits", ctypes.c_uint64), ("timed_copy", ctypes.c_uint64),
                 ("copy_ms", ctypes.c_double), ("timed_reduce", ctypes.c_uint64),
                 ("reduce_ms", ctypes.c_double), ("host_sleeps", ctypes.c_uint64),
-                ("host_sleep_timeouts", ctypes.c_uint64)]
+                ("host_sleep_timeouts", ctypes.c_uint64), ("groups_planned", ctypes.c_uint64),
+                ("plan_ms", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p

@@ -364,3 +364,9 @@ def test_degenerate_programs(k):
     """A one-rank world (self messages, one-rank and zero-count allreduce);
     empty one-shot and persistent groups, zero-count allreduce."""
     check(C.degenerate_programs()[k])
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_large_tags_keep_channels_apart(grouped):
+    """Channels whose tags share bits with shifted rank numbers stay apart."""
+    check(C.large_tag_program(grouped))

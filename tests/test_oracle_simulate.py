@@ -532,3 +532,14 @@ def test_degenerate_programs():
     for q in range(2):
         assert i32(r.buffers[q]["y"]).tolist() == [2, -2, 7]
         assert i32(r.buffers[q]["x"]).tolist() == [q + 1, -(q + 2), 7 * q]
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_large_tags_keep_channels_apart(grouped):
+    r = sim.run(C.large_tag_program(grouped))
+    assert not r.deadlock and not any(r.sync_errors)
+    assert i32(r.buffers[0]["r"]).tolist() == [22, 44, 55]
+    assert i32(r.buffers[1]["r"]).tolist() == [11, 33]
+    assert r.statuses[0]["self"] == (0, 1 << 24, "SUCCESS", 4)
+    assert r.statuses[0]["b5"] == (1, (1 << 24) + 5, "SUCCESS", 4)
+    assert r.statuses[1]["max"] == (0, (1 << 31) - 1, "SUCCESS", 4)

@@ -487,3 +487,27 @@ def degenerate_programs():
             Start("e"), Start("e")] for _ in range(2)]
     out.append(single_stream(2, b, ops, name="empty-groups"))
     return out
+
+
+def large_tag_program(grouped=False):
+    """Tags that share low bits with rank numbers shifted into a packed key:
+    (0 -> 1, tag 0) next to (0 -> 0, tag 2^24), (1 -> 0, tag 2^24 + 5) and
+    the largest tag, 2^31 - 1.  Each channel must stay separate.  grouped:
+    each rank's calls form one group."""
+    big = 1 << 24
+    b = [{"s": as_bytes(np.array([11, 22, 33], np.int32)), "r": np.zeros(12, np.uint8)},
+         {"s": as_bytes(np.array([44, 55], np.int32)), "r": np.zeros(8, np.uint8)}]
+    ops = [[Send("s", 0, 1, "int32", 1, 0, req="x"), Send("s", 4, 1, "int32", 0, big, req="y"),
+            Recv("r", 0, 1, "int32", 0, big, status="self"),
+            Recv("r", 4, 1, "int32", 1, big + 5, status="b5"),
+            Recv("r", 8, 1, "int32", 1, (1 << 31) - 1, status="max"),
+            Send("s", 8, 1, "int32", 1, (1 << 31) - 1),
+            Wait(["x", "y"], [None, None])],
+           [Recv("r", 0, 1, "int32", 0, 0, status="t0"),
+            Send("s", 0, 1, "int32", 0, big + 5, req="z"),
+            Send("s", 4, 1, "int32", 0, (1 << 31) - 1, req="w"),
+            Recv("r", 4, 1, "int32", 0, (1 << 31) - 1, status="max"),
+            Wait(["z", "w"], [None, None])]]
+    if grouped:
+        ops = [[GroupStart()] + o + [GroupEnd()] for o in ops]
+    return single_stream(2, b, ops, name="large-tags" + ("-grouped" if grouped else ""))
