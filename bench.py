@@ -1111,8 +1111,8 @@ def main():
                     help="copy/allreduce: run only the host-synchronised path (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(ranks are host threads sharing one MI355X)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: ranks are host threads "
+              "sharing one MI355X", file=sys.stderr)
         sys.exit(2)
     defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
                 "vcopy": (100, 10), "batch": (20, 5), "serve": (1, 0),
