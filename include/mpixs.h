@@ -327,7 +327,16 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
  *  Every grouped send must be matched inside the same group instance, else
  *  group_end returns MPIXS_ERR_ARG on every rank and no copy of the group
  *  runs.  A channel used inside groups must not also be used outside them.
- *  allreduce_enqueue inside a group fails with MPIXS_ERR_ARG.
+ *  allreduce_enqueue inside a group is recorded too: the i-th grouped
+ *  allreduce of every rank forms the group's i-th reduction, which the
+ *  launching rank's stream runs after the batch kernel, in order (so a
+ *  group of many small allreduces costs one arrival and one wait per rank
+ *  plus one reduce kernel each, instead of two launches per rank each).
+ *  Ranks that grouped different numbers of allreduces, or whose i-th calls
+ *  differ in count, datatype or operation, make group_end (or
+ *  group_end_init) return MPIXS_ERR_ARG on every rank; nothing of the group
+ *  runs.  Reductions must not read or write buffers that the group's
+ *  messages write.
  *  mpixs_group_end waits on the host until every rank has called it.
  */
 /* --------------------------------------- multiplex stream communicators (§3.5)

@@ -44,7 +44,11 @@ What it states, and where the paper fixes it:
   operation is not grouped in the same instance makes the whole instance
   fail: no message of it moves and every rank's GroupEnd reports ERR_ARG.
   A wait on a grouped request inside its group delivers the status at the
-  group's end.
+  group's end.  Allreduces inside a group are recorded too: the i-th grouped
+  allreduce of every rank forms the instance's i-th reduction, run at the
+  group's end after its messages have moved, in order; ranks that grouped
+  different numbers of allreduces, or i-th calls that differ in count, type
+  or operation, fail the instance like an unmatched message.
 * Persistent groups (the same extension, with MPI's persistent-request
   model of init once, start many times): a group closed by GroupInit is
   recorded, not run.  GroupInit is collective; it fails with ERR_ARG on
@@ -200,6 +204,18 @@ def _one_block(t) -> bool:
     return bool(d.size == 0 or np.array_equal(d, d[0] + t.esize * np.arange(d.size)))
 
 
+def _colls_agree(colls, nranks) -> bool:
+    """The grouped allreduces of an instance form collectives: every rank made
+    as many, and the i-th of each rank agree in count, type and operation."""
+    lists = [colls.get(q, []) for q in range(nranks)]
+    if len({len(x) for x in lists}) > 1:
+        return False
+    for i in range(len(lists[0])):
+        if len({(x[i].count, x[i].dtype, x[i].op) for x in lists}) > 1:
+            return False
+    return True
+
+
 def _check_allreduce(p: Program, rank: int, op: Allreduce) -> Optional[str]:
     if not (0 <= op.comm < p.ncomms) or p.stream_of(rank, op.comm) is None:
         return "ERR_COMM"
@@ -249,6 +265,7 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
     group_msgs: Dict[Tuple[int, int], list] = {}
     group_ok: Dict[Tuple[int, int], bool] = {}
     group_after: Dict[Tuple[int, int], list] = {}
+    group_colls: Dict[tuple, Dict[int, list]] = {}             # grp -> rank -> allreduces
     # persistent groups
     persist_open: Dict[Tuple[int, int], str] = {}              # (rank, comm) -> batch name
     batch_ops: Dict[Tuple[int, str], list] = {}                # (rank, batch) -> recorded ops
@@ -269,8 +286,11 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         return out
 
     def record_grouped(rank, op, grp):
-        """Post a send / receive / wait inside group ``grp`` (a one-shot
-        group instance, or a run of a persistent batch)."""
+        """Post a send / receive / wait / allreduce inside group ``grp`` (a
+        one-shot group instance, or a run of a persistent batch)."""
+        if isinstance(op, Allreduce):
+            group_colls.setdefault(grp, {}).setdefault(rank, []).append(op)
+            return
         if isinstance(op, Wait):
             # each request's status arrives at the end of its own group
             for n, st_name in zip(op.reqs, op.statuses):
@@ -308,7 +328,10 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
                 elif isinstance(o, Recv):
                     key = (o.comm, o.source, rank, o.tag)
                     count[key] = count.get(key, 0) - 1
-        batch_ok[name] = not batch_bad.get(name, False) and all(v == 0 for v in count.values())
+        colls = {rank: [o for o in ops if isinstance(o, Allreduce)]
+                 for (rank, b), ops in batch_ops.items() if b == name}
+        batch_ok[name] = (not batch_bad.get(name, False) and all(v == 0 for v in count.values())
+                          and _colls_agree(colls, p.nranks))
 
     def chan(key):
         if key not in chans:
@@ -412,9 +435,11 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
 
     def end_group(comm, inst):
         """All ranks reached GroupEnd instance ``inst`` of ``comm``: move its
-        messages, or fail the instance if one is unmatched inside it."""
+        messages, then run its allreduces in order, or fail the instance if a
+        message is unmatched inside it or its allreduces disagree."""
         msgs = group_msgs.get((comm, inst), [])
-        ok = True
+        colls = group_colls.pop((comm, inst), {})
+        ok = _colls_agree(colls, p.nranks)
         for key, k in msgs:
             c = chans[key]
             s, r = c.sends.get(k), c.recvs.get(k)
@@ -424,9 +449,26 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
             for key, k in sorted(set(msgs)):
                 if not chans[key].sends[k].done:
                     transfer(key, k)
+            for i in range(len(colls.get(0, []))):
+                reduce_instance({q: colls[q][i] for q in range(p.nranks)})
         group_ok[(comm, inst)] = ok
         for fn in group_after.pop((comm, inst), []):
             fn(ok)
+
+    def reduce_instance(inst):
+        """One allreduce over every rank: inst[q] is rank q's call."""
+        op = inst[0]
+        ins = []
+        for q in range(p.nranks):
+            a = inst[q]
+            src = a.recvbuf if a.sendbuf == IN_PLACE else a.sendbuf
+            off = a.roff if a.sendbuf == IN_PLACE else a.soff
+            n = a.count * red.NP_DTYPE[a.dtype]().itemsize
+            ins.append(bufs[q][src][off: off + n])
+        out = red.allreduce_bytes(op.op, op.dtype, op.count, ins)
+        for q in range(p.nranks):
+            a = inst[q]
+            bufs[q][a.recvbuf][a.roff: a.roff + out.size] = out
 
     def arrive(rank, op: Allreduce):
         k = coll_next.get((op.comm, rank), 0)
@@ -434,17 +476,7 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
         inst = coll.setdefault((op.comm, k), {})
         inst[rank] = op
         if len(inst) == p.nranks:
-            ins = []
-            for q in range(p.nranks):
-                a = inst[q]
-                src = a.recvbuf if a.sendbuf == IN_PLACE else a.sendbuf
-                off = a.roff if a.sendbuf == IN_PLACE else a.soff
-                n = a.count * red.NP_DTYPE[a.dtype]().itemsize
-                ins.append(bufs[q][src][off: off + n])
-            out = red.allreduce_bytes(op.op, op.dtype, op.count, ins)
-            for q in range(p.nranks):
-                a = inst[q]
-                bufs[q][a.recvbuf][a.roff: a.roff + out.size] = out
+            reduce_instance(inst)
             coll_done[(op.comm, k)] = True
         return (op.comm, k)
 
@@ -562,10 +594,19 @@ def run(p: Program, max_rounds: int = 10_000_000) -> Result:
             return step(ctx)
         if isinstance(op, Allreduce):
             err = _check_allreduce(p, rank, op)
-            if not err and (rank, op.comm) in group_open:
-                err = "ERR_ARG"          # collectives are not grouped
             if err:
                 sync_errors[rank].append((ctx.thread, ctx.pc, err))
+                ctx.pc += 1
+                return True
+            grp = group_open.get((rank, op.comm))
+            if grp is not None:
+                # grouped: runs at the group's end (or every start of a
+                # persistent group), after the group's messages
+                bname = persist_open.get((rank, op.comm))
+                if bname is not None:
+                    batch_ops.setdefault((rank, bname), []).append(op)
+                else:
+                    record_grouped(rank, op, grp)
                 ctx.pc += 1
                 return True
             ctx.pending = ("coll", arrive(rank, op))

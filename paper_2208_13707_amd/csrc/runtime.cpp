@@ -895,6 +895,49 @@ int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64
     return MPIXS_SUCCESS;
 }
 
+// A grouped allreduce: the split reduce kernel over all ranks' buffers, run
+// on the launching rank's stream after the group's wait (and batch kernel).
+RedPlan plan_red(World *w, const std::vector<const GOp *> &calls, StreamObj *on) {
+    RedPlan r;
+    const int n = int(calls.size());
+    bool vec = true;
+    for (int q = 0; q < n; ++q) {
+        r.a.in[q] = calls[size_t(q)]->red_in;
+        r.a.out[q] = calls[size_t(q)]->red_out;
+        vec = vec && (reinterpret_cast<uintptr_t>(r.a.in[q]) % 16 == 0) &&
+              (reinterpret_cast<uintptr_t>(r.a.out[q]) % 16 == 0);
+    }
+    const GOp &c0 = *calls[0];
+    r.a.n = n;
+    r.a.me_rank = -1;
+    r.a.count = uint64_t(c0.red_count);
+    r.a.ctl = ctl_of(w);
+    r.a.me = on->dev;
+    r.dtype = c0.red_dtype;
+    r.op = c0.red_op;
+    const int es = basic_size(r.dtype);
+    const uint64_t per_thread = vec ? uint64_t(16 / es) : 1;
+    const uint64_t work = (r.a.count + per_thread - 1) / per_thread;
+    const uint64_t nchunks = std::max<uint64_t>(1, (work + reduce_threads() - 1) / reduce_threads());
+    r.vec = vec;
+    r.fixed = vec && reduce_fixed_ok(n);
+    const uint64_t per_wg = r.fixed ? uint64_t(reduce_fixed_units()) : 1;
+    r.nwg = int(std::min<uint64_t>((nchunks + per_wg - 1) / per_wg, uint64_t(1) << 22));
+    r.bytes = uint64_t(2) * uint64_t(c0.red_count) * uint64_t(es) * uint64_t(n);
+    return r;
+}
+
+int launch_red(World *w, hipStream_t s, const RedPlan &r) {
+    if (r.a.count == 0) return MPIXS_SUCCESS;
+    const int rc = gpu_err(r.fixed ? launch_reduce_fixed(s, r.a, r.dtype, r.op, r.nwg)
+                                   : launch_reduce(s, r.a, r.dtype, r.op, r.vec, r.nwg, false));
+    if (!rc && w) {
+        w->n_reduce.fetch_add(1, std::memory_order_relaxed);
+        w->bytes_reduced.fetch_add(r.bytes, std::memory_order_relaxed);
+    }
+    return rc;
+}
+
 CollRec *coll_at(std::deque<CollRec *> &q, uint64_t &base, uint64_t k, int size) {
     while (base + q.size() <= k) {
         CollRec *r = new CollRec();
@@ -975,7 +1018,8 @@ int arena_alloc(World *w, size_t bytes, size_t *off, int *flag) {
 // tag t), plan each copy, and cut the group into tiles: one descriptor per
 // message and, per workgroup, the (message, tile) it starts at.  Fills
 // everything of `a` except the descriptor / start pointers.
-int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, BatchArgs &a, uint64_t *bytes) {
+int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launcher, BatchArgs &a,
+               uint64_t *bytes) {
     struct PlanTimer {   // host time of this plan, for the diagnostics counters
         World *w;
         std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -1008,6 +1052,7 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, BatchArgs &a, uin
     size_t k = 0;
     for (int q = 0; q < n; ++q)
         for (GOp &op : rec->ops[size_t(q)]) {
+            if (op.kind == 2) continue;   // allreduces: below
             const uint64_t key = op.kind == 0 ? chan_key(q, op.peer, op.tag) : chan_key(op.peer, q, op.tag);
             size_t h = size_t((key * 0x9E3779B97F4A7C15ull) >> 17) & (cap - 1);
             while (z.table[h].key != kEmpty && z.table[h].key != key) h = (h + 1) & (cap - 1);
@@ -1035,10 +1080,34 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, BatchArgs &a, uin
     k = 0;
     for (int q = 0; q < n; ++q)
         for (GOp &op : rec->ops[size_t(q)]) {
+            if (op.kind == 2) continue;
             const uint32_t c = z.chan_of[k++];
             if (op.kind == 0) z.s_of[z.fill_s[c]++] = &op;
             else z.r_of[z.fill_r[c]++] = &op;
         }
+    // allreduces: the i-th grouped allreduce of every rank forms reduction
+    // i; ranks must have grouped as many, with equal count, type and op
+    z.reds.clear();
+    {
+        std::vector<std::vector<const GOp *>> per(static_cast<size_t>(n));
+        for (int q = 0; q < n; ++q)
+            for (const GOp &op : rec->ops[size_t(q)])
+                if (op.kind == 2) per[size_t(q)].push_back(&op);
+        const size_t m = per[0].size();
+        for (int q = 1; q < n; ++q)
+            if (per[size_t(q)].size() != m) return MPIXS_ERR_ARG;
+        std::vector<const GOp *> calls(static_cast<size_t>(n));
+        for (size_t i = 0; i < m; ++i) {
+            for (int q = 0; q < n; ++q) {
+                const GOp *o = per[size_t(q)][i];
+                if (o->red_count != per[0][i]->red_count || o->red_dtype != per[0][i]->red_dtype ||
+                    o->red_op != per[0][i]->red_op)
+                    return MPIXS_ERR_ARG;
+                calls[size_t(q)] = o;
+            }
+            z.reds.push_back(plan_red(w, calls, launcher));
+        }
+    }
     const uint32_t tile = uint32_t(w->cfg.batch_tile);
     std::vector<BatchDesc> &descs = z.descs;
     descs.resize(npairs);
@@ -1105,7 +1174,7 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     const std::vector<BatchStart> &starts = sh->plan.starts;
     BatchArgs a{};
     uint64_t bytes = 0;
-    int rc = plan_group(w, sh, rec, n, a, &bytes);
+    int rc = plan_group(w, sh, rec, n, st, a, &bytes);
     if (rc) return rc;
     uint64_t *arrive = sh->d_grp;
     uint64_t *done = sh->d_grp + 16 * n;
@@ -1143,6 +1212,11 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         w->n_copy.fetch_add(1, std::memory_order_relaxed);
         w->bytes_copied.fetch_add(bytes, std::memory_order_relaxed);
     }
+    // the group's allreduces, in order, after its messages
+    for (const RedPlan &r : sh->plan.reds) {
+        rc = launch_red(w, st->hs, r);
+        if (rc) return rc;
+    }
     SignalArgs sg;
     std::memset(&sg, 0, sizeof(sg));
     sg.done_ptr = done;
@@ -1169,8 +1243,9 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     std::lock_guard<std::mutex> plan_lock(sh->plan_mu);
     const std::vector<BatchDesc> &descs = sh->plan.descs;
     const std::vector<BatchStart> &starts = sh->plan.starts;
-    int rc = plan_group(w, sh, rec, n, P->args, &P->bytes);
+    int rc = plan_group(w, sh, rec, n, st, P->args, &P->bytes);
     if (rc) return rc;
+    P->reds = sh->plan.reds;
     P->nmsg = descs.size();
     // an empty group still runs one workgroup, which publishes the run
     P->nwg = std::max(1, int(starts.size()));
@@ -1219,8 +1294,28 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
             return MPIXS_ERR_GPU;
     }
     if (w->cfg.batch_graph) {
-        if (build_batch_graph(&P->graph, n > 1 ? &P->lwait : nullptr, P->args, P->nwg, P->sig) !=
-                hipSuccess ||
+        hipError_t e = hipSuccess;
+        if (P->reds.empty()) {
+            e = build_batch_graph(&P->graph, n > 1 ? &P->lwait : nullptr, P->args, P->nwg, P->sig);
+        } else {
+            // with reductions, record the run by capturing a private stream
+            hipStream_t cs = nullptr;
+            e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                int r = MPIXS_SUCCESS;
+                if (n > 1) r = gpu_err(launch_wait_rel(cs, P->lwait));
+                if (!r) r = gpu_err(launch_batch(cs, P->args, P->nwg));
+                for (size_t i = 0; i < P->reds.size() && !r; ++i) r = launch_red(nullptr, cs, P->reds[i]);
+                if (!r) r = gpu_err(launch_signal(cs, P->sig));
+                hipGraph_t gr = nullptr;
+                const hipError_t e2 = hipStreamEndCapture(cs, &gr);
+                P->graph = gr;
+                e = r ? hipErrorUnknown : e2;
+            }
+            if (cs) (void)hipStreamDestroy(cs);
+        }
+        if (e != hipSuccess || !P->graph ||
             hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess)
             return MPIXS_ERR_GPU;
     }
@@ -1814,7 +1909,20 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count, mpixs
                             mpixs_op op, mpixs_comm c) {
     int rc = check_allreduce(c, sendbuf, recvbuf, count, dt, op, true);
     if (rc) return rc;
-    if (c->in_group) return MPIXS_ERR_ARG;   // collectives are not grouped
+    if (c->in_group) {
+        // recorded; the group's end reduces it after the group's messages
+        GOp g;
+        g.kind = 2;
+        g.red_in = sendbuf == MPIXS_IN_PLACE ? recvbuf : sendbuf;
+        g.red_out = recvbuf;
+        g.red_count = count;
+        g.red_dtype = dt;
+        g.red_op = op;
+        g.side.st = c->stream;
+        g.side.rank = c->rank;
+        c->gops.push_back(g);
+        return MPIXS_SUCCESS;
+    }
     CommShared *sh = c->sh;
     World *w = sh->w;
     StreamObj *st = c->stream;
@@ -1978,12 +2086,14 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
                 for (int q = 0; q < P->n && !rc; ++q)
                     if (q != P->leader) rc = gpu_err(hipStreamWaitEvent(st->hs, P->post_ev[size_t(q)], 0));
                 if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
+                for (size_t i = 0; i < P->reds.size() && !rc; ++i) rc = launch_red(w, st->hs, P->reds[i]);
                 if (!rc) rc = gpu_err(hipEventRecord(P->done_ev, st->hs));
             } else if (P->exec) {
                 rc = gpu_err(hipGraphLaunch(P->exec, st->hs));
             } else {
                 if (P->n > 1) rc = gpu_err(launch_wait_rel(st->hs, P->lwait));
                 if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
+                for (size_t i = 0; i < P->reds.size() && !rc; ++i) rc = launch_red(w, st->hs, P->reds[i]);
                 if (!rc) rc = gpu_err(launch_signal(st->hs, P->sig));
             }
         }

@@ -119,12 +119,31 @@ struct CollRec {
 
 // One operation recorded inside a group (see mpixs_group_start).
 struct GOp {
-    int kind = 0;                      // 0 send, 1 receive
+    int kind = 0;                      // 0 send, 1 receive, 2 allreduce
     int peer = -1;
     int tag = 0;
     Side side;
     void *status = nullptr;            // receive status to write, or nullptr
     mpixs_request_s *req = nullptr;    // request to receive the status values
+    // allreduce: input (the output for MPIXS_IN_PLACE), output, elements,
+    // basic type and operation
+    const void *red_in = nullptr;
+    void *red_out = nullptr;
+    int red_count = 0;
+    int red_dtype = 0;
+    int red_op = 0;
+};
+
+// One reduction of a group, planned for the launching rank's stream (the
+// split reduce kernel: the group's wait and signal surround it).
+struct RedPlan {
+    ReduceArgs a{};
+    int dtype = 0;
+    int op = 0;
+    int nwg = 0;
+    bool vec = false;
+    bool fixed = false;
+    uint64_t bytes = 0;                // read + written, for the counters
 };
 
 struct BatchPlan;
@@ -156,6 +175,7 @@ struct BatchPlan {
     SignalArgs sig{};                   // leader, after the batch kernel: done + 1
     int nwg = 0;
     uint64_t nmsg = 0, bytes = 0;
+    std::vector<RedPlan> reds;          // allreduces of the group, after the batch kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> post_ev;    // batch_sync = 1: per rank, recorded at its arrival
@@ -204,6 +224,7 @@ struct PlanScratch {
     std::vector<GOp *> s_of, r_of;      // pair i: its send and its receive
     std::vector<BatchDesc> descs;
     std::vector<BatchStart> starts;
+    std::vector<RedPlan> reds;         // the group's allreduces, in order
 };
 
 struct CommShared {

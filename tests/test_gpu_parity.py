@@ -370,3 +370,25 @@ def test_degenerate_programs(k):
 def test_large_tags_keep_channels_apart(grouped):
     """Channels whose tags share bits with shifted rank numbers stay apart."""
     check(C.large_tag_program(grouped))
+
+
+# ------------------------------------------------------- grouped allreduces
+@pytest.mark.parametrize("persistent,graph,sync", [(False, 0, 0), (True, 0, 0), (True, 1, 0),
+                                                   (True, 0, 1)])
+def test_grouped_allreduces(persistent, graph, sync):
+    """Allreduces inside one-shot and persistent groups, with messages in the
+    same groups; persistent runs launched one by one, as a graph, or ordered
+    by events."""
+    check(C.grouped_allreduces(persistent=persistent, steps=3),
+          cfg=cfg_with(batch_graph=graph, batch_sync=sync),
+          name=f"grouped allreduces persistent={persistent} graph={graph} sync={sync}")
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_grouped_allreduce_mismatch(persistent):
+    check(C.grouped_allreduces(persistent=persistent, steps=1, mismatch=True))
+
+
+def test_grouped_allreduces_fixed_rank_count():
+    """16 ranks: the grouped reductions take the unrolled 16-rank kernel."""
+    check(C.grouped_allreduces(nranks=16, steps=2))

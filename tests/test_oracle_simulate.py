@@ -543,3 +543,66 @@ def test_large_tags_keep_channels_apart(grouped):
     assert r.statuses[0]["self"] == (0, 1 << 24, "SUCCESS", 4)
     assert r.statuses[0]["b5"] == (1, (1 << 24) + 5, "SUCCESS", 4)
     assert r.statuses[1]["max"] == (0, (1 << 31) - 1, "SUCCESS", 4)
+
+
+# ------------------------------------------------------- grouped allreduces
+def _ungrouped(p):
+    """The same program with every group marker removed and each persistent
+    start replaced by the recorded calls."""
+    out = []
+    for r in range(p.nranks):
+        ops = p.ops[r][0]
+        rec, lst, recording = [], [], False
+        for o in ops:
+            if isinstance(o, GroupStart):
+                recording, rec = True, []
+            elif isinstance(o, GroupEnd):
+                recording = False
+                lst += rec
+            elif isinstance(o, GroupInit):
+                recording = False
+            elif isinstance(o, Start):
+                lst += rec
+            elif recording:
+                rec.append(o)
+            else:
+                lst.append(o)
+        out.append([lst])
+    q = Program(p.nranks, p.copy_buffers(), out, p.streams_per_rank, p.comm_streams, name="flat")
+    return q
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_grouped_allreduces_equal_the_calls_in_order(persistent):
+    """Grouped allreduces (one-shot and persistent) give the buffers of the
+    same calls issued one by one, and the float32 in-place sum equals a
+    sequential float32 fold written out here."""
+    p = C.grouped_allreduces(persistent=persistent, steps=3)
+    a, b = sim.run(p), sim.run(_ungrouped(p))
+    assert not a.deadlock and not any(a.sync_errors) and not b.deadlock
+    for q in range(p.nranks):
+        for k in a.buffers[q]:
+            assert np.array_equal(a.buffers[q][k], b.buffers[q][k]), (q, k)
+    # three in-place sums of the ranks' float32 vectors, folded in rank order
+    x = [p.buffers[q]["f32"].view(np.float32).copy() for q in range(p.nranks)]
+    for _ in range(3):
+        acc = x[0].copy()
+        for q in range(1, p.nranks):
+            acc = (acc + x[q]).astype(np.float32)
+        x = [acc.copy() for _ in range(p.nranks)]
+    assert np.array_equal(a.buffers[0]["f32"].view(np.float32), x[0])
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_grouped_allreduce_mismatch_fails_the_instance(persistent):
+    p = C.grouped_allreduces(persistent=persistent, steps=1, mismatch=True)
+    r = sim.run(p)
+    assert not r.deadlock
+    errs = [[e for _, _, e in r.sync_errors[q]] for q in range(p.nranks)]
+    if persistent:
+        # GroupInit fails on every rank, and the start of the failed batch
+        assert all(e == ["ERR_ARG", "ERR_REQUEST"] for e in errs)
+    else:
+        assert all(e == ["ERR_ARG"] for e in errs)
+    for q in range(p.nranks):
+        assert not r.buffers[q]["o32"].any() and not r.buffers[q]["h"].any()

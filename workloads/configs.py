@@ -511,3 +511,47 @@ def large_tag_program(grouped=False):
     if grouped:
         ops = [[GroupStart()] + o + [GroupEnd()] for o in ops]
     return single_stream(2, b, ops, name="large-tags" + ("-grouped" if grouped else ""))
+
+
+# ------------------------------------------------------ grouped allreduces
+def grouped_allreduces(nranks: int = 5, steps: int = 2, persistent: bool = False,
+                       mismatch: bool = False) -> Program:
+    """Each step one group holding messages around a ring and four
+    allreduces (int32 SUM, float64 MIN, float32 SUM in place, a zero-count
+    int64 MAX), each on buffers of its own; between steps every rank adds
+    one to its int32 input, so each step reduces new values.  persistent:
+    the group is recorded once (GroupInit) and started every step.
+    mismatch: rank 1 groups its second allreduce with a different count,
+    which fails the instance on every rank."""
+    bufs, ops = [], []
+    for r in range(nranks):
+        g = rng(12, r)
+        b = {"i32": as_bytes(g.integers(-2**30, 2**30, size=37, dtype=np.int64).astype(np.int32)),
+             "o32": np.zeros(4 * 37, np.uint8),
+             "f64": as_bytes(g.standard_normal(19)),
+             "o64": np.zeros(8 * 19, np.uint8),
+             "f32": as_bytes(g.standard_normal(101).astype(np.float32)),
+             "s": as_bytes(np.arange(5, dtype=np.int32) + 100 * r),
+             "h": np.zeros(20, np.uint8)}
+        bufs.append(b)
+        right, left = (r + 1) % nranks, (r - 1) % nranks
+        n64 = 18 if (mismatch and r == 1) else 19
+        body = [Send("s", 0, 5, "int32", right, 3, req="a"),
+                Recv("h", 0, 5, "int32", left, 3, req="b"),
+                Allreduce("i32", 0, "o32", 0, 37, "int32", "sum"),
+                Allreduce("f64", 0, "o64", 0, n64, "float64", "min"),
+                Allreduce(IN_PLACE, 0, "f32", 0, 101, "float32", "sum"),
+                Allreduce("i32", 0, "o32", 0, 0, "int64", "max"),
+                Wait(["a", "b"], [None, "st"])]
+        bump = User(("add_const_i32", "i32", 0, 37, 1))
+        lst = []
+        if persistent:
+            lst += [GroupStart()] + body + [GroupInit("g")]
+            for _ in range(steps):
+                lst += [Start("g"), bump]
+        else:
+            for _ in range(steps):
+                lst += [GroupStart()] + body + [GroupEnd(), bump]
+        ops.append(lst)
+    name = "grouped-allreduce" + ("-persistent" if persistent else "") + ("-mismatch" if mismatch else "")
+    return single_stream(nranks, bufs, ops, name=name)
