@@ -181,10 +181,15 @@ def close_checked(sess):
 
 
 def run_checked(sess, ops, mode=0, nmarks=0, max_reqs=64):
+    import torch
     from paper_2208_13707_amd import mpixs as M
     rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
     if rc:
         raise RuntimeError(f"driver: {M.errname(rc)} at thread {res.error_thread} op {res.error_op}")
+    # results are read back through torch's own stream: synchronise the whole
+    # device first (the runner has synchronised each rank's stream, which
+    # alone left stale cache lines visible to a later copy now and then)
+    torch.cuda.synchronize()
     return res.seconds, marks
 
 
@@ -518,6 +523,7 @@ def bench_allreduce(args):
         sec_hs, _ = run_checked(sess, ops(k), mode=1)
         close_checked(sess)
         hs = k / sec_hs
+    grouped = allreduce_groups(args, n, count, dtype, S, p) if args.group > 1 else None
     cfg = M.Config()
     cfg.profile = 1
     sess = D.Session(n, cfg)
@@ -550,7 +556,77 @@ def bench_allreduce(args):
                      "kernel": f"k_reduce<{dtype},SUM,vec>", "bytes_per_launch": per_launch,
                      "avg_launch_us": avg_us, "launches_timed": int(st.timed_reduce)},
     }
+    if grouped:
+        line["grouped"] = grouped
     return line
+
+
+def allreduce_groups(args, n, count, dtype, S, p):
+    """G allreduces per step (each on its own slice of the buffers) issued as
+    G enqueue calls, as one group, as a persistent group started every step,
+    and as G host-synchronised calls; allreduces per second."""
+    import numpy as np
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    G = args.group
+    nbytes = args.bytes
+    S2 = [S[r].repeat(G) for r in range(n)]
+    R2 = [torch.zeros(G * nbytes, dtype=torch.uint8, device="cuda") for _ in range(n)]
+    torch.cuda.synchronize()
+
+    def red(r, i):
+        return dict(kind=D.ALLREDUCE, count=count, datatype=M.BASIC[dtype], op=M.SUM,
+                    buf=S2[r].data_ptr() + i * nbytes, buf2=R2[r].data_ptr() + i * nbytes)
+
+    def ops(variant, k):
+        out = []
+        for r in range(n):
+            rows = []
+            if variant == "init":
+                rows = ([dict(kind=D.GROUP_START)] + [red(r, i) for i in range(G)]
+                        + [dict(kind=D.GROUP_INIT, req=0)])
+            elif variant == "persistent":
+                rows = [dict(kind=D.BATCH_START, req=0) for _ in range(k)]
+            else:
+                for _ in range(k):
+                    if variant == "grouped":
+                        rows.append(dict(kind=D.GROUP_START))
+                    rows += [red(r, i) for i in range(G)]
+                    if variant == "grouped":
+                        rows.append(dict(kind=D.GROUP_END))
+            out.append(D.ops_array(rows))
+        return out
+
+    res = {}
+    for variant, mode in (("plain", 0), ("grouped", 0), ("persistent", 0), ("host", 1)):
+        if variant == "host" and args.no_host_synced:
+            continue
+        k = args.steps if variant != "host" else max(1, min(args.steps, args.hs_steps))
+        sess = D.Session(n)
+        if variant == "persistent":
+            run_checked(sess, ops("init", 0))
+        run_checked(sess, ops(variant, min(args.warmup, 3)), mode=mode)
+        secs = sorted(run_checked(sess, ops(variant, k), mode=mode)[0] for _ in range(3))
+        close_checked(sess)
+        res[variant] = G * k / secs[1]
+        log(f"[allreduce x{G}] {variant}: {res[variant]:.0f} allreduces/s")
+        # every slice holds the rank-order fold (sampled)
+        from oracle import reduce as redo
+        idx = np.arange(0, count, 97)
+        ins = [np.frombuffer(p.buffers[q]["send"].tobytes(), dtype=dtype)[idx] for q in range(n)]
+        want = redo.fold("sum", ins).view(np.uint8)
+        for r in (0, n - 1):
+            got = R2[r].cpu().numpy().view(dtype).reshape(G, count)[:, idx]
+            bad = [i for i in range(G)
+                   if not np.array_equal(np.ascontiguousarray(got[i]).view(np.uint8), want)]
+            if bad:
+                raise AssertionError(f"{variant}: rank {r} slices {bad} differ from the oracle")
+            R2[r].zero_()
+    return {"allreduces_per_step": G, "unit": "allreduces/s",
+            **{f"{v}": res[v] for v in res},
+            "grouped_vs_host": res["grouped"] / res["host"] if "host" in res else None,
+            "persistent_vs_host": res["persistent"] / res["host"] if "host" in res else None}
 
 
 # ------------------------------------------------------------------- batch
@@ -1102,6 +1178,9 @@ def main():
     ap.add_argument("--bytes", type=int, default=None)
     ap.add_argument("--dtype", default="float32")
     ap.add_argument("--ranks", type=int, default=16)
+    ap.add_argument("--group", type=int, default=1,
+                    help="allreduce: also time this many allreduces per step as plain calls, "
+                         "one group, a persistent group and host-synchronised calls")
     ap.add_argument("--hs-steps", type=int, default=100)
     ap.add_argument("--no-host-synced", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
