@@ -419,6 +419,12 @@ def bench_halo(args):
                         "between one event pair"}
     else:
         roof = vector_copy_roofline(h["count"], steps)
+    # the achievable copy peak of this GPU, measured in the same run
+    cp = achievable_copy_gbps()
+    roof["achievable_copy_GBps"] = cp
+    roof["frac_of_achievable"] = roof["achieved"] / cp
+    log(f"[halo] 1 GiB copy kernel: {cp:.0f} GB/s; halo kernel at "
+        f"{roof['frac_of_achievable']:.2f} of it")
     gbps_pay = value * h["payload_bytes"] / 1e9
     hs = h.get("host_synced_msgs_per_s")
     line = {
@@ -1087,6 +1093,36 @@ def bench_pingpong(args):
 
 
 # -------------------------------------------------------------------- copy
+def achievable_copy_gbps(nbytes=1 << 30, launches=5):
+    """HBM bandwidth the library's own copy kernel reaches on this GPU: one
+    contiguous message of ``nbytes`` between two ranks, each launch timed
+    with a HIP event pair on its stream (algorithmic bytes 2 x nbytes)."""
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    ops = lambda k: [D.ops_array([dict(kind=D.SEND, peer=1, tag=7, count=nbytes,
+                                       datatype=M.UINT8, buf=src.data_ptr())] * k),
+                     D.ops_array([dict(kind=D.RECV, peer=0, tag=7, count=nbytes,
+                                       datatype=M.UINT8, buf=dst.data_ptr())] * k)]
+    cfg = M.Config()
+    cfg.profile = 1
+    sess = D.Session(2, cfg)
+    run_checked(sess, ops(2))
+    sess.reset_stats()
+    run_checked(sess, ops(launches))
+    st = sess.stats()
+    close_checked(sess)
+    if not torch.equal(src, dst):
+        raise AssertionError("copy calibration: destination differs from source")
+    avg_us = 1000 * st.copy_ms / max(1, st.timed_copy)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (avg_us * 1e-6) / 1e9
+
+
 def bench_copy(args):
     import torch
     from paper_2208_13707_amd import driver as D
