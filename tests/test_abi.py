@@ -91,3 +91,42 @@ def test_bad_batch_schedule_is_rejected_before_any_gpu_call(lib):
             setattr(c, field, value)
         rc, w = M.mpixs_world_create(2, c)
         assert M.errname(rc) == "ERR_ARG" and not w, fields
+
+
+def test_structs_match_the_header(tmp_path):
+    """Every struct the bindings marshal has the header's size and field
+    offsets (compiled from include/ with the host C compiler)."""
+    import ctypes
+    import shutil
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    ct = [("mpixs_config", M.Config), ("mpixs_status", M.Status), ("mpixs_stats", M.Stats),
+          ("mpixs_drv_thread", D.DrvThread), ("mpixs_drv_result", D.DrvResult)]
+    npy = [("mpixs_drv_op", D.OP_DTYPE), ("mpixs_drv_req", D.REQ_DTYPE),
+           ("mpixs_drv_req_result", D.RES_DTYPE)]
+    want = {}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mpixs.h"',
+             '#include "mpixs_driver.h"', "int main(void) {"]
+    for cname, cls in ct:
+        want[cname] = ctypes.sizeof(cls)
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            want[f"{cname}.{f}"] = getattr(cls, f).offset
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    for cname, dt in npy:
+        want[cname] = dt.itemsize
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in dt.names:
+            want[f"{cname}.{f}"] = dt.fields[f][1]
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    assert {k: int(v) for k, v in got.items()} == want
