@@ -163,6 +163,16 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
         (nreq > 0 && (!reqs || !results)) ||
         budget_bytes <= 0)
         return MPIXS_ERR_ARG;
+    for (int64_t i = 0; i < nreq; ++i) {
+        const mpixs_drv_req &q = reqs[i];
+        const bool p2p = q.kind == MPIXS_DRV_REQ_SENDRECV || q.kind == MPIXS_DRV_REQ_ISEND_WAIT;
+        if ((!p2p && q.kind != MPIXS_DRV_REQ_ALLREDUCE) || q.bytes < 0 || q.bytes > INT32_MAX ||
+            (i > 0 && q.arrival_us < reqs[i - 1].arrival_us) ||
+            (p2p && (q.src < 0 || q.src >= nranks || q.dst < 0 || q.dst >= nranks ||
+                     q.src == q.dst)) ||
+            (!p2p && q.bytes % 4))
+            return MPIXS_ERR_ARG;
+    }
     char *arena_mem = nullptr;
     uint64_t *dsum = nullptr;
     uint64_t *hsum = nullptr;
@@ -188,21 +198,6 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
     Arena arena{static_cast<size_t>(budget_bytes)};
     std::vector<Slot> slots(static_cast<size_t>(nslot));
     std::vector<std::vector<int64_t>> mine(static_cast<size_t>(nranks));
-    for (int64_t i = 0; i < nreq; ++i) {
-        const mpixs_drv_req &q = reqs[i];
-        const bool p2p = q.kind == MPIXS_DRV_REQ_SENDRECV || q.kind == MPIXS_DRV_REQ_ISEND_WAIT;
-        if ((!p2p && q.kind != MPIXS_DRV_REQ_ALLREDUCE) || q.bytes < 0 || q.bytes > INT32_MAX ||
-            (i > 0 && q.arrival_us < reqs[i - 1].arrival_us) ||
-            (p2p && (q.src < 0 || q.src >= nranks || q.dst < 0 || q.dst >= nranks ||
-                     q.src == q.dst)) ||
-            (!p2p && q.bytes % 4)) {
-            (void)hipFree(arena_mem);
-            (void)hipFree(dsum);
-            (void)hipHostFree(hsum);
-            (void)hipHostFree(hflag);
-            return MPIXS_ERR_ARG;
-        }
-    }
     for (int64_t i = 0; i < nreq; ++i) {
         const mpixs_drv_req &q = reqs[i];
         std::memset(&results[i], 0, sizeof(results[i]));
