@@ -332,6 +332,10 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
  *  launching rank's stream runs after the batch kernel, in order (so a
  *  group of many small allreduces costs one arrival and one wait per rank
  *  plus one reduce kernel each, instead of two launches per rank each).
+ *  When the group's allreduces all have one datatype and operation, each
+ *  reads at most 4 MiB over all ranks, and no byte of any of their buffers
+ *  belongs to two of them, they run as one reduce kernel (their order
+ *  cannot change a result then); stats.reductions_merged counts them.
  *  Ranks that grouped different numbers of allreduces, or whose i-th calls
  *  differ in count, datatype or operation, make group_end (or
  *  group_end_init) return MPIXS_ERR_ARG on every rank; nothing of the group
@@ -454,6 +458,7 @@ typedef struct {
     uint64_t host_sleep_timeouts; /* sleeps that ended by their 1 ms bound, not a wake-up */
     uint64_t groups_planned;    /* group instances matched and planned (one-shot or init) */
     double plan_ms;             /* host time the planning ranks spent on them */
+    uint64_t reductions_merged; /* grouped allreduces run inside one merged reduce kernel */
 } mpixs_stats;
 
 /* Counters of the world since creation (or the last reset).  With

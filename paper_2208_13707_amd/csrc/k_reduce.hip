@@ -163,8 +163,96 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_n(ReduceArgs a) {
     }
 }
 
+// A group's small reductions of one type and operator in one launch.
+// Workgroup b serves the last instance whose first_wg <= b, chunk
+// b - first_wg of it: RED_THREADS vectors (aligned instances; chunk 0 also
+// takes the tail elements) or RED_THREADS elements.  Same left fold in rank
+// order as k_reduce.  Instances share no byte, so they need no order.
+constexpr int RED_MAX_RANKS = 64;
+
+template <typename T, int OP>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
+    __shared__ uint32_t s_fatal;
+    __shared__ uint32_t s_inst;
+    __shared__ const void *s_ptr[2 * RED_MAX_RANKS];
+    if (threadIdx.x == 0) {
+        s_fatal = ld_relaxed32(&a.me->fatal);
+        // first_wg ascends from 0: keep desc[lo].first_wg <= b < desc[hi].first_wg
+        uint32_t lo = 0, hi = a.ninst;
+        const uint32_t b = blockIdx.x;
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (a.desc[mid].first_wg <= b) lo = mid;
+            else hi = mid;
+        }
+        s_inst = lo;
+    }
+    __syncthreads();
+    if (s_fatal) return;
+    const MultiRedDesc d = a.desc[s_inst];
+    const int n = int(d.n);
+    if (threadIdx.x < 2 * d.n) s_ptr[threadIdx.x] = a.ptrs[d.ptr + threadIdx.x];
+    __syncthreads();
+    const uint64_t c = blockIdx.x - d.first_wg;
+    auto fold_one = [&](uint64_t i) {
+        T acc = static_cast<const T *>(s_ptr[0])[i];
+        for (int q = 1; q < n; ++q) acc = combine<T, OP>(acc, static_cast<const T *>(s_ptr[q])[i]);
+        for (int q = 0; q < n; ++q) static_cast<T *>(const_cast<void *>(s_ptr[n + q]))[i] = acc;
+    };
+    if (d.vec) {
+        constexpr int L = int(16 / sizeof(T));
+        using V = T __attribute__((ext_vector_type(L)));
+        const uint64_t nvec = d.count / L;
+        const uint64_t v = c * RED_THREADS + threadIdx.x;
+        if (v < nvec) {
+            V acc = static_cast<const V *>(s_ptr[0])[v];
+            for (int q0 = 1; q0 < n; q0 += RED_GROUP) {
+                V x[RED_GROUP];
+#pragma unroll
+                for (int j = 0; j < RED_GROUP; ++j)
+                    if (q0 + j < n) x[j] = static_cast<const V *>(s_ptr[q0 + j])[v];
+#pragma unroll
+                for (int j = 0; j < RED_GROUP; ++j)
+                    if (q0 + j < n) {
+#pragma unroll
+                        for (int l = 0; l < L; ++l) acc[l] = combine<T, OP>(acc[l], x[j][l]);
+                    }
+            }
+            for (int q = 0; q < n; ++q) static_cast<V *>(const_cast<void *>(s_ptr[n + q]))[v] = acc;
+        }
+        if (c == 0) {
+            const uint64_t i = nvec * L + threadIdx.x;
+            if (i < d.count) fold_one(i);
+        }
+    } else {
+        const uint64_t i = c * RED_THREADS + threadIdx.x;
+        if (i < d.count) fold_one(i);
+    }
+}
+
 // ------------------------------------------------------------- launchers
 int reduce_threads() { return RED_THREADS; }
+
+template <typename T>
+static hipError_t reduce_multi_t(hipStream_t s, const MultiRedArgs &a, int op, int nwg) {
+    switch (op) {
+    case OP_SUM: hipLaunchKernelGGL((k_reduce_multi<T, OP_SUM>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case OP_PROD: hipLaunchKernelGGL((k_reduce_multi<T, OP_PROD>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case OP_MIN: hipLaunchKernelGGL((k_reduce_multi<T, OP_MIN>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_reduce_multi<T, OP_MAX>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg) {
+    if (a.ninst == 0 || nwg <= 0) return hipErrorInvalidValue;
+    switch (basic) {
+    case MPIXS_INT32: return reduce_multi_t<int32_t>(s, a, op, nwg);
+    case MPIXS_INT64: return reduce_multi_t<int64_t>(s, a, op, nwg);
+    case MPIXS_FLOAT32: return reduce_multi_t<float>(s, a, op, nwg);
+    default: return reduce_multi_t<double>(s, a, op, nwg);
+    }
+}
 
 template <typename T, int OP, bool F>
 static hipError_t reduce_op(hipStream_t s, const ReduceArgs &a, bool vec, int nwg) {

@@ -260,4 +260,23 @@ struct ReduceArgs {
     uint64_t ticket_last;
 };
 
+// Several small reductions of one element type and operator in one launch
+// (a group's allreduces).  Instance i owns workgroups [first_wg, next
+// instance's first_wg); its rank buffers are ptrs[ptr .. ptr+n) (inputs) and
+// ptrs[ptr+n .. ptr+2n) (outputs).  No instance's buffers overlap another's.
+struct MultiRedDesc {
+    uint64_t count;         // elements
+    uint32_t first_wg;
+    uint32_t ptr;
+    uint32_t n;
+    uint32_t vec;           // nonzero: every buffer 16-byte aligned
+};
+
+struct MultiRedArgs {
+    const MultiRedDesc *desc;
+    const void *const *ptrs;
+    uint32_t ninst;
+    DevStream *me;
+};
+
 }  // namespace mpixs

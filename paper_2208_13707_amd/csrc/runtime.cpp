@@ -938,6 +938,116 @@ int launch_red(World *w, hipStream_t s, const RedPlan &r) {
     return rc;
 }
 
+// Merge a group's allreduces into one launch when they are all small, of
+// one type and operator, and no byte of any of their buffers belongs to two
+// of them; otherwise m.on stays false and they run one by one, in order.
+// Zero-count allreduces do nothing either way and are left out.
+constexpr uint64_t kMultiRedMaxBytes = uint64_t(4) << 20;   // per allreduce, all ranks' input
+constexpr uint64_t kMultiRedMaxWG = uint64_t(1) << 20;
+
+void plan_multi_red(const std::vector<RedPlan> &reds, MultiRedPlan &m) {
+    m.on = false;
+    m.desc.clear();
+    m.ptrs.clear();
+    m.bytes = 0;
+    m.ninst = 0;
+    m.nwg = 0;
+    if (reds.size() < 2) return;
+    struct Span {
+        uintptr_t lo, hi;
+        uint32_t inst;
+    };
+    std::vector<Span> spans;
+    uint64_t wg = 0;
+    for (size_t i = 0; i < reds.size(); ++i) {
+        const RedPlan &r = reds[i];
+        if (r.dtype != reds[0].dtype || r.op != reds[0].op) return;
+        if (r.a.count == 0) continue;
+        if (r.a.n < 1 || r.a.n > 64) return;
+        const uint64_t es = uint64_t(basic_size(r.dtype));
+        const uint64_t len = r.a.count * es;
+        if (len * uint64_t(r.a.n) > kMultiRedMaxBytes) return;
+        const uint64_t units = r.vec ? std::max<uint64_t>(1, r.a.count / (16 / es)) : r.a.count;
+        const uint64_t nch = (units + uint64_t(reduce_threads()) - 1) / uint64_t(reduce_threads());
+        MultiRedDesc d{};
+        d.count = r.a.count;
+        d.first_wg = uint32_t(wg);
+        d.ptr = uint32_t(m.ptrs.size());
+        d.n = uint32_t(r.a.n);
+        d.vec = r.vec ? 1u : 0u;
+        for (int q = 0; q < r.a.n; ++q) {
+            m.ptrs.push_back(r.a.in[q]);
+            spans.push_back(Span{uintptr_t(r.a.in[q]), uintptr_t(r.a.in[q]) + len, uint32_t(i)});
+        }
+        for (int q = 0; q < r.a.n; ++q) {
+            m.ptrs.push_back(r.a.out[q]);
+            spans.push_back(Span{uintptr_t(r.a.out[q]), uintptr_t(r.a.out[q]) + len, uint32_t(i)});
+        }
+        m.desc.push_back(d);
+        m.bytes += r.bytes;
+        wg += nch;
+        if (wg > kMultiRedMaxWG) return;
+    }
+    if (m.desc.size() < 2) return;
+    // Sweep the spans by start, keeping the farthest end seen and its
+    // allreduce.  The first span (in this order) that overlaps a span of
+    // another allreduce always starts before that farthest end, and the end
+    // belongs to another allreduce (were it its own, that span and the
+    // overlapped one would both hold this start and overlap earlier).
+    std::sort(spans.begin(), spans.end(),
+              [](const Span &x, const Span &y) { return x.lo < y.lo || (x.lo == y.lo && x.hi < y.hi); });
+    uintptr_t end = 0;
+    uint32_t owner = 0;
+    bool any = false;
+    for (const Span &sp : spans) {
+        if (any && sp.lo < end && sp.inst != owner) return;
+        if (!any || sp.hi > end) {
+            end = sp.hi;
+            owner = sp.inst;
+            any = true;
+        }
+    }
+    m.dtype = reds[0].dtype;
+    m.op = reds[0].op;
+    m.nwg = int(wg);
+    m.ninst = uint32_t(m.desc.size());
+    m.on = true;
+}
+
+// Counters of a run whose allreduces a graph replay launched.
+void count_reds(World *w, const std::vector<RedPlan> &reds, const MultiRedPlan &m) {
+    if (m.on) {
+        w->n_reduce.fetch_add(1, std::memory_order_relaxed);
+        w->reds_merged.fetch_add(m.ninst, std::memory_order_relaxed);
+        w->bytes_reduced.fetch_add(m.bytes, std::memory_order_relaxed);
+        return;
+    }
+    for (const RedPlan &r : reds)
+        if (r.a.count > 0) {
+            w->n_reduce.fetch_add(1, std::memory_order_relaxed);
+            w->bytes_reduced.fetch_add(r.bytes, std::memory_order_relaxed);
+        }
+}
+
+// The group's allreduces on stream s (w may be null: graph capture).
+int launch_reds(World *w, hipStream_t s, const std::vector<RedPlan> &reds, const MultiRedPlan &m,
+                const MultiRedArgs &ma) {
+    if (m.on) {
+        const int rc = gpu_err(launch_reduce_multi(s, ma, m.dtype, m.op, m.nwg));
+        if (!rc && w) {
+            w->n_reduce.fetch_add(1, std::memory_order_relaxed);
+            w->reds_merged.fetch_add(m.ninst, std::memory_order_relaxed);
+            w->bytes_reduced.fetch_add(m.bytes, std::memory_order_relaxed);
+        }
+        return rc;
+    }
+    for (const RedPlan &r : reds) {
+        const int rc = launch_red(w, s, r);
+        if (rc) return rc;
+    }
+    return MPIXS_SUCCESS;
+}
+
 CollRec *coll_at(std::deque<CollRec *> &q, uint64_t &base, uint64_t k, int size) {
     while (base + q.size() <= k) {
         CollRec *r = new CollRec();
@@ -1107,6 +1217,7 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
             }
             z.reds.push_back(plan_red(w, calls, launcher));
         }
+        plan_multi_red(z.reds, z.mred);
     }
     const uint32_t tile = uint32_t(w->cfg.batch_tile);
     std::vector<BatchDesc> &descs = z.descs;
@@ -1191,14 +1302,24 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         if (rc) return rc;
     }
     int flag = -1;
-    if (!descs.empty()) {
-        const size_t dbytes = descs.size() * sizeof(BatchDesc);
-        const size_t sbytes = starts.size() * sizeof(BatchStart);
+    // arena range: batch descriptors, workgroup starts, merged-reduce
+    // descriptors and pointer table, each 256-byte aligned
+    const MultiRedPlan &mr = sh->plan.mred;
+    const size_t dbytes = descs.size() * sizeof(BatchDesc);
+    const size_t sbytes = starts.size() * sizeof(BatchStart);
+    const size_t bbytes = descs.empty() ? 0 : ((dbytes + 255) & ~size_t(255)) + ((sbytes + 255) & ~size_t(255));
+    const size_t mdbytes = mr.on ? (mr.desc.size() * sizeof(MultiRedDesc) + 255) & ~size_t(255) : 0;
+    const size_t mpbytes = mr.on ? mr.ptrs.size() * sizeof(void *) : 0;
+    uint8_t *h = nullptr;
+    if (bbytes + mdbytes + mpbytes > 0) {
         size_t off = 0;
-        rc = arena_alloc(w, dbytes + sbytes + 256, &off, &flag);
+        rc = arena_alloc(w, bbytes + mdbytes + mpbytes, &off, &flag);
         if (rc) return rc;
-        BatchDesc *hd = reinterpret_cast<BatchDesc *>(w->h_arena + off);
-        BatchStart *hs = reinterpret_cast<BatchStart *>(w->h_arena + off + ((dbytes + 255) & ~size_t(255)));
+        h = reinterpret_cast<uint8_t *>(w->h_arena + off);
+    }
+    if (!descs.empty()) {
+        BatchDesc *hd = reinterpret_cast<BatchDesc *>(h);
+        BatchStart *hs = reinterpret_cast<BatchStart *>(h + ((dbytes + 255) & ~size_t(255)));
         std::memcpy(hd, descs.data(), dbytes);
         std::memcpy(hs, starts.data(), sbytes);
         a.desc = hd;
@@ -1212,11 +1333,20 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         w->n_copy.fetch_add(1, std::memory_order_relaxed);
         w->bytes_copied.fetch_add(bytes, std::memory_order_relaxed);
     }
-    // the group's allreduces, in order, after its messages
-    for (const RedPlan &r : sh->plan.reds) {
-        rc = launch_red(w, st->hs, r);
-        if (rc) return rc;
+    // the group's allreduces, in order (or merged), after its messages
+    MultiRedArgs ma{};
+    if (mr.on) {
+        MultiRedDesc *md = reinterpret_cast<MultiRedDesc *>(h + bbytes);
+        const void **mp = reinterpret_cast<const void **>(h + bbytes + mdbytes);
+        std::memcpy(md, mr.desc.data(), mr.desc.size() * sizeof(MultiRedDesc));
+        std::memcpy(mp, mr.ptrs.data(), mpbytes);
+        ma.desc = md;
+        ma.ptrs = mp;
+        ma.ninst = mr.ninst;
+        ma.me = st->dev;
     }
+    rc = launch_reds(w, st->hs, sh->plan.reds, mr, ma);
+    if (rc) return rc;
     SignalArgs sg;
     std::memset(&sg, 0, sizeof(sg));
     sg.done_ptr = done;
@@ -1246,6 +1376,7 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     int rc = plan_group(w, sh, rec, n, st, P->args, &P->bytes);
     if (rc) return rc;
     P->reds = sh->plan.reds;
+    P->mred = sh->plan.mred;
     P->nmsg = descs.size();
     // an empty group still runs one workgroup, which publishes the run
     P->nwg = std::max(1, int(starts.size()));
@@ -1253,11 +1384,24 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     const size_t cbytes = size_t(n + 1) * 16 * sizeof(uint64_t);
     const size_t dbytes = (descs.size() * sizeof(BatchDesc) + 255) & ~size_t(255);
     const size_t sbytes = starts.size() * sizeof(BatchStart);
-    if (hipMalloc(reinterpret_cast<void **>(&P->d_mem), cbytes + dbytes + sbytes) != hipSuccess)
+    // merged-reduce descriptors and pointer table after the starts
+    const size_t moff = cbytes + dbytes + ((sbytes + 255) & ~size_t(255));
+    const size_t mdbytes = P->mred.on ? (P->mred.desc.size() * sizeof(MultiRedDesc) + 255) & ~size_t(255) : 0;
+    const size_t mpbytes = P->mred.on ? P->mred.ptrs.size() * sizeof(void *) : 0;
+    const size_t total = P->mred.on ? moff + mdbytes + mpbytes : cbytes + dbytes + sbytes;
+    if (hipMalloc(reinterpret_cast<void **>(&P->d_mem), total) != hipSuccess)
         return MPIXS_ERR_NOMEM;
-    std::vector<uint8_t> img(cbytes + dbytes + sbytes, 0);
+    std::vector<uint8_t> img(total, 0);
     if (!descs.empty()) std::memcpy(img.data() + cbytes, descs.data(), descs.size() * sizeof(BatchDesc));
     if (!starts.empty()) std::memcpy(img.data() + cbytes + dbytes, starts.data(), sbytes);
+    if (P->mred.on) {
+        std::memcpy(img.data() + moff, P->mred.desc.data(), P->mred.desc.size() * sizeof(MultiRedDesc));
+        std::memcpy(img.data() + moff + mdbytes, P->mred.ptrs.data(), mpbytes);
+        P->margs.desc = reinterpret_cast<const MultiRedDesc *>(P->d_mem + moff);
+        P->margs.ptrs = reinterpret_cast<const void *const *>(P->d_mem + moff + mdbytes);
+        P->margs.ninst = P->mred.ninst;
+        P->margs.me = st->dev;
+    }
     if (hipMemcpy(P->d_mem, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess)
         return MPIXS_ERR_GPU;
     P->d_ctr = reinterpret_cast<uint64_t *>(P->d_mem);
@@ -1306,7 +1450,7 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
                 int r = MPIXS_SUCCESS;
                 if (n > 1) r = gpu_err(launch_wait_rel(cs, P->lwait));
                 if (!r) r = gpu_err(launch_batch(cs, P->args, P->nwg));
-                for (size_t i = 0; i < P->reds.size() && !r; ++i) r = launch_red(nullptr, cs, P->reds[i]);
+                if (!r) r = launch_reds(nullptr, cs, P->reds, P->mred, P->margs);
                 if (!r) r = gpu_err(launch_signal(cs, P->sig));
                 hipGraph_t gr = nullptr;
                 const hipError_t e2 = hipStreamEndCapture(cs, &gr);
@@ -2086,14 +2230,15 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
                 for (int q = 0; q < P->n && !rc; ++q)
                     if (q != P->leader) rc = gpu_err(hipStreamWaitEvent(st->hs, P->post_ev[size_t(q)], 0));
                 if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
-                for (size_t i = 0; i < P->reds.size() && !rc; ++i) rc = launch_red(w, st->hs, P->reds[i]);
+                if (!rc) rc = launch_reds(w, st->hs, P->reds, P->mred, P->margs);
                 if (!rc) rc = gpu_err(hipEventRecord(P->done_ev, st->hs));
             } else if (P->exec) {
                 rc = gpu_err(hipGraphLaunch(P->exec, st->hs));
+                if (!rc) count_reds(w, P->reds, P->mred);
             } else {
                 if (P->n > 1) rc = gpu_err(launch_wait_rel(st->hs, P->lwait));
                 if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
-                for (size_t i = 0; i < P->reds.size() && !rc; ++i) rc = launch_red(w, st->hs, P->reds[i]);
+                if (!rc) rc = launch_reds(w, st->hs, P->reds, P->mred, P->margs);
                 if (!rc) rc = gpu_err(launch_signal(st->hs, P->sig));
             }
         }
@@ -2304,6 +2449,7 @@ int mpixs_world_get_stats(mpixs_world w, mpixs_stats *s) {
     s->host_sleep_timeouts = w->host_sleep_timeouts.load();
     s->groups_planned = w->groups_planned.load();
     s->plan_ms = double(w->plan_ns.load()) * 1e-6;
+    s->reductions_merged = w->reds_merged.load();
     s->timed_copy = w->timed_copy;
     s->copy_ms = w->copy_ms;
     s->timed_reduce = w->timed_reduce;
@@ -2321,6 +2467,7 @@ int mpixs_world_reset_stats(mpixs_world w) {
     w->host_sleep_timeouts = 0;
     w->groups_planned = 0;
     w->plan_ns = 0;
+    w->reds_merged = 0;
     w->n_copy = 0;
     w->n_reduce = 0;
     w->bytes_copied = 0;

@@ -146,6 +146,22 @@ struct RedPlan {
     uint64_t bytes = 0;                // read + written, for the counters
 };
 
+// A group's allreduces merged into one reduce launch: all of one type and
+// operator, each at most kMultiRedMaxBytes of input over all ranks, and no
+// byte of any buffer shared by two of them (so their order cannot matter).
+// Descriptors and the pointer table are copied next to the group's batch
+// descriptors.
+struct MultiRedPlan {
+    bool on = false;
+    int dtype = 0;
+    int op = 0;
+    int nwg = 0;
+    uint32_t ninst = 0;
+    uint64_t bytes = 0;                // read + written, for the counters
+    std::vector<MultiRedDesc> desc;
+    std::vector<const void *> ptrs;
+};
+
 struct BatchPlan;
 
 struct GroupRec {
@@ -176,6 +192,8 @@ struct BatchPlan {
     int nwg = 0;
     uint64_t nmsg = 0, bytes = 0;
     std::vector<RedPlan> reds;          // allreduces of the group, after the batch kernel
+    MultiRedPlan mred;                  // or all of them in one launch
+    MultiRedArgs margs{};               // its descriptors in d_mem
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> post_ev;    // batch_sync = 1: per rank, recorded at its arrival
@@ -225,6 +243,7 @@ struct PlanScratch {
     std::vector<BatchDesc> descs;
     std::vector<BatchStart> starts;
     std::vector<RedPlan> reds;         // the group's allreduces, in order
+    MultiRedPlan mred;                 // the same, merged when allowed
 };
 
 struct CommShared {
@@ -339,6 +358,7 @@ struct World {
     std::atomic<uint64_t> bytes_copied{0}, bytes_reduced{0}, host_waits{0};
     std::atomic<uint64_t> host_sleeps{0}, host_sleep_timeouts{0};
     std::atomic<uint64_t> groups_planned{0}, plan_ns{0};
+    std::atomic<uint64_t> reds_merged{0};   // allreduces run inside a merged reduce launch
     // host-pinned (coherent) ring of batch descriptor tables; an entry is
     // recycled once the batch's signal kernel has set its flag
     struct ArenaUse {

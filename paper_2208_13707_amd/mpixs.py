@@ -63,7 +63,7 @@ class Stats(ctypes.Structure):
                 ("copy_ms", ctypes.c_double), ("timed_reduce", ctypes.c_uint64),
                 ("reduce_ms", ctypes.c_double), ("host_sleeps", ctypes.c_uint64),
                 ("host_sleep_timeouts", ctypes.c_uint64), ("groups_planned", ctypes.c_uint64),
-                ("plan_ms", ctypes.c_double)]
+                ("plan_ms", ctypes.c_double), ("reductions_merged", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p

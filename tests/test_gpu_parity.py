@@ -34,6 +34,17 @@ def check(p, cfg=None, host_synced=False, name=None):
     return g, ref
 
 
+def check_stats(p, cfg=None, name=None):
+    """check() that also reads the world's statistics before it is freed."""
+    _say(name or p.name)
+    ref = sim.run(p)
+    assert not ref.deadlock, "test program must be safe"
+    g = run_program(p, cfg=cfg, stats=True)
+    diffs = compare(p, g, ref)
+    assert not diffs, "\n".join(diffs[:20])
+    return g, ref
+
+
 def cfg_with(**kw):
     from paper_2208_13707_amd import mpixs as M
     c = M.Config()
@@ -387,6 +398,29 @@ def test_grouped_allreduces(persistent, graph, sync):
 @pytest.mark.parametrize("persistent", [False, True])
 def test_grouped_allreduce_mismatch(persistent):
     check(C.grouped_allreduces(persistent=persistent, steps=1, mismatch=True))
+
+
+@pytest.mark.parametrize("persistent,graph,sync,chained", [
+    (False, 0, 0, False), (True, 0, 0, False), (True, 1, 0, False), (True, 0, 1, False),
+    (False, 0, 0, True), (True, 1, 0, True),
+])
+def test_merged_allreduces(persistent, graph, sync, chained):
+    """A group whose allreduces are all float32 sums on buffers of their own
+    runs them as one merged reduce kernel (vector chunks, ragged tails, an
+    unaligned buffer, fewer elements than a vector, in place, zero count);
+    with a call that reads another's result they must run one by one."""
+    steps = 3
+    g, _ = check_stats(C.merged_allreduces(persistent=persistent, chained=chained, steps=steps),
+                       cfg=cfg_with(batch_graph=graph, batch_sync=sync),
+                       name=f"merged allreduces persistent={persistent} graph={graph} "
+                            f"sync={sync} chained={chained}")
+    # five nonzero allreduces per run of the group
+    assert g.stats.reductions_merged == (0 if chained else 5 * steps)
+
+
+def test_merged_allreduces_sixteen_ranks():
+    g, _ = check_stats(C.merged_allreduces(nranks=16, steps=2), name="merged allreduces 16 ranks")
+    assert g.stats.reductions_merged == 5 * 2
 
 
 def test_grouped_allreduces_fixed_rank_count():

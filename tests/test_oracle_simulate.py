@@ -593,6 +593,38 @@ def test_grouped_allreduces_equal_the_calls_in_order(persistent):
     assert np.array_equal(a.buffers[0]["f32"].view(np.float32), x[0])
 
 
+@pytest.mark.parametrize("persistent,chained", [(False, False), (True, False), (False, True),
+                                                (True, True)])
+def test_merged_allreduces_equal_the_calls_in_order(persistent, chained):
+    """A group of float32 sums only (the kind the library may run as one
+    kernel) gives the buffers of the same calls issued one by one; the
+    2501-element result equals a float32 fold in rank order written out
+    here, with the inputs bumped by one ulp pattern between steps, and the
+    chained call (which reads that result) sees the final value of the same
+    step."""
+    steps = 2
+    p = C.merged_allreduces(persistent=persistent, chained=chained, steps=steps)
+    a, b = sim.run(p), sim.run(_ungrouped(p))
+    assert not a.deadlock and not any(a.sync_errors) and not b.deadlock
+    for q in range(p.nranks):
+        for k in a.buffers[q]:
+            assert np.array_equal(a.buffers[q][k], b.buffers[q][k]), (q, k)
+    x = [p.buffers[q]["bi"].view(np.int32).copy() for q in range(p.nranks)]
+    for step in range(steps):
+        acc = x[0].view(np.float32).copy()
+        for q in range(1, p.nranks):
+            acc = (acc + x[q].view(np.float32)).astype(np.float32)
+        x = [v + np.int32(1) for v in x]
+    for q in range(p.nranks):
+        assert np.array_equal(a.buffers[q]["bo"].view(np.float32), acc)
+        assert not a.buffers[q]["z"].any()
+        if chained:
+            chain = acc.copy()
+            for _ in range(1, p.nranks):
+                chain = (chain + acc).astype(np.float32)
+            assert np.array_equal(a.buffers[q]["eo"].view(np.float32), chain)
+
+
 @pytest.mark.parametrize("persistent", [False, True])
 def test_grouped_allreduce_mismatch_fails_the_instance(persistent):
     p = C.grouped_allreduces(persistent=persistent, steps=1, mismatch=True)

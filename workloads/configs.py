@@ -555,3 +555,55 @@ def grouped_allreduces(nranks: int = 5, steps: int = 2, persistent: bool = False
         ops.append(lst)
     name = "grouped-allreduce" + ("-persistent" if persistent else "") + ("-mismatch" if mismatch else "")
     return single_stream(nranks, bufs, ops, name=name)
+
+
+def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
+                      chained: bool = False) -> Program:
+    """Each step one group whose allreduces are all float32 sums on buffers
+    of their own: 3 elements (less than one 16-byte vector), 2501 elements
+    (several 256-vector chunks and a one-element tail), 37 elements at a
+    4-byte offset (not 16-byte aligned, so element by element), 700
+    elements, 101 elements in place and a zero-count call; a message pair
+    rides in the same group.  Between steps every rank adds one to the bit
+    patterns of its inputs (a one-ulp change), so each step reduces new
+    values.  chained: one more allreduce reads the 2501-element result, so
+    two calls share bytes and must run in order.  persistent: the group is
+    recorded once (GroupInit) and started every step."""
+    specs = [("a", 3, 0), ("b", 2501, 0), ("c", 37, 4), ("d", 700, 0)]
+    bufs, ops = [], []
+    for r in range(nranks):
+        g = rng(13, r)
+        b = {}
+        for name, cnt, off in specs:
+            b[name + "i"] = np.concatenate(
+                [np.zeros(off, np.uint8), as_bytes(g.standard_normal(cnt).astype(np.float32))])
+            b[name + "o"] = np.zeros(off + 4 * cnt, np.uint8)
+        b["ip"] = as_bytes(g.standard_normal(101).astype(np.float32))
+        b["z"] = np.zeros(16, np.uint8)
+        b["s"] = as_bytes(np.arange(3, dtype=np.int32) + 10 * r)
+        b["h"] = np.zeros(12, np.uint8)
+        if chained:
+            b["eo"] = np.zeros(4 * 2501, np.uint8)
+        bufs.append(b)
+        right, left = (r + 1) % nranks, (r - 1) % nranks
+        body = [Send("s", 0, 3, "int32", right, 7, req="a"),
+                Recv("h", 0, 3, "int32", left, 7, req="b")]
+        body += [Allreduce(name + "i", off, name + "o", off, cnt, "float32", "sum")
+                 for name, cnt, off in specs]
+        body += [Allreduce(IN_PLACE, 0, "ip", 0, 101, "float32", "sum"),
+                 Allreduce("ai", 0, "z", 0, 0, "float32", "sum")]
+        if chained:
+            body.append(Allreduce("bo", 0, "eo", 0, 2501, "float32", "sum"))
+        body.append(Wait(["a", "b"], [None, "st"]))
+        bump = [User(("add_const_i32", name + "i", off, cnt, 1)) for name, cnt, off in specs]
+        lst = []
+        if persistent:
+            lst += [GroupStart()] + body + [GroupInit("g")]
+            for _ in range(steps):
+                lst += [Start("g")] + bump
+        else:
+            for _ in range(steps):
+                lst += [GroupStart()] + body + [GroupEnd()] + bump
+        ops.append(lst)
+    name = "merged-allreduce" + ("-persistent" if persistent else "") + ("-chained" if chained else "")
+    return single_stream(nranks, bufs, ops, name=name)
