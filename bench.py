@@ -499,6 +499,19 @@ def bench_allreduce(args):
             out.append(D.ops_array(rows))
         return out
 
+    if args.group > 1 and args.group_only:
+        # only the grouped comparison (e.g. under a profiler, without the
+        # single-call passes)
+        grouped = allreduce_groups(args, n, count, dtype, S, p)
+        best = max((v for k, v in grouped.items() if k in ("plain", "grouped", "persistent")),
+                   default=0.0)
+        return {"metric": "enqueued allreduces/s, several per step", "value": best,
+                "unit": "allreduces/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": 1000 * args.group / best if best else None, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+                "config": {"workload": f"allreduce_sum_{n}ranks_{dtype}_{nbytes}B_x{args.group}",
+                           "ranks": n, "bytes_per_rank": nbytes},
+                "grouped": grouped}
     sess = D.Session(n)
     if args.via_host_synced:
         # counter collection serialises dispatches, which the cross-stream
@@ -605,8 +618,9 @@ def allreduce_groups(args, n, count, dtype, S, p):
         return out
 
     res = {}
+    chosen = args.group_variants.split(",")
     for variant, mode in (("plain", 0), ("grouped", 0), ("persistent", 0), ("host", 1)):
-        if variant == "host" and args.no_host_synced:
+        if variant == "host" and args.no_host_synced or variant not in chosen:
             continue
         k = args.steps if variant != "host" else max(1, min(args.steps, args.hs_steps))
         sess = D.Session(n)
@@ -631,8 +645,9 @@ def allreduce_groups(args, n, count, dtype, S, p):
             R2[r].zero_()
     return {"allreduces_per_step": G, "unit": "allreduces/s",
             **{f"{v}": res[v] for v in res},
-            "grouped_vs_host": res["grouped"] / res["host"] if "host" in res else None,
-            "persistent_vs_host": res["persistent"] / res["host"] if "host" in res else None}
+            "grouped_vs_host": res["grouped"] / res["host"] if {"grouped", "host"} <= set(res) else None,
+            "persistent_vs_host": (res["persistent"] / res["host"]
+                                   if {"persistent", "host"} <= set(res) else None)}
 
 
 # ------------------------------------------------------------------- batch
@@ -1217,6 +1232,10 @@ def main():
     ap.add_argument("--group", type=int, default=1,
                     help="allreduce: also time this many allreduces per step as plain calls, "
                          "one group, a persistent group and host-synchronised calls")
+    ap.add_argument("--group-variants", default="plain,grouped,persistent,host",
+                    help="allreduce --group: which of the four ways to time")
+    ap.add_argument("--group-only", action="store_true",
+                    help="allreduce --group: skip the single-call passes")
     ap.add_argument("--hs-steps", type=int, default=100)
     ap.add_argument("--no-host-synced", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -173,23 +173,37 @@ constexpr int RED_MAX_RANKS = 64;
 template <typename T, int OP>
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
     __shared__ uint32_t s_fatal;
-    __shared__ uint32_t s_inst;
+    __shared__ MultiRedDesc s_d;
     __shared__ const void *s_ptr[2 * RED_MAX_RANKS];
+    const uint32_t b = blockIdx.x;
     if (threadIdx.x == 0) {
         s_fatal = ld_relaxed32(&a.me->fatal);
-        // first_wg ascends from 0: keep desc[lo].first_wg <= b < desc[hi].first_wg
-        uint32_t lo = 0, hi = a.ninst;
-        const uint32_t b = blockIdx.x;
+        s_d = MultiRedDesc{};   // no instance found: the workgroup does nothing
+    }
+    __syncthreads();
+    // first_wg ascends strictly from 0.  Up to RED_THREADS instances every
+    // thread reads one descriptor at once (the table may sit in host memory,
+    // where dependent reads each cost a bus round trip); beyond, thread 0
+    // bisects.
+    if (a.ninst <= RED_THREADS) {
+        const uint32_t t = threadIdx.x;
+        if (t < a.ninst) {
+            const MultiRedDesc d = a.desc[t];
+            const uint32_t next = t + 1 < a.ninst ? a.desc[t + 1].first_wg : 0xffffffffu;
+            if (d.first_wg <= b && b < next) s_d = d;
+        }
+    } else if (threadIdx.x == 0) {
+        uint32_t lo = 0, hi = a.ninst;   // desc[lo].first_wg <= b < desc[hi].first_wg
         while (hi - lo > 1) {
             const uint32_t mid = lo + (hi - lo) / 2;
             if (a.desc[mid].first_wg <= b) lo = mid;
             else hi = mid;
         }
-        s_inst = lo;
+        s_d = a.desc[lo];
     }
     __syncthreads();
     if (s_fatal) return;
-    const MultiRedDesc d = a.desc[s_inst];
+    const MultiRedDesc d = s_d;
     const int n = int(d.n);
     if (threadIdx.x < 2 * d.n) s_ptr[threadIdx.x] = a.ptrs[d.ptr + threadIdx.x];
     __syncthreads();
