@@ -333,7 +333,7 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
  *  group of many small allreduces costs one arrival and one wait per rank
  *  plus one reduce kernel each, instead of two launches per rank each).
  *  When the group's allreduces all have one datatype and operation, each
- *  reads at most 4 MiB over all ranks, and no byte of any of their buffers
+ *  reads at most 64 MiB over all ranks, and no byte of any of their buffers
  *  belongs to two of them, they run as one reduce kernel (their order
  *  cannot change a result then); stats.reductions_merged counts them.
  *  Ranks that grouped different numbers of allreduces, or whose i-th calls

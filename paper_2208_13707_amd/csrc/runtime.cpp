@@ -942,7 +942,7 @@ int launch_red(World *w, hipStream_t s, const RedPlan &r) {
 // one type and operator, and no byte of any of their buffers belongs to two
 // of them; otherwise m.on stays false and they run one by one, in order.
 // Zero-count allreduces do nothing either way and are left out.
-constexpr uint64_t kMultiRedMaxBytes = uint64_t(4) << 20;   // per allreduce, all ranks' input
+constexpr uint64_t kMultiRedMaxBytes = uint64_t(64) << 20;   // per allreduce, all ranks' input
 constexpr uint64_t kMultiRedMaxWG = uint64_t(1) << 20;
 
 void plan_multi_red(const std::vector<RedPlan> &reds, MultiRedPlan &m) {
@@ -1378,7 +1378,8 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     P->reds = sh->plan.reds;
     P->mred = sh->plan.mred;
     P->nmsg = descs.size();
-    // an empty group still runs one workgroup, which publishes the run
+    // a group without messages launches no batch kernel in its runs (the
+    // graph of an entirely empty group keeps a one-workgroup node)
     P->nwg = std::max(1, int(starts.size()));
     // counters: arrive[q] at word 16q, done at 16n
     const size_t cbytes = size_t(n + 1) * 16 * sizeof(uint64_t);
@@ -1449,7 +1450,7 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
             if (e == hipSuccess) {
                 int r = MPIXS_SUCCESS;
                 if (n > 1) r = gpu_err(launch_wait_rel(cs, P->lwait));
-                if (!r) r = gpu_err(launch_batch(cs, P->args, P->nwg));
+                if (!r && P->nmsg > 0) r = gpu_err(launch_batch(cs, P->args, P->nwg));
                 if (!r) r = launch_reds(nullptr, cs, P->reds, P->mred, P->margs);
                 if (!r) r = gpu_err(launch_signal(cs, P->sig));
                 hipGraph_t gr = nullptr;
@@ -2229,7 +2230,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
                 // `launched`), so every wait here sees run e's record
                 for (int q = 0; q < P->n && !rc; ++q)
                     if (q != P->leader) rc = gpu_err(hipStreamWaitEvent(st->hs, P->post_ev[size_t(q)], 0));
-                if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
+                if (!rc && P->nmsg > 0) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
                 if (!rc) rc = launch_reds(w, st->hs, P->reds, P->mred, P->margs);
                 if (!rc) rc = gpu_err(hipEventRecord(P->done_ev, st->hs));
             } else if (P->exec) {
@@ -2237,7 +2238,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
                 if (!rc) count_reds(w, P->reds, P->mred);
             } else {
                 if (P->n > 1) rc = gpu_err(launch_wait_rel(st->hs, P->lwait));
-                if (!rc) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
+                if (!rc && P->nmsg > 0) rc = gpu_err(launch_batch(st->hs, P->args, P->nwg));
                 if (!rc) rc = launch_reds(w, st->hs, P->reds, P->mred, P->margs);
                 if (!rc) rc = gpu_err(launch_signal(st->hs, P->sig));
             }

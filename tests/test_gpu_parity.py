@@ -418,6 +418,15 @@ def test_merged_allreduces(persistent, graph, sync, chained):
     assert g.stats.reductions_merged == (0 if chained else 5 * steps)
 
 
+@pytest.mark.parametrize("persistent,graph", [(False, 0), (True, 0), (True, 1)])
+def test_merged_allreduces_without_messages(persistent, graph):
+    """Groups of allreduces only: a persistent run launches no batch kernel."""
+    g, _ = check_stats(C.merged_allreduces(persistent=persistent, steps=3, messages=False),
+                       cfg=cfg_with(batch_graph=graph),
+                       name=f"merged allreduces without messages persistent={persistent} graph={graph}")
+    assert g.stats.reductions_merged == 5 * 3
+
+
 def test_merged_allreduces_sixteen_ranks():
     g, _ = check_stats(C.merged_allreduces(nranks=16, steps=2), name="merged allreduces 16 ranks")
     assert g.stats.reductions_merged == 5 * 2

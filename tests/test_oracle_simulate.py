@@ -593,9 +593,10 @@ def test_grouped_allreduces_equal_the_calls_in_order(persistent):
     assert np.array_equal(a.buffers[0]["f32"].view(np.float32), x[0])
 
 
-@pytest.mark.parametrize("persistent,chained", [(False, False), (True, False), (False, True),
-                                                (True, True)])
-def test_merged_allreduces_equal_the_calls_in_order(persistent, chained):
+@pytest.mark.parametrize("persistent,chained,messages", [
+    (False, False, True), (True, False, True), (False, True, True), (True, True, True),
+    (True, False, False)])
+def test_merged_allreduces_equal_the_calls_in_order(persistent, chained, messages):
     """A group of float32 sums only (the kind the library may run as one
     kernel) gives the buffers of the same calls issued one by one; the
     2501-element result equals a float32 fold in rank order written out
@@ -603,7 +604,7 @@ def test_merged_allreduces_equal_the_calls_in_order(persistent, chained):
     chained call (which reads that result) sees the final value of the same
     step."""
     steps = 2
-    p = C.merged_allreduces(persistent=persistent, chained=chained, steps=steps)
+    p = C.merged_allreduces(persistent=persistent, chained=chained, steps=steps, messages=messages)
     a, b = sim.run(p), sim.run(_ungrouped(p))
     assert not a.deadlock and not any(a.sync_errors) and not b.deadlock
     for q in range(p.nranks):

@@ -558,7 +558,7 @@ def grouped_allreduces(nranks: int = 5, steps: int = 2, persistent: bool = False
 
 
 def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
-                      chained: bool = False) -> Program:
+                      chained: bool = False, messages: bool = True) -> Program:
     """Each step one group whose allreduces are all float32 sums on buffers
     of their own: 3 elements (less than one 16-byte vector), 2501 elements
     (several 256-vector chunks and a one-element tail), 37 elements at a
@@ -568,7 +568,8 @@ def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
     patterns of its inputs (a one-ulp change), so each step reduces new
     values.  chained: one more allreduce reads the 2501-element result, so
     two calls share bytes and must run in order.  persistent: the group is
-    recorded once (GroupInit) and started every step."""
+    recorded once (GroupInit) and started every step.  messages=False: the
+    group holds the allreduces only."""
     specs = [("a", 3, 0), ("b", 2501, 0), ("c", 37, 4), ("d", 700, 0)]
     bufs, ops = [], []
     for r in range(nranks):
@@ -587,14 +588,15 @@ def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
         bufs.append(b)
         right, left = (r + 1) % nranks, (r - 1) % nranks
         body = [Send("s", 0, 3, "int32", right, 7, req="a"),
-                Recv("h", 0, 3, "int32", left, 7, req="b")]
+                Recv("h", 0, 3, "int32", left, 7, req="b")] if messages else []
         body += [Allreduce(name + "i", off, name + "o", off, cnt, "float32", "sum")
                  for name, cnt, off in specs]
         body += [Allreduce(IN_PLACE, 0, "ip", 0, 101, "float32", "sum"),
                  Allreduce("ai", 0, "z", 0, 0, "float32", "sum")]
         if chained:
             body.append(Allreduce("bo", 0, "eo", 0, 2501, "float32", "sum"))
-        body.append(Wait(["a", "b"], [None, "st"]))
+        if messages:
+            body.append(Wait(["a", "b"], [None, "st"]))
         bump = [User(("add_const_i32", name + "i", off, cnt, 1)) for name, cnt, off in specs]
         lst = []
         if persistent:
@@ -605,5 +607,6 @@ def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
             for _ in range(steps):
                 lst += [GroupStart()] + body + [GroupEnd()] + bump
         ops.append(lst)
-    name = "merged-allreduce" + ("-persistent" if persistent else "") + ("-chained" if chained else "")
+    name = ("merged-allreduce" + ("-persistent" if persistent else "") + ("-chained" if chained else "")
+            + ("" if messages else "-no-messages"))
     return single_stream(nranks, bufs, ops, name=name)
