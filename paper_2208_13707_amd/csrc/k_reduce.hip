@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_n(ReduceArgs a) {
 // order as k_reduce.  Instances share no byte, so they need no order.
 constexpr int RED_MAX_RANKS = 64;
 
-template <typename T, int OP>
+template <typename T, int OP, bool NT>
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
     __shared__ uint32_t s_fatal;
     __shared__ MultiRedDesc s_d;
@@ -219,12 +219,14 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
         const uint64_t nvec = d.count / L;
         const uint64_t v = c * RED_THREADS + threadIdx.x;
         if (v < nvec) {
-            V acc = static_cast<const V *>(s_ptr[0])[v];
+            V acc = ld_unit<V, NT>(reinterpret_cast<uint64_t>(static_cast<const V *>(s_ptr[0]) + v));
             for (int q0 = 1; q0 < n; q0 += RED_GROUP) {
                 V x[RED_GROUP];
 #pragma unroll
                 for (int j = 0; j < RED_GROUP; ++j)
-                    if (q0 + j < n) x[j] = static_cast<const V *>(s_ptr[q0 + j])[v];
+                    if (q0 + j < n)
+                        x[j] = ld_unit<V, NT>(
+                            reinterpret_cast<uint64_t>(static_cast<const V *>(s_ptr[q0 + j]) + v));
 #pragma unroll
                 for (int j = 0; j < RED_GROUP; ++j)
                     if (q0 + j < n) {
@@ -232,7 +234,9 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
                         for (int l = 0; l < L; ++l) acc[l] = combine<T, OP>(acc[l], x[j][l]);
                     }
             }
-            for (int q = 0; q < n; ++q) static_cast<V *>(const_cast<void *>(s_ptr[n + q]))[v] = acc;
+            for (int q = 0; q < n; ++q)
+                st_unit<V, NT>(reinterpret_cast<uint64_t>(static_cast<V *>(const_cast<void *>(s_ptr[n + q])) + v),
+                               acc);
         }
         if (c == 0) {
             const uint64_t i = nvec * L + threadIdx.x;
@@ -247,25 +251,30 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
 // ------------------------------------------------------------- launchers
 int reduce_threads() { return RED_THREADS; }
 
-template <typename T>
+template <typename T, bool NT>
 static hipError_t reduce_multi_t(hipStream_t s, const MultiRedArgs &a, int op, int nwg) {
     switch (op) {
-    case OP_SUM: hipLaunchKernelGGL((k_reduce_multi<T, OP_SUM>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
-    case OP_PROD: hipLaunchKernelGGL((k_reduce_multi<T, OP_PROD>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
-    case OP_MIN: hipLaunchKernelGGL((k_reduce_multi<T, OP_MIN>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_reduce_multi<T, OP_MAX>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case OP_SUM: hipLaunchKernelGGL((k_reduce_multi<T, OP_SUM, NT>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case OP_PROD: hipLaunchKernelGGL((k_reduce_multi<T, OP_PROD, NT>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    case OP_MIN: hipLaunchKernelGGL((k_reduce_multi<T, OP_MIN, NT>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_reduce_multi<T, OP_MAX, NT>), dim3(nwg), dim3(RED_THREADS), 0, s, a); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg) {
-    if (a.ninst == 0 || nwg <= 0) return hipErrorInvalidValue;
+template <bool NT>
+static hipError_t reduce_multi_f(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg) {
     switch (basic) {
-    case MPIXS_INT32: return reduce_multi_t<int32_t>(s, a, op, nwg);
-    case MPIXS_INT64: return reduce_multi_t<int64_t>(s, a, op, nwg);
-    case MPIXS_FLOAT32: return reduce_multi_t<float>(s, a, op, nwg);
-    default: return reduce_multi_t<double>(s, a, op, nwg);
+    case MPIXS_INT32: return reduce_multi_t<int32_t, NT>(s, a, op, nwg);
+    case MPIXS_INT64: return reduce_multi_t<int64_t, NT>(s, a, op, nwg);
+    case MPIXS_FLOAT32: return reduce_multi_t<float, NT>(s, a, op, nwg);
+    default: return reduce_multi_t<double, NT>(s, a, op, nwg);
     }
+}
+
+hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg, bool nt) {
+    if (a.ninst == 0 || nwg <= 0) return hipErrorInvalidValue;
+    return nt ? reduce_multi_f<true>(s, a, basic, op, nwg) : reduce_multi_f<false>(s, a, basic, op, nwg);
 }
 
 template <typename T, int OP, bool F>

@@ -17,9 +17,10 @@ hipError_t launch_reduce(hipStream_t s, const ReduceArgs &a, int basic, int op, 
 bool reduce_fixed_ok(int n);
 int reduce_fixed_units();            // vectors per lane of launch_reduce_fixed
 hipError_t launch_reduce_fixed(hipStream_t s, const ReduceArgs &a, int basic, int op, int nwg);
-// a group's small reductions of one type and operator, one workgroup per
-// chunk of reduce_threads() vectors (or elements when not 16-byte aligned)
-hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg);
+// a group's reductions of one type and operator, one workgroup per chunk of
+// reduce_threads() vectors (or elements when not 16-byte aligned); nt:
+// nontemporal vector loads and stores (launches much larger than the caches)
+hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg, bool nt);
 hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg);
 bool batch_tile_ok(uint32_t tile);   // a tile size the batch kernel is built for
 hipError_t launch_post_inc(hipStream_t s, uint64_t *p);

@@ -944,6 +944,8 @@ int launch_red(World *w, hipStream_t s, const RedPlan &r) {
 // Zero-count allreduces do nothing either way and are left out.
 constexpr uint64_t kMultiRedMaxBytes = uint64_t(64) << 20;   // per allreduce, all ranks' input
 constexpr uint64_t kMultiRedMaxWG = uint64_t(1) << 20;
+// merged launches moving at least this much use nontemporal accesses
+constexpr uint64_t kMultiRedNtBytes = uint64_t(64) << 20;
 
 void plan_multi_red(const std::vector<RedPlan> &reds, MultiRedPlan &m) {
     m.on = false;
@@ -1033,7 +1035,7 @@ void count_reds(World *w, const std::vector<RedPlan> &reds, const MultiRedPlan &
 int launch_reds(World *w, hipStream_t s, const std::vector<RedPlan> &reds, const MultiRedPlan &m,
                 const MultiRedArgs &ma) {
     if (m.on) {
-        const int rc = gpu_err(launch_reduce_multi(s, ma, m.dtype, m.op, m.nwg));
+        const int rc = gpu_err(launch_reduce_multi(s, ma, m.dtype, m.op, m.nwg, m.bytes >= kMultiRedNtBytes));
         if (!rc && w) {
             w->n_reduce.fetch_add(1, std::memory_order_relaxed);
             w->reds_merged.fetch_add(m.ninst, std::memory_order_relaxed);

@@ -432,6 +432,16 @@ def test_merged_allreduces_sixteen_ranks():
     assert g.stats.reductions_merged == 5 * 2
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_merged_allreduces_large(persistent):
+    """16 ranks with one more allreduce of 600,001 float32 elements: the
+    merged launch moves about 80 MB and takes nontemporal accesses."""
+    g, _ = check_stats(C.merged_allreduces(nranks=16, steps=2, persistent=persistent, big=600_001),
+                       name=f"merged allreduces large persistent={persistent}")
+    assert g.stats.reductions_merged == 6 * 2
+    assert g.stats.bytes_reduced >= 2 * (64 << 20)
+
+
 def test_grouped_allreduces_fixed_rank_count():
     """16 ranks: the grouped reductions take the unrolled 16-rank kernel."""
     check(C.grouped_allreduces(nranks=16, steps=2))

@@ -558,7 +558,7 @@ def grouped_allreduces(nranks: int = 5, steps: int = 2, persistent: bool = False
 
 
 def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
-                      chained: bool = False, messages: bool = True) -> Program:
+                      chained: bool = False, messages: bool = True, big: int = 0) -> Program:
     """Each step one group whose allreduces are all float32 sums on buffers
     of their own: 3 elements (less than one 16-byte vector), 2501 elements
     (several 256-vector chunks and a one-element tail), 37 elements at a
@@ -569,8 +569,11 @@ def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
     values.  chained: one more allreduce reads the 2501-element result, so
     two calls share bytes and must run in order.  persistent: the group is
     recorded once (GroupInit) and started every step.  messages=False: the
-    group holds the allreduces only."""
+    group holds the allreduces only.  big: one more allreduce of that many
+    elements (large groups take nontemporal accesses)."""
     specs = [("a", 3, 0), ("b", 2501, 0), ("c", 37, 4), ("d", 700, 0)]
+    if big:
+        specs.append(("g", big, 0))
     bufs, ops = [], []
     for r in range(nranks):
         g = rng(13, r)
@@ -608,5 +611,5 @@ def merged_allreduces(nranks: int = 6, steps: int = 2, persistent: bool = False,
                 lst += [GroupStart()] + body + [GroupEnd()] + bump
         ops.append(lst)
     name = ("merged-allreduce" + ("-persistent" if persistent else "") + ("-chained" if chained else "")
-            + ("" if messages else "-no-messages"))
+            + ("" if messages else "-no-messages") + (f"-big{big}" if big else ""))
     return single_stream(nranks, bufs, ops, name=name)
