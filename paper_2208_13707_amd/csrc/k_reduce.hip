@@ -207,7 +207,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
     const int n = int(d.n);
     if (threadIdx.x < 2 * d.n) s_ptr[threadIdx.x] = a.ptrs[d.ptr + threadIdx.x];
     __syncthreads();
-    const uint64_t c = blockIdx.x - d.first_wg;
+    // a chunk is U passes of RED_THREADS units; lane k-th unit at
+    // c * RED_THREADS * U + k * RED_THREADS + threadIdx.x
+    constexpr int U = NT ? 2 : 1;
+    constexpr int G = RED_GROUP / U;   // inputs of each pass loaded back to back
+    const uint64_t base = (blockIdx.x - d.first_wg) * uint64_t(RED_THREADS * U) + threadIdx.x;
     auto fold_one = [&](uint64_t i) {
         T acc = static_cast<const T *>(s_ptr[0])[i];
         for (int q = 1; q < n; ++q) acc = combine<T, OP>(acc, static_cast<const T *>(s_ptr[q])[i]);
@@ -217,34 +221,53 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_multi(MultiRedArgs a) {
         constexpr int L = int(16 / sizeof(T));
         using V = T __attribute__((ext_vector_type(L)));
         const uint64_t nvec = d.count / L;
-        const uint64_t v = c * RED_THREADS + threadIdx.x;
-        if (v < nvec) {
-            V acc = ld_unit<V, NT>(reinterpret_cast<uint64_t>(static_cast<const V *>(s_ptr[0]) + v));
-            for (int q0 = 1; q0 < n; q0 += RED_GROUP) {
-                V x[RED_GROUP];
+        V acc[U];
 #pragma unroll
-                for (int j = 0; j < RED_GROUP; ++j)
-                    if (q0 + j < n)
-                        x[j] = ld_unit<V, NT>(
+        for (int k = 0; k < U; ++k) {
+            const uint64_t v = base + uint64_t(k) * RED_THREADS;
+            if (v < nvec) acc[k] = ld_unit<V, NT>(reinterpret_cast<uint64_t>(static_cast<const V *>(s_ptr[0]) + v));
+        }
+        for (int q0 = 1; q0 < n; q0 += G) {
+            V x[U][G];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint64_t v = base + uint64_t(k) * RED_THREADS;
+#pragma unroll
+                for (int j = 0; j < G; ++j)
+                    if (v < nvec && q0 + j < n)
+                        x[k][j] = ld_unit<V, NT>(
                             reinterpret_cast<uint64_t>(static_cast<const V *>(s_ptr[q0 + j]) + v));
+            }
 #pragma unroll
-                for (int j = 0; j < RED_GROUP; ++j)
-                    if (q0 + j < n) {
+            for (int k = 0; k < U; ++k) {
+                const uint64_t v = base + uint64_t(k) * RED_THREADS;
 #pragma unroll
-                        for (int l = 0; l < L; ++l) acc[l] = combine<T, OP>(acc[l], x[j][l]);
+                for (int j = 0; j < G; ++j)
+                    if (v < nvec && q0 + j < n) {
+#pragma unroll
+                        for (int l = 0; l < L; ++l) acc[k][l] = combine<T, OP>(acc[k][l], x[k][j][l]);
                     }
             }
-            for (int q = 0; q < n; ++q)
-                st_unit<V, NT>(reinterpret_cast<uint64_t>(static_cast<V *>(const_cast<void *>(s_ptr[n + q])) + v),
-                               acc);
         }
-        if (c == 0) {
+        for (int q = 0; q < n; ++q) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint64_t v = base + uint64_t(k) * RED_THREADS;
+                if (v < nvec)
+                    st_unit<V, NT>(
+                        reinterpret_cast<uint64_t>(static_cast<V *>(const_cast<void *>(s_ptr[n + q])) + v), acc[k]);
+            }
+        }
+        if (blockIdx.x == d.first_wg) {
             const uint64_t i = nvec * L + threadIdx.x;
             if (i < d.count) fold_one(i);
         }
     } else {
-        const uint64_t i = c * RED_THREADS + threadIdx.x;
-        if (i < d.count) fold_one(i);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint64_t i = base + uint64_t(k) * RED_THREADS;
+            if (i < d.count) fold_one(i);
+        }
     }
 }
 
@@ -271,6 +294,8 @@ static hipError_t reduce_multi_f(hipStream_t s, const MultiRedArgs &a, int basic
     default: return reduce_multi_t<double, NT>(s, a, op, nwg);
     }
 }
+
+int reduce_multi_units(bool nt) { return RED_THREADS * (nt ? 2 : 1); }
 
 hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg, bool nt) {
     if (a.ninst == 0 || nwg <= 0) return hipErrorInvalidValue;

@@ -18,9 +18,10 @@ bool reduce_fixed_ok(int n);
 int reduce_fixed_units();            // vectors per lane of launch_reduce_fixed
 hipError_t launch_reduce_fixed(hipStream_t s, const ReduceArgs &a, int basic, int op, int nwg);
 // a group's reductions of one type and operator, one workgroup per chunk of
-// reduce_threads() vectors (or elements when not 16-byte aligned); nt:
+// reduce_multi_units(nt) vectors (or elements when not 16-byte aligned); nt:
 // nontemporal vector loads and stores (launches much larger than the caches)
 hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, int op, int nwg, bool nt);
+int reduce_multi_units(bool nt);     // vectors (or elements) per workgroup of launch_reduce_multi
 hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg);
 bool batch_tile_ok(uint32_t tile);   // a tile size the batch kernel is built for
 hipError_t launch_post_inc(hipStream_t s, uint64_t *p);

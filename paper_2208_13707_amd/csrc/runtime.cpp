@@ -949,6 +949,7 @@ constexpr uint64_t kMultiRedNtBytes = uint64_t(64) << 20;
 
 void plan_multi_red(const std::vector<RedPlan> &reds, MultiRedPlan &m) {
     m.on = false;
+    m.nt = false;
     m.desc.clear();
     m.ptrs.clear();
     m.bytes = 0;
@@ -960,7 +961,7 @@ void plan_multi_red(const std::vector<RedPlan> &reds, MultiRedPlan &m) {
         uint32_t inst;
     };
     std::vector<Span> spans;
-    uint64_t wg = 0;
+    std::vector<uint64_t> units;       // per merged allreduce
     for (size_t i = 0; i < reds.size(); ++i) {
         const RedPlan &r = reds[i];
         if (r.dtype != reds[0].dtype || r.op != reds[0].op) return;
@@ -969,11 +970,9 @@ void plan_multi_red(const std::vector<RedPlan> &reds, MultiRedPlan &m) {
         const uint64_t es = uint64_t(basic_size(r.dtype));
         const uint64_t len = r.a.count * es;
         if (len * uint64_t(r.a.n) > kMultiRedMaxBytes) return;
-        const uint64_t units = r.vec ? std::max<uint64_t>(1, r.a.count / (16 / es)) : r.a.count;
-        const uint64_t nch = (units + uint64_t(reduce_threads()) - 1) / uint64_t(reduce_threads());
+        units.push_back(r.vec ? std::max<uint64_t>(1, r.a.count / (16 / es)) : r.a.count);
         MultiRedDesc d{};
         d.count = r.a.count;
-        d.first_wg = uint32_t(wg);
         d.ptr = uint32_t(m.ptrs.size());
         d.n = uint32_t(r.a.n);
         d.vec = r.vec ? 1u : 0u;
@@ -987,10 +986,17 @@ void plan_multi_red(const std::vector<RedPlan> &reds, MultiRedPlan &m) {
         }
         m.desc.push_back(d);
         m.bytes += r.bytes;
-        wg += nch;
-        if (wg > kMultiRedMaxWG) return;
     }
     if (m.desc.size() < 2) return;
+    // workgroups: chunks of reduce_multi_units(nt) vectors (or elements)
+    m.nt = m.bytes >= kMultiRedNtBytes;
+    const uint64_t per = uint64_t(reduce_multi_units(m.nt));
+    uint64_t wg = 0;
+    for (size_t i = 0; i < m.desc.size(); ++i) {
+        m.desc[i].first_wg = uint32_t(wg);
+        wg += (units[i] + per - 1) / per;
+        if (wg > kMultiRedMaxWG) return;
+    }
     // Sweep the spans by start, keeping the farthest end seen and its
     // allreduce.  The first span (in this order) that overlaps a span of
     // another allreduce always starts before that farthest end, and the end
@@ -1035,7 +1041,7 @@ void count_reds(World *w, const std::vector<RedPlan> &reds, const MultiRedPlan &
 int launch_reds(World *w, hipStream_t s, const std::vector<RedPlan> &reds, const MultiRedPlan &m,
                 const MultiRedArgs &ma) {
     if (m.on) {
-        const int rc = gpu_err(launch_reduce_multi(s, ma, m.dtype, m.op, m.nwg, m.bytes >= kMultiRedNtBytes));
+        const int rc = gpu_err(launch_reduce_multi(s, ma, m.dtype, m.op, m.nwg, m.nt));
         if (!rc && w) {
             w->n_reduce.fetch_add(1, std::memory_order_relaxed);
             w->reds_merged.fetch_add(m.ninst, std::memory_order_relaxed);

@@ -153,6 +153,7 @@ struct RedPlan {
 // descriptors.
 struct MultiRedPlan {
     bool on = false;
+    bool nt = false;                   // nontemporal (large) launch
     int dtype = 0;
     int op = 0;
     int nwg = 0;
