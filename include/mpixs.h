@@ -331,7 +331,7 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count,
  *  allreduce of every rank forms the group's i-th reduction, which the
  *  launching rank's stream runs after the batch kernel, in order (so a
  *  group of many small allreduces costs one arrival and one wait per rank
- *  plus one reduce kernel each, instead of two launches per rank each).
+ *  plus the reduce kernels, instead of two launches per rank each).
  *  When the group's allreduces all have one datatype and operation, each
  *  reads at most 64 MiB over all ranks, and no byte of any of their buffers
  *  belongs to two of them, they run as one reduce kernel (their order
