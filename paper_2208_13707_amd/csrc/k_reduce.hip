@@ -163,11 +163,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_n(ReduceArgs a) {
     }
 }
 
-// A group's small reductions of one type and operator in one launch.
-// Workgroup b serves the last instance whose first_wg <= b, chunk
-// b - first_wg of it: RED_THREADS vectors (aligned instances; chunk 0 also
-// takes the tail elements) or RED_THREADS elements.  Same left fold in rank
-// order as k_reduce.  Instances share no byte, so they need no order.
+// A group's reductions of one type and operator in one launch.  Workgroup b
+// serves the last instance whose first_wg <= b, chunk b - first_wg of it:
+// RED_THREADS x U vectors (aligned instances; chunk 0 also takes the tail
+// elements) or RED_THREADS x U elements, U = 2 in nontemporal launches (the
+// large ones) and 1 otherwise.  Same left fold in rank order as k_reduce.
+// Instances share no byte, so they need no order.
 constexpr int RED_MAX_RANKS = 64;
 
 template <typename T, int OP, bool NT>
