@@ -1293,7 +1293,13 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     const std::vector<BatchStart> &starts = sh->plan.starts;
     BatchArgs a{};
     uint64_t bytes = 0;
-    int rc = plan_group(w, sh, rec, n, st, a, &bytes);
+    // producer first: the other ranks enqueue their arrival kernels outside
+    // the group lock, and the wait for them is enqueued only once all are.
+    // Waiting before planning measured faster on large groups (the posting
+    // threads slow a concurrent plan) and as fast on small ones.
+    int rc = host_wait(w, &rec->posted, [&] { return rec->posted.load(std::memory_order_acquire) >= n - 1; });
+    if (rc) return rc;
+    rc = plan_group(w, sh, rec, n, st, a, &bytes);
     if (rc) return rc;
     uint64_t *arrive = sh->d_grp;
     uint64_t *done = sh->d_grp + 16 * n;
@@ -2167,8 +2173,14 @@ int group_finish(mpixs_comm c, int kind, BatchPlan **plan) {
         rec->launched.store(1, std::memory_order_release);
         host_notify(&rec->launched);
     } else {
-        if (kind == 1) rc = do_post(w, st, sh->d_grp + 16 * c->rank, g + 1);
         sh->grp_mu.unlock();
+        if (kind == 1) {
+            // counted even when the launch failed, so the planning rank
+            // never waits for it; the failure is this rank's error
+            rc = do_post(w, st, sh->d_grp + 16 * c->rank, g + 1);
+            rec->posted.fetch_add(1, std::memory_order_release);
+            host_notify(&rec->posted);
+        }
         if (!rc) rc = host_wait(w, &rec->launched, [&] { return rec->launched.load(std::memory_order_acquire) != 0; });
         if (!rc) rc = rec->error;
         if (!rc && kind == 1) {

@@ -174,6 +174,7 @@ struct GroupRec {
     std::vector<std::vector<GOp>> ops;  // per rank
     std::vector<StreamObj *> streams;
     std::atomic<int> launched{0};
+    std::atomic<int> posted{0};         // one-shot: arrival kernels the other ranks have enqueued
     int error = 0;
     std::atomic<int> refs{0};
 };
