@@ -2102,12 +2102,20 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count, mpixs
     rec->arrived++;
     if (rec->arrived == n) {
         sh->coll_mu.unlock();
-        rc = do_reduce(w, st, rec, n, c->rank, arrive, k + 1, done, k + 1);
+        // producer first: the other ranks launch their arrival kernels
+        // outside the lock; the reduction that waits for them is enqueued
+        // once all are
+        rc = host_wait(w, &rec->posted, [&] { return rec->posted.load(std::memory_order_acquire) >= n - 1; });
+        if (!rc) rc = do_reduce(w, st, rec, n, c->rank, arrive, k + 1, done, k + 1);
         rec->reduce_enq.store(1, std::memory_order_release);
         host_notify(&rec->reduce_enq);
     } else {
-        rc = do_post(w, st, arrive + 16 * c->rank, k + 1);
         sh->coll_mu.unlock();
+        // counted even when the launch failed, so the reducing rank never
+        // waits for it; the failure is this rank's error
+        rc = do_post(w, st, arrive + 16 * c->rank, k + 1);
+        rec->posted.fetch_add(1, std::memory_order_release);
+        host_notify(&rec->posted);
         if (!rc) rc = host_wait(w, &rec->reduce_enq, [&] { return rec->reduce_enq.load(std::memory_order_acquire) != 0; });
         if (!rc) {
             WaitArgs a = wait_one(done, k + 1);

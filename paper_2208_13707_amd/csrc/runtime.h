@@ -110,6 +110,7 @@ struct Channel {
 struct CollRec {
     int arrived = 0;
     std::atomic<int> reduce_enq{0};
+    std::atomic<int> posted{0};        // arrival kernels the non-reducing ranks have enqueued
     std::atomic<int> done_host{0};
     std::atomic<int> refs{0};
     const void *in[64] = {};
