@@ -190,18 +190,7 @@ def _check_p2p(p: Program, rank: int, op) -> Optional[str]:
             return "ERR_RANK"
     if isinstance(op, Recv) and tm.overlaps(t, op.count):
         return "ERR_TYPE"
-    if op.count * t.size >= 2 ** 32 and not _one_block(t):
-        # the library's stated size limit for layouts that are not one
-        # contiguous block per element (an implementation limit, not the
-        # paper's); mirrored so that synchronous codes agree at any size
-        return "ERR_COUNT"
     return None
-
-
-def _one_block(t) -> bool:
-    """The element's bytes form one contiguous run in typemap order."""
-    d = t.disps
-    return bool(d.size == 0 or np.array_equal(d, d[0] + t.esize * np.arange(d.size)))
 
 
 def _colls_agree(colls, nranks) -> bool:
