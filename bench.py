@@ -181,15 +181,12 @@ def close_checked(sess):
 
 
 def run_checked(sess, ops, mode=0, nmarks=0, max_reqs=64):
-    import torch
     from paper_2208_13707_amd import mpixs as M
     rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
     if rc:
         raise RuntimeError(f"driver: {M.errname(rc)} at thread {res.error_thread} op {res.error_op}")
-    # results are read back through torch's own stream: synchronise the whole
-    # device first (the runner has synchronised each rank's stream, which
-    # alone left stale cache lines visible to a later copy now and then)
-    torch.cuda.synchronize()
+    # every rank thread of the runner has synchronised its own stream: the
+    # results may be read on torch's stream now, with no device-wide sync
     return res.seconds, marks
 
 
@@ -525,8 +522,8 @@ def bench_allreduce(args):
     sec, _ = run_checked(sess, ops(args.steps))
     _, marks = run_checked(sess, ops(args.steps, True), nmarks=2 * args.steps)
     lat = step_latencies(marks, args.steps)
-    close_checked(sess)
-    # sampled check against the oracle's fold (every 4097th element)
+    # sampled check against the oracle's fold (every 4097th element), read
+    # after the rank streams' own synchronisation
     from oracle import reduce as red
     idx = np.arange(0, count, 4097)
     ins = [np.frombuffer(p.buffers[r]["send"].tobytes(), dtype=dtype)[idx] for r in range(n)]
@@ -534,6 +531,7 @@ def bench_allreduce(args):
     for r in (0, n - 1):
         got = np.frombuffer(R[r].cpu().numpy().tobytes(), dtype=dtype)[idx]
         assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), "allreduce != oracle"
+    close_checked(sess)
     hs = None
     if not args.no_host_synced:
         sess = D.Session(n)
@@ -628,10 +626,10 @@ def allreduce_groups(args, n, count, dtype, S, p):
             run_checked(sess, ops("init", 0))
         run_checked(sess, ops(variant, min(args.warmup, 3)), mode=mode)
         secs = sorted(run_checked(sess, ops(variant, k), mode=mode)[0] for _ in range(3))
-        close_checked(sess)
         res[variant] = G * k / secs[1]
         log(f"[allreduce x{G}] {variant}: {res[variant]:.0f} allreduces/s")
-        # every slice holds the rank-order fold (sampled)
+        # every slice holds the rank-order fold (sampled), read after the
+        # rank streams' own synchronisation
         from oracle import reduce as redo
         idx = np.arange(0, count, 97)
         ins = [np.frombuffer(p.buffers[q]["send"].tobytes(), dtype=dtype)[idx] for q in range(n)]
@@ -643,6 +641,8 @@ def allreduce_groups(args, n, count, dtype, S, p):
             if bad:
                 raise AssertionError(f"{variant}: rank {r} slices {bad} differ from the oracle")
             R2[r].zero_()
+        torch.cuda.current_stream().synchronize()
+        close_checked(sess)
     return {"allreduces_per_step": G, "unit": "allreduces/s",
             **{f"{v}": res[v] for v in res},
             "grouped_vs_host": res["grouped"] / res["host"] if {"grouped", "host"} <= set(res) else None,
@@ -990,12 +990,12 @@ def bench_nto1(args):
             # exact check is made on a single step, where every message
             # meets exactly one of the step's receives
             R["mux"].zero_()
-            torch.cuda.synchronize()
+            torch.cuda.current_stream().synchronize()
             s_ops, r_ops = ops(variant, 1)
             rc, _, _ = sess.run(s_ops, r_ops, mode=mode, max_reqs=n * per)
             if rc:
                 raise RuntimeError(f"nto1 {variant}: {M.errname(rc)}")
-            torch.cuda.synchronize()
+            # each runner thread synchronised its own stream
             want = np.sort(np.concatenate([s.cpu().numpy() for s in S]))
             if not np.array_equal(np.sort(R["mux"].cpu().numpy()), want):
                 raise AssertionError("multiplex N-to-1 lost or duplicated a message")

@@ -269,6 +269,18 @@ int mpixs_type_get_extent(mpixs_datatype type, int64_t *lb, int64_t *extent);
  *                 transfer; *req is consumed and set to NULL at this call.
  *  waitall_enqueue: requests must all belong to one stream (§3.4), else
  *                 MPIXS_ERR_STREAM; statuses may be NULL.
+ *  Buffers (§6's GPU example; ownership stays with the caller): the bytes a
+ *  message or allreduce touches must lie in device memory (hipMalloc,
+ *  managed memory, torch tensors on the device) and, where HIP knows the
+ *  allocation's range, inside that allocation; a status (or a waitall
+ *  status array) may also lie in pinned host memory (hipHostMalloc).
+ *  Anything else -- pageable host memory above all -- is MPIXS_ERR_BUFFER at
+ *  the call, with no side effect, checked after the other arguments and the
+ *  size limit below, with
+ *  hipPointerGetAttributes / hipMemGetAddressRange.  Each stream keeps the
+ *  ranges it has found valid (16 allocations, replaced round-robin), so a
+ *  range freed and reused for other memory while the stream lives still
+ *  passes as the allocation it was.  Zero-byte messages are not checked.
  *  Sizes: a message whose datatype is dense (its element is one contiguous
  *  block: a basic type, a contiguous type, a vector or indexed type that
  *  reduces to one block) may have any byte count; any other message must
@@ -459,6 +471,9 @@ typedef struct {
     uint64_t groups_planned;    /* group instances matched and planned (one-shot or init) */
     double plan_ms;             /* host time the planning ranks spent on them */
     uint64_t reductions_merged; /* grouped allreduces run inside one merged reduce kernel */
+    uint64_t channels_recycled; /* matching-table blocks handed to a new channel (§3.1 frees) */
+    uint64_t streams_recycled;  /* stream blocks of freed streams taken by new streams */
+    uint64_t comm_lines_recycled; /* collective lines of freed communicators reused */
 } mpixs_stats;
 
 /* Counters of the world since creation (or the last reset).  With

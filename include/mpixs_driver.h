@@ -86,8 +86,10 @@ typedef struct {
  * stream: the sender fills its buffer with the request's payload and sends
  * (send_enqueue, or isend_enqueue + wait_enqueue), the receiver receives and
  * a checksum of the received bytes is written to host memory; for an
- * allreduce every rank fills its input and calls allreduce_enqueue (int32
- * SUM over all ranks) and rank 0 checksums its output.  A reaper thread
+ * allreduce every rank fills its input, calls allreduce_enqueue (int32 SUM
+ * over all ranks) and checksums its own output, the request's checksum being
+ * the sum over ranks r of (2r + 1) times rank r's checksum (so with every
+ * output equal to the fold, n^2 times its checksum, modulo 2^64).  A reaper thread
  * watches the completion flags (written by the device), frees the buffers
  * and timestamps the requests, so later arrivals are admitted as memory
  * frees up while earlier requests are still on the GPU.
@@ -129,10 +131,16 @@ typedef struct {
  * cannot be allocated or a request does not fit it; otherwise the first
  * error of an enqueue call (0 if none).  *wall_s receives the time from the
  * start to the last completion.  The buffers live in one device allocation
- * of budget_bytes made by this call and freed before it returns. */
+ * of budget_bytes made by this call and freed before it returns.
+ * Capture: for k < ncapture, request capture[2k] also copies its result
+ * bytes, before they are checksummed, to capture_dev + capture[2k+1] (device
+ * memory of the caller): the received bytes, or for an allreduce every
+ * rank's output, rank r's at offset r * bytes.  capture may be NULL when
+ * ncapture is 0. */
 int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *comms,
                     void *const *streams, const mpixs_drv_req *reqs, int64_t nreq,
-                    int64_t budget_bytes, mpixs_drv_req_result *results, double *wall_s);
+                    int64_t budget_bytes, mpixs_drv_req_result *results, double *wall_s,
+                    const int64_t *capture, int64_t ncapture, void *capture_dev);
 
 /* ------------------------------------------------ host message-rate model
  * A CPU-only analog of the paper's multithreaded message-rate measurement

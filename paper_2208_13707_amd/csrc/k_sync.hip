@@ -23,7 +23,14 @@ __global__ void __launch_bounds__(64) k_wait(WaitArgs a) {
     const int lane = threadIdx.x;
     uint32_t err = 0;
     const uint32_t fatal0 = ld_relaxed32(&a.me->fatal);
-    if (!fatal0 && lane < a.n) err = spin_wait(a.ptr[lane], a.target[lane], a.ctl);
+    if (!fatal0 && lane < a.n) {
+        err = spin_wait(a.ptr[lane], a.target[lane], a.ctl);
+        // after spin_wait's acquire fence: nothing of this message touches
+        // the block any more, so the host may hand it on
+        if (!err && a.rel_base && a.rel_idx[lane])
+            __hip_atomic_store(a.rel_base + (a.rel_idx[lane] - 1), a.target[lane],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     if (err) set_fatal(a.me, err);
     __syncthreads();
     if (lane == 0) {

@@ -140,6 +140,9 @@ struct WaitCtl {
 };
 
 // Up to 64 (pointer, target) pairs: wait until *ptr >= target for each.
+// A lane whose rel_idx is nonzero is the last device user of channel block
+// rel_idx - 1: once its wait has passed it writes its target to that
+// block's host-pinned release word, which lets the host hand the block on.
 struct WaitArgs {
     const uint64_t *ptr[64];
     uint64_t target[64];
@@ -149,6 +152,8 @@ struct WaitArgs {
     DevStream *me;          // stream the kernel runs on
     void *status;           // optional receive status to write after the wait
     StatusVal st;
+    uint64_t *rel_base;     // host-pinned release words, one per channel block
+    uint32_t rel_idx[64];
 };
 
 struct CopyArgs {

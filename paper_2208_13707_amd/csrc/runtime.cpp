@@ -393,11 +393,9 @@ Channel *get_channel(mpixs_comm_s *c, int src, int dst, int tag, bool host_mode)
         if (jt != sh->dir.end()) {
             ch = jt->second;
         } else {
-            World *w = sh->w;
-            const uint32_t idx = w->chan_next.fetch_add(1);
-            if (idx >= w->chan_cap) return nullptr;
+            // the device block is attached by the first enqueued message
             ch = new Channel();
-            ch->d = w->d_chans + idx;
+            ch->owner = sh;
             sh->dir.emplace(key, ch);
         }
     }
@@ -416,13 +414,187 @@ void rec_release(Channel *ch, Rec *r) {
     }
 }
 
+// ------------------------------------------------------- block recycling
+// Move blocks whose last device user has written their release word to the
+// free list.  Caller holds w->chan_mu.  A block still attached to a channel
+// is detached only if the channel's lock is free at once (the caller may
+// hold another channel's lock) and nothing was issued on the channel since
+// it became quiescent.
+void reclaim_blocks(World *w) {
+    auto released = [&](uint32_t idx, uint64_t v) {
+        return __atomic_load_n(&w->h_rel[idx], __ATOMIC_ACQUIRE) == v;
+    };
+    size_t j = 0;
+    for (size_t i = 0; i < w->chan_limbo.size(); ++i) {
+        const auto e = w->chan_limbo[i];
+        if (released(e.first, e.second)) w->chan_free.push_back(e);
+        else w->chan_limbo[j++] = e;
+    }
+    w->chan_limbo.resize(j);
+    j = 0;
+    for (size_t i = 0; i < w->chan_drain.size(); ++i) {
+        Channel *ch = w->chan_drain[i];
+        bool keep = true;
+        if (ch->mu.try_lock()) {
+            if (ch->idx == kNoBlock || ch->seq[0] != ch->drain_seq || ch->seq[1] != ch->drain_seq) {
+                keep = false;   // issued on since: a later wait marks it again
+            } else if (released(ch->idx, ch->drain_val)) {
+                w->chan_free.emplace_back(ch->idx, ch->drain_val);
+                ch->idx = kNoBlock;
+                ch->d = nullptr;
+                keep = false;
+            }
+            if (!keep) ch->draining = false;
+            ch->mu.unlock();
+        }
+        if (keep) w->chan_drain[j++] = ch;
+    }
+    w->chan_drain.resize(j);
+}
+
+// Attach a device block to a channel whose next message is number k.
+// Caller holds ch->mu (or owns a channel nobody else sees yet).  Takes a
+// recycled block first, then a fresh one; with the pool exhausted it waits
+// up to the world's timeout for blocks whose release waits are already
+// enqueued.  MPIXS_ERR_NOMEM when none can come.
+int attach_block(World *w, Channel *ch, uint64_t k) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> g(w->chan_mu);
+            uint32_t idx = kNoBlock;
+            uint64_t floor = 0;
+            if (w->chan_free.empty() && w->chan_next.load(std::memory_order_relaxed) >= w->chan_cap)
+                reclaim_blocks(w);
+            if (!w->chan_free.empty()) {
+                idx = w->chan_free.back().first;
+                floor = w->chan_free.back().second;
+                w->chan_free.pop_back();
+                w->chans_recycled.fetch_add(1, std::memory_order_relaxed);
+            } else if (w->chan_next.load(std::memory_order_relaxed) < w->chan_cap) {
+                idx = w->chan_next.fetch_add(1);
+            }
+            if (idx != kNoBlock) {
+                ch->idx = idx;
+                ch->d = w->d_chans + idx;
+                ch->ebase = floor;
+                ch->kbase = k;
+                return MPIXS_SUCCESS;
+            }
+            if (w->chan_limbo.empty() && w->chan_drain.empty()) return MPIXS_ERR_NOMEM;
+        }
+        if (w->aborted.load()) return MPIXS_ERR_ABORTED;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(w->cfg.timeout_ms))
+            return MPIXS_ERR_NOMEM;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+// The first side's wait for message k is the message's last device use.
+// It may release the block when the channel is one message's, or when
+// nothing else has been issued on the channel (quiescent after k).
+bool want_release(Channel *ch, const Rec *rec, uint64_t k) {
+    if (ch->priv) return true;
+    std::lock_guard<std::mutex> g(ch->mu);
+    return ch->seq[0] == k + 1 && ch->seq[1] == k + 1 && ch->idx == rec->didx;
+}
+
+// After the releasing wait is enqueued: record what its release word will
+// read once it has passed.
+void note_release(World *w, Channel *ch, const Rec *rec, uint64_t k) {
+    std::lock_guard<std::mutex> g(w->chan_mu);
+    if (ch->priv) {
+        w->chan_limbo.emplace_back(rec->didx, rec->dv);
+        return;
+    }
+    if (k + 1 < ch->drain_seq) return;
+    ch->drain_seq = k + 1;
+    ch->drain_val = rec->dv;
+    if (!ch->draining) {
+        ch->draining = true;
+        w->chan_drain.push_back(ch);
+    }
+}
+
+void set_rec_block(Channel *ch, Rec *rec, uint64_t k) {
+    if (!rec->d) {
+        rec->d = ch->d;
+        rec->didx = ch->idx;
+        rec->dv = ch->dval(k);
+    }
+}
+
 bool type_ok(mpixs_datatype dt, const TypeObj **t) {
     *t = type_lookup(dt);
     return *t != nullptr;
 }
 
+// ERR_BUFFER unless the bytes [p + lo, p + hi) lie in memory the GPU can
+// access: device memory (hipMalloc, managed memory) or, where host_ok (for
+// statuses), pinned host memory -- never pageable host memory, which is
+// what a host program would pass by mistake (the GPU example of §6 sends a
+// malloc'ed buffer).  When HIP knows the allocation's range, the bytes must
+// lie inside it.  HIP is asked once per allocation and stream; the range is
+// then kept in the stream's cache.  The check cannot see frees: a range
+// freed and reused for other memory while the stream lives passes as the
+// allocation it was.
+int check_buf(StreamObj *st, const void *p, int64_t lo, int64_t hi, bool host_ok) {
+    if (hi <= lo) return MPIXS_SUCCESS;
+    if (!p) return MPIXS_ERR_BUFFER;
+    const uintptr_t a = uintptr_t(p) + uintptr_t(lo);
+    const uintptr_t b = uintptr_t(p) + uintptr_t(hi);
+    if (b < a) return MPIXS_ERR_BUFFER;
+    if (st) {
+        const BufCache &c = st->bufs;
+        for (int i = 0; i < BufCache::N; ++i)
+            if (c.hi[i] && a >= c.lo[i] && b <= c.hi[i] && (host_ok || !c.host[i]))
+                return MPIXS_SUCCESS;
+    }
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof(at));
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();   // unknown to HIP: pageable host memory
+        return MPIXS_ERR_BUFFER;
+    }
+    bool host = false;
+    switch (at.type) {
+    case hipMemoryTypeDevice:
+    case hipMemoryTypeManaged:
+    case hipMemoryTypeUnified: break;
+    case hipMemoryTypeHost: host = true; break;
+    default: return MPIXS_ERR_BUFFER;
+    }
+    if (host && !host_ok) return MPIXS_ERR_BUFFER;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess || !base) {
+        (void)hipGetLastError();   // range unknown: accepted, not cached
+        return MPIXS_SUCCESS;
+    }
+    const uintptr_t blo = uintptr_t(base), bhi = blo + size;
+    if (a < blo || b > bhi) return MPIXS_ERR_BUFFER;
+    if (st) {
+        BufCache &c = st->bufs;
+        c.lo[c.next] = blo;
+        c.hi[c.next] = bhi;
+        c.host[c.next] = host;
+        c.next = (c.next + 1) % BufCache::N;
+    }
+    return MPIXS_SUCCESS;
+}
+
+// Byte span [lo, hi) that `count` elements of a type touch from a buffer.
+void type_span(const TypeObj *t, int count, int64_t *lo, int64_t *hi) {
+    if (count <= 0 || t->L.size == 0) {
+        *lo = *hi = 0;
+        return;
+    }
+    *lo = t->L.lb;
+    *hi = int64_t(count - 1) * t->L.extent + t->L.ub;
+}
+
 // Argument checks in a fixed order: communicator, count, datatype, peer,
-// tag, overlapping receive type, buffer.
+// tag, overlapping receive type, the library's size limit, buffer.
 int check_p2p(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, int peer, int tag,
               bool recv, const TypeObj **t) {
     if (!c || !c->sh) return MPIXS_ERR_COMM;
@@ -435,8 +607,13 @@ int check_p2p(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, in
     if (!(wild && tag == MPIXS_ANY_TAG) && tag < 0) return MPIXS_ERR_TAG;
     if (recv && count > 0 && (*t)->L.overlap) return MPIXS_ERR_TYPE;
     const int64_t bytes = int64_t(count) * (*t)->L.size;
-    if (bytes > 0 && !buf) return MPIXS_ERR_BUFFER;
     if (!(*t)->L.dense() && bytes >= (int64_t(1) << 32)) return MPIXS_ERR_COUNT;
+    if (bytes > 0) {
+        int64_t lo, hi;
+        type_span(*t, count, &lo, &hi);
+        const int rc = check_buf(c->stream, buf, lo, hi, false);
+        if (rc) return rc;
+    }
     if (c->sh->w->aborted.load()) return MPIXS_ERR_ABORTED;
     return MPIXS_SUCCESS;
 }
@@ -448,12 +625,18 @@ int complete_first(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, i
                    mpixs_status *status) {
     int rc = host_wait(w, &rec->copy_enq, [&] { return rec->copy_enq.load(std::memory_order_acquire) != 0; });
     if (rc) return rc;
-    WaitArgs a = wait_one(&ch->d->done, k + 1);
+    WaitArgs a = wait_one(&rec->d->done, rec->dv);
     if (side == 1) {
         a.status = status;
         a.st = rec->st;
     }
+    const bool rel = want_release(ch, rec, k);
+    if (rel) {
+        a.rel_base = w->h_rel;
+        a.rel_idx[0] = rec->didx + 1;
+    }
     rc = do_wait(w, st, a);
+    if (!rc && rel) note_release(w, ch, rec, k);
     rec_release(ch, rec);
     return rc;
 }
@@ -537,8 +720,9 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
         const int mtag = side == 0 ? tag : partner.tag;
         const StatusVal sv = match_status(rec->s, rec->r, mtag);
         const bool recv_here = side == 1;
-        rc = do_copy(w, st, rec->s, rec->r, sv, &ch->d->ready[1 - side], 1, &ch->d->done, 1,
-                     (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
+        rc = do_copy(w, st, rec->s, rec->r, sv, &rec->d->ready[1 - side], rec->dv, &rec->d->done,
+                     rec->dv, (recv_here && !req) ? static_cast<void *>(status) : nullptr,
+                     recv_here);
         rec->st = sv;
         rec->copy_enq.store(1, std::memory_order_release);
         host_notify(&rec->copy_enq);
@@ -557,15 +741,16 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     // first of the pair: a fresh one-message channel, published in the queue
     // and then posted outside the lock (a partner waits on the host until
     // the post is enqueued)
-    const uint32_t idx = w->chan_next.fetch_add(1);
-    if (idx >= w->chan_cap) {
-        delete r;
-        return MPIXS_ERR_NOMEM;
-    }
     Channel *ch = new Channel();
     ch->priv = true;
-    ch->d = w->d_chans + idx;
+    rc = attach_block(w, ch, 0);
+    if (rc) {
+        delete ch;
+        delete r;
+        return rc;
+    }
     Rec *rec = ch->at(0);
+    set_rec_block(ch, rec, 0);
     (side == 0 ? rec->s : rec->r) = mine;
     QOp op;
     op.ch = ch;
@@ -575,7 +760,7 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     op.tag = tag;
     (side == 0 ? q.unexpected : q.posted).push_back(op);
     lk.unlock();
-    rc = do_post(w, st, &ch->d->ready[side], 1);
+    rc = do_post(w, st, &rec->d->ready[side], rec->dv);
     rec->arrived.fetch_or(side == 0 ? ARR_S : ARR_R, std::memory_order_release);
     host_notify(&rec->arrived);
     if (rc) {
@@ -601,6 +786,7 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
         int tag, mpixs_status *status, mpixs_request *req) {
     const TypeObj *t = nullptr;
     int rc = check_p2p(c, buf, count, dt, peer, tag, side == 1, &t);
+    if (!rc && status) rc = check_buf(c->stream, status, 0, sizeof(mpixs_status), true);
     if (rc) return rc;
     World *w = c->sh->w;
     StreamObj *st = c->stream;
@@ -643,7 +829,6 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
         r = new mpixs_request_s();
         r->stream = st;
     }
-    const uint64_t k = ch->seq[side]++;
     Side me;
     me.buf = buf;
     me.count = count;
@@ -655,7 +840,18 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
     const uint32_t other = side == 0 ? ARR_R : ARR_S;
 
     ch->mu.lock();
+    const uint64_t k = ch->seq[side];
+    if (!ch->d) {
+        rc = attach_block(w, ch, k);
+        if (rc) {
+            ch->mu.unlock();
+            delete r;
+            return rc;
+        }
+    }
+    ch->seq[side] = k + 1;
     Rec *rec = ch->at(k);
+    set_rec_block(ch, rec, k);
     (side == 0 ? rec->s : rec->r) = me;
     const bool second = (rec->arrived.load(std::memory_order_relaxed) & other) != 0;
     if (second) {
@@ -664,7 +860,7 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
         const Side &R = rec->r;
         const StatusVal sv = match_status(S, R, tag);
         const bool recv_here = side == 1;
-        rc = do_copy(w, st, S, R, sv, &ch->d->ready[1 - side], k + 1, &ch->d->done, k + 1,
+        rc = do_copy(w, st, S, R, sv, &rec->d->ready[1 - side], rec->dv, &rec->d->done, rec->dv,
                      (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
         rec->st = sv;
         rec->copy_enq.store(1, std::memory_order_release);
@@ -681,7 +877,7 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
         }
         return rc;
     }
-    rc = do_post(w, st, &ch->d->ready[side], k + 1);
+    rc = do_post(w, st, &rec->d->ready[side], rec->dv);
     rec->arrived.fetch_or(mine, std::memory_order_release);
     host_notify(&rec->arrived);
     ch->mu.unlock();
@@ -714,6 +910,11 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
         if (st && rs != st) return MPIXS_ERR_STREAM;
         st = rs;
     }
+    if (statuses) {
+        const int rc = check_buf(st, statuses, 0,
+                                 int64_t(array_status ? n : 1) * int64_t(sizeof(mpixs_status)), true);
+        if (rc) return rc;
+    }
     World *w = reqs[0]->comm->sh->w;
     int rc = MPIXS_SUCCESS;
     // grouped requests: inside their group the status pointer is recorded;
@@ -743,11 +944,28 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
     auto flush = [&]() -> int {
         if (a.n == 0) return MPIXS_SUCCESS;
         int r2 = do_wait(w, st, a);
-        for (auto &pr : batch)
-            if (pr.second->rec) rec_release(pr.second->ch, pr.second->rec);
+        for (size_t j = 0; j < batch.size(); ++j) {
+            mpixs_request_s *q = batch[j].second;
+            if (!q->rec) continue;
+            if (!r2 && a.rel_idx[j]) note_release(w, q->ch, q->rec, q->k);
+            rec_release(q->ch, q->rec);
+        }
         std::memset(&a, 0, sizeof(a));
         batch.clear();
         return r2;
+    };
+    // one first-side wait lane, releasing the message's block when it is
+    // the block's last device use
+    auto lane_of = [&](WaitArgs &x, mpixs_request_s *q) -> bool {
+        x.ptr[x.n] = &q->rec->d->done;
+        x.target[x.n] = q->rec->dv;
+        const bool rel = want_release(q->ch, q->rec, q->k);
+        if (rel) {
+            x.rel_base = w->h_rel;
+            x.rel_idx[x.n] = q->rec->didx + 1;
+        }
+        x.n++;
+        return rel;
     };
     for (int i = 0; i < n && !rc; ++i) {
         mpixs_request_s *r = reqs[i];
@@ -767,31 +985,22 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
         }
         rc = host_wait(w, &r->rec->copy_enq, [&] { return r->rec->copy_enq.load(std::memory_order_acquire) != 0; });
         if (rc) break;
-        if (r->side == 1 && status) {
-            // one status per wait kernel
+        if (r->side == 1 && (status || r->rec->st.error)) {
+            // a status (or a sticky error) per wait kernel
             rc = flush();
             if (rc) break;
-            WaitArgs s = wait_one(&r->ch->d->done, r->k + 1);
+            WaitArgs s;
+            std::memset(&s, 0, sizeof(s));
+            const bool rel = lane_of(s, r);
             s.status = status;
             s.st = r->rec->st;
             rc = do_wait(w, st, s);
+            if (!rc && rel) note_release(w, r->ch, r->rec, r->k);
             rec_release(r->ch, r->rec);
             r->rec = nullptr;
             continue;
         }
-        if (r->side == 1 && r->rec->st.error) {
-            rc = flush();
-            if (rc) break;
-            WaitArgs s = wait_one(&r->ch->d->done, r->k + 1);
-            s.st = r->rec->st;
-            rc = do_wait(w, st, s);
-            rec_release(r->ch, r->rec);
-            r->rec = nullptr;
-            continue;
-        }
-        a.ptr[a.n] = &r->ch->d->done;
-        a.target[a.n] = r->k + 1;
-        a.n++;
+        lane_of(a, r);
         batch.emplace_back(i, r);
         if (a.n == 64) rc = flush();
     }
@@ -815,7 +1024,13 @@ int check_allreduce(mpixs_comm_s *c, const void *sendbuf, void *recvbuf, int cou
         return MPIXS_ERR_TYPE;
     if (op < MPIXS_SUM || op > MPIXS_MAX) return MPIXS_ERR_OP;
     if (c->sh->size > 64) return MPIXS_ERR_COMM;
-    if (count > 0 && (!recvbuf || !sendbuf)) return MPIXS_ERR_BUFFER;
+    if (count > 0) {
+        const int64_t bytes = int64_t(count) * basic_size(dt);
+        int rc = sendbuf == MPIXS_IN_PLACE ? MPIXS_SUCCESS
+                                           : check_buf(c->stream, sendbuf, 0, bytes, false);
+        if (!rc) rc = check_buf(c->stream, recvbuf, 0, bytes, false);
+        if (rc) return rc;
+    }
     if (c->sh->w->aborted.load()) return MPIXS_ERR_ABORTED;
     return MPIXS_SUCCESS;
 }
@@ -1523,6 +1738,21 @@ void Channel::collect() {
 }
 
 CommShared::~CommShared() {
+    if (w && !dir.empty()) {
+        // every message of the communicator has been waited for: a channel's
+        // block frees once its last wait has passed (blocks of channels that
+        // never became quiescent stay with the pool)
+        std::lock_guard<std::mutex> g(w->chan_mu);
+        auto &dr = w->chan_drain;
+        dr.erase(std::remove_if(dr.begin(), dr.end(), [&](Channel *ch) { return ch->owner == this; }),
+                 dr.end());
+        for (auto &kv : dir) {
+            Channel *ch = kv.second;
+            if (ch->idx != kNoBlock && ch->drain_val && ch->seq[0] == ch->drain_seq &&
+                ch->seq[1] == ch->drain_seq)
+                w->chan_limbo.emplace_back(ch->idx, ch->drain_val);
+        }
+    }
     for (auto &kv : dir) delete kv.second;
     for (CollRec *r : colls) delete r;
     for (CollRec *r : hcolls) delete r;
@@ -1604,13 +1834,17 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
         hipHostMalloc(reinterpret_cast<void **>(&w->h_arena), w->arena_bytes,
                       hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&w->h_flags), sizeof(uint32_t) * size_t(w->nflags),
+                      hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w->h_rel), sizeof(uint64_t) * size_t(w->chan_cap),
                       hipHostMallocCoherent) != hipSuccess) {
         (void)hipFree(w->d_pool);
         if (w->h_abort) (void)hipHostFree(w->h_abort);
         if (w->h_arena) (void)hipHostFree(w->h_arena);
+        if (w->h_flags) (void)hipHostFree(w->h_flags);
         delete w;
         return MPIXS_ERR_NOMEM;
     }
+    std::memset(w->h_rel, 0, sizeof(uint64_t) * size_t(w->chan_cap));
     *w->h_abort = 0;
     std::memset(w->h_flags, 0, sizeof(uint32_t) * size_t(w->nflags));
     for (int i = w->nflags - 1; i >= 0; --i) w->free_flags.push_back(i);
@@ -1661,6 +1895,7 @@ int mpixs_world_free(mpixs_world *pw) {
     (void)hipHostFree(w->h_abort);
     (void)hipHostFree(w->h_arena);
     (void)hipHostFree(w->h_flags);
+    (void)hipHostFree(w->h_rel);
     for (auto *h : w->world_handles) delete h;
     delete w->world_sh;
     delete w;
@@ -1681,6 +1916,7 @@ int mpixs_world_wait(mpixs_world w, int timeout_ms) {
         for (;;) {
             hipError_t e = hipStreamQuery(s);
             if (e == hipSuccess) break;
+            if (e == hipErrorNotReady) (void)hipGetLastError();
             if (e != hipErrorNotReady) return MPIXS_ERR_GPU;
             if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms))
                 return MPIXS_ERR_TIMEOUT;
@@ -1770,8 +2006,20 @@ int mpixs_stream_create(mpixs_world w, mpixs_info info, mpixs_stream *out) {
             ep = w->ep_rr;
             w->ep_rr = (w->ep_rr + 1) % w->cfg.max_streams;
         }
-        const int slot = w->stream_next.fetch_add(1);
-        if (slot >= w->stream_cap) return MPIXS_ERR_NOMEM;
+        // a block a freed stream returned (clean: no error recorded), else a
+        // fresh one; a returned block keeps its ticket count, which the new
+        // stream continues from
+        int slot;
+        uint64_t tickets = 0;
+        if (!w->stream_free.empty()) {
+            slot = w->stream_free.back().first;
+            tickets = w->stream_free.back().second;
+            w->stream_free.pop_back();
+            w->streams_recycled.fetch_add(1, std::memory_order_relaxed);
+        } else {
+            slot = w->stream_next.fetch_add(1);
+            if (slot >= w->stream_cap) return MPIXS_ERR_NOMEM;
+        }
         w->ep_users[size_t(ep)]++;
         mpixs_stream_s *s = new mpixs_stream_s();
         s->w = w;
@@ -1779,6 +2027,8 @@ int mpixs_stream_create(mpixs_world w, mpixs_info info, mpixs_stream *out) {
         s->hs = hs;
         s->endpoint = ep;
         s->dev = w->d_streams + slot;
+        s->tickets = tickets;
+        s->id = w->next_stream_id.fetch_add(1);
         *out = s;
     }
     {
@@ -1795,11 +2045,26 @@ int mpixs_stream_free(mpixs_stream *ps) {
     if (s->comm_refs.load() > 0) return MPIXS_ERR_PENDING;
     if (s->gpu) {
         hipError_t e = hipStreamQuery(s->hs);
-        if (e == hipErrorNotReady) return MPIXS_ERR_PENDING;
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();   // not an error of a later call
+            return MPIXS_ERR_PENDING;
+        }
+    }
+    // The stream is idle, and every kernel of another stream that writes its
+    // block (a batch recording a receive's error) was waited for on it: the
+    // block may go to the next stream if it holds no error (a read on the
+    // idle stream itself); a block with an error stays out of use.
+    bool clean = true;
+    if (s->gpu) {
+        uint32_t v[2] = {1, 1};
+        clean = hipMemcpyAsync(v, &s->dev->first_error, sizeof(v), hipMemcpyDeviceToHost,
+                               s->hs) == hipSuccess &&
+                hipStreamSynchronize(s->hs) == hipSuccess && v[0] == 0 && v[1] == 0;
     }
     {
         std::lock_guard<std::mutex> g(w->ep_mu);
         w->ep_users[size_t(s->endpoint)]--;
+        if (clean) w->stream_free.emplace_back(int(s->dev - w->d_streams), s->tickets);
     }
     {
         std::lock_guard<std::mutex> g(w->reg_mu);
@@ -1827,6 +2092,68 @@ int mpixs_stream_get_error(mpixs_stream s, int *first_error) {
 }
 
 // ========================================================== communicator
+namespace {
+
+// Collective lines for a new communicator: the lines of a freed one of the
+// same size once no stream its ranks used can still run one of its kernels
+// (each is freed, or idle now), else fresh lines, else (pool exhausted) the
+// first freed lines of that size after synchronising their live streams.
+// Floors: the instance numbers to start from.
+int take_coll_lines(World *w, size_t words, size_t *off, uint64_t *floor_coll,
+                    uint64_t *floor_group) {
+    std::lock_guard<std::mutex> g(w->coll_mu);
+    // users still alive (same object and id), under the registry lock
+    auto live_users = [&](const CollLines &cl) {
+        std::vector<hipStream_t> hs;
+        std::lock_guard<std::mutex> g2(w->reg_mu);
+        for (const auto &u : cl.users) {
+            auto it = w->streams.find(u.first);
+            if (it != w->streams.end() && (*it)->id == u.second && (*it)->gpu)
+                hs.push_back((*it)->hs);
+        }
+        return hs;
+    };
+    auto take = [&](size_t i) {
+        const CollLines &cl = w->coll_free[i];
+        *off = cl.off;
+        *floor_coll = cl.floor_coll;
+        *floor_group = cl.floor_group;
+        w->coll_free.erase(w->coll_free.begin() + long(i));
+        w->colls_recycled.fetch_add(1, std::memory_order_relaxed);
+        return MPIXS_SUCCESS;
+    };
+    for (size_t i = 0; i < w->coll_free.size(); ++i) {
+        if (w->coll_free[i].words != words) continue;
+        bool idle = true;
+        for (hipStream_t h : live_users(w->coll_free[i])) {
+            const hipError_t q = hipStreamQuery(h);
+            if (q == hipErrorNotReady) (void)hipGetLastError();
+            if (q != hipSuccess) {
+                idle = false;
+                break;
+            }
+        }
+        if (idle) return take(i);
+    }
+    if (w->coll_next.load() + words <= w->coll_words) {
+        const size_t o = w->coll_next.fetch_add(words);
+        if (o + words <= w->coll_words) {
+            *off = o;
+            *floor_coll = *floor_group = 0;
+            return MPIXS_SUCCESS;
+        }
+    }
+    for (size_t i = 0; i < w->coll_free.size(); ++i) {
+        if (w->coll_free[i].words != words) continue;
+        for (hipStream_t h : live_users(w->coll_free[i]))
+            if (hipStreamSynchronize(h) != hipSuccess) return MPIXS_ERR_GPU;
+        return take(i);
+    }
+    return MPIXS_ERR_NOMEM;
+}
+
+}  // namespace
+
 int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm *newcomm) {
     if (!parent || !parent->sh || !newcomm) return MPIXS_ERR_COMM;
     CommShared *ps = parent->sh;
@@ -1839,8 +2166,10 @@ int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm 
         CreateRec &cr = ps->creates[k];
         if (!cr.sh) {
             const size_t words = size_t(16) * size_t(ps->size + 1);
-            const size_t off = w->coll_next.fetch_add(2 * words);
-            if (off + 2 * words > w->coll_words) return MPIXS_ERR_NOMEM;
+            size_t off = 0;
+            uint64_t fc = 0, fg = 0;
+            const int rc0 = take_coll_lines(w, 2 * words, &off, &fc, &fg);
+            if (rc0) return rc0;
             cr.sh = new CommShared();
             cr.sh->w = w;
             cr.sh->size = ps->size;
@@ -1849,6 +2178,10 @@ int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm 
             cr.sh->mq.reset(new MatchQueue[size_t(ps->size)]);
             cr.sh->d_coll = w->d_coll + off;
             cr.sh->d_grp = w->d_coll + off + words;
+            cr.sh->coll_off = off;
+            cr.sh->coll_words = 2 * words;
+            cr.sh->floor_coll = cr.sh->coll_base = cr.sh->max_coll = fc;
+            cr.sh->floor_group = cr.sh->group_base = cr.sh->max_group = fg;
         }
         cr.sh->streams[size_t(parent->rank)] = s;
         cr.arrived++;
@@ -1870,6 +2203,8 @@ int mpixs_comm_create_with_stream(mpixs_comm parent, mpixs_stream s, mpixs_comm 
     c->sh = sh;
     c->rank = parent->rank;
     c->stream = s;
+    c->coll_seq = sh->floor_coll;
+    c->group_seq = sh->floor_group;
     if (s) s->comm_refs.fetch_add(1);
     sh->handles.fetch_add(1);
     w->live_comms.fetch_add(1);
@@ -1883,9 +2218,30 @@ int mpixs_comm_free(mpixs_comm *pc) {
     if (c->world_handle) return MPIXS_ERR_COMM;
     if (c->pending.load() > 0) return MPIXS_ERR_PENDING;
     World *w = c->sh->w;
+    CommShared *sh = c->sh;
+    if (sh->coll_words) {
+        // what this rank leaves for the reuse of the collective lines: its
+        // instance counts, and the stream its kernels ran on
+        std::lock_guard<std::mutex> g(sh->free_mu);
+        sh->max_coll = std::max(sh->max_coll, c->coll_seq);
+        sh->max_group = std::max(sh->max_group, c->group_seq);
+        if (c->stream) sh->users.emplace_back(c->stream, c->stream->id);
+    }
     if (c->stream) c->stream->comm_refs.fetch_sub(1);
     for (StreamObj *s : c->mstreams) s->comm_refs.fetch_sub(1);
-    if (c->sh->handles.fetch_sub(1) == 1) delete c->sh;
+    if (sh->handles.fetch_sub(1) == 1) {
+        if (sh->coll_words) {
+            CollLines cl;
+            cl.off = sh->coll_off;
+            cl.words = sh->coll_words;
+            cl.floor_coll = sh->max_coll;
+            cl.floor_group = sh->max_group;
+            cl.users.swap(sh->users);
+            std::lock_guard<std::mutex> g(w->coll_mu);
+            w->coll_free.push_back(std::move(cl));
+        }
+        delete sh;
+    }
     w->live_comms.fetch_sub(1);
     delete c;
     *pc = nullptr;
@@ -1933,8 +2289,8 @@ int mpixs_irecv_enqueue(void *buf, int count, mpixs_datatype dt, int source, int
 namespace {
 
 // Argument checks of the index-addressed calls, in the order of check_p2p
-// (communicator, count, datatype, peer, tag, stream indices, overlap,
-// buffer).  The local index names the stream the operation is enqueued on.
+// (communicator, count, datatype, peer, tag, stream indices, overlap, size
+// limit, buffer).  The local index names the stream the operation is enqueued on.
 int check_mp(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, int peer, int tag,
              bool recv, int src_idx, int dst_idx, const TypeObj **t, StreamObj **st) {
     if (!c || !c->sh || !c->sh->multiplex) return MPIXS_ERR_COMM;
@@ -1954,8 +2310,13 @@ int check_mp(mpixs_comm_s *c, const void *buf, int count, mpixs_datatype dt, int
     }
     if (recv && count > 0 && (*t)->L.overlap) return MPIXS_ERR_TYPE;
     const int64_t bytes = int64_t(count) * (*t)->L.size;
-    if (bytes > 0 && !buf) return MPIXS_ERR_BUFFER;
     if (!(*t)->L.dense() && bytes >= (int64_t(1) << 32)) return MPIXS_ERR_COUNT;
+    if (bytes > 0) {
+        int64_t lo, hi;
+        type_span(*t, count, &lo, &hi);
+        const int rc = check_buf(c->mstreams[size_t(local)], buf, lo, hi, false);
+        if (rc) return rc;
+    }
     if (sh->w->aborted.load()) return MPIXS_ERR_ABORTED;
     *st = c->mstreams[size_t(local)];
     return MPIXS_SUCCESS;
@@ -1965,7 +2326,8 @@ int mp_p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype
            int tag, int src_idx, int dst_idx, mpixs_status *status, mpixs_request *req) {
     const TypeObj *t = nullptr;
     StreamObj *st = nullptr;
-    const int rc = check_mp(c, buf, count, dt, peer, tag, side == 1, src_idx, dst_idx, &t, &st);
+    int rc = check_mp(c, buf, count, dt, peer, tag, side == 1, src_idx, dst_idx, &t, &st);
+    if (!rc && status) rc = check_buf(st, status, 0, sizeof(mpixs_status), true);
     if (rc) return rc;
     return side == 0 ? p2p_queue(c, 0, buf, count, t, peer, tag, status, req, st, src_idx, dst_idx)
                      : p2p_queue(c, 1, buf, count, t, peer, tag, status, req, st, dst_idx, src_idx);
@@ -2360,6 +2722,7 @@ int mpixs_recv(void *buf, int count, mpixs_datatype dt, int source, int tag, mpi
                mpixs_status *status) {
     const TypeObj *t = nullptr;
     int rc = check_p2p(c, buf, count, dt, source, tag, true, &t);
+    if (!rc && status) rc = check_buf(c->stream, status, 0, sizeof(mpixs_status), true);
     if (rc) return rc;
     if (c->sh->w->cfg.matching == 1) return MPIXS_ERR_COMM;   // sequence channels only
     World *w = c->sh->w;
@@ -2479,6 +2842,9 @@ int mpixs_world_get_stats(mpixs_world w, mpixs_stats *s) {
     s->groups_planned = w->groups_planned.load();
     s->plan_ms = double(w->plan_ns.load()) * 1e-6;
     s->reductions_merged = w->reds_merged.load();
+    s->channels_recycled = w->chans_recycled.load();
+    s->streams_recycled = w->streams_recycled.load();
+    s->comm_lines_recycled = w->colls_recycled.load();
     s->timed_copy = w->timed_copy;
     s->copy_ms = w->copy_ms;
     s->timed_reduce = w->timed_reduce;
@@ -2497,6 +2863,9 @@ int mpixs_world_reset_stats(mpixs_world w) {
     w->groups_planned = 0;
     w->plan_ns = 0;
     w->reds_merged = 0;
+    w->chans_recycled = 0;
+    w->streams_recycled = 0;
+    w->colls_recycled = 0;
     w->n_copy = 0;
     w->n_reduce = 0;
     w->bytes_copied = 0;

@@ -54,6 +54,16 @@ int basic_size(int basic);
 struct World;
 struct CommShared;
 
+// Allocations a stream's enqueue calls have found accessible by the GPU
+// (address ranges; host = pinned host memory, accepted for statuses only).
+// Filled round-robin; used by the stream's one thread, so it needs no lock.
+struct BufCache {
+    static constexpr int N = 16;
+    uintptr_t lo[N] = {}, hi[N] = {};
+    bool host[N] = {};
+    int next = 0;
+};
+
 struct StreamObj {
     World *w = nullptr;
     bool gpu = false;
@@ -62,6 +72,8 @@ struct StreamObj {
     DevStream *dev = nullptr;
     uint64_t tickets = 0;                 // tickets issued on dev->ticket
     std::atomic<int> comm_refs{0};
+    BufCache bufs;
+    uint64_t id = 0;                      // unique in the world (a freed stream's address may return)
 };
 
 struct Side {
@@ -93,18 +105,41 @@ struct Rec {
     std::atomic<int> refs{2};
     Side s, r;
     StatusVal st{};
+    // the message's device counters: block, and the value its ready / done
+    // counters reach for this message (set with the record, under the
+    // channel's lock)
+    DevChan *d = nullptr;
+    uint32_t didx = 0;
+    uint64_t dv = 0;
 };
 
+constexpr uint32_t kNoBlock = 0xffffffffu;
+
+// A channel's device block is attached when a message needs it and may be
+// handed back once the channel is quiescent (both sides have issued the same
+// number of operations and the last of them has passed its wait on the
+// device).  A block keeps its counter values across owners: an owner that
+// attaches it at sequence number kbase with counters at most ebase uses the
+// value ebase + (k - kbase) + 1 for its message k, above anything a former
+// owner wrote, so the counters only ever grow.
 struct Channel {
     DevChan *d = nullptr;
+    uint32_t idx = kNoBlock;           // index of d in the world's pool
+    uint64_t ebase = 0, kbase = 0;
     bool priv = false;                 // one message's channel (ordered-queue matching)
-    uint64_t seq[2] = {0, 0};          // [0] touched by the source thread, [1] by the destination
+    uint64_t seq[2] = {0, 0};          // operations issued per side (under mu)
     std::mutex mu;
     std::deque<Rec *> recs;
     uint64_t base = 0;                 // sequence number of recs.front()
+    // quiescent at drain_seq operations per side, once the device has
+    // written drain_val to the block's release word (under the world's chan_mu)
+    bool draining = false;
+    uint64_t drain_seq = 0, drain_val = 0;
+    CommShared *owner = nullptr;
     ~Channel();
     Rec *at(uint64_t k);               // caller holds mu
     void collect();                    // caller holds mu
+    uint64_t dval(uint64_t k) const { return ebase + (k - kbase) + 1; }
 };
 
 struct CollRec {
@@ -214,6 +249,17 @@ struct CreateRec {
     CommShared *sh = nullptr;
 };
 
+// Collective lines of a freed communicator: reusable once every stream its
+// ranks used is idle or freed (a stream is freed only when idle), so no
+// kernel of the old communicator can still write them; a new owner
+// continues the instance numbers from the floors, so its counter targets
+// stay above the values already there.
+struct CollLines {
+    size_t off = 0, words = 0;
+    uint64_t floor_coll = 0, floor_group = 0;
+    std::vector<std::pair<StreamObj *, uint64_t>> users;   // stream and its id
+};
+
 // Ordered-queue matching (mpixs_config.matching = 1): per destination rank,
 // the receives posted and the sends enqueued that have not met a partner
 // yet, each with its own one-message channel.
@@ -278,6 +324,14 @@ struct CommShared {
     std::vector<std::vector<StreamObj *>> mst;
     std::vector<int> ep_base;
     bool ep_ready = false;             // under create_mu of the parent
+    // device collective lines (d_coll, d_grp): offset and words in the
+    // world's collective pool, the instance numbers they start from, and
+    // what the freeing ranks leave for their reuse (under free_mu)
+    size_t coll_off = 0, coll_words = 0;
+    uint64_t floor_coll = 0, floor_group = 0;
+    std::mutex free_mu;
+    std::vector<std::pair<StreamObj *, uint64_t>> users;
+    uint64_t max_coll = 0, max_group = 0;
     ~CommShared();
 };
 
@@ -343,6 +397,21 @@ struct World {
     uint64_t *d_coll = nullptr;
     size_t coll_words = 0;
     std::atomic<size_t> coll_next{0};
+    // block recycling: channel blocks (index, counter floor) ready for a new
+    // owner; channels whose block may be handed back once the device has
+    // written the release word; blocks of dead one-message channels waiting
+    // for their release word; stream blocks returned by mpixs_stream_free
+    // (block index, ticket count); collective lines of freed communicators
+    std::mutex chan_mu;
+    std::vector<std::pair<uint32_t, uint64_t>> chan_free;
+    std::vector<Channel *> chan_drain;
+    std::vector<std::pair<uint32_t, uint64_t>> chan_limbo;
+    uint64_t *h_rel = nullptr;         // host-pinned release word per channel block
+    std::vector<std::pair<int, uint64_t>> stream_free;   // under ep_mu
+    std::mutex coll_mu;
+    std::vector<CollLines> coll_free;
+    std::atomic<uint64_t> next_stream_id{1};
+    std::atomic<uint64_t> chans_recycled{0}, streams_recycled{0}, colls_recycled{0};
     uint32_t *h_abort = nullptr;       // host-pinned, read by device waits
     std::atomic<int> aborted{0};
     uint64_t timeout_ticks = 0;

@@ -49,10 +49,12 @@ __global__ void __launch_bounds__(256) k_fill(uint8_t *p, int64_t n, uint64_t se
     }
 }
 
-// sum_j byte_j * (j + 1) mod 2^64, accumulated with device atomics in
-// acc[0]; the last workgroup to finish (ticket in acc[1]) publishes the sum
+// weight * sum_j byte_j * (j + 1) mod 2^64, accumulated with device atomics
+// in acc[0]; the last of `total` workgroups (of this launch and of the other
+// launches into the same accumulator; ticket in acc[1]) publishes the sum
 // and the completion flag to host memory.
-__global__ void __launch_bounds__(256) k_checksum(const uint8_t *p, int64_t n, uint64_t *acc,
+__global__ void __launch_bounds__(256) k_checksum(const uint8_t *p, int64_t n, uint64_t weight,
+                                                   uint64_t total, uint64_t *acc,
                                                    uint64_t *host_sum, uint32_t *host_flag) {
     uint64_t s = 0;
     for (int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x; j < n; j += int64_t(gridDim.x) * 256)
@@ -65,10 +67,10 @@ __global__ void __launch_bounds__(256) k_checksum(const uint8_t *p, int64_t n, u
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
-    __hip_atomic_fetch_add(&acc[0], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&acc[0], red[0] * weight, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t t = __hip_atomic_fetch_add(&acc[1], uint64_t(1), __ATOMIC_ACQ_REL,
                                               __HIP_MEMORY_SCOPE_AGENT);
-    if (t + 1 != gridDim.x) return;
+    if (t + 1 != total) return;
     *host_sum = __hip_atomic_load(&acc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(host_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -158,11 +160,18 @@ size_t round256(int64_t n) { return size_t((n + 255) / 256 * 256); }
 extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *comms,
                                void *const *streams, const mpixs_drv_req *reqs, int64_t nreq,
                                int64_t budget_bytes, mpixs_drv_req_result *results,
-                               double *wall_s) {
+                               double *wall_s, const int64_t *capture, int64_t ncapture,
+                               void *capture_dev) {
     if (!world || nranks <= 0 || !comms || !streams || nreq < 0 || nreq >= INT32_MAX ||
         (nreq > 0 && (!reqs || !results)) ||
-        budget_bytes <= 0)
+        budget_bytes <= 0 || ncapture < 0 || (ncapture > 0 && (!capture || !capture_dev)))
         return MPIXS_ERR_ARG;
+    std::vector<int64_t> cap_off(size_t(std::max<int64_t>(nreq, 0)), -1);
+    for (int64_t k = 0; k < ncapture; ++k) {
+        if (capture[2 * k] < 0 || capture[2 * k] >= nreq || capture[2 * k + 1] < 0)
+            return MPIXS_ERR_ARG;
+        cap_off[size_t(capture[2 * k])] = capture[2 * k + 1];
+    }
     for (int64_t i = 0; i < nreq; ++i) {
         const mpixs_drv_req &q = reqs[i];
         const bool p2p = q.kind == MPIXS_DRV_REQ_SENDRECV || q.kind == MPIXS_DRV_REQ_ISEND_WAIT;
@@ -282,9 +291,18 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                 hipLaunchKernelGGL(k_fill, dim3(grid_for(q.bytes, 8)), dim3(256), 0, hs, in,
                                    q.bytes, q.seed + uint64_t(r));
                 rc = mpixs_allreduce_enqueue(in, out, int(q.bytes / 4), MPIXS_INT32, MPIXS_SUM, c);
-                if (!rc && r == 0) {
-                    hipLaunchKernelGGL(k_checksum, dim3(grid_for(q.bytes, 64)), dim3(256), 0, hs,
-                                       out, q.bytes, dsum + 2 * i, hsum + i, hflag + i);
+                if (!rc && cap_off[size_t(i)] >= 0 &&
+                    hipMemcpyAsync(static_cast<char *>(capture_dev) + cap_off[size_t(i)] +
+                                       size_t(r) * size_t(q.bytes),
+                                   out, size_t(q.bytes), hipMemcpyDeviceToDevice, hs) != hipSuccess)
+                    rc = MPIXS_ERR_GPU;
+                if (!rc) {
+                    // every rank checksums its own output; the last
+                    // workgroup of all ranks' launches publishes the sum
+                    const int g = grid_for(q.bytes, 64);
+                    hipLaunchKernelGGL(k_checksum, dim3(g), dim3(256), 0, hs, out, q.bytes,
+                                       uint64_t(2 * r + 1), uint64_t(g) * uint64_t(nranks),
+                                       dsum + 2 * i, hsum + i, hflag + i);
                 }
             } else {
                 uint8_t *sb = reinterpret_cast<uint8_t *>(base);
@@ -310,9 +328,16 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                         rc = mpixs_irecv_enqueue(rb, int(q.bytes), MPIXS_UINT8, q.src, tag, c, &rq);
                         if (!rc) rc = mpixs_wait_enqueue(&rq, nullptr);
                     }
+                    if (!rc && cap_off[size_t(i)] >= 0 &&
+                        hipMemcpyAsync(static_cast<char *>(capture_dev) + cap_off[size_t(i)], rb,
+                                       size_t(q.bytes), hipMemcpyDeviceToDevice,
+                                       hs) != hipSuccess)
+                        rc = MPIXS_ERR_GPU;
                     if (!rc) {
-                        hipLaunchKernelGGL(k_checksum, dim3(grid_for(q.bytes, 64)), dim3(256), 0,
-                                           hs, rb, q.bytes, dsum + 2 * i, hsum + i, hflag + i);
+                        const int g = grid_for(q.bytes, 64);
+                        hipLaunchKernelGGL(k_checksum, dim3(g), dim3(256), 0, hs, rb, q.bytes,
+                                           uint64_t(1), uint64_t(g), dsum + 2 * i, hsum + i,
+                                           hflag + i);
                     }
                 }
             }

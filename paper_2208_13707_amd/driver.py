@@ -51,6 +51,7 @@ _hip = None
 def _hiplib():
     global _hip
     if _hip is None:
+        M.lib()   # loads torch's HIP runtime first: this resolves to it
         _hip = ctypes.CDLL("libamdhip64.so")
         _hip.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
         _hip.hipStreamCreateWithFlags.restype = ctypes.c_int
@@ -132,13 +133,16 @@ RES_DTYPE = np.dtype([("admit_us", "<f8"), ("done_us", "<f8"), ("checksum", "<u8
                       ("error", "<i4"), ("pad", "<i4")])
 
 
-def mpixs_drv_serve(world, comms, streams, reqs: np.ndarray, budget_bytes: int):
-    """Run the serving harness; returns (rc, results array, wall seconds)."""
+def mpixs_drv_serve(world, comms, streams, reqs: np.ndarray, budget_bytes: int,
+                    capture=None, capture_dev: int = 0):
+    """Run the serving harness; returns (rc, results array, wall seconds).
+    capture: optional list of (request index, byte offset in capture_dev)."""
     L = dlib()
     f = L.mpixs_drv_serve
     f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                   ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
-                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                  ctypes.c_int64, ctypes.c_void_p]
     f.restype = ctypes.c_int
     n = len(comms)
     ca = (ctypes.c_void_p * n)(*comms)
@@ -146,8 +150,10 @@ def mpixs_drv_serve(world, comms, streams, reqs: np.ndarray, budget_bytes: int):
     reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
     res = np.zeros(max(1, len(reqs)), dtype=RES_DTYPE)
     wall = ctypes.c_double()
+    cap = np.ascontiguousarray(np.array(capture or [], dtype=np.int64).reshape(-1))
     rc = f(world, n, ca, sa, reqs.ctypes.data, len(reqs), budget_bytes, res.ctypes.data,
-           ctypes.byref(wall))
+           ctypes.byref(wall), cap.ctypes.data if cap.size else None, cap.size // 2,
+           capture_dev or None)
     return rc, res[: len(reqs)], wall.value
 
 
@@ -227,9 +233,9 @@ class Session:
                              self.hip_streams, mode=mode, nmarks=nmarks, max_reqs=max_reqs,
                              batches=self.batches)
 
-    def serve(self, sched, budget_bytes=8 << 30):
+    def serve(self, sched, budget_bytes=8 << 30, capture=None, capture_dev=0):
         return mpixs_drv_serve(self.world, self.comms, self.hip_streams, requests_array(sched),
-                               budget_bytes)
+                               budget_bytes, capture, capture_dev)
 
     def stats(self):
         return M.mpixs_world_get_stats(self.world)[1]

@@ -63,7 +63,9 @@ class Stats(ctypes.Structure):
                 ("copy_ms", ctypes.c_double), ("timed_reduce", ctypes.c_uint64),
                 ("reduce_ms", ctypes.c_double), ("host_sleeps", ctypes.c_uint64),
                 ("host_sleep_timeouts", ctypes.c_uint64), ("groups_planned", ctypes.c_uint64),
-                ("plan_ms", ctypes.c_double), ("reductions_merged", ctypes.c_uint64)]
+                ("plan_ms", ctypes.c_double), ("reductions_merged", ctypes.c_uint64),
+                ("channels_recycled", ctypes.c_uint64), ("streams_recycled", ctypes.c_uint64),
+                ("comm_lines_recycled", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p
@@ -133,6 +135,10 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2208_13707_amd.build` (no fallback exists)")
+        # torch ships its own HIP runtime; loaded first, it is the one the
+        # library binds to, so buffers, streams and kernels share one runtime
+        # (loaded the other way round, the process would hold two)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, args in SIGNATURES.items():
             f = getattr(L, name)

@@ -130,3 +130,19 @@ def test_structs_match_the_header(tmp_path):
     got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
                                                         text=True).stdout.splitlines())
     assert {k: int(v) for k, v in got.items()} == want
+
+
+def test_one_hip_runtime_whatever_is_loaded_first():
+    """Loading the library first still leaves one HIP runtime in the process
+    (torch's, which the binding loads before the library)."""
+    code = ("from paper_2208_13707_amd import mpixs as M\n"
+            "from paper_2208_13707_amd import driver as D\n"
+            "M.lib(); D._hiplib()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().split(chr(10))\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run(["python", "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
