@@ -437,6 +437,26 @@ int mpixs_group_end_init(mpixs_comm comm, mpixs_batch *batch);
 int mpixs_batch_start_enqueue(mpixs_batch batch);
 int mpixs_batch_free(mpixs_batch *batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mpixs_group_end_init_static(comm, &batch) is mpixs_group_end_init whose
+ * plan (counters, descriptors, tile schedule) goes into a static region of
+ * 4 MiB (4,194,304 bytes) that each GPU holds for the life of the process,
+ * instead of memory allocated for it; it calls no hipMalloc or hipFree and
+ * creates no graph or event (runs use the device counters whatever
+ * mpixs_config.batch_graph and batch_sync say).  The plan needs 128 bytes
+ * per rank and 128 more, 224 per message, 8 per batch-kernel workgroup and,
+ * for merged allreduces, 24 per allreduce and 16 per allreduce and rank,
+ * each part rounded up to 256 bytes; a larger one fails with
+ * MPIXS_ERR_NOMEM on every rank, nothing planned.  One region per GPU: the
+ * region holds the last such plan made on the GPU, and a start of an earlier
+ * one returns MPIXS_ERR_REQUEST.  Making a new one while runs of the
+ * previous one are still executing on the GPU is a race (the caller orders
+ * them); counters start at zero with every plan.  Collective over comm, all
+ * ranks calling this same function (else MPIXS_ERR_ARG on every rank);
+ * start and free it like any batch. */
+int mpixs_group_end_init_static(mpixs_comm comm, mpixs_batch *batch);
+
 /* ------------------------------------ conventional, host-synchronised calls
  * The comparison path of §2.4: MPI calls that run in the CPU context and
  * fully synchronise with the GPU.  Each call synchronises its rank's HIP

@@ -38,7 +38,8 @@ enum {
     MPIXS_DRV_STREAM_SEND = 13,  /* mpixs_stream_send_enqueue                      */
     MPIXS_DRV_STREAM_ISEND = 14, /* mpixs_stream_isend_enqueue into slot `req`     */
     MPIXS_DRV_STREAM_RECV = 15,  /* mpixs_stream_recv_enqueue                      */
-    MPIXS_DRV_STREAM_IRECV = 16  /* mpixs_stream_irecv_enqueue into slot `req`     */
+    MPIXS_DRV_STREAM_IRECV = 16, /* mpixs_stream_irecv_enqueue into slot `req`     */
+    MPIXS_DRV_GROUP_INIT_STATIC = 17 /* mpixs_group_end_init_static(comm, &batches[req]) */
 };
 
 typedef struct {

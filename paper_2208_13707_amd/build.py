@@ -24,7 +24,7 @@ HIP_FLAGS = [
 
 LIBS = {
     "libmpixs.so": ["k_sync.hip", "k_copy.hip", "k_reduce.hip", "k_batch.hip", "k_batch_nt.hip",
-                    "runtime.cpp", "types.cpp"],
+                    "batch_static.hip", "runtime.cpp", "types.cpp"],
     "libmpixs_driver.so": ["driver.cpp", "serve.hip", "hostrate.cpp"],
 }
 

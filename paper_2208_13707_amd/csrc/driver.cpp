@@ -84,12 +84,15 @@ int run_ops(const mpixs_drv_thread &t, int mode, std::vector<mpixs_request> &req
                                             o.peer, o.tag, c, o.op, o.pad, &reqs[size_t(o.req)]);
             break;
         case MPIXS_DRV_GROUP_INIT:
+        case MPIXS_DRV_GROUP_INIT_STATIC:
         case MPIXS_DRV_BATCH_START:
         case MPIXS_DRV_BATCH_FREE:
             if (!t.batches || o.req < 0 || o.req >= t.nbatches) {
                 rc = MPIXS_ERR_ARG;
             } else if (o.kind == MPIXS_DRV_GROUP_INIT) {
                 rc = mpixs_group_end_init(c, &t.batches[o.req]);
+            } else if (o.kind == MPIXS_DRV_GROUP_INIT_STATIC) {
+                rc = mpixs_group_end_init_static(c, &t.batches[o.req]);
             } else if (o.kind == MPIXS_DRV_BATCH_START) {
                 rc = mpixs_batch_start_enqueue(t.batches[o.req]);
             } else {

@@ -1591,7 +1591,7 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
 // its own relative counters (arrive[q] at word 16q, done at word 16n), and
 // optionally build the launching rank's part of a run as a graph.
 int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
-                 BatchPlan **out) {
+                 BatchPlan **out, bool static_mem) {
     const int n = sh->size;
     std::unique_ptr<BatchPlan> P(new BatchPlan());
     P->w = w;
@@ -1619,8 +1619,16 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     const size_t mdbytes = P->mred.on ? (P->mred.desc.size() * sizeof(MultiRedDesc) + 255) & ~size_t(255) : 0;
     const size_t mpbytes = P->mred.on ? P->mred.ptrs.size() * sizeof(void *) : 0;
     const size_t total = P->mred.on ? moff + mdbytes + mpbytes : cbytes + dbytes + sbytes;
-    if (hipMalloc(reinterpret_cast<void **>(&P->d_mem), total) != hipSuccess)
+    if (static_mem) {
+        // the device's static region: no allocation; the counters start at
+        // zero with the image below
+        P->static_mem = true;
+        P->device = w->device;
+        rc = static_batch_region(w->device, total, &P->d_mem, &P->static_gen);
+        if (rc) return rc;
+    } else if (hipMalloc(reinterpret_cast<void **>(&P->d_mem), total) != hipSuccess) {
         return MPIXS_ERR_NOMEM;
+    }
     std::vector<uint8_t> img(total, 0);
     if (!descs.empty()) std::memcpy(img.data() + cbytes, descs.data(), descs.size() * sizeof(BatchDesc));
     if (!starts.empty()) std::memcpy(img.data() + cbytes + dbytes, starts.data(), sbytes);
@@ -1655,7 +1663,7 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     P->sig.done_ptr = P->d_ctr + 16 * n;
     P->sig.inc = 1;
     P->sig.me = st->dev;
-    if (w->cfg.batch_sync == 1) {
+    if (w->cfg.batch_sync == 1 && !static_mem) {
         // event dependencies instead of counters: rank q records post_ev[q]
         // after its prior work, the leader's stream waits for those, runs the
         // batch kernel and records done_ev, every other stream waits for it
@@ -1667,7 +1675,7 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         if (hipEventCreateWithFlags(&P->done_ev, hipEventDisableTiming) != hipSuccess)
             return MPIXS_ERR_GPU;
     }
-    if (w->cfg.batch_graph) {
+    if (w->cfg.batch_graph && !static_mem) {
         hipError_t e = hipSuccess;
         if (P->reds.empty()) {
             e = build_batch_graph(&P->graph, n > 1 ? &P->lwait : nullptr, P->args, P->nwg, P->sig);
@@ -1765,7 +1773,7 @@ BatchPlan::~BatchPlan() {
     if (done_ev) (void)hipEventDestroy(done_ev);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (d_mem) (void)hipFree(d_mem);
+    if (d_mem && !static_mem) (void)hipFree(d_mem);
 }
 
 }  // namespace mpixs
@@ -1804,6 +1812,7 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
         rate_khz <= 0)
         rate_khz = 100000;
     w->timeout_ticks = uint64_t(c.timeout_ms) * uint64_t(rate_khz);
+    static_batch_setup(w->device);
 
     w->stream_cap = std::max(1024, 4 * c.max_streams);
     w->chan_cap = uint32_t(c.max_channels);
@@ -2531,14 +2540,14 @@ int group_finish(mpixs_comm c, int kind, BatchPlan **plan) {
     rec->streams[size_t(c->rank)] = st;
     if (rec->kind == 0) rec->kind = kind;
     else if (rec->kind != kind) rec->mismatch = true;
-    if (kind == 2 && unwaited) rec->bad = true;
+    if (kind >= 2 && unwaited) rec->bad = true;
     const bool last = ++rec->arrived == n;
     int rc = MPIXS_SUCCESS;
     if (last) {
         sh->grp_mu.unlock();
         if (rec->mismatch || rec->bad) rc = MPIXS_ERR_ARG;
         else if (kind == 1) rc = group_launch(w, sh, rec, c->rank, st, g);
-        else rc = batch_create(w, sh, rec, c->rank, st, &rec->batch);
+        else rc = batch_create(w, sh, rec, c->rank, st, &rec->batch, kind == 3);
         rec->error = rc;
         rec->launched.store(1, std::memory_order_release);
         host_notify(&rec->launched);
@@ -2558,7 +2567,7 @@ int group_finish(mpixs_comm c, int kind, BatchPlan **plan) {
             rc = do_wait(w, st, a);
         }
     }
-    if (!rc && kind == 2) *plan = rec->batch;
+    if (!rc && kind >= 2) *plan = rec->batch;
     if (rec->refs.fetch_sub(1) == 1) {
         std::lock_guard<std::mutex> lk(sh->grp_mu);
         while (!sh->groups.empty() && sh->groups.front()->refs.load() == 0) {
@@ -2596,11 +2605,29 @@ int mpixs_group_end_init(mpixs_comm c, mpixs_batch *batch) {
     return MPIXS_SUCCESS;
 }
 
+int mpixs_group_end_init_static(mpixs_comm c, mpixs_batch *batch) {
+    if (!c || !c->sh) return MPIXS_ERR_COMM;
+    if (!c->in_group || !batch) return MPIXS_ERR_ARG;
+    *batch = nullptr;
+    BatchPlan *P = nullptr;
+    const int rc = group_finish(c, 3, &P);
+    if (rc) return rc;
+    mpixs_batch_s *b = new mpixs_batch_s();
+    b->p = P;
+    b->comm = c;
+    b->rank = c->rank;
+    c->pending.fetch_add(1);
+    *batch = b;
+    return MPIXS_SUCCESS;
+}
+
 int mpixs_batch_start_enqueue(mpixs_batch b) {
     if (!b || !b->p) return MPIXS_ERR_REQUEST;
     mpixs_comm_s *c = b->comm;
     if (c->in_group) return MPIXS_ERR_ARG;
     BatchPlan *P = b->p;
+    // a later static plan on this GPU has overwritten this one's region
+    if (P->static_mem && !static_batch_current(P->device, P->static_gen)) return MPIXS_ERR_REQUEST;
     World *w = P->w;
     StreamObj *st = c->stream;
     if (w->aborted.load()) return MPIXS_ERR_ABORTED;

@@ -223,6 +223,9 @@ struct BatchPlan {
     int n = 0;
     int leader = -1;                    // the rank whose stream launches the batch kernel
     uint8_t *d_mem = nullptr;
+    bool static_mem = false;            // d_mem is the device's static region (not freed)
+    int device = 0;
+    uint64_t static_gen = 0;            // the region's contents this plan wrote
     uint64_t *d_ctr = nullptr;
     BatchArgs args{};
     RelWaitArgs lwait{};                // leader: every other rank arrived for this run
@@ -242,6 +245,17 @@ struct BatchPlan {
     std::atomic<int> refs{0};
     ~BatchPlan();
 };
+
+// The static region for persistent batches planned without allocating
+// (mpixs_group_end_init_static), one per GPU.  static_batch_setup finds this
+// device's copy (called once per device, with it current, when a world is
+// created there); static_batch_region hands it to a new plan (ERR_NOMEM when
+// the plan needs more, ERR_GPU without a region) and counts its owners;
+// static_batch_current tells whether a plan still owns it.
+constexpr size_t kStaticBatchBytes = size_t(4) << 20;
+void static_batch_setup(int device);
+int static_batch_region(int device, size_t bytes, uint8_t **ptr, uint64_t *gen);
+bool static_batch_current(int device, uint64_t gen);
 
 struct CreateRec {
     int arrived = 0;

@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 DRIVER_PATH = os.path.join(_HERE, "libmpixs_driver.so")
 
 (SEND, ISEND, RECV, IRECV, WAITALL, ALLREDUCE, MARK, GROUP_START, GROUP_END, GROUP_INIT,
- BATCH_START, BATCH_FREE, STREAM_SEND, STREAM_ISEND, STREAM_RECV, STREAM_IRECV) = range(1, 17)
+ BATCH_START, BATCH_FREE, STREAM_SEND, STREAM_ISEND, STREAM_RECV, STREAM_IRECV,
+ GROUP_INIT_STATIC) = range(1, 18)
 BATCH_SLOTS = 8
 
 OP_DTYPE = np.dtype([

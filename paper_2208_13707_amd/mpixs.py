@@ -110,6 +110,7 @@ SIGNATURES = {
     "mpixs_group_start": [_vp],
     "mpixs_group_end": [_vp],
     "mpixs_group_end_init": [_vp, _pp],
+    "mpixs_group_end_init_static": [_vp, _pp],
     "mpixs_comm_create_multiplex": [_vp, _i, _pp, _pp],
     "mpixs_stream_send_enqueue": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _i, _i],
     "mpixs_stream_recv_enqueue": [_vp, _i, ctypes.c_int32, _i, _i, _vp, _i, _i, _vp],
@@ -380,6 +381,13 @@ def mpixs_group_end_init(comm):
     """Returns (rc, batch handle or None)."""
     h = ctypes.c_void_p()
     rc = lib().mpixs_group_end_init(comm, ctypes.byref(h))
+    return rc, h.value
+
+
+def mpixs_group_end_init_static(comm):
+    """Returns (rc, batch handle or None)."""
+    h = ctypes.c_void_p()
+    rc = lib().mpixs_group_end_init_static(comm, ctypes.byref(h))
     return rc, h.value
 
 
