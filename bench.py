@@ -1,23 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of stream-ordered enqueue traffic on one MI355X.
 
-Default workload (a "step" = one pass of the ring halo exchange): 8 ranks
-(host threads, one HIP stream each) in a bidirectional ring; every step each
-rank isend_enqueue()s columns 0..2 and 3..5 of its float32[count, 8] array A
-as vector(count, 3, 8, float32) to its right and left neighbours, receives
-the neighbours' halos into H with recv_enqueue() and waitall_enqueue()s its
-sends; tag = step.  count = 43690 (524,280 payload bytes per message), 16
-messages per step.
+Default workload (a "step" = one pass of the whole batch): 10,000 enqueued
+send/recv pairs among 32 ranks (host threads, one HIP stream each), sizes
+log-uniform from 8 B to 256 KiB, tags 0..63, 30 % vector datatypes, the
+rest contiguous; every rank isends all its messages, irecvs all its
+messages and waits for all of them.  The same batch runs four ways: a
+persistent batch (planned once, one batch kernel per step; the headline), a
+one-shot group per step, the plain enqueue path (one copy per message) and
+the host-synchronised path; all four must give identical bytes, and the
+oracle checks one batch.
 
-Prints ONE JSON line: enqueued messages/s (value), payload and algorithmic
-GB/s, the same workload through the host-synchronised path, p50/p99 step
-latency, the roofline of the dominant kernel (the typemap copy), and the CPU
-oracle timed on a bounded sample of the same workload.
+Prints ONE JSON line: messages/s (value), algorithmic GB/s and HBM fraction,
+the host-synchronised rate and speedups, p50/p99 batch latency, the roofline
+of the dominant kernel (the batch kernel), the CPU oracle timed on one
+batch, and two more configurations: the 16-rank allreduce at 64 MiB per rank
+(float32 and int64: calls/s, HBM fraction, host-synchronised calls/s) and the
+8-rank ring halo of vector(43690, 3, 8) float32 messages with tag = step
+(value: the plain enqueue path; grouped, persistent and host-synchronised
+beside it).
 
-Other workloads (--workload): pingpong (2 ranks, 1000 x 4 KiB int32),
+Other workloads (--workload): halo, pingpong (2 ranks, 1000 x 4 KiB int32),
 allreduce (16 ranks, SUM, --bytes per rank, --dtype), copy (one contiguous
-message of --bytes between two ranks), batch, serve, nto1, and hostrate (CPU
-only: the host message-rate model of three engine locking policies).
+message of --bytes between two ranks), serve, nto1, and hostrate (CPU only:
+the host message-rate model of three engine locking policies).
 """
 from __future__ import annotations
 
@@ -33,17 +39,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 
 
-def kernel_sources():
-    """Every source file that defines device code, in a fixed order."""
-    src = os.path.join(ROOT, "paper_2208_13707_amd", "csrc")
-    names = sorted(f for f in os.listdir(src)
-                   if f.startswith("k_") or f in ("kernels_common.h", "mpixs_dev.h"))
-    return [os.path.join(src, f) for f in names]
-
-
 def measured_traffic(key):
     """HBM bytes per launch of a kernel from the committed counter runs, or
-    None when the kernel sources changed since those counters were taken."""
+    None when the device sources that kernel is built from changed since
+    those counters were taken."""
     import hashlib
     import json as _json
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -51,12 +50,17 @@ def measured_traffic(key):
         rec = _json.load(open(path))
     except OSError:
         return None
-    h = hashlib.sha256()
-    for path in kernel_sources():
-        h.update(open(path, "rb").read())
-    if h.hexdigest() != rec.get("kernels_sha256") or key not in rec:
+    ent = rec.get(key)
+    if not ent:
         return None
-    return rec[key]["read_bytes"] + rec[key]["write_bytes"]
+    src = os.path.join(ROOT, "paper_2208_13707_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ent["sources"]:
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != ent.get("sources_sha256"):
+        return None
+    return ent["read_bytes"] + ent["write_bytes"]
 
 
 def log(msg):
@@ -686,12 +690,17 @@ def bench_batch(args):
     torch.cuda.synchronize()
     maxreq = max(len(p.ops[r][0]) for r in range(n)) + 1
 
-    def ops(variant, reps, tag_base=0):
+    def ops(variant, reps, tag_base=0, marks=False):
         out = []
         for r in range(n):
             rows = []
             if variant in ("persistent", "tune") and reps > 0:
-                rows += [dict(kind=D.BATCH_START, req=0)] * reps
+                for j in range(reps):
+                    if marks:
+                        rows.append(dict(kind=D.MARK, req=2 * j))
+                    rows.append(dict(kind=D.BATCH_START, req=0))
+                    if marks:
+                        rows.append(dict(kind=D.MARK, req=2 * j + 1))
                 out.append(D.ops_array(rows))
                 continue
             for _ in range(max(reps, 1)):
@@ -789,6 +798,10 @@ def bench_batch(args):
         if variant == "persistent":
             bk = time_batch_kernel(sess, 20)
             log(f"[batch] persistent: batch kernel alone {bk[0]:.1f} us")
+            # per-batch latency: HIP events around every start on every stream
+            _, mk = run_checked(sess, ops(variant, k, tagb, marks=True), max_reqs=maxreq,
+                                nmarks=2 * k)
+            lat = step_latencies(mk, k)
         close_checked(sess)
         res[variant] = npairs * k / sec
         log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.3f} ms per batch)")
@@ -801,15 +814,22 @@ def bench_batch(args):
             if not torch.equal(R[v][r], R["grouped"][r]):
                 raise AssertionError(f"{v} path differs from grouped on rank {r}")
     head = res["persistent"]
+    bk_us, bk_payload, bk_wg = bk
+    per_launch = 2 * bk_payload
+    gbps_alg = per_launch * head / npairs / 1e9
     line = {
-        "metric": "enqueued msgs/s vs host-synced path (uneven batch)",
+        "metric": "enqueued msgs/s + GB/s (frac of HBM peak) vs host-synced path; p50/p99 latency",
         "value": head, "unit": "msgs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1000 * npairs / head,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"batch_{npairs}pairs_{n}ranks_8B-256KiB_30pct_vector",
+                   "ranks": n, "pairs": npairs, "payload_bytes_per_batch": bk_payload,
                    "variant": "persistent batch: planned once, one batch kernel per step",
                    "schedule": sched},
+        "gbps_algorithmic": gbps_alg,
+        "hbm_frac": gbps_alg / HBM_PEAK_GBS,
+        "latency_us": {"p50": pct(lat, 50), "p99": pct(lat, 99), "of": "batch (10,000 messages)"},
         "persistent_init_ms": init_ms,
         "one_shot_group": {"value": res["grouped"], "unit": "msgs/s"},
         "plain_enqueue": {"value": res["plain"], "unit": "msgs/s"},
@@ -818,8 +838,6 @@ def bench_batch(args):
                         "one_shot_group_speedup": res["grouped"] / res["host"] if "host" in res else None,
                         "plain_speedup": res["plain"] / res["host"] if "host" in res else None},
     }
-    bk_us, bk_payload, bk_wg = bk
-    per_launch = 2 * bk_payload
     ach = per_launch / (bk_us * 1e-6) / 1e9
     line["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("batch_10000"),
@@ -1191,12 +1209,51 @@ def bench_copy(args):
     return line
 
 
+def extra_configs(args):
+    """The allreduce configuration at 64 MiB per rank (float32 and int64) and
+    the ring-halo configuration (tag = step), each at its full size, for the
+    default line."""
+    import copy
+    out = {}
+    ar = {}
+    for dtype in ("float32", "int64"):
+        a = copy.copy(args)
+        a.workload, a.bytes, a.dtype, a.ranks, a.group = "allreduce", 64 << 20, dtype, 16, 1
+        a.steps, a.warmup, a.hs_steps, a.via_host_synced = 20, 5, 20, False
+        r = bench_allreduce(a)
+        ar[dtype] = {"calls_per_s": r["value"], "gbps_algorithmic": r["gbps_algorithmic"],
+                     "hbm_frac": r["hbm_frac"], "host_synced": r["host_synced"],
+                     "latency_us": r["latency_us"], "roofline": r["roofline"]}
+        log(f"[extra] allreduce 16 x 64 MiB {dtype}: {r['value']:.0f} calls/s, "
+            f"HBM frac {r['hbm_frac']:.3f} (kernel {r['roofline']['frac']:.3f})")
+    out["config3_allreduce_16ranks_64MiB"] = ar
+    a = copy.copy(args)
+    a.workload, a.count, a.steps, a.warmup, a.sweep = "halo", 43690, 100, 10, False
+    a.no_cpu_baseline, a.hs_steps = True, 100
+    h = bench_halo(a)
+    out["config2_ring_halo_count43690"] = {
+        "value": h["plain_enqueue"]["value"], "unit": "msgs/s",
+        "variant": "plain enqueue (one copy per message, tag = step)",
+        "plain_enqueue": h["plain_enqueue"], "grouped_enqueue": h["grouped_enqueue"],
+        "persistent_enqueue": h["persistent_enqueue"],
+        "host_synced": h["host_synced"],
+        "plain_vs_host_synced": h["host_synced"]["plain_speedup"],
+        # the plain path's data kernel: one message's typemap copy
+        "roofline": vector_copy_roofline(43690, 100),
+        "roofline_batch_kernel": h["roofline"]}
+    log(f"[extra] halo plain enqueue {h['plain_enqueue']['value']:.0f} msgs/s, "
+        f"host-synced {h['host_synced']['value']:.0f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="halo",
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batch: leave out the allreduce and halo configurations")
+    ap.add_argument("--workload", default="batch",
                     choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch", "serve",
                              "nto1", "hostrate"])
     ap.add_argument("--hostrate-msgs", type=int, default=1000000,
@@ -1269,6 +1326,9 @@ def main():
               "copy": bench_copy, "batch": bench_batch, "serve": bench_serve,
               "nto1": bench_nto1}[args.workload]
         line = fn(args)
+        if args.workload == "batch" and not args.no_extras and not args.kernel_only \
+                and not args.only_grouped:
+            line.update(extra_configs(args))
     print(json.dumps(line), flush=True)
 
 
