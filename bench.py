@@ -243,6 +243,67 @@ def vector_copy_roofline(count, k):
             "note": "data kernel of one halo message, launched back to back between one event pair"}
 
 
+def pattern_rates(payload=128 << 20, reps=20, bls=tuple(range(1, 17)), log_rows=False):
+    """The copy kernel of the library on one message of `payload` bytes in
+    each layout pattern (launched back to back between one pair of HIP
+    events on its stream): contiguous, and vector(c, bl, 2 bl, float32) on
+    both sides (half of every extent used) for each block length bl, as
+    algorithmic TB/s (2 x payload / time).  These are what the memory system
+    allows for each pattern: below 64-byte blocks a vector destination is
+    written in partial 64-byte granules and its source read in whole lines."""
+    import ctypes
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    f = M.lib().mpixs_debug_time_copy
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_void_p,
+                  ctypes.c_int, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_int)]
+    f.restype = ctypes.c_int
+    src = torch.empty(2 * payload, dtype=torch.uint8, device="cuda").fill_(7)
+    dst = torch.zeros(2 * payload, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    hs = D.hip_stream_create()
+    out = {}
+    try:
+        cases = [("contig", None)] + [(bl, bl) for bl in bls]
+        for key, bl in cases:
+            if bl is None:
+                st = rt = M.UINT8
+                cnt = payload
+            else:
+                st = rt = make_vector(M, payload // (4 * bl), bl, 2 * bl, M.FLOAT32)
+                cnt = 1
+            avg = ctypes.c_double()
+            w = ctypes.c_int()
+            rc = f(hs, src.data_ptr(), cnt, st, dst.data_ptr(), cnt, rt, reps, ctypes.byref(avg),
+                   ctypes.byref(w))
+            if bl is not None:
+                M.mpixs_type_free(st)
+            if rc:
+                raise RuntimeError(f"mpixs_debug_time_copy: {M.errname(rc)}")
+            pay = payload if bl is None else payload // (4 * bl) * 4 * bl
+            out[key] = 2 * pay / (avg.value * 1e-6) / 1e12
+            if log_rows:
+                log(f"[patterns] {'contiguous' if bl is None else f'vector bl={bl:2d} ({4 * bl:3d} B blocks)'}: "
+                    f"{avg.value:8.1f} us, {out[key]:.2f} TB/s algorithmic")
+    finally:
+        D.hip_stream_destroy(hs)
+        del src, dst
+    return out
+
+
+def pattern_bound_us(msgs, rates):
+    """Lower bound on a batch kernel's time: every message at its pattern's
+    copy rate (contiguous, or the vector block length's), no overheads."""
+    t = 0.0
+    for m in msgs:
+        tree = m["tree"]
+        key = tree[2] if isinstance(tree, tuple) and tree[0] == "vector" else "contig"
+        t += 2 * m["size"] / (rates[key] * 1e12)
+    return t * 1e6
+
+
 def halo_cpu_baseline(count, budget_s=15.0):
     """The oracle as it stands on a bounded sample of the same workload."""
     from oracle import simulate as sim
@@ -296,7 +357,11 @@ def bench_halo(args):
         payload = 12 * count
         res = {"count": count, "payload_bytes": payload}
         # ---- enqueue path: warmup, then K timed steps
-        sess = D.Session(n)
+        pc = None
+        if args.fuse_max_bytes is not None:
+            pc = M.Config()
+            pc.fuse_max_bytes = args.fuse_max_bytes
+        sess = D.Session(n, pc)
         ops = [halo_ops(D, r, n, A[r], H[r], vt, warm, 0, 0) for r in range(n)]
         run_checked(sess, ops)
         ops = [halo_ops(D, r, n, A[r], H[r], vt, steps, 0, 0) for r in range(n)]
@@ -839,8 +904,13 @@ def bench_batch(args):
                         "plain_speedup": res["plain"] / res["host"] if "host" in res else None},
     }
     ach = per_launch / (bk_us * 1e-6) / 1e9
+    rates = pattern_rates(log_rows=True)
+    bound = pattern_bound_us(msgs, rates)
     line["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("batch_10000"),
+                        "pattern_bound_us": bound,
+                        "frac_of_pattern_bound": bound / bk_us,
+                        "pattern_rates_TBps": {str(k): v for k, v in rates.items()},
                         "kernel": f"mpixs::k_batch<{sched['tile']}, "
                                   f"{'true' if batch_nt_used(args.batch_nt, bk_payload) else 'false'}>",
                         "bytes_per_launch": per_launch, "avg_launch_us": bk_us,
@@ -1255,7 +1325,7 @@ def main():
                     help="batch: leave out the allreduce and halo configurations")
     ap.add_argument("--workload", default="batch",
                     choices=["halo", "pingpong", "allreduce", "copy", "vcopy", "batch", "serve",
-                             "nto1", "hostrate"])
+                             "nto1", "hostrate", "patterns"])
     ap.add_argument("--hostrate-msgs", type=int, default=1000000,
                     help="hostrate: messages per thread pair")
     ap.add_argument("--nto1-senders", type=int, default=8)
@@ -1282,6 +1352,8 @@ def main():
                     help="persistent batches: 0 device counters, 1 HIP events")
     ap.add_argument("--ranks-batch", type=int, default=32)
     ap.add_argument("--count", type=int, default=43690)
+    ap.add_argument("--fuse-max-bytes", type=int, default=None,
+                    help="halo: mpixs_config.fuse_max_bytes of the plain enqueue path")
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")
     ap.add_argument("--bytes", type=int, default=None)
     ap.add_argument("--dtype", default="float32")
@@ -1306,7 +1378,7 @@ def main():
               "sharing one MI355X", file=sys.stderr)
         sys.exit(2)
     defaults = {"halo": (100, 10), "pingpong": (1000, 40), "allreduce": (20, 5), "copy": (10, 3),
-                "vcopy": (100, 10), "batch": (20, 5), "serve": (1, 0),
+                "vcopy": (100, 10), "batch": (20, 5), "serve": (1, 0), "patterns": (20, 1),
                 "nto1": (200, 20), "hostrate": (1, 0)}
     k, w = defaults[args.workload]
     args.steps = args.steps or k
@@ -1321,6 +1393,9 @@ def main():
     if args.workload == "vcopy":
         line = {"workload": f"vector_copy_count{args.count}",
                 "roofline": vector_copy_roofline(args.count, args.steps)}
+    elif args.workload == "patterns":
+        line = {"workload": "copy kernel per layout pattern, 128 MiB payload",
+                "unit": "TB/s algorithmic", "rates": pattern_rates(log_rows=True)}
     else:
         fn = {"halo": bench_halo, "allreduce": bench_allreduce, "pingpong": bench_pingpong,
               "copy": bench_copy, "batch": bench_batch, "serve": bench_serve,

@@ -124,7 +124,7 @@ typedef struct {
     int32_t fuse_max_bytes;   /* messages (and allreduces, counting all ranks' inputs) up
                                  to this size wait and copy in one kernel of at most 32
                                  workgroups; larger ones use a one-wave wait kernel, a
-                                 full-grid data kernel and a signal kernel [2097152];
+                                 full-grid data kernel and a signal kernel [65536];
                                  -1: never fuse */
     int32_t timeout_ms;       /* host waits for a peer's enqueue, and device waits for a
                                  peer's stream, give up after this [30000] */

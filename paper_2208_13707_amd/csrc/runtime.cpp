@@ -1790,7 +1790,10 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     if (cfg) w->cfg = *cfg;
     mpixs_config &c = w->cfg;
     if (c.max_streams <= 0) c.max_streams = 256;
-    if (c.fuse_max_bytes == 0) c.fuse_max_bytes = 2 << 20;
+    // fused (at most 32 workgroups, wait inside) up to 64 KiB: above it a
+    // full-grid copy between a wait and a signal kernel is faster despite
+    // the two extra launches (ring-halo sweep of the plain enqueue path)
+    if (c.fuse_max_bytes == 0) c.fuse_max_bytes = 64 << 10;
     if (c.timeout_ms <= 0) c.timeout_ms = 30000;
     if (c.max_channels <= 0) c.max_channels = 1 << 20;
     if (c.max_collectives <= 0) c.max_collectives = 4096;
