@@ -1546,6 +1546,18 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         if (rc) return rc;
         h = reinterpret_cast<uint8_t *>(w->h_arena + off);
     }
+    // A failed launch before anything that reads the arena range was
+    // enqueued hands the range back at once (the ring frees in order, so a
+    // range held forever would stall every later group).  After a kernel that
+    // reads it was enqueued, the range must stay until that kernel is done:
+    // the instance is broken on every rank, so the world is aborted and all
+    // of its waits end.
+    bool range_read = false;
+    auto fail = [&](int code) {
+        if (flag >= 0 && !range_read) __atomic_store_n(&w->h_flags[flag], 1u, __ATOMIC_RELEASE);
+        if (range_read) mpixs_world_abort(reinterpret_cast<mpixs_world>(w));
+        return code;
+    };
     if (!descs.empty()) {
         BatchDesc *hd = reinterpret_cast<BatchDesc *>(h);
         BatchStart *hs = reinterpret_cast<BatchStart *>(h + ((dbytes + 255) & ~size_t(255)));
@@ -1558,7 +1570,8 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         if (profile_on(w)) prof_begin(w, st->hs, &e0);
         rc = gpu_err(launch_batch(st->hs, a, int(starts.size())));
         if (profile_on(w)) prof_end(w, st->hs, e0, 0);
-        if (rc) return rc;
+        if (rc) return fail(rc);
+        range_read = true;
         w->n_copy.fetch_add(1, std::memory_order_relaxed);
         w->bytes_copied.fetch_add(bytes, std::memory_order_relaxed);
     }
@@ -1575,7 +1588,7 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         ma.me = st->dev;
     }
     rc = launch_reds(w, st->hs, sh->plan.reds, mr, ma);
-    if (rc) return rc;
+    if (rc) return fail(rc);
     SignalArgs sg;
     std::memset(&sg, 0, sizeof(sg));
     sg.done_ptr = done;
@@ -1583,6 +1596,7 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     sg.me = st->dev;
     sg.host_flag = flag >= 0 ? &w->h_flags[flag] : nullptr;
     rc = gpu_err(launch_signal(st->hs, sg));
+    if (rc) return fail(rc);
     w->n_post.fetch_add(1, std::memory_order_relaxed);
     return rc;
 }
