@@ -232,6 +232,11 @@ int mpixs_type_vector(int count, int blocklength, int stride, mpixs_datatype old
 int mpixs_type_indexed(int count, const int blocklengths[], const int displacements[],
                        mpixs_datatype oldtype, mpixs_datatype *newtype);
 int mpixs_type_commit(mpixs_datatype *type);
+/* mpixs_type_free releases the handle (set to MPIXS_DATATYPE_NULL).  The
+ * type's description -- and an irregular indexed type's segment table in
+ * pinned memory -- stays allocated until the process ends, since operations
+ * enqueued before the free and persistent batches may still read it; a
+ * process can make at most 2^20 datatypes. */
 int mpixs_type_free(mpixs_datatype *type);
 int mpixs_type_size(mpixs_datatype type, int64_t *bytes);
 int mpixs_type_get_extent(mpixs_datatype type, int64_t *lb, int64_t *extent);
