@@ -184,13 +184,18 @@ def close_checked(sess):
         raise RuntimeError(f"asynchronous stream errors: {errs}")
 
 
-def run_checked(sess, ops, mode=0, nmarks=0, max_reqs=64):
+def run_checked(sess, ops, mode=0, nmarks=0, max_reqs=64, enqueue=False):
+    """Runs the rank programs; returns (seconds, marks), or with enqueue=True
+    (seconds, marks, enqueue_seconds): when the last rank thread returned
+    from its last call, before the stream syncs (the host's share)."""
     from paper_2208_13707_amd import mpixs as M
     rc, res, marks = sess.run(ops, mode=mode, nmarks=nmarks, max_reqs=max_reqs)
     if rc:
         raise RuntimeError(f"driver: {M.errname(rc)} at thread {res.error_thread} op {res.error_op}")
     # every rank thread of the runner has synchronised its own stream: the
     # results may be read on torch's stream now, with no device-wide sync
+    if enqueue:
+        return res.seconds, marks, res.enqueue_seconds
     return res.seconds, marks
 
 
@@ -366,10 +371,11 @@ def bench_halo(args):
         run_checked(sess, ops)
         ops = [halo_ops(D, r, n, A[r], H[r], vt, steps, 0, 0) for r in range(n)]
         torch.cuda.synchronize()
-        sec, _ = run_checked(sess, ops)
+        sec, _, enq = run_checked(sess, ops, enqueue=True)
         st = sess.stats()
         msgs = 16 * steps
         res.update(msgs_per_s=msgs / sec, ms_per_step=1000 * sec / steps,
+                   enqueue_ms_per_step=1000 * enq / steps,
                    gbps_payload=msgs * payload / sec / 1e9,
                    gbps_algorithmic=2 * msgs * payload / sec / 1e9,
                    kernels_per_msg=(st.kernels_post + st.kernels_wait + st.kernels_copy) /
@@ -449,7 +455,8 @@ def bench_halo(args):
         if count == args.count:
             headline = res
         out_sweep.append(res)
-        log(f"[halo] count={count}: {res['msgs_per_s']:.0f} msgs/s, "
+        log(f"[halo] count={count}: {res['msgs_per_s']:.0f} msgs/s "
+            f"(enqueue {1000 * res['enqueue_ms_per_step']:.1f} of {1000 * res['ms_per_step']:.1f} us/step), "
             f"grouped {res['grouped_msgs_per_s']:.0f} msgs/s, "
             f"persistent {res['persistent_msgs_per_s']:.0f} msgs/s, "
             f"{res['gbps_algorithmic']:.1f} GB/s alg, "
@@ -514,6 +521,7 @@ def bench_halo(args):
         "gbps_algorithmic": 2 * gbps_pay,
         "hbm_frac": 2 * gbps_pay / HBM_PEAK_GBS,
         "plain_enqueue": {"value": h["msgs_per_s"], "ms_per_step": h["ms_per_step"],
+                          "enqueue_ms_per_step": h["enqueue_ms_per_step"],
                           "p50_step_us": h["p50_step_us"], "p99_step_us": h["p99_step_us"]},
         "grouped_enqueue": {"value": h["grouped_msgs_per_s"], "ms_per_step": h["grouped_ms_per_step"],
                             "p50_step_us": h["grouped_p50_step_us"],

@@ -76,6 +76,8 @@ typedef struct {
     int32_t first_error;     /* first non-zero return code, 0 if none */
     int32_t error_thread;
     int64_t error_op;
+    double enqueue_seconds;  /* max over threads of (return of its last call - common start),
+                                before its stream is synchronised: the host's share */
 } mpixs_drv_result;
 
 /* ------------------------------------------------------------- serving

@@ -16,7 +16,7 @@ namespace {
 using clk = std::chrono::steady_clock;
 
 struct ThreadOut {
-    clk::time_point start, end;
+    clk::time_point start, end, enq_end;
     int err = 0;
     int64_t err_op = -1;
     std::vector<hipEvent_t> marks;
@@ -143,6 +143,7 @@ extern "C" int mpixs_drv_run(mpixs_world world, int nthreads, const mpixs_drv_th
             while (!go.load(std::memory_order_acquire)) _mm_pause();
             out.start = clk::now();
             if (run_ops(t, mode, reqs, out)) mpixs_world_abort(world);
+            out.enq_end = clk::now();
             if (hipStreamSynchronize(static_cast<hipStream_t>(t.hip_stream)) != hipSuccess &&
                 !out.err)
                 out.err = MPIXS_ERR_GPU;
@@ -153,12 +154,13 @@ extern "C" int mpixs_drv_run(mpixs_world world, int nthreads, const mpixs_drv_th
     t_go = clk::now();
     go.store(1, std::memory_order_release);
     for (auto &x : th) x.join();
-    clk::time_point end = t_go;
+    clk::time_point end = t_go, enq_end = t_go;
     result->first_error = 0;
     result->error_thread = -1;
     result->error_op = -1;
     for (int i = 0; i < nthreads; ++i) {
         end = std::max(end, outs[size_t(i)].end);
+        enq_end = std::max(enq_end, outs[size_t(i)].enq_end);
         if (outs[size_t(i)].err && !result->first_error) {
             result->first_error = outs[size_t(i)].err;
             result->error_thread = i;
@@ -166,6 +168,7 @@ extern "C" int mpixs_drv_run(mpixs_world world, int nthreads, const mpixs_drv_th
         }
     }
     result->seconds = std::chrono::duration<double>(end - t_go).count();
+    result->enqueue_seconds = std::chrono::duration<double>(enq_end - t_go).count();
     if (marks_ms && max_marks > 0 && !outs[0].marks.empty()) {
         for (int i = 0; i < nthreads; ++i) {
             for (int m = 0; m < max_marks; ++m) {

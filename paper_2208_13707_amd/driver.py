@@ -42,7 +42,8 @@ class DrvThread(ctypes.Structure):
 
 class DrvResult(ctypes.Structure):
     _fields_ = [("seconds", ctypes.c_double), ("first_error", ctypes.c_int32),
-                ("error_thread", ctypes.c_int32), ("error_op", ctypes.c_int64)]
+                ("error_thread", ctypes.c_int32), ("error_op", ctypes.c_int64),
+                ("enqueue_seconds", ctypes.c_double)]
 
 
 _dlib = None
