@@ -13,7 +13,8 @@ namespace mpixs {
 // ----------------------------------------------------------------- batch
 // One kernel for every copy of a group.  Workgroup b runs a contiguous range
 // of tiles (balanced: base or base + 1), starting at the (message, tile)
-// the host computed for it, and walks the messages in order; the message's
+// the host computed for it, and walks the messages in order, copying its
+// tiles of each message as one run; the message's
 // descriptor is read (host-pinned memory for a one-shot group, device
 // memory for a persistent batch) into LDS when the workgroup reaches it.
 // A tile is TILE * 16 bytes of one message; the unit size and map kinds of
@@ -21,12 +22,17 @@ namespace mpixs {
 template <int TILE, bool NT, int W, int SK, int DK>
 __device__ __forceinline__ void tile_copy(const BatchDesc &d, uint64_t u0, uint64_t u1) {
     using T = typename Unit<W>::T;
-    // a tile holds TILE * 16 / W units, K per lane; a lane issues up to 8
-    // loads before its first store, so a tile of narrow units costs one
-    // memory round trip instead of one per chunk (the stores could alias
-    // later loads, so the compiler cannot hoist them by itself)
+    // [u0, u1) is a workgroup's run of consecutive tiles of one message; a
+    // tile holds TILE * 16 / W units, K per lane.  A lane issues B loads
+    // before its first store (the stores could alias later loads, so the
+    // compiler cannot hoist them by itself): all of a tile's units up to 8,
+    // and at least 2 sixteen-byte or 4 narrower units, so that a run of
+    // small-tile units keeps more than one load per lane in flight (4
+    // sixteen-byte units per lane measured 15 % slower on contiguous
+    // messages)
     constexpr int K = TILE / COPY_THREADS * (16 / W);
-    constexpr int B = K < 8 ? K : 8;
+    constexpr int BMIN = W == 16 ? 2 : 4;
+    constexpr int B = K > BMIN ? (K < 8 ? K : 8) : BMIN;
     for (uint64_t c0 = u0; c0 < u1; c0 += uint64_t(B) * COPY_THREADS) {
         T v[B];
 #pragma unroll
@@ -78,7 +84,7 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
         reinterpret_cast<W16 *>(&sd)[threadIdx.x] =
             reinterpret_cast<const W16 *>(a.desc + m)[threadIdx.x];
     __syncthreads();
-    for (uint64_t i = 0; i < cnt; ++i) {
+    for (uint64_t i = 0; i < cnt;) {
         if (tin >= sd.ntiles) {
             ++m;
             tin = 0;
@@ -88,11 +94,14 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
                     reinterpret_cast<const W16 *>(a.desc + m)[threadIdx.x];
             __syncthreads();
         }
+        // this workgroup's remaining tiles of message m, copied as one run
+        const uint64_t left = cnt - i;
+        const uint64_t k = left < uint64_t(sd.ntiles - tin) ? left : uint64_t(sd.ntiles - tin);
         if (!s_fatal) {
             const uint64_t tu = uint64_t(TILE) * (16u / sd.w);   // units per tile
             const uint64_t u0 = uint64_t(tin) * tu;
-            const uint64_t u1 = u0 + tu < sd.units ? u0 + tu : sd.units;
-            if (tin + 1 == sd.ntiles && threadIdx.x < sd.tail) {
+            const uint64_t u1 = u0 + k * tu < sd.units ? u0 + k * tu : sd.units;
+            if (tin + k == sd.ntiles && threadIdx.x < sd.tail) {
                 // byte tail of a copy dense on both sides
                 const uint64_t off = sd.units * sd.w + threadIdx.x;
                 reinterpret_cast<uint8_t *>(sd.dst.base)[off] =
@@ -113,7 +122,8 @@ __global__ void __launch_bounds__(COPY_THREADS) k_batch(BatchArgs a) {
             if (!s_fatal && sd.st.error && sd.rstream)
                 set_first_error(sd.rstream, uint32_t(sd.st.error));
         }
-        ++tin;
+        tin += uint32_t(k);
+        i += k;
     }
 }
 
