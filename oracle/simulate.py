@@ -81,8 +81,10 @@ Readings where the paper is silent (each is listed in the design notes):
   overlapping receive typemap (ERR_TYPE); for allreduce: communicator, count,
   datatype (basic types only), operation (ERR_OP); for wait / waitall:
   unknown request (ERR_REQUEST), requests of different streams (ERR_STREAM).
-  Parity unpinned: these codes follow the readings above and have no worked
-  example in the paper.
+  The paper prints no example of these codes, so the order is this
+  simulator's reading; the tests pin that the simulator follows it, with
+  expected codes written out by hand for fixed programs of erroneous calls
+  (and that such calls move nothing).
 """
 from __future__ import annotations
 
