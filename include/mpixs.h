@@ -224,7 +224,9 @@ int mpixs_comm_size(mpixs_comm comm, int *size);
  * (i*stride + j)*extent(T); indexed(count, bls, displs, T) places element j
  * of block i at (displs[i] + j)*extent(T).  Counts, blocklengths, strides
  * and displacements must be >= 0.  A type must be committed before use;
- * commit compiles it into the form the copy kernels read.
+ * commit compiles it into the form the copy kernels read (an irregular
+ * indexed type: a table of its segments in the memory of the GPU current at
+ * commit, MPIXS_ERR_NOMEM / MPIXS_ERR_GPU if that fails).
  */
 int mpixs_type_contiguous(int count, mpixs_datatype oldtype, mpixs_datatype *newtype);
 int mpixs_type_vector(int count, int blocklength, int stride, mpixs_datatype oldtype,
@@ -234,7 +236,7 @@ int mpixs_type_indexed(int count, const int blocklengths[], const int displaceme
 int mpixs_type_commit(mpixs_datatype *type);
 /* mpixs_type_free releases the handle (set to MPIXS_DATATYPE_NULL).  The
  * type's description -- and an irregular indexed type's segment table in
- * pinned memory -- stays allocated until the process ends, since operations
+ * device memory -- stays allocated until the process ends, since operations
  * enqueued before the free and persistent batches may still read it; a
  * process can make at most 2^20 datatypes. */
 int mpixs_type_free(mpixs_datatype *type);

@@ -82,7 +82,7 @@ struct DMap {
     int64_t s_blk;    // bytes between blocks (VEC)
     FastDiv d_upc;
     FastDiv d_bu;
-    const SegEnt *seg;  // SEG table (nseg entries), in host-pinned memory
+    const SegEnt *seg;  // SEG table (nseg entries), in device memory
 };
 
 template <int K, int W>

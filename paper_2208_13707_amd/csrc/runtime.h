@@ -40,7 +40,7 @@ struct TypeObj {
     Layout L;
     bool predefined = false;
     bool committed = false;
-    SegEnt *table = nullptr;   // SEG form: nseg entries in host-pinned memory
+    SegEnt *table = nullptr;   // SEG form: nseg entries in device memory
     int64_t nseg = 0;
 };
 

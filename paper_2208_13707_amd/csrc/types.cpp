@@ -8,7 +8,7 @@
 //        (a basic type, contiguous, a vector of dense blocks, any indexed
 //        type whose blocks turn out evenly spaced);
 //   SEG  an explicit segment list (anything else), uploaded at commit into
-//        host-pinned memory with the packed prefix of every segment.
+//        device memory with the packed prefix of every segment.
 // Composition never expands a REG layout unless the result is irregular, so
 // vectors with millions of blocks stay O(1).
 #include <hip/hip_runtime.h>
@@ -318,16 +318,23 @@ int mpixs_type_commit(mpixs_datatype *type) {
     if (!t) return MPIXS_ERR_TYPE;
     if (t->committed) return MPIXS_SUCCESS;
     if (!t->L.reg) {
+        // the copy kernels binary-search the table for every unit, so it
+        // lives in device memory (cached in L2), not in host memory
         const int64_t n = int64_t(t->L.segs.size());
-        SegEnt *tab = nullptr;
-        if (hipHostMalloc(reinterpret_cast<void **>(&tab), size_t(n) * sizeof(SegEnt),
-                          hipHostMallocDefault) != hipSuccess)
-            return MPIXS_ERR_NOMEM;
+        std::vector<SegEnt> host(static_cast<size_t>(n));
         int64_t pre = 0;
         for (int64_t i = 0; i < n; ++i) {
-            tab[i].off = t->L.segs[i].first;
-            tab[i].pre = pre;
-            pre += t->L.segs[i].second;
+            host[size_t(i)].off = t->L.segs[size_t(i)].first;
+            host[size_t(i)].pre = pre;
+            pre += t->L.segs[size_t(i)].second;
+        }
+        SegEnt *tab = nullptr;
+        if (hipMalloc(reinterpret_cast<void **>(&tab), size_t(n) * sizeof(SegEnt)) != hipSuccess)
+            return MPIXS_ERR_NOMEM;
+        if (hipMemcpy(tab, host.data(), size_t(n) * sizeof(SegEnt), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            (void)hipFree(tab);
+            return MPIXS_ERR_GPU;
         }
         t->table = tab;
         t->nseg = n;
@@ -342,7 +349,7 @@ int mpixs_type_free(mpixs_datatype *type) {
     std::lock_guard<std::mutex> g(g_types_mu);
     if (*type < 64 || *type >= g_ntypes.load() || !types_table()[*type].load()) return MPIXS_ERR_TYPE;
     // The object and its tables stay allocated: enqueued operations may still
-    // read them, and freeing pinned memory can synchronise the device.
+    // read them, and freeing device memory can synchronise the device.
     types_table()[*type].store(nullptr, std::memory_order_release);
     *type = MPIXS_DATATYPE_NULL;
     return MPIXS_SUCCESS;
