@@ -150,7 +150,14 @@ typedef struct {
                                  signal kernel around the batch kernel), 1 HIP events
                                  (hipEventRecord / hipStreamWaitEvent, no extra kernels;
                                  not with batch_graph = 1) [0] */
-    int32_t reserved[2];
+    int32_t eager_max_bytes;  /* a blocking send whose receive is not yet enqueued, of
+                                 at most eager_max_bytes, is packed into device staging
+                                 on the sender's stream and completes there (eager; an
+                                 empty one only posts), so the call returns at once;
+                                 larger ones, or all when staging or half the matching
+                                 table is held by eager messages, wait for their receive
+                                 to be enqueued (rendezvous) [65536]; -1: never eager */
+    int32_t eager_arena_mib;  /* device staging of eager sends, MiB [64] */
 } mpixs_config;
 
 /* -------------------------------------------------------------- world (N ranks)
@@ -501,6 +508,8 @@ typedef struct {
     uint64_t channels_recycled; /* matching-table blocks handed to a new channel (§3.1 frees) */
     uint64_t streams_recycled;  /* stream blocks of freed streams taken by new streams */
     uint64_t comm_lines_recycled; /* collective lines of freed communicators reused */
+    uint64_t eager_sends;       /* blocking sends complete on the sender's stream before
+                                   their receive was enqueued (eager; empty ones included) */
 } mpixs_stats;
 
 /* Counters of the world since creation (or the last reset).  With

@@ -70,6 +70,12 @@ __global__ void __launch_bounds__(COPY_THREADS) k_copy(CopyArgs a) {
             if (a.status) write_status(a.status, a.st, fatal);
             if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
             if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+            if (a.host_flag)
+                __hip_atomic_store(a.host_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            // release: the done store above lands before the host may hand
+            // the block to a new owner
+            if (a.rel_word)
+                __hip_atomic_store(a.rel_word, a.rel_val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }

@@ -50,6 +50,8 @@ __global__ void __launch_bounds__(64) k_signal(SignalArgs a) {
     if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
     if (a.done_ptr) st_release(a.done_ptr, a.inc ? ld_acquire(a.done_ptr) + 1 : a.done_val);
     if (a.host_flag) __hip_atomic_store(a.host_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    // release: done lands before the host may hand the block to a new owner
+    if (a.rel_word) __hip_atomic_store(a.rel_word, a.rel_val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Persistent batches keep their counters relative: each run of a rank adds

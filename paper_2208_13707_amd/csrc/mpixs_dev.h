@@ -173,11 +173,18 @@ struct CopyArgs {
     StatusVal st;
     int32_t set_error;            // copy st.error into me->first_error
     int32_t pad;
+    // fused only, after done: a host-pinned word set to 1 (the host may
+    // recycle what the kernel read), and a host-pinned release word set to
+    // rel_val (the kernel was the last device use of a channel block)
+    uint32_t *host_flag;
+    uint64_t *rel_word;
+    uint64_t rel_val;
 };
 
 // Completion of a message or collective after the stream's data kernel:
 // optional status and sticky error, then done = val, then (optional) a
-// host-pinned word set to 1 so the host may recycle what the kernel read.
+// host-pinned word set to 1 so the host may recycle what the kernel read,
+// and (optional) a channel block's host-pinned release word set to rel_val.
 struct SignalArgs {
     uint64_t *done_ptr;
     uint64_t done_val;
@@ -187,6 +194,8 @@ struct SignalArgs {
     int32_t set_error;
     int32_t inc;            // nonzero: done = done + 1 (single writer), done_val unused
     uint32_t *host_flag;
+    uint64_t *rel_word;
+    uint64_t rel_val;
 };
 
 // Relative wait of a persistent batch: lane q < n (bit q of skip clear)

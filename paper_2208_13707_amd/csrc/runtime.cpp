@@ -307,13 +307,22 @@ WaitArgs wait_one(const uint64_t *p, uint64_t target) {
     return a;
 }
 
+// What a copy's completion writes besides done: a host flag set to 1 once
+// nothing reads the source any more (eager staging), and a channel block's
+// release word (the copy is the block's last device use).
+struct CopyExtra {
+    uint32_t *host_flag = nullptr;
+    uint64_t *rel_word = nullptr;
+    uint64_t rel_val = 0;
+};
+
 // Copy message S -> R on stream `on`.  wait_ptr/target: the other side's
 // ready counter (nullptr on the host-synchronised path).  done_ptr: the
 // channel's done counter (nullptr: none).  status/set_error: the receive
 // status and sticky error when `on` is the receiver's stream.
 int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusVal &st,
             const uint64_t *wait_ptr, uint64_t wait_target, uint64_t *done_ptr, uint64_t done_val,
-            void *status, bool set_error) {
+            void *status, bool set_error, const CopyExtra *x = nullptr) {
     const int64_t nbytes = st.count_bytes;
     DMap ms, mr;
     int wsz = 16;
@@ -342,6 +351,11 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
         a.status = status;
         a.st = st;
         a.set_error = set_error ? 1 : 0;
+        if (x) {
+            a.host_flag = x->host_flag;
+            a.rel_word = x->rel_word;
+            a.rel_val = x->rel_val;
+        }
         if (profile_on(w)) prof_begin(w, on->hs, &e0);
         rc = gpu_err(launch_copy(on->hs, a, wsz, int(nwg), true));
         if (profile_on(w)) prof_end(w, on->hs, e0, 0);
@@ -361,7 +375,7 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
             if (profile_on(w)) prof_end(w, on->hs, e0, 0);
             if (rc) return rc;
         }
-        if (done_ptr || status || (set_error && st.error)) {
+        if (done_ptr || status || (set_error && st.error) || x) {
             SignalArgs sg;
             std::memset(&sg, 0, sizeof(sg));
             sg.done_ptr = done_ptr;
@@ -370,6 +384,11 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
             sg.status = status;
             sg.st = st;
             sg.set_error = set_error ? 1 : 0;
+            if (x) {
+                sg.host_flag = x->host_flag;
+                sg.rel_word = x->rel_word;
+                sg.rel_val = x->rel_val;
+            }
             rc = gpu_err(launch_signal(on->hs, sg));
             if (rc) return rc;
             w->n_post.fetch_add(1, std::memory_order_relaxed);
@@ -378,6 +397,61 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
     w->n_copy.fetch_add(1, std::memory_order_relaxed);
     w->bytes_copied.fetch_add(uint64_t(nbytes), std::memory_order_relaxed);
     return MPIXS_SUCCESS;
+}
+
+// Reserve `bytes` of the eager staging ring and a completion flag, or give
+// up at once when the ring is full: the send then takes the rendezvous
+// protocol, so no sender ever waits for staging.  Slots are recycled in
+// order once the receiver's copy has set their flags.
+bool stage_alloc(World *w, size_t bytes, uint8_t **ptr, int *flag) {
+    World::StageRing &g = w->stage;
+    if (!g.base) return false;
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes > g.bytes) return false;
+    std::lock_guard<std::mutex> lk(g.mu);
+    while (!g.live.empty() && __atomic_load_n(&g.flags[g.live.front().flag], __ATOMIC_ACQUIRE) == 1) {
+        g.free_flags.push_back(g.live.front().flag);
+        g.live.pop_front();
+    }
+    if (g.live.empty()) g.head = 0;
+    if (g.free_flags.empty()) return false;
+    size_t at = 0;
+    if (!g.live.empty()) {
+        const size_t tail = g.live.front().off;
+        if (g.head >= tail) {
+            if (g.head + bytes <= g.bytes) at = g.head;
+            else if (bytes < tail) at = 0;
+            else return false;
+        } else if (g.head + bytes < tail) {
+            at = g.head;
+        } else {
+            return false;
+        }
+    }
+    const int f = g.free_flags.back();
+    g.free_flags.pop_back();
+    __atomic_store_n(&g.flags[f], 0u, __ATOMIC_RELEASE);
+    g.live.push_back(World::ArenaUse{at, bytes, f});
+    g.head = at + bytes;
+    *ptr = g.base + at;
+    *flag = f;
+    return true;
+}
+
+// A staging slot that no kernel will read (its launch failed) is free again.
+void stage_drop(World *w, int flag) {
+    __atomic_store_n(&w->stage.flags[flag], 1u, __ATOMIC_RELEASE);
+}
+
+// The packed bytes of an eager send in staging, as a contiguous side.
+Side stage_side(uint8_t *stage, int64_t bytes, int rank) {
+    Side p;
+    p.buf = stage;
+    p.count = int(bytes);
+    p.t = type_lookup(MPIXS_UINT8);
+    p.bytes = bytes;
+    p.rank = rank;
+    return p;
 }
 
 // --------------------------------------------------------------- channels
@@ -455,8 +529,9 @@ void reclaim_blocks(World *w) {
 // Attach a device block to a channel whose next message is number k.
 // Caller holds ch->mu (or owns a channel nobody else sees yet).  Takes a
 // recycled block first, then a fresh one; with the pool exhausted it waits
-// up to the world's timeout for blocks whose release waits are already
-// enqueued.  MPIXS_ERR_NOMEM when none can come.
+// up to the world's timeout for blocks whose releases are already enqueued
+// or held by eager messages whose receives are still to come.
+// MPIXS_ERR_NOMEM when none can come.
 int attach_block(World *w, Channel *ch, uint64_t k) {
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
@@ -481,7 +556,11 @@ int attach_block(World *w, Channel *ch, uint64_t k) {
                 ch->kbase = k;
                 return MPIXS_SUCCESS;
             }
-            if (w->chan_limbo.empty() && w->chan_drain.empty()) return MPIXS_ERR_NOMEM;
+            // blocks can still come from releases already enqueued, or from
+            // eager messages once their receives are enqueued
+            if (w->chan_limbo.empty() && w->chan_drain.empty() &&
+                w->eager_held.load(std::memory_order_relaxed) == 0)
+                return MPIXS_ERR_NOMEM;
         }
         if (w->aborted.load()) return MPIXS_ERR_ABORTED;
         if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(w->cfg.timeout_ms))
@@ -860,8 +939,27 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
         const Side &R = rec->r;
         const StatusVal sv = match_status(S, R, tag);
         const bool recv_here = side == 1;
-        rc = do_copy(w, st, S, R, sv, &rec->d->ready[1 - side], rec->dv, &rec->d->done, rec->dv,
-                     (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
+        if (rec->eager) {
+            // an eager send: copy from its staging once the sender's pack has
+            // published ready; the copy frees the staging slot and, when the
+            // channel is quiescent, is its block's last device use
+            w->eager_held.fetch_sub(1, std::memory_order_relaxed);
+            CopyExtra x;
+            if (rec->stage) x.host_flag = &w->stage.flags[rec->stage_flag];
+            const bool rel = want_release(ch, rec, k);
+            if (rel) {
+                x.rel_word = &w->h_rel[rec->didx];
+                x.rel_val = rec->dv;
+            }
+            rc = do_copy(w, st, rec->stage ? stage_side(rec->stage, S.bytes, S.rank) : S, R, sv,
+                         &rec->d->ready[0], rec->dv, &rec->d->done, rec->dv,
+                         req ? nullptr : static_cast<void *>(status), true, &x);
+            if (rc && rec->stage) stage_drop(w, rec->stage_flag);
+            else if (!rc && rel) note_release(w, ch, rec, k);
+        } else {
+            rc = do_copy(w, st, S, R, sv, &rec->d->ready[1 - side], rec->dv, &rec->d->done, rec->dv,
+                         (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
+        }
         rec->st = sv;
         rec->copy_enq.store(1, std::memory_order_release);
         host_notify(&rec->copy_enq);
@@ -876,6 +974,42 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
             *req = r;
         }
         return rc;
+    }
+    uint8_t *stage = nullptr;
+    int flag = -1;
+    if (side == 0 && !req && me.bytes <= int64_t(w->cfg.eager_max_bytes) &&
+        w->eager_held.load(std::memory_order_relaxed) < int64_t(w->chan_cap / 2) &&
+        (me.bytes == 0 || stage_alloc(w, size_t(me.bytes), &stage, &flag))) {
+        // eager (a blocking send whose receive is not enqueued yet, which
+        // would otherwise hold this thread until it is): pack into staging on
+        // this stream, whose last workgroup publishes ready (an empty message
+        // only posts ready); the send is then complete in stream order and
+        // waits for nothing.  A nonblocking send keeps the rendezvous: its
+        // call returns at once anyway, and a post costs less than a pack.
+        if (stage) {
+            StatusVal pv{};
+            pv.count_bytes = me.bytes;
+            rc = do_copy(w, st, me, stage_side(stage, me.bytes, c->rank), pv, nullptr, 0,
+                         &rec->d->ready[0], rec->dv, nullptr, false);
+        } else {
+            rc = do_post(w, st, &rec->d->ready[0], rec->dv);
+        }
+        if (rc) {
+            if (stage) stage_drop(w, flag);
+            ch->seq[side] = k;   // nothing was enqueued: the call has no effect
+            ch->mu.unlock();
+            return rc;
+        }
+        rec->eager = true;
+        rec->stage = stage;
+        rec->stage_flag = flag;
+        w->eager_held.fetch_add(1, std::memory_order_relaxed);
+        rec->arrived.fetch_or(mine, std::memory_order_release);
+        host_notify(&rec->arrived);
+        ch->mu.unlock();
+        w->n_eager.fetch_add(1, std::memory_order_relaxed);
+        rec_release(ch, rec);   // nothing of the send waits for its receive
+        return MPIXS_SUCCESS;
     }
     rc = do_post(w, st, &rec->d->ready[side], rec->dv);
     rec->arrived.fetch_or(mine, std::memory_order_release);
@@ -1813,10 +1947,13 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     if (c.max_collectives <= 0) c.max_collectives = 4096;
     if (c.batch_tile == 0) c.batch_tile = int32_t(BATCH_TILE_DEFAULT);
     if (c.batch_max_wg <= 0) c.batch_max_wg = 16384;
+    if (c.eager_max_bytes == 0) c.eager_max_bytes = 64 << 10;
+    if (c.eager_arena_mib <= 0) c.eager_arena_mib = 64;
     if (!batch_tile_ok(uint32_t(c.batch_tile)) || c.batch_max_wg > (1 << 20) ||
         c.batch_graph < 0 || c.batch_graph > 1 || c.batch_nontemporal < 0 ||
         c.batch_nontemporal > 2 || c.matching < 0 || c.matching > 1 || c.batch_sync < 0 ||
-        c.batch_sync > 1 || (c.batch_sync == 1 && c.batch_graph == 1)) {
+        c.batch_sync > 1 || (c.batch_sync == 1 && c.batch_graph == 1) || c.eager_max_bytes < -1 ||
+        c.eager_arena_mib > 65536) {
         delete w;
         return MPIXS_ERR_ARG;
     }
@@ -1847,6 +1984,14 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
         delete w;
         return MPIXS_ERR_GPU;
     }
+    w->stage.bytes = size_t(c.eager_arena_mib) << 20;
+    w->stage.nflags = 16384;
+    if (c.eager_max_bytes > 0 &&
+        hipMalloc(reinterpret_cast<void **>(&w->stage.base), w->stage.bytes) != hipSuccess) {
+        (void)hipFree(w->d_pool);
+        delete w;
+        return MPIXS_ERR_NOMEM;
+    }
     w->d_streams = reinterpret_cast<DevStream *>(w->d_pool);
     w->d_chans = reinterpret_cast<DevChan *>(w->d_pool + s_bytes);
     w->d_coll = reinterpret_cast<uint64_t *>(w->d_pool + s_bytes + c_bytes);
@@ -1862,11 +2007,15 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
         hipHostMalloc(reinterpret_cast<void **>(&w->h_flags), sizeof(uint32_t) * size_t(w->nflags),
                       hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&w->h_rel), sizeof(uint64_t) * size_t(w->chan_cap),
-                      hipHostMallocCoherent) != hipSuccess) {
+                      hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w->stage.flags),
+                      sizeof(uint32_t) * size_t(w->stage.nflags), hipHostMallocCoherent) != hipSuccess) {
         (void)hipFree(w->d_pool);
+        if (w->stage.base) (void)hipFree(w->stage.base);
         if (w->h_abort) (void)hipHostFree(w->h_abort);
         if (w->h_arena) (void)hipHostFree(w->h_arena);
         if (w->h_flags) (void)hipHostFree(w->h_flags);
+        if (w->h_rel) (void)hipHostFree(w->h_rel);
         delete w;
         return MPIXS_ERR_NOMEM;
     }
@@ -1874,6 +2023,8 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
     *w->h_abort = 0;
     std::memset(w->h_flags, 0, sizeof(uint32_t) * size_t(w->nflags));
     for (int i = w->nflags - 1; i >= 0; --i) w->free_flags.push_back(i);
+    std::memset(w->stage.flags, 0, sizeof(uint32_t) * size_t(w->stage.nflags));
+    for (int i = w->stage.nflags - 1; i >= 0; --i) w->stage.free_flags.push_back(i);
     w->ep_users.assign(size_t(c.max_streams), 0);
 
     CommShared *sh = new CommShared();
@@ -1922,6 +2073,8 @@ int mpixs_world_free(mpixs_world *pw) {
     (void)hipHostFree(w->h_arena);
     (void)hipHostFree(w->h_flags);
     (void)hipHostFree(w->h_rel);
+    if (w->stage.base) (void)hipFree(w->stage.base);
+    (void)hipHostFree(w->stage.flags);
     for (auto *h : w->world_handles) delete h;
     delete w->world_sh;
     delete w;
@@ -2887,6 +3040,7 @@ int mpixs_world_get_stats(mpixs_world w, mpixs_stats *s) {
     s->plan_ms = double(w->plan_ns.load()) * 1e-6;
     s->reductions_merged = w->reds_merged.load();
     s->channels_recycled = w->chans_recycled.load();
+    s->eager_sends = w->n_eager.load();
     s->streams_recycled = w->streams_recycled.load();
     s->comm_lines_recycled = w->colls_recycled.load();
     s->timed_copy = w->timed_copy;
@@ -2908,6 +3062,7 @@ int mpixs_world_reset_stats(mpixs_world w) {
     w->plan_ns = 0;
     w->reds_merged = 0;
     w->chans_recycled = 0;
+    w->n_eager = 0;
     w->streams_recycled = 0;
     w->colls_recycled = 0;
     w->n_copy = 0;

@@ -111,6 +111,12 @@ struct Rec {
     DevChan *d = nullptr;
     uint32_t didx = 0;
     uint64_t dv = 0;
+    // eager send (complete on the sender's stream, the receiver's copy is
+    // the message's last device use): the packed message in device staging
+    // and the staging slot's host flag, set by that copy (none when empty)
+    bool eager = false;
+    uint8_t *stage = nullptr;
+    int stage_flag = -1;
 };
 
 constexpr uint32_t kNoBlock = 0xffffffffu;
@@ -459,6 +465,22 @@ struct World {
     uint32_t *h_flags = nullptr;
     int nflags = 0;
     std::vector<int> free_flags;
+    // device staging ring of eager sends, recycled in order like the batch
+    // arena: a slot is free again once the receiver's copy has set its flag
+    struct StageRing {
+        std::mutex mu;
+        uint8_t *base = nullptr;   // device memory
+        size_t bytes = 0, head = 0;
+        std::deque<ArenaUse> live;
+        uint32_t *flags = nullptr;   // host-pinned, coherent
+        int nflags = 0;
+        std::vector<int> free_flags;
+    } stage;
+    std::atomic<uint64_t> n_eager{0};
+    // eager messages whose receive is not enqueued yet: each holds its
+    // channel's block until then, so they may take at most half the pool
+    // (the rest serves rendezvous, whose waits bound what is in flight)
+    std::atomic<int64_t> eager_held{0};
     std::mutex prof_mu;
     std::vector<ProfPair> prof;
     uint64_t timed_copy = 0, timed_reduce = 0;

@@ -44,7 +44,7 @@ class Config(ctypes.Structure):
                 ("batch_tile", ctypes.c_int32), ("batch_max_wg", ctypes.c_int32),
                 ("batch_graph", ctypes.c_int32), ("batch_nontemporal", ctypes.c_int32),
                 ("matching", ctypes.c_int32), ("batch_sync", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("eager_max_bytes", ctypes.c_int32), ("eager_arena_mib", ctypes.c_int32)]
 
 
 class Status(ctypes.Structure):
@@ -65,7 +65,7 @@ class Stats(ctypes.Structure):
                 ("host_sleep_timeouts", ctypes.c_uint64), ("groups_planned", ctypes.c_uint64),
                 ("plan_ms", ctypes.c_double), ("reductions_merged", ctypes.c_uint64),
                 ("channels_recycled", ctypes.c_uint64), ("streams_recycled", ctypes.c_uint64),
-                ("comm_lines_recycled", ctypes.c_uint64)]
+                ("comm_lines_recycled", ctypes.c_uint64), ("eager_sends", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p

@@ -4,10 +4,10 @@
 //
 // Memory calls work on host memory, with a registry of allocations so that
 // the library's buffer checks see device and pinned ranges.  Kernel launches
-// are counted and otherwise do nothing, except the two device stores the
-// host side of the library reads back: a signal kernel's host flag (arena
-// recycling) and a wait kernel's release words (channel-block recycling),
-// which are written at once as if the kernel had run.
+// are counted and otherwise do nothing, except the device stores the host
+// side of the library reads back: host flags (batch arena and eager staging
+// recycling) and release words (channel-block recycling) of signal, fused
+// copy and wait kernels, which are written at once as if the kernel had run.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -180,9 +180,15 @@ hipError_t launch_wait(hipStream_t, const WaitArgs &a) {
 }
 hipError_t launch_signal(hipStream_t, const SignalArgs &a) {
     if (a.host_flag) __atomic_store_n(a.host_flag, 1u, __ATOMIC_RELEASE);
+    if (a.rel_word) __atomic_store_n(a.rel_word, a.rel_val, __ATOMIC_RELEASE);
     return counted();
 }
-hipError_t launch_copy(hipStream_t, const CopyArgs &, int, int, bool) { return counted(); }
+hipError_t launch_copy(hipStream_t, const CopyArgs &a, int, int, bool fused) {
+    // a fused copy's last workgroup writes these after done
+    if (fused && a.host_flag) __atomic_store_n(a.host_flag, 1u, __ATOMIC_RELEASE);
+    if (fused && a.rel_word) __atomic_store_n(a.rel_word, a.rel_val, __ATOMIC_RELEASE);
+    return counted();
+}
 hipError_t launch_reduce(hipStream_t, const ReduceArgs &, int, int, bool, int, bool) {
     return counted();
 }
