@@ -720,6 +720,62 @@ int complete_first(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, i
     return rc;
 }
 
+// Eager send (a blocking send that arrives first, of at most
+// eager_max_bytes): pack message k into device staging on the sender's
+// stream; the pack's last workgroup publishes ready[0] (an empty message only
+// posts it).  Returns false, having done nothing, when the send must take the
+// rendezvous instead (too large, staging full, or eager messages already hold
+// half of the matching table).  Caller holds what orders the record (the
+// channel's lock, or sole ownership of a fresh channel).
+bool eager_try(World *w, StreamObj *st, Rec *rec, const Side &me, int *rc) {
+    *rc = MPIXS_SUCCESS;
+    if (me.bytes > int64_t(w->cfg.eager_max_bytes) ||
+        w->eager_held.load(std::memory_order_relaxed) >= int64_t(w->chan_cap / 2))
+        return false;
+    uint8_t *stage = nullptr;
+    int flag = -1;
+    if (me.bytes > 0 && !stage_alloc(w, size_t(me.bytes), &stage, &flag)) return false;
+    if (stage) {
+        StatusVal pv{};
+        pv.count_bytes = me.bytes;
+        *rc = do_copy(w, st, me, stage_side(stage, me.bytes, me.rank), pv, nullptr, 0,
+                      &rec->d->ready[0], rec->dv, nullptr, false);
+    } else {
+        *rc = do_post(w, st, &rec->d->ready[0], rec->dv);
+    }
+    if (*rc) {
+        if (stage) stage_drop(w, flag);
+        return true;
+    }
+    rec->eager = true;
+    rec->stage = stage;
+    rec->stage_flag = flag;
+    w->eager_held.fetch_add(1, std::memory_order_relaxed);
+    w->n_eager.fetch_add(1, std::memory_order_relaxed);
+    return true;
+}
+
+// The receive of an eager send, on the receiver's stream: copy from staging
+// once the pack has published ready, free the staging slot and, when the
+// channel is quiescent, release its block (this copy is its last device use).
+int eager_copy(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, const StatusVal &sv,
+               void *status) {
+    w->eager_held.fetch_sub(1, std::memory_order_relaxed);
+    CopyExtra x;
+    if (rec->stage) x.host_flag = &w->stage.flags[rec->stage_flag];
+    const bool rel = want_release(ch, rec, k);
+    if (rel) {
+        x.rel_word = &w->h_rel[rec->didx];
+        x.rel_val = rec->dv;
+    }
+    const Side &S = rec->s;
+    const int rc = do_copy(w, st, rec->stage ? stage_side(rec->stage, S.bytes, S.rank) : S, rec->r,
+                           sv, &rec->d->ready[0], rec->dv, &rec->d->done, rec->dv, status, true, &x);
+    if (rc && rec->stage) stage_drop(w, rec->stage_flag);
+    else if (!rc && rel) note_release(w, ch, rec, k);
+    return rc;
+}
+
 // Ordered-queue matching (§2.1 with wildcards): a send meets the earliest
 // posted receive of its destination that accepts (source, tag); a receive
 // meets the earliest enqueued send that it accepts; otherwise the operation
@@ -799,9 +855,12 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
         const int mtag = side == 0 ? tag : partner.tag;
         const StatusVal sv = match_status(rec->s, rec->r, mtag);
         const bool recv_here = side == 1;
-        rc = do_copy(w, st, rec->s, rec->r, sv, &rec->d->ready[1 - side], rec->dv, &rec->d->done,
-                     rec->dv, (recv_here && !req) ? static_cast<void *>(status) : nullptr,
-                     recv_here);
+        if (rec->eager)
+            rc = eager_copy(w, st, ch, rec, 0, sv, req ? nullptr : static_cast<void *>(status));
+        else
+            rc = do_copy(w, st, rec->s, rec->r, sv, &rec->d->ready[1 - side], rec->dv, &rec->d->done,
+                         rec->dv, (recv_here && !req) ? static_cast<void *>(status) : nullptr,
+                         recv_here);
         rec->st = sv;
         rec->copy_enq.store(1, std::memory_order_release);
         host_notify(&rec->copy_enq);
@@ -839,7 +898,9 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
     op.tag = tag;
     (side == 0 ? q.unexpected : q.posted).push_back(op);
     lk.unlock();
-    rc = do_post(w, st, &rec->d->ready[side], rec->dv);
+    // a partner reads the record only once `arrived` shows this side's post
+    const bool eager = side == 0 && !req && eager_try(w, st, rec, mine, &rc);
+    if (!eager) rc = do_post(w, st, &rec->d->ready[side], rec->dv);
     rec->arrived.fetch_or(side == 0 ? ARR_S : ARR_R, std::memory_order_release);
     host_notify(&rec->arrived);
     if (rc) {
@@ -848,6 +909,10 @@ int p2p_queue(mpixs_comm_s *c, int side, const void *buf, int count, const TypeO
         mpixs_world_abort(reinterpret_cast<mpixs_world>(w));
         delete r;
         return rc;
+    }
+    if (eager) {
+        rec_release(ch, rec);   // nothing of the send waits for its receive
+        return MPIXS_SUCCESS;
     }
     if (!r) return complete_first(w, st, ch, rec, 0, side, status);
     r->comm = c;
@@ -940,22 +1005,7 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
         const StatusVal sv = match_status(S, R, tag);
         const bool recv_here = side == 1;
         if (rec->eager) {
-            // an eager send: copy from its staging once the sender's pack has
-            // published ready; the copy frees the staging slot and, when the
-            // channel is quiescent, is its block's last device use
-            w->eager_held.fetch_sub(1, std::memory_order_relaxed);
-            CopyExtra x;
-            if (rec->stage) x.host_flag = &w->stage.flags[rec->stage_flag];
-            const bool rel = want_release(ch, rec, k);
-            if (rel) {
-                x.rel_word = &w->h_rel[rec->didx];
-                x.rel_val = rec->dv;
-            }
-            rc = do_copy(w, st, rec->stage ? stage_side(rec->stage, S.bytes, S.rank) : S, R, sv,
-                         &rec->d->ready[0], rec->dv, &rec->d->done, rec->dv,
-                         req ? nullptr : static_cast<void *>(status), true, &x);
-            if (rc && rec->stage) stage_drop(w, rec->stage_flag);
-            else if (!rc && rel) note_release(w, ch, rec, k);
+            rc = eager_copy(w, st, ch, rec, k, sv, req ? nullptr : static_cast<void *>(status));
         } else {
             rc = do_copy(w, st, S, R, sv, &rec->d->ready[1 - side], rec->dv, &rec->d->done, rec->dv,
                          (recv_here && !req) ? static_cast<void *>(status) : nullptr, recv_here);
@@ -975,39 +1025,18 @@ int p2p(mpixs_comm_s *c, int side, const void *buf, int count, mpixs_datatype dt
         }
         return rc;
     }
-    uint8_t *stage = nullptr;
-    int flag = -1;
-    if (side == 0 && !req && me.bytes <= int64_t(w->cfg.eager_max_bytes) &&
-        w->eager_held.load(std::memory_order_relaxed) < int64_t(w->chan_cap / 2) &&
-        (me.bytes == 0 || stage_alloc(w, size_t(me.bytes), &stage, &flag))) {
-        // eager (a blocking send whose receive is not enqueued yet, which
-        // would otherwise hold this thread until it is): pack into staging on
-        // this stream, whose last workgroup publishes ready (an empty message
-        // only posts ready); the send is then complete in stream order and
-        // waits for nothing.  A nonblocking send keeps the rendezvous: its
-        // call returns at once anyway, and a post costs less than a pack.
-        if (stage) {
-            StatusVal pv{};
-            pv.count_bytes = me.bytes;
-            rc = do_copy(w, st, me, stage_side(stage, me.bytes, c->rank), pv, nullptr, 0,
-                         &rec->d->ready[0], rec->dv, nullptr, false);
-        } else {
-            rc = do_post(w, st, &rec->d->ready[0], rec->dv);
-        }
+    // a blocking send that arrives first: eager when it can be (a
+    // nonblocking send keeps the rendezvous: its call returns at once anyway,
+    // and a post costs less than a pack)
+    if (side == 0 && !req && eager_try(w, st, rec, me, &rc)) {
         if (rc) {
-            if (stage) stage_drop(w, flag);
             ch->seq[side] = k;   // nothing was enqueued: the call has no effect
             ch->mu.unlock();
             return rc;
         }
-        rec->eager = true;
-        rec->stage = stage;
-        rec->stage_flag = flag;
-        w->eager_held.fetch_add(1, std::memory_order_relaxed);
         rec->arrived.fetch_or(mine, std::memory_order_release);
         host_notify(&rec->arrived);
         ch->mu.unlock();
-        w->n_eager.fetch_add(1, std::memory_order_relaxed);
         rec_release(ch, rec);   // nothing of the send waits for its receive
         return MPIXS_SUCCESS;
     }

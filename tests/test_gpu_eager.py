@@ -7,7 +7,8 @@ so the call returns without waiting for its receiver:
 
 * blocking sends of every layout kind (contiguous, vector, irregular
   indexed, odd byte counts, an empty message, a second message on a
-  channel) all return before any receive is enqueued, from one host thread;
+  channel) all return before any receive is enqueued, from one host thread,
+  under both matching modes (sequence pairing, ordered queues);
   the receives that follow (one truncating, one of another basic type) give
   the oracle's bytes and statuses, and the statistics count every send as
   eager;
@@ -82,7 +83,7 @@ CASES = [
 ]
 
 
-def _program():
+def _program(matching):
     rng = np.random.default_rng(11)
     soff, roff, sends, recvs = 0, 0, [], []
     for i, (sc, st, rc, rt, tag) in enumerate(CASES):
@@ -92,19 +93,21 @@ def _program():
         roff += -(-max(1, _span(rt, rc)) // 256) * 256
     b0 = {"s": rng.integers(0, 256, soff, dtype=np.uint8)}
     b1 = {"r": np.full(roff, 0xEE, np.uint8)}
-    return Program(2, [b0, b1], [[sends], [recvs]], 1, name="eager-cases")
+    return Program(2, [b0, b1], [[sends], [recvs]], 1, name="eager-cases", matching=matching)
 
 
-def test_eager_blocking_sends_complete_before_their_receives():
+@pytest.mark.parametrize("matching", ["sequence", "queue"])
+def test_eager_blocking_sends_complete_before_their_receives(matching):
     import torch
     from paper_2208_13707_amd import driver as D
     from paper_2208_13707_amd import mpixs as M
-    _say(f"eager: {len(CASES)} blocking sends return before any receive; bytes and statuses vs the oracle")
-    p = _program()
+    _say(f"eager ({matching} matching): {len(CASES)} blocking sends return before any receive; "
+         "bytes and statuses vs the oracle")
+    p = _program(matching)
     ref = sim.run(p)
     assert not ref.deadlock and not any(ref.sync_errors)
     # a send that waited for its receive would time out here (one thread)
-    sess = D.Session(2, _cfg(timeout_ms=5000))
+    sess = D.Session(2, _cfg(timeout_ms=5000, matching=1 if matching == "queue" else 0))
     try:
         T = _Types(M)
         s = torch.from_numpy(p.buffers[0]["s"].copy()).cuda()
