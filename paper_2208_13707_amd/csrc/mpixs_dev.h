@@ -71,15 +71,20 @@ struct SegEnt {
 //   VEC:    c = u / upc, r = u % upc, b = r / bu, o = r % bu
 //           base + c * s_copy + b * s_blk + o * W
 //   SEG:    c = u / upc, rb = (u % upc) * W, i = last segment with pre <= rb
+//           (lut[rb >> shift] when the type has a granule table, else a
+//           binary search of the prefixes)
 //           base + c * s_copy + seg[i].off + (rb - seg[i].pre)
 struct DMap {
     uint64_t base;
     uint32_t kind;
     uint32_t upc;     // units per copy (VEC, SEG)
-    uint32_t bu;      // units per block (VEC)
+    uint32_t bu;      // VEC: units per block; SEG: log2 of the granule of lut
     uint32_t nseg;    // segments per copy (SEG)
     int64_t s_copy;   // bytes between copies
-    int64_t s_blk;    // bytes between blocks (VEC)
+    union {
+        int64_t s_blk;          // VEC: bytes between blocks
+        const uint32_t *lut;    // SEG: segment of each packed granule, or nullptr
+    };
     FastDiv d_upc;
     FastDiv d_bu;
     const SegEnt *seg;  // SEG table (nseg entries), in device memory
@@ -100,11 +105,17 @@ MPIXS_HD inline uint64_t map_addr(const DMap &m, uint64_t u) {
         const uint32_t u32 = uint32_t(u);
         const uint32_t c = fd_div(u32, m.d_upc);
         const int64_t rb = int64_t(u32 - c * m.upc) * W;
-        // last segment whose packed prefix is <= rb
-        uint32_t lo = 0, hi = m.nseg;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (m.seg[mid].pre <= rb) lo = mid; else hi = mid;
+        // last segment whose packed prefix is <= rb: one load of the granule
+        // table (units never straddle a granule), else a binary search
+        uint32_t lo = 0;
+        if (m.lut) {
+            lo = m.lut[uint64_t(rb) >> m.bu];
+        } else {
+            uint32_t hi = m.nseg;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (m.seg[mid].pre <= rb) lo = mid; else hi = mid;
+            }
         }
         const SegEnt e = m.seg[lo];
         return m.base + uint64_t(int64_t(c) * m.s_copy + e.off + (rb - e.pre));

@@ -207,6 +207,8 @@ void plan_map(const Side &sd, MapPlan &p) {
     p.m.s_copy = L.extent;
     p.m.seg = sd.t->table;
     p.m.nseg = uint32_t(sd.t->nseg);
+    p.m.lut = sd.t->lut;
+    p.m.bu = sd.t->lut_shift;
     int64_t g = int64_t(buf) | L.gcd;
     if (sd.count > 1) g |= L.extent;
     p.g = g;
@@ -3127,11 +3129,16 @@ int mpixs_debug_copy_plan(uint64_t sbuf, int scount, mpixs_datatype stype, uint6
     std::vector<SegEnt> tab_s, tab_r;
     host_table(ts, tab_s);
     host_table(tr, tab_r);
+    // host copies of the granule tables too, so the plan takes the same
+    // lookups as the kernels
+    std::vector<uint32_t> lut_s, lut_r;
     TypeObj cs = *ts, cr = *tr;
     cs.table = tab_s.data();
     cs.nseg = int64_t(tab_s.size());
+    cs.lut = (!cs.L.reg && seg_lut(cs.L, &lut_s, &cs.lut_shift)) ? lut_s.data() : nullptr;
     cr.table = tab_r.data();
     cr.nseg = int64_t(tab_r.size());
+    cr.lut = (!cr.L.reg && seg_lut(cr.L, &lut_r, &cr.lut_shift)) ? lut_r.data() : nullptr;
     Side S, R;
     S.buf = reinterpret_cast<const void *>(sbuf);
     S.count = scount;

@@ -42,8 +42,14 @@ struct TypeObj {
     bool committed = false;
     SegEnt *table = nullptr;   // SEG form: nseg entries in device memory
     int64_t nseg = 0;
+    // SEG form: the segment holding each packed granule of 2^lut_shift bytes
+    // of an element (device memory; nullptr for elements too large)
+    uint32_t *lut = nullptr;
+    uint32_t lut_shift = 0;
 };
 
+// Segment-lookup (granule) table of a SEG layout; false when too large.
+bool seg_lut(const Layout &L, std::vector<uint32_t> *lut, uint32_t *shift);
 // Returns nullptr unless `dt` names a committed datatype.
 const TypeObj *type_lookup(mpixs_datatype dt);
 // Any datatype, committed or not (nullptr if unknown).

@@ -27,6 +27,8 @@ namespace mpixs {
 namespace {
 
 constexpr int64_t kMaxSegs = int64_t(1) << 24;
+// granules of one element a segment-lookup table may map (16 MiB of table)
+constexpr int64_t kMaxLut = int64_t(1) << 22;
 
 // Handles index a fixed table that only grows; lookups take no lock (the
 // enqueue path looks a datatype up on every call, from every rank thread).
@@ -252,6 +254,30 @@ const TypeObj *type_lookup(mpixs_datatype dt) {
 
 const TypeObj *type_any(mpixs_datatype dt) { return any_type(dt); }
 
+// Granule table of a SEG layout: the packed bytes of one element in
+// granules of the largest power of two (<= 16) dividing every segment
+// length, each mapped to the index of its segment -- one load instead of a
+// binary search.  Any copy unit divides the segment lengths, so no unit
+// straddles a granule.  False for elements of more than kMaxLut granules
+// (they keep the search).
+bool seg_lut(const Layout &L, std::vector<uint32_t> *lut, uint32_t *shift) {
+    int64_t gl = 0;
+    for (const auto &sg : L.segs) gl = gcd64(gl, sg.second);
+    uint32_t s = 0;
+    while (s < 4 && gl > 0 && ((gl >> s) & 1) == 0) ++s;
+    const int64_t ngran = L.size >> s;
+    if (ngran <= 0 || ngran > kMaxLut) return false;
+    lut->assign(static_cast<size_t>(ngran), 0);
+    int64_t pre = 0;
+    for (size_t i = 0; i < L.segs.size(); ++i) {
+        for (int64_t b = pre >> s; b < (pre + L.segs[i].second) >> s; ++b)
+            (*lut)[size_t(b)] = uint32_t(i);
+        pre += L.segs[i].second;
+    }
+    *shift = s;
+    return true;
+}
+
 }  // namespace mpixs
 
 using namespace mpixs;
@@ -338,6 +364,19 @@ int mpixs_type_commit(mpixs_datatype *type) {
         }
         t->table = tab;
         t->nseg = n;
+        std::vector<uint32_t> lut;
+        uint32_t shift = 0;
+        if (seg_lut(t->L, &lut, &shift)) {
+            uint32_t *d = nullptr;
+            const size_t nb = lut.size() * sizeof(uint32_t);
+            if (hipMalloc(reinterpret_cast<void **>(&d), nb) == hipSuccess &&
+                hipMemcpy(d, lut.data(), nb, hipMemcpyHostToDevice) == hipSuccess) {
+                t->lut = d;
+                t->lut_shift = shift;
+            } else if (d) {
+                (void)hipFree(d);   // the search still works without it
+            }
+        }
     }
     t->committed = true;
     return MPIXS_SUCCESS;
