@@ -946,7 +946,9 @@ def bench_serve(args):
     """Config 5: 64 rank threads serve an open-loop Poisson stream of
     requests (60 % send/recv, 30 % isend+wait, 10 % allreduce-sum int32 over
     all ranks; bytes log-uniform 64 B .. 4 MiB) admitted under an 8 GB device
-    budget; arrival rate swept 1e4 .. 1e6 per second."""
+    budget; arrival rate swept 1e4 .. 1e6 per second.  Each rate is served
+    again through the host-synchronised calls on the same schedule, whose
+    results must be identical."""
     import numpy as np
     from paper_2208_13707_amd import driver as D
     from workloads import configs as C
@@ -955,30 +957,46 @@ def bench_serve(args):
     n = args.serve_ranks
     sess = D.Session(n)
     rates = [float(x) for x in args.serve_rates.split(",")]
+    sums = D.SERVE_RANK0_SUM if args.serve_sums == "rank0" else 0
     rows = []
     try:
-        rc, _, _ = sess.serve(C.serving_schedule(1e4, 64, nranks=n, seed=99), args.budget)
+        rc, _, _ = sess.serve(C.serving_schedule(1e4, 64, nranks=n, seed=99), args.budget,
+                              flags=sums)
         if rc:
             raise RuntimeError(f"serve warm-up failed: {rc}")
         for k, rate in enumerate(rates):
             nreq = int(min(args.serve_max, max(200, rate * args.serve_seconds)))
             sched = C.serving_schedule(rate, nreq, nranks=n, seed=k + 1)
-            rc, res, wall = sess.serve(sched, args.budget)
+            rc, res, wall = sess.serve(sched, args.budget, flags=sums)
             if rc:
                 raise RuntimeError(f"serve at rate {rate:g}: error {rc}")
             arr = np.array([q["arrival_us"] for q in sched])
             lat = res["done_us"] - arr
             wait = res["admit_us"] - arr
-            # sampled check of results (point-to-point requests; payloads are
-            # regenerated on the host from their published definition)
-            for i in range(0, nreq, max(1, nreq // 50)):
-                q = sched[i]
-                if q["kind"] == 2:
-                    continue
-                b = payload.fill(q["seed"], q["bytes"])
+            # sampled check of results: payloads are regenerated on the host
+            # from their published definition; an allreduce's expected output
+            # is the int32 sum (wrapping) of its ranks' payloads -- checked
+            # for up to three allreduces of at most 256 KiB per rate
+            def wsum(b):
                 j = np.arange(1, b.size + 1, dtype=np.uint64)
                 with np.errstate(over="ignore"):
-                    want = int((b.astype(np.uint64) * j).sum(dtype=np.uint64))
+                    return int((b.astype(np.uint64) * j).sum(dtype=np.uint64))
+            n_ar = 0
+            for i in list(range(0, nreq, max(1, nreq // 50))) + \
+                    [k for k, q in enumerate(sched) if q["kind"] == 2 and q["bytes"] <= 1 << 18]:
+                q = sched[i]
+                if q["kind"] == 2:
+                    if q["bytes"] > 1 << 18 or n_ar >= 3:
+                        continue
+                    n_ar += 1
+                    acc = np.zeros(q["bytes"] // 4, dtype=np.int32)
+                    with np.errstate(over="ignore"):
+                        for r in range(n):
+                            acc += payload.fill(q["seed"] + r, q["bytes"]).view(np.int32)
+                    # every rank's output is the sum: rank r weighted 2r + 1
+                    want = wsum(acc.view(np.uint8)) * (1 if sums else n * n) % (1 << 64)
+                else:
+                    want = wsum(payload.fill(q["seed"], q["bytes"]))
                 if int(res["checksum"][i]) != want:
                     raise AssertionError(f"request {i}: checksum differs")
             row = {"offered_per_s": rate, "requests": nreq,
@@ -987,12 +1005,31 @@ def bench_serve(args):
                    "p99_admission_wait_us": pct(wait, 99),
                    "gbps_payload": float(sum(q["bytes"] * (n if q["kind"] == 2 else 1)
                                              for q in sched)) / wall / 1e9}
+            if not args.no_host_synced:
+                # the comparison path on the same schedule: host-synchronised
+                # calls, every checksum equal to the enqueue path's
+                rc, hres, hwall = sess.serve(sched, args.budget, flags=sums | D.SERVE_HOST_SYNCED)
+                if rc:
+                    raise RuntimeError(f"host-synced serve at rate {rate:g}: error {rc}")
+                if not np.array_equal(hres["checksum"], res["checksum"]):
+                    raise AssertionError(f"rate {rate:g}: host-synced results differ")
+                hlat = hres["done_us"] - arr
+                hs = nreq / hwall if hwall > 0 else None
+                row["host_synced"] = {"served_per_s": hs, "p50_latency_us": pct(hlat, 50),
+                                      "p99_latency_us": pct(hlat, 99)}
+                row["speedup"] = (row["served_per_s"] / hs) if hs else None
             rows.append(row)
             log(f"[serve] offered {rate:9.0f}/s: served {row['served_per_s']:9.0f}/s, "
-                f"p50 {row['p50_latency_us']:8.1f} us, p99 {row['p99_latency_us']:9.1f} us")
+                f"p50 {row['p50_latency_us']:8.1f} us, p99 {row['p99_latency_us']:9.1f} us"
+                + (f"; host-synced {row['host_synced']['served_per_s']:9.0f}/s, "
+                   f"p50 {row['host_synced']['p50_latency_us']:8.1f} us, "
+                   f"p99 {row['host_synced']['p99_latency_us']:9.1f} us"
+                   if "host_synced" in row else ""))
     finally:
         close_checked(sess)
     best = max(rows, key=lambda r: r["served_per_s"] or 0)
+    hs_rates = [r["host_synced"]["served_per_s"] or 0 for r in rows if "host_synced" in r]
+    hs_best = max(hs_rates) if hs_rates else None
     return {
         "metric": "served requests/s with p50/p99 latency (open-loop Poisson arrivals)",
         "value": best["served_per_s"], "unit": "requests/s", "n_gpus": 1,
@@ -1001,6 +1038,12 @@ def bench_serve(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"serving_{n}ranks_mix60-30-10_64B-4MiB",
                    "budget_bytes": args.budget},
+        "host_synced": {"value": hs_best, "unit": "requests/s",
+                        "speedup": (best["served_per_s"] / hs_best) if hs_best else None},
+        "checked": ("sampled point-to-point requests and up to 3 allreduces of <= 256 KiB per "
+                    "rate against host-computed checksums (allreduce outputs checksummed on "
+                    + ("rank 0" if sums else "every rank") + "); host-synchronised results "
+                    "equal to the enqueue path's"),
         "sweep": rows,
     }
 
@@ -1288,9 +1331,10 @@ def bench_copy(args):
 
 
 def extra_configs(args):
-    """The allreduce configuration at 64 MiB per rank (float32 and int64) and
-    the ring-halo configuration (tag = step), each at its full size, for the
-    default line."""
+    """The allreduce configuration at 64 MiB per rank (float32 and int64), the
+    ring-halo configuration (tag = step), each at its full size, and the
+    serving configuration (64 ranks, 64 B .. 4 MiB, 8 GB budget) at an
+    unsaturated and a saturating arrival rate, for the default line."""
     import copy
     out = {}
     ar = {}
@@ -1321,6 +1365,16 @@ def extra_configs(args):
         "roofline_batch_kernel": h["roofline"]}
     log(f"[extra] halo plain enqueue {h['plain_enqueue']['value']:.0f} msgs/s, "
         f"host-synced {h['host_synced']['value']:.0f}")
+    a = copy.copy(args)
+    a.workload, a.serve_rates, a.serve_seconds = "serve", "1e4,1e6", 0.5
+    sv = bench_serve(a)
+    out["config5_serving_64ranks"] = {
+        "value": sv["value"], "unit": "requests/s", "host_synced": sv["host_synced"],
+        "budget_bytes": sv["config"]["budget_bytes"], "sweep": sv["sweep"],
+        "checked": sv["checked"]}
+    hs = sv["host_synced"]["value"]
+    log(f"[extra] serving 64 ranks: {sv['value']:.0f} requests/s, host-synced "
+        + (f"{hs:.0f}" if hs else "not run"))
     return out
 
 
@@ -1342,6 +1396,10 @@ def main():
     ap.add_argument("--serve-rates", default="1e4,3e4,1e5,3e5,1e6")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
     ap.add_argument("--serve-max", type=int, default=20000)
+    ap.add_argument("--serve-sums", choices=["all", "rank0"], default="rank0",
+                    help="serve: checksum rank 0's allreduce output (the harness's own "
+                         "verification; 64 checksum kernels per allreduce cost about 40 %% "
+                         "of the throughput) or every rank's")
     ap.add_argument("--budget", type=int, default=8 << 30)
     ap.add_argument("--pairs", type=int, default=10000)
     ap.add_argument("--only-grouped", action="store_true",

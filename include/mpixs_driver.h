@@ -139,11 +139,20 @@ typedef struct {
  * bytes, before they are checksummed, to capture_dev + capture[2k+1] (device
  * memory of the caller): the received bytes, or for an allreduce every
  * rank's output, rank r's at offset r * bytes.  capture may be NULL when
- * ncapture is 0. */
+ * ncapture is 0.
+ * flags: MPIXS_DRV_SERVE_HOST_SYNCED serves with the host-synchronised calls
+ * (mpixs_send / mpixs_recv for both point-to-point kinds, mpixs_allreduce),
+ * the comparison path of §2.4 with the same schedule, buffers and checksums,
+ * instead of the enqueue calls (send/recv_enqueue, isend_enqueue +
+ * wait_enqueue, allreduce_enqueue); MPIXS_DRV_SERVE_RANK0_SUM checksums an
+ * allreduce's output on rank 0 only (its checksum is then the fold's
+ * checksum) instead of on every rank.  Other bits: MPIXS_ERR_ARG. */
+#define MPIXS_DRV_SERVE_HOST_SYNCED 1
+#define MPIXS_DRV_SERVE_RANK0_SUM 2
 int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *comms,
                     void *const *streams, const mpixs_drv_req *reqs, int64_t nreq,
                     int64_t budget_bytes, mpixs_drv_req_result *results, double *wall_s,
-                    const int64_t *capture, int64_t ncapture, void *capture_dev);
+                    const int64_t *capture, int64_t ncapture, void *capture_dev, int flags);
 
 /* ------------------------------------------------ host message-rate model
  * A CPU-only analog of the paper's multithreaded message-rate measurement

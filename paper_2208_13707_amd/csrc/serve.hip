@@ -161,9 +161,12 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                                void *const *streams, const mpixs_drv_req *reqs, int64_t nreq,
                                int64_t budget_bytes, mpixs_drv_req_result *results,
                                double *wall_s, const int64_t *capture, int64_t ncapture,
-                               void *capture_dev) {
+                               void *capture_dev, int flags) {
+    const bool mode = (flags & MPIXS_DRV_SERVE_HOST_SYNCED) != 0;
+    const bool rank0_sum = (flags & MPIXS_DRV_SERVE_RANK0_SUM) != 0;
     if (!world || nranks <= 0 || !comms || !streams || nreq < 0 || nreq >= INT32_MAX ||
         (nreq > 0 && (!reqs || !results)) ||
+        (flags & ~(MPIXS_DRV_SERVE_HOST_SYNCED | MPIXS_DRV_SERVE_RANK0_SUM)) ||
         budget_bytes <= 0 || ncapture < 0 || (ncapture > 0 && (!capture || !capture_dev)))
         return MPIXS_ERR_ARG;
     std::vector<int64_t> cap_off(size_t(std::max<int64_t>(nreq, 0)), -1);
@@ -290,19 +293,22 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                 uint8_t *out = reinterpret_cast<uint8_t *>(base + each * size_t(nranks + r));
                 hipLaunchKernelGGL(k_fill, dim3(grid_for(q.bytes, 8)), dim3(256), 0, hs, in,
                                    q.bytes, q.seed + uint64_t(r));
-                rc = mpixs_allreduce_enqueue(in, out, int(q.bytes / 4), MPIXS_INT32, MPIXS_SUM, c);
+                rc = mode ? mpixs_allreduce(in, out, int(q.bytes / 4), MPIXS_INT32, MPIXS_SUM, c)
+                          : mpixs_allreduce_enqueue(in, out, int(q.bytes / 4), MPIXS_INT32, MPIXS_SUM,
+                                                    c);
                 if (!rc && cap_off[size_t(i)] >= 0 &&
                     hipMemcpyAsync(static_cast<char *>(capture_dev) + cap_off[size_t(i)] +
                                        size_t(r) * size_t(q.bytes),
                                    out, size_t(q.bytes), hipMemcpyDeviceToDevice, hs) != hipSuccess)
                     rc = MPIXS_ERR_GPU;
-                if (!rc) {
-                    // every rank checksums its own output; the last
-                    // workgroup of all ranks' launches publishes the sum
+                if (!rc && (!rank0_sum || r == 0)) {
+                    // every rank checksums its own output (or rank 0 alone);
+                    // the last workgroup of the launches publishes the sum
                     const int g = grid_for(q.bytes, 64);
+                    const uint64_t parts = rank0_sum ? 1 : uint64_t(nranks);
                     hipLaunchKernelGGL(k_checksum, dim3(g), dim3(256), 0, hs, out, q.bytes,
-                                       uint64_t(2 * r + 1), uint64_t(g) * uint64_t(nranks),
-                                       dsum + 2 * i, hsum + i, hflag + i);
+                                       rank0_sum ? uint64_t(1) : uint64_t(2 * r + 1),
+                                       uint64_t(g) * parts, dsum + 2 * i, hsum + i, hflag + i);
                 }
             } else {
                 uint8_t *sb = reinterpret_cast<uint8_t *>(base);
@@ -311,7 +317,9 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                 if (r == q.src) {
                     hipLaunchKernelGGL(k_fill, dim3(grid_for(q.bytes, 8)), dim3(256), 0, hs, sb,
                                        q.bytes, q.seed);
-                    if (q.kind == MPIXS_DRV_REQ_SENDRECV) {
+                    if (mode) {
+                        rc = mpixs_send(sb, int(q.bytes), MPIXS_UINT8, q.dst, tag, c);
+                    } else if (q.kind == MPIXS_DRV_REQ_SENDRECV) {
                         rc = mpixs_send_enqueue(sb, int(q.bytes), MPIXS_UINT8, q.dst, tag, c);
                     } else {
                         mpixs_request rq = nullptr;
@@ -320,7 +328,9 @@ extern "C" int mpixs_drv_serve(mpixs_world world, int nranks, const mpixs_comm *
                     }
                 }
                 if (!rc && r == q.dst) {
-                    if (q.kind == MPIXS_DRV_REQ_SENDRECV) {
+                    if (mode) {
+                        rc = mpixs_recv(rb, int(q.bytes), MPIXS_UINT8, q.src, tag, c, nullptr);
+                    } else if (q.kind == MPIXS_DRV_REQ_SENDRECV) {
                         rc = mpixs_recv_enqueue(rb, int(q.bytes), MPIXS_UINT8, q.src, tag, c,
                                                 nullptr);
                     } else {

@@ -135,16 +135,22 @@ RES_DTYPE = np.dtype([("admit_us", "<f8"), ("done_us", "<f8"), ("checksum", "<u8
                       ("error", "<i4"), ("pad", "<i4")])
 
 
+SERVE_HOST_SYNCED = 1   # MPIXS_DRV_SERVE_HOST_SYNCED
+SERVE_RANK0_SUM = 2     # MPIXS_DRV_SERVE_RANK0_SUM
+
+
 def mpixs_drv_serve(world, comms, streams, reqs: np.ndarray, budget_bytes: int,
-                    capture=None, capture_dev: int = 0):
+                    capture=None, capture_dev: int = 0, flags: int = 0):
     """Run the serving harness; returns (rc, results array, wall seconds).
-    capture: optional list of (request index, byte offset in capture_dev)."""
+    capture: optional list of (request index, byte offset in capture_dev);
+    flags: SERVE_HOST_SYNCED (host-synchronised calls instead of enqueue
+    calls), SERVE_RANK0_SUM (allreduces checksummed on rank 0 only)."""
     L = dlib()
     f = L.mpixs_drv_serve
     f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                   ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
-                  ctypes.c_int64, ctypes.c_void_p]
+                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_int]
     f.restype = ctypes.c_int
     n = len(comms)
     ca = (ctypes.c_void_p * n)(*comms)
@@ -155,7 +161,7 @@ def mpixs_drv_serve(world, comms, streams, reqs: np.ndarray, budget_bytes: int,
     cap = np.ascontiguousarray(np.array(capture or [], dtype=np.int64).reshape(-1))
     rc = f(world, n, ca, sa, reqs.ctypes.data, len(reqs), budget_bytes, res.ctypes.data,
            ctypes.byref(wall), cap.ctypes.data if cap.size else None, cap.size // 2,
-           capture_dev or None)
+           capture_dev or None, flags)
     return rc, res[: len(reqs)], wall.value
 
 
@@ -235,9 +241,9 @@ class Session:
                              self.hip_streams, mode=mode, nmarks=nmarks, max_reqs=max_reqs,
                              batches=self.batches)
 
-    def serve(self, sched, budget_bytes=8 << 30, capture=None, capture_dev=0):
+    def serve(self, sched, budget_bytes=8 << 30, capture=None, capture_dev=0, flags=0):
         return mpixs_drv_serve(self.world, self.comms, self.hip_streams, requests_array(sched),
-                               budget_bytes, capture, capture_dev)
+                               budget_bytes, capture, capture_dev, flags)
 
     def stats(self):
         return M.mpixs_world_get_stats(self.world)[1]

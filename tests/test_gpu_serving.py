@@ -1,5 +1,6 @@
 """Serving harness on the GPU: every request's result equals its expected
-value, alone and in the mix (requests admitted as memory frees up).
+value, alone and in the mix (requests admitted as memory frees up), and
+the host-synchronised comparison path gives the same results.
 
 The expected values come from the payload definition (SplitMix64 bytes) and
 the oracle's fold, computed on the host.  An allreduce request's checksum
@@ -60,6 +61,29 @@ def test_serving_results_alone_and_in_mix():
             q["arrival_us"] = 0.0
             rc, r1, _ = sess.serve([q], budget_bytes=4 << 20)
             assert rc == 0 and int(r1["checksum"][0]) == want[i]
+    finally:
+        sess.close()
+
+
+def test_serving_host_synced_path_gives_identical_results():
+    """The comparison path (host-synchronised calls, §2.4) on the same
+    schedule: every checksum equals the enqueue path's and the expected one."""
+    from paper_2208_13707_amd import driver as D
+    n = 16
+    sched = C.serving_schedule(rate=1e5, nreq=200, nranks=n, max_bytes=1 << 18, seed=5)
+    print(f"[gpu-case] serving {len(sched)} requests, 16 ranks, enqueue and host-synced",
+          file=sys.stderr, flush=True)
+    sess = D.Session(n)
+    try:
+        want = [expected(q, n) for q in sched]
+        got = {}
+        for mode in (0, D.SERVE_HOST_SYNCED):
+            rc, res, wall = sess.serve(sched, budget_bytes=64 << 20, flags=mode)
+            assert rc == 0, f"mode {mode}: {rc}"
+            assert np.all(res["error"] == 0)
+            got[mode] = [int(x) for x in res["checksum"]]
+            assert got[mode] == want, f"mode {mode}"
+        assert got[0] == got[D.SERVE_HOST_SYNCED]
     finally:
         sess.close()
 
