@@ -1193,6 +1193,37 @@ def bench_hostrate(args):
 
 
 # ---------------------------------------------------------------- pingpong
+def trace_breakdown(M, world, cap):
+    """Per-message step times from the device trace: the events of one
+    message share its channel block and counter value (POST and MATCH on the
+    first side's ready word, DONE and COMPLETE on done); p50/p99 of
+    POST -> MATCH (the other side reaching the message after it was posted),
+    MATCH -> DONE (the copy) and DONE -> COMPLETE (the first side seeing it),
+    in microseconds of device time."""
+    from collections import defaultdict
+    rc, total, ev = M.mpixs_world_trace(world, cap)
+    if rc:
+        raise RuntimeError(f"mpixs_world_trace: {M.errname(rc)}")
+    groups = defaultdict(dict)
+    for e in ev:
+        groups[(e.counter & ~63, e.value)].setdefault(e.kind, e)
+    steps = {"post_to_match_us": [], "match_to_done_us": [], "done_to_complete_us": []}
+    eager = 0
+    for g in groups.values():
+        if set(g) == {M.TRACE_POST, M.TRACE_MATCH, M.TRACE_DONE, M.TRACE_COMPLETE}:
+            t = [g[k].time_ns for k in (M.TRACE_POST, M.TRACE_MATCH, M.TRACE_DONE,
+                                        M.TRACE_COMPLETE)]
+            for name, a, b in (("post_to_match_us", 0, 1), ("match_to_done_us", 1, 2),
+                               ("done_to_complete_us", 2, 3)):
+                steps[name].append((t[b] - t[a]) / 1000.0)
+        elif set(g) == {M.TRACE_MATCH, M.TRACE_DONE}:
+            eager += 1      # an eager send's staged copy (its pack is a DONE of its own)
+    out = {"events": total, "messages": len(steps["post_to_match_us"]), "eager_copies": eager}
+    for name, xs in steps.items():
+        out[name] = {"p50": pct(xs, 50), "p99": pct(xs, 99)}
+    return out
+
+
 def bench_pingpong(args):
     import numpy as np
     import torch
@@ -1232,6 +1263,15 @@ def bench_pingpong(args):
             out["one_way_p99_us"] = pct(rtt, 99) / 2
         close_checked(sess)
         out[mode] = nmsg / sec
+    if args.trace:
+        # a separate traced pass: the per-message step times on the device
+        cfg = M.Config()
+        cfg.trace_events = 8 * nmsg
+        sess = D.Session(2, cfg)
+        run_checked(sess, ops(nmsg // 2, 0))
+        out["trace"] = trace_breakdown(M, sess.world, 8 * nmsg)
+        close_checked(sess)
+        log(f"[pingpong] trace: {json.dumps(out['trace'])}")
     assert np.array_equal(X[0].cpu().numpy(), p.buffers[0]["x"]), "echo changed the data"
     return {
         "metric": "enqueued msgs/s vs host-synced path; p50/p99 one-way latency",
@@ -1243,6 +1283,7 @@ def bench_pingpong(args):
                         "speedup": out[0] / out[1] if 1 in out else None},
         "latency_us": {"p50": out["one_way_p50_us"], "p99": out["one_way_p99_us"],
                        "of": "one-way (round trip / 2)"},
+        "trace": out.get("trace"),
     }
 
 
@@ -1396,6 +1437,9 @@ def main():
     ap.add_argument("--serve-rates", default="1e4,3e4,1e5,3e5,1e6")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
     ap.add_argument("--serve-max", type=int, default=20000)
+    ap.add_argument("--trace", action="store_true",
+                    help="pingpong: also a traced pass, with the per-message step times "
+                         "read from the device trace")
     ap.add_argument("--serve-sums", choices=["all", "rank0"], default="rank0",
                     help="serve: checksum rank 0's allreduce output (the harness's own "
                          "verification; 64 checksum kernels per allreduce cost about 40 %% "

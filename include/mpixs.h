@@ -158,7 +158,41 @@ typedef struct {
                                  table is held by eager messages, wait for their receive
                                  to be enqueued (rendezvous) [65536]; -1: never eager */
     int32_t eager_arena_mib;  /* device staging of eager sends, MiB [64] */
+    int32_t trace_events;     /* capacity of the device event trace (rounded up to a power
+                                 of two, at most 2^24; the newest events overwrite the
+                                 oldest), read by mpixs_world_trace; 0: no tracing [0] */
+    int32_t reserved[3];
 } mpixs_config;
+
+/* ------------------------------------------------------------------ tracing
+ * With mpixs_config.trace_events > 0 the kernels record, in a device ring,
+ * when each step of an operation happens on the GPU (§3.4: the operations
+ * run on the stream; these are their times there):
+ *   POST      a stream reached an operation and published it (a first side's
+ *             ready post, an allreduce or group arrival, a persistent run's
+ *             arrival);
+ *   MATCH     a stream's wait for its peer's post passed (the side that
+ *             copies or reduces; a persistent run's wait for the arrivals);
+ *   DONE      a copy, reduce or batch published its completion (also an eager
+ *             pack publishing its ready);
+ *   COMPLETE  a first side's wait for that completion passed.
+ * `counter` is the device address of the counter the step concerns (a
+ * channel's ready or done word, a collective line), `value` its value for
+ * this operation, so the steps of one message share (counter, value) pairs:
+ * POST and MATCH on the first side's ready word, DONE and COMPLETE on done.
+ * Recording costs one device atomic and one 32-byte store per event. */
+typedef struct {
+    uint64_t time_ns;     /* device wall clock, in ns */
+    uint32_t kind;        /* MPIXS_TRACE_* */
+    uint32_t stream;      /* device block index of the stream it happened on */
+    uint64_t counter;
+    uint64_t value;
+} mpixs_trace_event;
+
+#define MPIXS_TRACE_POST 1
+#define MPIXS_TRACE_MATCH 2
+#define MPIXS_TRACE_DONE 3
+#define MPIXS_TRACE_COMPLETE 4
 
 /* -------------------------------------------------------------- world (N ranks)
  * mpixs_world_create: make a world of nranks (1..4096) ranks on the current
@@ -517,6 +551,15 @@ typedef struct {
  * the streams to be idle (call after synchronising). */
 int mpixs_world_get_stats(mpixs_world w, mpixs_stats *stats);
 int mpixs_world_reset_stats(mpixs_world w);
+/* Copy the newest min(max, kept) recorded trace events, oldest first, into
+ * events[0 ..]; *copied receives how many were copied and *total the number
+ * recorded since the world was created, of which the ring keeps the last
+ * trace_events (rounded up to a power of two).  Call while the world's
+ * streams are idle (the copy does not order itself after their kernels).
+ * MPIXS_ERR_ARG when tracing is off, for a NULL copied or total, or a
+ * negative max (events may be NULL when max is 0). */
+int mpixs_world_trace(mpixs_world w, mpixs_trace_event *events, int64_t max, int64_t *copied,
+                      int64_t *total);
 const char *mpixs_error_string(int err);
 
 #ifdef __cplusplus

@@ -45,6 +45,8 @@ __global__ void __launch_bounds__(COPY_THREADS) k_copy(CopyArgs a) {
     }
     __syncthreads();
     if (FUSED && a.wait_ptr) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (FUSED && a.trace && a.wait_ptr && !s_fatal && blockIdx.x == 0 && threadIdx.x == 0)
+        trace_ev(a.me, MPIXS_TRACE_MATCH, a.wait_ptr, a.wait_target);
     if (!s_fatal) {
         const uint64_t n = a.units;
         constexpr uint64_t CH = uint64_t(COPY_THREADS) * COPY_UNROLL;
@@ -69,7 +71,10 @@ __global__ void __launch_bounds__(COPY_THREADS) k_copy(CopyArgs a) {
             const uint32_t fatal = ld_relaxed32(&a.me->fatal);
             if (a.status) write_status(a.status, a.st, fatal);
             if (!fatal && a.set_error && a.st.error) set_first_error(a.me, uint32_t(a.st.error));
-            if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+            if (a.done_ptr) {
+                st_release(a.done_ptr, a.done_val);
+                if (a.trace) trace_ev(a.me, MPIXS_TRACE_DONE, a.done_ptr, a.done_val);
+            }
             if (a.host_flag)
                 __hip_atomic_store(a.host_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             // release: the done store above lands before the host may hand

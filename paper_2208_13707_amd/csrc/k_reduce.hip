@@ -54,6 +54,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
         if (threadIdx.x == 0) s_fatal = ld_relaxed32(&a.me->fatal);
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (a.trace && !s_fatal && blockIdx.x == 0 && threadIdx.x == 0)
+            trace_ev(a.me, MPIXS_TRACE_MATCH, a.arrive, a.arrive_target);
     }
     if (!s_fatal) {
         const int n = a.n;
@@ -98,7 +100,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(ReduceArgs a) {
     }
     if constexpr (FUSED) {
         if (last_workgroup(a.me, a.ticket_last) && threadIdx.x == 0) {
-            if (a.done_ptr) st_release(a.done_ptr, a.done_val);
+            if (a.done_ptr) {
+                st_release(a.done_ptr, a.done_val);
+                if (a.trace) trace_ev(a.me, MPIXS_TRACE_DONE, a.done_ptr, a.done_val);
+            }
         }
     }
 }

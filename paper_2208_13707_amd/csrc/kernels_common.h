@@ -57,6 +57,23 @@ __device__ __forceinline__ void set_fatal(DevStream *s, uint32_t e) {
 // one acquire fence follows success.  An acquire load in every poll would
 // invalidate caches on each iteration, under the feet of the kernels that
 // run beside the waiting wave.
+// One trace event from a stream's kernel: a slot of the world's ring by a
+// device-wide counter, then one store of the record.
+__device__ __forceinline__ void trace_ev(DevStream *me, uint32_t kind, const void *counter,
+                                         uint64_t value) {
+    TraceEv *ring = me->trace;
+    if (!ring) return;
+    const uint64_t i = __hip_atomic_fetch_add(me->trace_head, uint64_t(1), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    TraceEv e;
+    e.ticks = wall_clock64();
+    e.kind = kind;
+    e.stream = me->slot;
+    e.counter = reinterpret_cast<uint64_t>(counter);
+    e.value = value;
+    ring[i & me->trace_mask] = e;
+}
+
 __device__ uint32_t spin_wait(const uint64_t *p, uint64_t target, const WaitCtl &ctl) {
     if (ld_relaxed64(p) >= target) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

@@ -129,11 +129,27 @@ struct alignas(64) DevChan {
     uint64_t pad[5];
 };
 
+// One event of the device trace (the public record, with ticks in place of
+// nanoseconds).
+struct TraceEv {
+    uint64_t ticks;
+    uint32_t kind;
+    uint32_t stream;
+    uint64_t counter;
+    uint64_t value;
+};
+
 struct alignas(128) DevStream {
     uint32_t first_error;  // first asynchronous error of this stream (0: none)
     uint32_t fatal;        // non-zero: a wait gave up; later data movement is skipped
     uint64_t ticket;       // completion tickets of multi-workgroup kernels
-    uint64_t pad[14];
+    // the world's trace ring (written once at world creation); kernels read
+    // it only when their arguments ask for an event
+    TraceEv *trace;
+    uint64_t *trace_head;
+    uint32_t trace_mask;
+    uint32_t slot;         // this block's index
+    uint64_t pad[11];
 };
 
 // -------------------------------------------------------------- arguments
@@ -158,7 +174,7 @@ struct WaitArgs {
     const uint64_t *ptr[64];
     uint64_t target[64];
     int32_t n;
-    int32_t pad;
+    uint32_t trace;         // trace kind each passing lane records (0: none)
     WaitCtl ctl;
     DevStream *me;          // stream the kernel runs on
     void *status;           // optional receive status to write after the wait
@@ -183,7 +199,7 @@ struct CopyArgs {
     void *status;                 // optional receive status
     StatusVal st;
     int32_t set_error;            // copy st.error into me->first_error
-    int32_t pad;
+    uint32_t trace;               // fused: record MATCH after the wait, DONE at publish
     // fused only, after done: a host-pinned word set to 1 (the host may
     // recycle what the kernel read), and a host-pinned release word set to
     // rel_val (the kernel was the last device use of a channel block)
@@ -207,6 +223,8 @@ struct SignalArgs {
     uint32_t *host_flag;
     uint64_t *rel_word;
     uint64_t rel_val;
+    uint32_t trace;         // record DONE
+    uint32_t pad;
 };
 
 // Relative wait of a persistent batch: lane q < n (bit q of skip clear)
@@ -221,6 +239,8 @@ struct RelWaitArgs {
     uint32_t stride;        // in uint64_t words
     WaitCtl ctl;
     DevStream *me;
+    uint32_t trace;         // record MATCH per passing lane
+    uint32_t pad;
 };
 
 // ----------------------------------------------------------------- batches
@@ -255,6 +275,7 @@ struct BatchStart {
 };
 
 static_assert(sizeof(BatchDesc) % 16 == 0, "descriptors are fetched in 16-byte words");
+static_assert(sizeof(DevStream) == 128, "one stream block per 128 bytes");
 
 struct BatchArgs {
     const BatchDesc *desc;
@@ -283,6 +304,8 @@ struct ReduceArgs {
     uint64_t done_val;
     DevStream *me;
     uint64_t ticket_last;
+    uint32_t trace;               // fused: record MATCH after the arrivals, DONE at publish
+    uint32_t pad;
 };
 
 // Several small reductions of one element type and operator in one launch

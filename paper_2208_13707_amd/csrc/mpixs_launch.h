@@ -7,7 +7,7 @@
 
 namespace mpixs {
 
-hipError_t launch_post(hipStream_t s, uint64_t *p, uint64_t v);
+hipError_t launch_post(hipStream_t s, uint64_t *p, uint64_t v, DevStream *tr);   // tr: POST event (nullptr: none)
 hipError_t launch_wait(hipStream_t s, const WaitArgs &a);
 hipError_t launch_signal(hipStream_t s, const SignalArgs &a);
 hipError_t launch_copy(hipStream_t s, const CopyArgs &a, int w, int nwg, bool fused);
@@ -24,7 +24,7 @@ hipError_t launch_reduce_multi(hipStream_t s, const MultiRedArgs &a, int basic, 
 int reduce_multi_units(bool nt);     // vectors (or elements) per workgroup of launch_reduce_multi
 hipError_t launch_batch(hipStream_t s, const BatchArgs &a, int nwg);
 bool batch_tile_ok(uint32_t tile);   // a tile size the batch kernel is built for
-hipError_t launch_post_inc(hipStream_t s, uint64_t *p);
+hipError_t launch_post_inc(hipStream_t s, uint64_t *p, DevStream *tr);
 const void *wait_rel_kernel();        // kernel handles for graph nodes
 const void *signal_kernel();
 hipError_t launch_wait_rel(hipStream_t s, const RelWaitArgs &a);

@@ -288,14 +288,22 @@ StatusVal match_status(const Side &s, const Side &r, int tag) {
 }
 
 // ------------------------------------------------------------- launchers
+// The stream block a kernel records trace events through, or nullptr when
+// the world does not trace; and a trace kind, or 0 when it does not.
+DevStream *trace_of(const World *w, const StreamObj *st) { return w->d_trace ? st->dev : nullptr; }
+uint32_t trace_kind(const World *w, uint32_t kind) { return w->d_trace ? kind : 0; }
+
 int do_post(World *w, StreamObj *st, uint64_t *p, uint64_t v) {
     w->n_post.fetch_add(1, std::memory_order_relaxed);
-    return gpu_err(launch_post(st->hs, p, v));
+    return gpu_err(launch_post(st->hs, p, v, trace_of(w, st)));
 }
 
-int do_wait(World *w, StreamObj *st, WaitArgs &a) {
+// kind: what a passing lane records (MPIXS_TRACE_MATCH for a wait on a
+// peer's post, MPIXS_TRACE_COMPLETE for a wait on a completion)
+int do_wait(World *w, StreamObj *st, WaitArgs &a, uint32_t kind) {
     a.ctl = ctl_of(w);
     a.me = st->dev;
+    a.trace = trace_kind(w, kind);
     w->n_wait.fetch_add(1, std::memory_order_relaxed);
     return gpu_err(launch_wait(st->hs, a));
 }
@@ -353,6 +361,7 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
         a.status = status;
         a.st = st;
         a.set_error = set_error ? 1 : 0;
+        a.trace = trace_kind(w, 1);
         if (x) {
             a.host_flag = x->host_flag;
             a.rel_word = x->rel_word;
@@ -367,7 +376,7 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
         // wait kernel, full-grid data kernel, signal kernel
         if (wait_ptr) {
             WaitArgs wa = wait_one(wait_ptr, wait_target);
-            rc = do_wait(w, on, wa);
+            rc = do_wait(w, on, wa, MPIXS_TRACE_MATCH);
             if (rc) return rc;
         }
         if (units > 0) {
@@ -386,6 +395,7 @@ int do_copy(World *w, StreamObj *on, const Side &S, const Side &R, const StatusV
             sg.status = status;
             sg.st = st;
             sg.set_error = set_error ? 1 : 0;
+            sg.trace = trace_kind(w, 1);
             if (x) {
                 sg.host_flag = x->host_flag;
                 sg.rel_word = x->rel_word;
@@ -716,7 +726,7 @@ int complete_first(World *w, StreamObj *st, Channel *ch, Rec *rec, uint64_t k, i
         a.rel_base = w->h_rel;
         a.rel_idx[0] = rec->didx + 1;
     }
-    rc = do_wait(w, st, a);
+    rc = do_wait(w, st, a, MPIXS_TRACE_COMPLETE);
     if (!rc && rel) note_release(w, ch, rec, k);
     rec_release(ch, rec);
     return rc;
@@ -1098,7 +1108,7 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
             std::memset(&s, 0, sizeof(s));
             s.status = status;
             s.st = r->st;
-            rc = do_wait(w, st, s);
+            rc = do_wait(w, st, s, 0);
         }
     }
     // first-side requests: host-wait for each copy launch, then one wait
@@ -1108,7 +1118,7 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
     std::vector<std::pair<int, mpixs_request_s *>> batch;
     auto flush = [&]() -> int {
         if (a.n == 0) return MPIXS_SUCCESS;
-        int r2 = do_wait(w, st, a);
+        int r2 = do_wait(w, st, a, MPIXS_TRACE_COMPLETE);
         for (size_t j = 0; j < batch.size(); ++j) {
             mpixs_request_s *q = batch[j].second;
             if (!q->rec) continue;
@@ -1144,7 +1154,7 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
                 s.status = status;
                 s.st = r->st;
                 rc = flush();
-                if (!rc) rc = do_wait(w, st, s);
+                if (!rc) rc = do_wait(w, st, s, 0);
             }
             continue;
         }
@@ -1159,7 +1169,7 @@ int wait_many(int n, mpixs_request *reqs, mpixs_status *statuses, bool array_sta
             const bool rel = lane_of(s, r);
             s.status = status;
             s.st = r->rec->st;
-            rc = do_wait(w, st, s);
+            rc = do_wait(w, st, s, MPIXS_TRACE_COMPLETE);
             if (!rc && rel) note_release(w, r->ch, r->rec, r->k);
             rec_release(r->ch, r->rec);
             r->rec = nullptr;
@@ -1233,6 +1243,7 @@ int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64
         a.done_ptr = done_ptr;
         a.done_val = done_val;
         a.ticket_last = on->tickets + nwg - 1;
+        a.trace = trace_kind(w, 1);
         if (profile_on(w)) prof_begin(w, on->hs, &e0);
         rc = gpu_err(launch_reduce(on->hs, a, rec->dtype, rec->op, vec, int(nwg), true));
         if (profile_on(w)) prof_end(w, on->hs, e0, 1);
@@ -1248,7 +1259,7 @@ int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64
                 wa.target[wa.n] = target;
                 wa.n++;
             }
-            rc = do_wait(w, on, wa);
+            rc = do_wait(w, on, wa, MPIXS_TRACE_MATCH);
             if (rc) return rc;
         }
         const bool fixed = vec && reduce_fixed_ok(n);
@@ -1265,6 +1276,7 @@ int do_reduce(World *w, StreamObj *on, CollRec *rec, int n, int me, const uint64
             sg.done_ptr = done_ptr;
             sg.done_val = done_val;
             sg.me = on->dev;
+            sg.trace = trace_kind(w, 1);
             rc = gpu_err(launch_signal(on->hs, sg));
             if (rc) return rc;
             w->n_post.fetch_add(1, std::memory_order_relaxed);
@@ -1692,7 +1704,7 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
             wa.target[wa.n] = g + 1;
             wa.n++;
         }
-        rc = do_wait(w, st, wa);
+        rc = do_wait(w, st, wa, MPIXS_TRACE_MATCH);
         if (rc) return rc;
     }
     int flag = -1;
@@ -1759,6 +1771,7 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     sg.done_ptr = done;
     sg.done_val = g + 1;
     sg.me = st->dev;
+    sg.trace = trace_kind(w, 1);
     sg.host_flag = flag >= 0 ? &w->h_flags[flag] : nullptr;
     rc = gpu_err(launch_signal(st->hs, sg));
     if (rc) return fail(rc);
@@ -1834,6 +1847,7 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     P->lwait.delta = 1;
     P->lwait.ctl = ctl_of(w);
     P->lwait.me = st->dev;
+    P->lwait.trace = trace_kind(w, MPIXS_TRACE_MATCH);
     // done + 1 after the batch kernel: the kernel boundary makes its stores
     // visible, so one release store publishes the run (a release in every
     // workgroup instead costs an L2 writeback each and was measured several
@@ -1842,6 +1856,7 @@ int batch_create(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     P->sig.done_ptr = P->d_ctr + 16 * n;
     P->sig.inc = 1;
     P->sig.me = st->dev;
+    P->sig.trace = trace_kind(w, 1);
     if (w->cfg.batch_sync == 1 && !static_mem) {
         // event dependencies instead of counters: rank q records post_ev[q]
         // after its prior work, the leader's stream waits for those, runs the
@@ -1984,7 +1999,7 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
         c.batch_graph < 0 || c.batch_graph > 1 || c.batch_nontemporal < 0 ||
         c.batch_nontemporal > 2 || c.matching < 0 || c.matching > 1 || c.batch_sync < 0 ||
         c.batch_sync > 1 || (c.batch_sync == 1 && c.batch_graph == 1) || c.eager_max_bytes < -1 ||
-        c.eager_arena_mib > 65536) {
+        c.eager_arena_mib > 65536 || c.trace_events < 0 || c.trace_events > (1 << 24)) {
         delete w;
         return MPIXS_ERR_ARG;
     }
@@ -1997,6 +2012,7 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
         rate_khz <= 0)
         rate_khz = 100000;
     w->timeout_ticks = uint64_t(c.timeout_ms) * uint64_t(rate_khz);
+    w->trace_rate_khz = rate_khz;
     static_batch_setup(w->device);
 
     w->stream_cap = std::max(1024, 4 * c.max_streams);
@@ -2024,6 +2040,35 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
         return MPIXS_ERR_NOMEM;
     }
     w->d_streams = reinterpret_cast<DevStream *>(w->d_pool);
+    if (c.trace_events > 0) {
+        // the ring, and every stream block pointing at it (blocks are only
+        // ever handed out from this pool, so this is done once)
+        w->trace_cap = 1;
+        while (w->trace_cap < uint64_t(c.trace_events)) w->trace_cap <<= 1;
+        std::vector<DevStream> blocks(static_cast<size_t>(w->stream_cap));
+        bool ok = hipMalloc(reinterpret_cast<void **>(&w->d_trace), w->trace_cap * sizeof(TraceEv)) ==
+                      hipSuccess &&
+                  hipMalloc(reinterpret_cast<void **>(&w->d_trace_head), sizeof(uint64_t)) ==
+                      hipSuccess &&
+                  hipMemset(w->d_trace_head, 0, sizeof(uint64_t)) == hipSuccess;
+        for (size_t i = 0; ok && i < blocks.size(); ++i) {
+            std::memset(&blocks[i], 0, sizeof(DevStream));
+            blocks[i].trace = w->d_trace;
+            blocks[i].trace_head = w->d_trace_head;
+            blocks[i].trace_mask = uint32_t(w->trace_cap - 1);
+            blocks[i].slot = uint32_t(i);
+        }
+        ok = ok && hipMemcpy(w->d_streams, blocks.data(), blocks.size() * sizeof(DevStream),
+                             hipMemcpyHostToDevice) == hipSuccess;
+        if (!ok) {
+            if (w->d_trace) (void)hipFree(w->d_trace);
+            if (w->d_trace_head) (void)hipFree(w->d_trace_head);
+            if (w->stage.base) (void)hipFree(w->stage.base);
+            (void)hipFree(w->d_pool);
+            delete w;
+            return MPIXS_ERR_NOMEM;
+        }
+    }
     w->d_chans = reinterpret_cast<DevChan *>(w->d_pool + s_bytes);
     w->d_coll = reinterpret_cast<uint64_t *>(w->d_pool + s_bytes + c_bytes);
     if (c.batch_arena_mib <= 0) c.batch_arena_mib = 64;
@@ -2043,6 +2088,8 @@ int mpixs_world_create(int nranks, const mpixs_config *cfg, mpixs_world *out) {
                       sizeof(uint32_t) * size_t(w->stage.nflags), hipHostMallocCoherent) != hipSuccess) {
         (void)hipFree(w->d_pool);
         if (w->stage.base) (void)hipFree(w->stage.base);
+        if (w->d_trace) (void)hipFree(w->d_trace);
+        if (w->d_trace_head) (void)hipFree(w->d_trace_head);
         if (w->h_abort) (void)hipHostFree(w->h_abort);
         if (w->h_arena) (void)hipHostFree(w->h_arena);
         if (w->h_flags) (void)hipHostFree(w->h_flags);
@@ -2106,6 +2153,8 @@ int mpixs_world_free(mpixs_world *pw) {
     (void)hipHostFree(w->h_rel);
     if (w->stage.base) (void)hipFree(w->stage.base);
     (void)hipHostFree(w->stage.flags);
+    if (w->d_trace) (void)hipFree(w->d_trace);
+    if (w->d_trace_head) (void)hipFree(w->d_trace_head);
     for (auto *h : w->world_handles) delete h;
     delete w->world_sh;
     delete w;
@@ -2691,7 +2740,7 @@ int mpixs_allreduce_enqueue(const void *sendbuf, void *recvbuf, int count, mpixs
         if (!rc) rc = host_wait(w, &rec->reduce_enq, [&] { return rec->reduce_enq.load(std::memory_order_acquire) != 0; });
         if (!rc) {
             WaitArgs a = wait_one(done, k + 1);
-            rc = do_wait(w, st, a);
+            rc = do_wait(w, st, a, MPIXS_TRACE_COMPLETE);
         }
     }
     if (rec->refs.fetch_sub(1) == 1) {
@@ -2765,7 +2814,7 @@ int group_finish(mpixs_comm c, int kind, BatchPlan **plan) {
         if (!rc) rc = rec->error;
         if (!rc && kind == 1) {
             WaitArgs a = wait_one(sh->d_grp + 16 * n, g + 1);
-            rc = do_wait(w, st, a);
+            rc = do_wait(w, st, a, MPIXS_TRACE_COMPLETE);
         }
     }
     if (!rc && kind >= 2) *plan = rec->batch;
@@ -2873,7 +2922,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
         }
     } else {
         if (P->done_ev) rc = gpu_err(hipEventRecord(P->post_ev[size_t(b->rank)], st->hs));
-        else rc = gpu_err(launch_post_inc(st->hs, P->d_ctr + 16 * b->rank));
+        else rc = gpu_err(launch_post_inc(st->hs, P->d_ctr + 16 * b->rank, trace_of(w, st)));
         if (rc) return rc;
         P->posted[b->rank].store(e, std::memory_order_release);
         host_notify(&P->posted[b->rank]);
@@ -2893,6 +2942,7 @@ int mpixs_batch_start_enqueue(mpixs_batch b) {
             a.base = P->d_ctr + 16 * b->rank;
             a.ctl = ctl_of(w);
             a.me = st->dev;
+            a.trace = trace_kind(w, MPIXS_TRACE_COMPLETE);
             rc = gpu_err(launch_wait_rel(st->hs, a));
             w->n_wait.fetch_add(1, std::memory_order_relaxed);
         }
@@ -3078,6 +3128,36 @@ int mpixs_world_get_stats(mpixs_world w, mpixs_stats *s) {
     s->copy_ms = w->copy_ms;
     s->timed_reduce = w->timed_reduce;
     s->reduce_ms = w->reduce_ms;
+    return MPIXS_SUCCESS;
+}
+
+int mpixs_world_trace(mpixs_world w, mpixs_trace_event *events, int64_t max, int64_t *copied,
+                      int64_t *total) {
+    if (!w || !w->d_trace || !copied || !total || max < 0 || (max > 0 && !events))
+        return MPIXS_ERR_ARG;
+    *copied = 0;
+    uint64_t head = 0;
+    if (hipMemcpy(&head, w->d_trace_head, sizeof(head), hipMemcpyDeviceToHost) != hipSuccess)
+        return MPIXS_ERR_GPU;
+    *total = int64_t(head);
+    // the last min(head, cap, max) events, oldest first
+    const uint64_t kept = std::min<uint64_t>(head, w->trace_cap);
+    const uint64_t n = std::min<uint64_t>(kept, uint64_t(max));
+    if (n == 0) return MPIXS_SUCCESS;
+    *copied = int64_t(n);
+    std::vector<TraceEv> ring(static_cast<size_t>(w->trace_cap));
+    if (hipMemcpy(ring.data(), w->d_trace, ring.size() * sizeof(TraceEv), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return MPIXS_ERR_GPU;
+    const double ns_per_tick = 1e6 / double(w->trace_rate_khz);
+    for (uint64_t j = 0; j < n; ++j) {
+        const TraceEv &e = ring[size_t((head - n + j) & (w->trace_cap - 1))];
+        events[j].time_ns = uint64_t(double(e.ticks) * ns_per_tick);
+        events[j].kind = e.kind;
+        events[j].stream = e.stream;
+        events[j].counter = e.counter;
+        events[j].value = e.value;
+    }
     return MPIXS_SUCCESS;
 }
 

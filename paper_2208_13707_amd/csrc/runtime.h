@@ -483,6 +483,11 @@ struct World {
         std::vector<int> free_flags;
     } stage;
     std::atomic<uint64_t> n_eager{0};
+    // device trace ring (trace_events > 0): events and the slot counter
+    TraceEv *d_trace = nullptr;
+    uint64_t *d_trace_head = nullptr;
+    uint64_t trace_cap = 0;
+    int trace_rate_khz = 0;
     // eager messages whose receive is not enqueued yet: each holds its
     // channel's block until then, so they may take at most half the pool
     // (the rest serves rendezvous, whose waits bound what is in flight)

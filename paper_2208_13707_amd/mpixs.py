@@ -44,7 +44,8 @@ class Config(ctypes.Structure):
                 ("batch_tile", ctypes.c_int32), ("batch_max_wg", ctypes.c_int32),
                 ("batch_graph", ctypes.c_int32), ("batch_nontemporal", ctypes.c_int32),
                 ("matching", ctypes.c_int32), ("batch_sync", ctypes.c_int32),
-                ("eager_max_bytes", ctypes.c_int32), ("eager_arena_mib", ctypes.c_int32)]
+                ("eager_max_bytes", ctypes.c_int32), ("eager_arena_mib", ctypes.c_int32),
+                ("trace_events", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Status(ctypes.Structure):
@@ -53,6 +54,14 @@ class Status(ctypes.Structure):
 
 
 STATUS_BYTES = ctypes.sizeof(Status)
+
+
+class TraceEvent(ctypes.Structure):
+    _fields_ = [("time_ns", ctypes.c_uint64), ("kind", ctypes.c_uint32),
+                ("stream", ctypes.c_uint32), ("counter", ctypes.c_uint64), ("value", ctypes.c_uint64)]
+
+
+TRACE_POST, TRACE_MATCH, TRACE_DONE, TRACE_COMPLETE = 1, 2, 3, 4
 
 
 class Stats(ctypes.Structure):
@@ -123,6 +132,8 @@ SIGNATURES = {
     "mpixs_allreduce": [_vp, _vp, _i, ctypes.c_int32, ctypes.c_int32, _vp],
     "mpixs_world_get_stats": [_vp, ctypes.POINTER(Stats)],
     "mpixs_world_reset_stats": [_vp],
+    "mpixs_world_trace": [_vp, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64)],
     "mpixs_error_string": [_i],
 }
 
@@ -417,6 +428,17 @@ def mpixs_world_get_stats(world):
     s = Stats()
     rc = lib().mpixs_world_get_stats(world, ctypes.byref(s))
     return rc, s
+
+
+def mpixs_world_trace(world, max_events: int):
+    """(rc, total recorded, list of TraceEvent) -- the newest max_events."""
+    buf = (TraceEvent * max(1, max_events))()
+    copied = ctypes.c_int64()
+    total = ctypes.c_int64()
+    rc = lib().mpixs_world_trace(world, buf, max_events, ctypes.byref(copied), ctypes.byref(total))
+    if rc:
+        return rc, 0, []
+    return rc, total.value, [buf[i] for i in range(copied.value)]
 
 
 def mpixs_world_reset_stats(world):

@@ -169,7 +169,7 @@ std::mutex g_region_mu;
 int g_k_wait_rel, g_k_signal;
 }  // namespace
 
-hipError_t launch_post(hipStream_t, uint64_t *, uint64_t) { return counted(); }
+hipError_t launch_post(hipStream_t, uint64_t *, uint64_t, DevStream *) { return counted(); }
 hipError_t launch_wait(hipStream_t, const WaitArgs &a) {
     // the wait "has passed": its releasing lanes write their release words
     if (a.rel_base)
@@ -201,7 +201,7 @@ hipError_t launch_reduce_multi(hipStream_t, const MultiRedArgs &, int, int, int,
 int reduce_multi_units(bool nt) { return 256 * (nt ? 2 : 1); }
 hipError_t launch_batch(hipStream_t, const BatchArgs &, int) { return counted(); }
 bool batch_tile_ok(uint32_t t) { return t == 256 || t == 512 || t == 1024 || t == 2048 || t == 4096; }
-hipError_t launch_post_inc(hipStream_t, uint64_t *) { return counted(); }
+hipError_t launch_post_inc(hipStream_t, uint64_t *, DevStream *) { return counted(); }
 const void *wait_rel_kernel() { return &g_k_wait_rel; }
 const void *signal_kernel() { return &g_k_signal; }
 hipError_t launch_wait_rel(hipStream_t, const RelWaitArgs &) { return counted(); }

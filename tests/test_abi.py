@@ -103,6 +103,7 @@ def test_structs_match_the_header(tmp_path):
     from paper_2208_13707_amd import driver as D
     from paper_2208_13707_amd import mpixs as M
     ct = [("mpixs_config", M.Config), ("mpixs_status", M.Status), ("mpixs_stats", M.Stats),
+          ("mpixs_trace_event", M.TraceEvent),
           ("mpixs_drv_thread", D.DrvThread), ("mpixs_drv_result", D.DrvResult)]
     npy = [("mpixs_drv_op", D.OP_DTYPE), ("mpixs_drv_req", D.REQ_DTYPE),
            ("mpixs_drv_req_result", D.RES_DTYPE)]
