@@ -363,9 +363,12 @@ def bench_halo(args):
         res = {"count": count, "payload_bytes": payload}
         # ---- enqueue path: warmup, then K timed steps
         pc = None
-        if args.fuse_max_bytes is not None:
+        if args.fuse_max_bytes is not None or args.trace:
             pc = M.Config()
-            pc.fuse_max_bytes = args.fuse_max_bytes
+            if args.fuse_max_bytes is not None:
+                pc.fuse_max_bytes = args.fuse_max_bytes
+            if args.trace:
+                pc.trace_events = 1 << 16
         sess = D.Session(n, pc)
         ops = [halo_ops(D, r, n, A[r], H[r], vt, warm, 0, 0) for r in range(n)]
         run_checked(sess, ops)
@@ -380,6 +383,11 @@ def bench_halo(args):
                    gbps_algorithmic=2 * msgs * payload / sec / 1e9,
                    kernels_per_msg=(st.kernels_post + st.kernels_wait + st.kernels_copy) /
                    max(1, 16 * (steps + warm)))
+        if args.trace:
+            # the timed steps' messages, one by one on the device (the ring
+            # holds the last 16,384 messages: all of the timed steps')
+            res["trace"] = trace_breakdown(M, sess.world, min(1 << 16, 4 * 16 * steps))
+            log(f"[halo] count={count} trace: {json.dumps(res['trace'])}")
         # ---- latency pass (HIP events at step boundaries on every stream)
         ops = [halo_ops(D, r, n, A[r], H[r], vt, steps, 0, 0, marks=True) for r in range(n)]
         _, marks = run_checked(sess, ops, nmarks=2 * steps)
@@ -1438,8 +1446,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=0.5)
     ap.add_argument("--serve-max", type=int, default=20000)
     ap.add_argument("--trace", action="store_true",
-                    help="pingpong: also a traced pass, with the per-message step times "
-                         "read from the device trace")
+                    help="pingpong: also a traced pass; halo: trace the plain path's timed "
+                         "steps (per-message step times read from the device trace)")
     ap.add_argument("--serve-sums", choices=["all", "rank0"], default="rank0",
                     help="serve: checksum rank 0's allreduce output (the harness's own "
                          "verification; 64 checksum kernels per allreduce cost about 40 %% "
