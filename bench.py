@@ -39,10 +39,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 
 
-def measured_traffic(key):
+def measured_traffic(key, workgroups=None):
     """HBM bytes per launch of a kernel from the committed counter runs, or
     None when the device sources that kernel is built from changed since
-    those counters were taken."""
+    those counters were taken, or when the counters were taken at another
+    grid size than the launch being reported (`workgroups`)."""
     import hashlib
     import json as _json
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -59,6 +60,8 @@ def measured_traffic(key):
         with open(os.path.join(src, name), "rb") as f:
             h.update(f.read())
     if h.hexdigest() != ent.get("sources_sha256"):
+        return None
+    if workgroups is not None and ent.get("workgroups") != workgroups:
         return None
     return ent["read_bytes"] + ent["write_bytes"]
 
@@ -923,7 +926,7 @@ def bench_batch(args):
     rates = pattern_rates(log_rows=True)
     bound = pattern_bound_us(msgs, rates)
     line["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("batch_10000"),
+                        "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("batch_10000", bk_wg),
                         "pattern_bound_us": bound,
                         "frac_of_pattern_bound": bound / bk_us,
                         "pattern_rates_TBps": {str(k): v for k, v in rates.items()},
@@ -1462,7 +1465,7 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="batch: pick the persistent batch schedule by a grid search first")
     ap.add_argument("--batch-tile", type=int, default=256)
-    ap.add_argument("--batch-max-wg", type=int, default=16384)
+    ap.add_argument("--batch-max-wg", type=int, default=32768)
     ap.add_argument("--batch-graph", type=int, default=0)
     ap.add_argument("--batch-nt", type=int, default=0,
                     help="batch kernel nontemporal accesses: 0 auto, 1 on, 2 off")

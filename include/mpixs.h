@@ -134,7 +134,7 @@ typedef struct {
     int32_t batch_arena_mib;  /* host-pinned memory for batch descriptors, MiB [64] */
     int32_t batch_tile;       /* tile of the batch kernel in 16-byte units: 256, 512, 1024,
                                  2048 or 4096 [256]; other values: MPIXS_ERR_ARG */
-    int32_t batch_max_wg;     /* workgroups of one batch kernel, at most [16384] */
+    int32_t batch_max_wg;     /* workgroups of one batch kernel, at most [32768] */
     int32_t batch_graph;      /* persistent batches: 1 replays the launching rank's part
                                  of a run (wait, batch kernel, signal) as one HIP graph,
                                  0 launches the three kernels one by one [0] */

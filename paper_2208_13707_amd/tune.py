@@ -20,7 +20,7 @@ from . import driver as D
 from . import mpixs as M
 
 TILES = (256, 1024, 4096)
-MAX_WG = (1024, 4096, 16384)
+MAX_WG = (4096, 16384, 32768, 65536)
 # (batch_graph, batch_sync): kernels one by one, graph replay, HIP events
 ORDERING = ((0, 0), (1, 0), (0, 1))
 
