@@ -887,6 +887,16 @@ def bench_batch(args):
                                 nmarks=2 * k)
             lat = step_latencies(mk, k)
         close_checked(sess)
+        if variant == "persistent" and args.trace:
+            # a traced session of its own: where each run's time goes
+            cfg.trace_events = 1 << 15
+            ts = D.Session(n, cfg)
+            run_checked(ts, ops(variant, 0, tagb), max_reqs=maxreq)
+            ts_sec = run_checked(ts, ops(variant, k, tagb), max_reqs=maxreq)[0]
+            tr = batch_trace_breakdown(M, ts.world, min(1 << 15, 96 * n * k))
+            close_checked(ts)
+            tr["ms_per_batch_traced"] = 1000 * ts_sec / k
+            log(f"[batch] persistent trace: {json.dumps(tr)}")
         res[variant] = npairs * k / sec
         log(f"[batch] {variant}: {res[variant]:.0f} msgs/s ({1000 * sec / k:.3f} ms per batch)")
     if args.only_grouped:
@@ -1235,6 +1245,53 @@ def trace_breakdown(M, world, cap):
     return out
 
 
+def batch_trace_breakdown(M, world, cap):
+    """Per-run step times of a persistent batch from the device trace.  Run e
+    leaves: every other rank's arrival (POST on its arrival word, value e),
+    the launching rank's wait seeing each arrival (MATCH, same word and
+    value), the signal after the batch kernel (DONE on the done word, value
+    e) and every other rank's wait seeing it (COMPLETE, done word, value e).
+    p50 / p99 over runs of (device microseconds):
+    period (DONE of e-1 to DONE of e), others' turn (DONE of e-1 to the last
+    POST of e: the other ranks' waits and next arrivals), launch wait (last
+    POST to last MATCH), kernel (last MATCH to DONE: the batch kernel and the
+    signal), and per other rank DONE -> COMPLETE and COMPLETE -> its next
+    POST."""
+    from collections import defaultdict
+    rc, total, ev = M.mpixs_world_trace(world, cap)
+    if rc:
+        raise RuntimeError(f"mpixs_world_trace: {M.errname(rc)}")
+    by = defaultdict(lambda: defaultdict(list))
+    for e in ev:
+        by[e.value][e.kind].append(e)
+    done = {v: k[M.TRACE_DONE][0].time_ns for v, k in by.items() if len(k[M.TRACE_DONE]) == 1}
+    cols = {k: [] for k in ("period_us", "others_turn_us", "launch_wait_us", "kernel_us",
+                            "done_to_complete_us", "complete_to_next_post_us")}
+    runs = 0
+    for v in sorted(done):
+        k = by[v]
+        if v - 1 not in done or not k[M.TRACE_POST] or not k[M.TRACE_MATCH]:
+            continue
+        runs += 1
+        last_post = max(e.time_ns for e in k[M.TRACE_POST])
+        last_match = max(e.time_ns for e in k[M.TRACE_MATCH])
+        cols["period_us"].append((done[v] - done[v - 1]) / 1e3)
+        cols["others_turn_us"].append((last_post - done[v - 1]) / 1e3)
+        cols["launch_wait_us"].append((last_match - last_post) / 1e3)
+        cols["kernel_us"].append((done[v] - last_match) / 1e3)
+        prev = by[v - 1]
+        comp = {e.stream: e.time_ns for e in prev[M.TRACE_COMPLETE]}
+        for e in prev[M.TRACE_COMPLETE]:
+            cols["done_to_complete_us"].append((e.time_ns - done[v - 1]) / 1e3)
+        for e in k[M.TRACE_POST]:
+            if e.stream in comp:
+                cols["complete_to_next_post_us"].append((e.time_ns - comp[e.stream]) / 1e3)
+    out = {"events": total, "runs": runs}
+    for name, xs in cols.items():
+        out[name] = {"p50": pct(xs, 50), "p99": pct(xs, 99)}
+    return out
+
+
 def bench_pingpong(args):
     import numpy as np
     import torch
@@ -1450,7 +1507,8 @@ def main():
     ap.add_argument("--serve-max", type=int, default=20000)
     ap.add_argument("--trace", action="store_true",
                     help="pingpong: also a traced pass; halo: trace the plain path's timed "
-                         "steps (per-message step times read from the device trace)")
+                         "steps (per-message step times read from the device trace); batch: "
+                         "a traced pass of the persistent batch (per-run step times)")
     ap.add_argument("--serve-sums", choices=["all", "rank0"], default="rank0",
                     help="serve: checksum rank 0's allreduce output (the harness's own "
                          "verification; 64 checksum kernels per allreduce cost about 40 %% "
