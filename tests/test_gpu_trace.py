@@ -10,8 +10,11 @@ decrease in that order, the copying stream records MATCH and DONE, and the
 first side's stream POST and COMPLETE.  Checked on the fused (4 KiB) and
 split (128 KiB) copy paths with 2 ranks, and on an allreduce: the non-last
 rank's arrival is a POST matched by the reducing rank, whose DONE the other
-rank completes.  A ring smaller than the events keeps the newest ones, and a
-world without tracing refuses the read.
+rank completes.  A persistent batch leaves, for run e, every other rank's
+arrival (POST, value e), the launching rank's wait seeing each (MATCH), one
+DONE after the batch kernel and every other rank's COMPLETE, in that order,
+and each rank's next arrival after its completion.  A ring smaller than the
+events keeps the newest ones, and a world without tracing refuses the read.
 """
 import sys
 from collections import defaultdict
@@ -126,6 +129,65 @@ def test_trace_ring_keeps_the_newest_events_and_is_off_by_default():
         _messages(D, M, sess, 2, 256, 0)
         rc, _, _ = M.mpixs_world_trace(sess.world, 10)
         assert M.errname(rc) == "ERR_ARG"
+    finally:
+        torch.cuda.synchronize()
+        sess.close()
+
+
+def test_trace_of_a_persistent_batch_orders_every_run():
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    n, runs, count = 4, 6, 1024
+    _say(f"trace: persistent ring batch, {n} ranks, {runs} runs of 4 KiB messages")
+    src = [torch.full((count,), 10 * (r + 1), dtype=torch.int32, device="cuda") for r in range(n)]
+    dst = [torch.zeros(count, dtype=torch.int32, device="cuda") for _ in range(n)]
+    torch.cuda.synchronize()
+    sess = D.Session(n, _cfg(trace_events=4096))
+    try:
+        ops = []
+        for r in range(n):
+            rows = [dict(kind=D.GROUP_START),
+                    dict(kind=D.ISEND, peer=(r + 1) % n, tag=7, count=count, datatype=M.INT32,
+                         buf=src[r].data_ptr(), req=0),
+                    dict(kind=D.IRECV, peer=(r - 1) % n, tag=7, count=count, datatype=M.INT32,
+                         buf=dst[r].data_ptr(), req=1),
+                    dict(kind=D.WAITALL, req=0, nreq=2),
+                    dict(kind=D.GROUP_INIT, req=2)]
+            rows += [dict(kind=D.BATCH_START, req=2)] * runs
+            ops.append(D.ops_array(rows))
+        rc, _, _ = sess.run(ops, max_reqs=3)
+        assert rc == 0, M.errname(rc)
+        for r in range(n):
+            assert torch.equal(dst[r], src[(r - 1) % n]), r
+        rc, total, ev = M.mpixs_world_trace(sess.world, 4096)
+        assert rc == 0 and total == len(ev)
+        by = defaultdict(lambda: defaultdict(list))
+        for e in ev:
+            by[e.value][e.kind].append(e)
+        done = sorted(v for v in by if by[v][M.TRACE_DONE])
+        assert done == list(range(1, runs + 1)), done
+        leader = by[1][M.TRACE_DONE][0].stream
+        for v in done:
+            k = by[v]
+            assert len(k[M.TRACE_DONE]) == 1
+            d = k[M.TRACE_DONE][0]
+            assert d.stream == leader
+            posts = {e.stream: e for e in k[M.TRACE_POST]}
+            matches = {e.counter: e for e in k[M.TRACE_MATCH]}
+            comps = {e.stream: e for e in k[M.TRACE_COMPLETE]}
+            # every other rank arrives once, is seen once, completes once
+            assert len(posts) == len(k[M.TRACE_POST]) == n - 1 and leader not in posts
+            assert len(matches) == len(k[M.TRACE_MATCH]) == n - 1
+            assert all(e.stream == leader for e in k[M.TRACE_MATCH])
+            assert set(comps) == set(posts) and len(k[M.TRACE_COMPLETE]) == n - 1
+            for s, p in posts.items():
+                m = matches[p.counter]                      # the same arrival word
+                assert p.time_ns <= m.time_ns <= d.time_ns <= comps[s].time_ns, (v, s)
+                assert comps[s].counter == d.counter       # the done word
+                if v > 1:
+                    assert by[v - 1][M.TRACE_COMPLETE] and \
+                        {e.stream: e for e in by[v - 1][M.TRACE_COMPLETE]}[s].time_ns <= p.time_ns
     finally:
         torch.cuda.synchronize()
         sess.close()
