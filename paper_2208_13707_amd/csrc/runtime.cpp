@@ -1551,8 +1551,15 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
     PlanScratch &z = sh->plan;
     size_t nops = 0;
     for (int q = 0; q < n; ++q) nops += rec->ops[size_t(q)].size();
+    // a matched group has at most nops / 2 channels, so the table is at most
+    // half full (and a group of unmatched operations, refused below, still
+    // finds a free slot for each of its at most nops channels)
     size_t cap = 16;
-    while (cap < 2 * nops) cap <<= 1;
+    int lg = 4;
+    while (cap < nops) {
+        cap <<= 1;
+        ++lg;
+    }
     constexpr uint64_t kEmpty = ~uint64_t(0);   // no channel key has bit 63 set
     z.table.assign(cap, PlanScratch::Slot{kEmpty, 0});
     z.chan_of.resize(nops);
@@ -1564,7 +1571,9 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
         for (GOp &op : rec->ops[size_t(q)]) {
             if (op.kind == 2) continue;   // allreduces: below
             const uint64_t key = op.kind == 0 ? chan_key(q, op.peer, op.tag) : chan_key(op.peer, q, op.tag);
-            size_t h = size_t((key * 0x9E3779B97F4A7C15ull) >> 17) & (cap - 1);
+            // Fibonacci hashing: the product's top lg bits (its low bits
+            // depend on the tag alone, which clusters every channel of a tag)
+            size_t h = size_t((key * 0x9E3779B97F4A7C15ull) >> (64 - lg));
             while (z.table[h].key != kEmpty && z.table[h].key != key) h = (h + 1) & (cap - 1);
             if (z.table[h].key == kEmpty) {
                 z.table[h] = PlanScratch::Slot{key, uint32_t(z.nsend.size())};
