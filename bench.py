@@ -364,12 +364,23 @@ def bench_halo(args):
         vt = make_vector(M, count, 3, 8, M.FLOAT32)
         payload = 12 * count
         res = {"count": count, "payload_bytes": payload}
+        fuse = args.fuse_max_bytes
+        if args.tune_plain:
+            # the plain path's fuse threshold chosen by timing this program
+            # (the halo has no blocking sends, so the eager threshold is moot)
+            from paper_2208_13707_amd import tune
+            best, rows = tune.tune_plain(
+                n, lambda k: [halo_ops(D, r, n, A[r], H[r], vt, k, 0, 0) for r in range(n)],
+                candidates=[(f, 0) for f in tune.FUSE], steps=max(10, min(steps, 50)), warm=5,
+                log=log)
+            fuse = best["fuse"]
+            res["tuned_plain"] = {"chosen": best, "grid": rows}
         # ---- enqueue path: warmup, then K timed steps
         pc = None
-        if args.fuse_max_bytes is not None or args.trace:
+        if fuse is not None or args.trace:
             pc = M.Config()
-            if args.fuse_max_bytes is not None:
-                pc.fuse_max_bytes = args.fuse_max_bytes
+            if fuse is not None:
+                pc.fuse_max_bytes = fuse
             if args.trace:
                 pc.trace_events = 1 << 16
         sess = D.Session(n, pc)
@@ -1534,6 +1545,8 @@ def main():
     ap.add_argument("--fuse-max-bytes", type=int, default=None,
                     help="halo: mpixs_config.fuse_max_bytes of the plain enqueue path")
     ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")
+    ap.add_argument("--tune-plain", action="store_true",
+                    help="halo: choose the plain path's fuse threshold by a grid search first")
     ap.add_argument("--bytes", type=int, default=None)
     ap.add_argument("--dtype", default="float32")
     ap.add_argument("--ranks", type=int, default=16)
