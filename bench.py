@@ -504,7 +504,7 @@ def bench_halo(args):
         ach = per_launch / (bk["avg_launch_us"] * 1e-6) / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS,
-                "traffic": measured_traffic(f"halo_batch_count{h['count']}"),
+                "traffic": measured_traffic(f"halo_batch_count{h['count']}", bk["workgroups"]),
                 "kernel": f"mpixs::k_batch<{args.batch_tile}, "
                           f"{'true' if batch_nt_used(args.batch_nt, bk['payload_bytes']) else 'false'}>",
                 "bytes_per_launch": per_launch,
