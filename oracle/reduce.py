@@ -13,7 +13,13 @@ over the ranks in order 0..N-1, with (+) the MPI operation:
 * floats (float32, float64): IEEE-754 binary arithmetic in the buffer's own
   precision, round to nearest even, one rounding per operation (numpy applies
   each elementwise operation separately, so no fused multiply-add occurs);
-* min / max keep the earlier operand when the two compare equal.
+* min / max keep the earlier operand when the two compare equal, and also
+  when either is a NaN: IEEE-754 makes every ordered comparison with a NaN
+  false, so a NaN accumulator stays (its exact bits) and a NaN arriving
+  later is passed over;
+* sum / prod with a NaN operand give a NaN (IEEE-754); which NaN (sign and
+  payload bits) is not fixed by the standard, so only "is a NaN" is
+  compared there.
 """
 from __future__ import annotations
 

@@ -126,3 +126,33 @@ def test_planted_reverse_order_is_caught(monkeypatch):
     for x in (2**-24, 2**-24):
         acc = _f32(acc + x)
     assert float(red.fold("sum", ins)[0]) != acc
+
+
+def _nan32(bits):
+    return np.array([bits], dtype=np.uint32).view(np.float32)[0]
+
+
+@pytest.mark.parametrize("op", ["min", "max"])
+def test_min_max_with_nan_keep_the_accumulator(op):
+    """IEEE-754: an ordered comparison with a NaN is false.  So the fold's
+    "x beats acc" never fires when either is a NaN: rank 0's NaN (payload and
+    sign included) survives the fold, and a later rank's NaN is skipped."""
+    qn = _nan32(0xFFC01234)                   # negative quiet NaN with a payload
+    first = [np.array([qn, qn], np.float32), np.array([1.0, -5.0], np.float32),
+             np.array([-2.0, 7.0], np.float32)]
+    got = red.fold(op, first)
+    assert got.view(np.uint32).tolist() == [0xFFC01234, 0xFFC01234]
+    later = [np.array([1.0, 3.0], np.float32), np.array([qn, qn], np.float32),
+             np.array([0.5, 4.0], np.float32)]
+    got = red.fold(op, later)
+    want = [0.5, 3.0] if op == "min" else [1.0, 4.0]
+    assert got.tolist() == want and not np.any(np.isnan(got))
+
+
+@pytest.mark.parametrize("op", ["sum", "prod"])
+@pytest.mark.parametrize("pos", [0, 1, 2])
+def test_sum_prod_with_nan_give_nan(op, pos):
+    ins = [np.array([2.0, 3.0], np.float64) for _ in range(3)]
+    ins[pos] = np.array([np.nan, 3.0], np.float64)
+    got = red.fold(op, ins)
+    assert np.isnan(got[0]) and got[1] == (9.0 if op == "sum" else 27.0)
