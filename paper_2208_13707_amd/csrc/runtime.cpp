@@ -1528,6 +1528,21 @@ int arena_alloc(World *w, size_t bytes, size_t *off, int *flag) {
 // tag t), plan each copy, and cut the group into tiles: one descriptor per
 // message and, per workgroup, the (message, tile) it starts at.  Fills
 // everything of `a` except the descriptor / start pointers.
+// Descriptor chunks of a group's plan, and the size from which the waiting
+// ranks help with them (below it the wake-ups cost more than they save).
+constexpr size_t kPlanChunk = 256;
+constexpr size_t kPlanHelpPairs = 2048;
+
+// Take chunks of the group's published planning job until none is left.
+void plan_help(GroupRec *rec) {
+    for (;;) {
+        const size_t c = rec->help_next.fetch_add(1, std::memory_order_relaxed);
+        if (c >= rec->help_chunks) return;
+        rec->help_fn(c);
+        rec->help_done.fetch_add(1, std::memory_order_release);
+    }
+}
+
 int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launcher, BatchArgs &a,
                uint64_t *bytes) {
     struct PlanTimer {   // host time of this plan, for the diagnostics counters
@@ -1633,14 +1648,19 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
     descs.resize(npairs);
     uint64_t total_tiles = 0;
     *bytes = 0;
-    for (size_t c = 0; c < nch; ++c) {
-        const int tag = z.ctag[c];
-        for (size_t i = z.first[c]; i < z.first[c + 1]; ++i) {
+    // descriptors in chunks of pairs; each chunk's tiles and bytes summed
+    // apart (a channel's pairs share its tag, which every send carries)
+    const size_t nchunks = (npairs + kPlanChunk - 1) / kPlanChunk;
+    z.part.assign(2 * nchunks, 0);
+    auto chunk = [&descs, &z, tile, npairs](size_t c) {
+        uint64_t tiles = 0, nbytes = 0;
+        const size_t end = std::min(npairs, (c + 1) * kPlanChunk);
+        for (size_t i = c * kPlanChunk; i < end; ++i) {
             GOp *S = z.s_of[i];
             GOp *R = z.r_of[i];
             BatchDesc &d = descs[i];
             std::memset(&d, 0, sizeof(d));
-            d.st = match_status(S->side, R->side, tag);
+            d.st = match_status(S->side, R->side, S->tag);
             int wsz = 16;
             uint64_t units = 0;
             plan_copy(S->side, R->side, d.st.count_bytes, &d.src, &d.dst, &wsz, &units, &d.tail);
@@ -1651,9 +1671,27 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
             d.status = R->status;
             d.rstream = R->side.st->dev;
             if (R->req) R->req->st = d.st;
-            total_tiles += d.ntiles;
-            *bytes += uint64_t(d.st.count_bytes);
+            tiles += d.ntiles;
+            nbytes += uint64_t(d.st.count_bytes);
         }
+        z.part[2 * c] = tiles;
+        z.part[2 * c + 1] = nbytes;
+    };
+    if (n > 1 && npairs >= kPlanHelpPairs) {
+        // the other ranks wait for this launch on the host: let them take
+        // chunks too (those asleep are woken through the launch's key)
+        rec->help_fn = chunk;
+        rec->help_chunks = nchunks;
+        rec->help_on.store(1, std::memory_order_release);
+        host_notify(&rec->launched);
+        plan_help(rec);
+        while (rec->help_done.load(std::memory_order_acquire) < nchunks) std::this_thread::yield();
+    } else {
+        for (size_t c = 0; c < nchunks; ++c) chunk(c);
+    }
+    for (size_t c = 0; c < nchunks; ++c) {
+        total_tiles += z.part[2 * c];
+        *bytes += z.part[2 * c + 1];
     }
     std::vector<BatchStart> &starts = z.starts;
     std::memset(&a, 0, sizeof(a));
@@ -2821,7 +2859,18 @@ int group_finish(mpixs_comm c, int kind, BatchPlan **plan) {
             rec->posted.fetch_add(1, std::memory_order_release);
             host_notify(&rec->posted);
         }
-        if (!rc) rc = host_wait(w, &rec->launched, [&] { return rec->launched.load(std::memory_order_acquire) != 0; });
+        // wait for the launch, taking chunks of the plan when the planning
+        // rank publishes them
+        auto ready = [&] {
+            return rec->launched.load(std::memory_order_acquire) != 0 ||
+                   (rec->help_on.load(std::memory_order_acquire) != 0 &&
+                    rec->help_next.load(std::memory_order_relaxed) < rec->help_chunks);
+        };
+        while (!rc) {
+            rc = host_wait(w, &rec->launched, ready);
+            if (rc || rec->launched.load(std::memory_order_acquire) != 0) break;
+            plan_help(rec);
+        }
         if (!rc) rc = rec->error;
         if (!rc && kind == 1) {
             WaitArgs a = wait_one(sh->d_grp + 16 * n, g + 1);

@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstdint>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -225,6 +226,14 @@ struct GroupRec {
     std::atomic<int> posted{0};         // one-shot: arrival kernels the other ranks have enqueued
     int error = 0;
     std::atomic<int> refs{0};
+    // Planning help: the planning rank may split the descriptor pass of a
+    // large group into chunks; the other ranks, waiting for the launch,
+    // take chunks until none is left (help_fn is set before help_on).
+    std::function<void(size_t)> help_fn;
+    size_t help_chunks = 0;
+    std::atomic<int> help_on{0};
+    std::atomic<size_t> help_next{0};
+    std::atomic<size_t> help_done{0};
 };
 
 // A persistent batch: a group planned once, run by every start.  Device
@@ -317,6 +326,7 @@ struct PlanScratch {
     std::vector<GOp *> s_of, r_of;      // pair i: its send and its receive
     std::vector<BatchDesc> descs;
     std::vector<BatchStart> starts;
+    std::vector<uint64_t> part;         // per descriptor chunk: tiles, bytes
     std::vector<RedPlan> reds;         // the group's allreduces, in order
     MultiRedPlan mred;                 // the same, merged when allowed
 };

@@ -1,5 +1,6 @@
 // Threaded patterns of the library's host side, run against the recording
-// HIP stand-in (hipstub.cpp) under AddressSanitizer or ThreadSanitizer:
+// HIP stand-in (hipstub.cpp) under AddressSanitizer or ThreadSanitizer (large
+// groups whose waiting ranks help plan them among them):
 // every call's return code is checked, nothing moves data.  Patterns: a
 // 32-rank uneven batch through the plain enqueue path, 16-rank enqueued
 // allreduces, one-shot groups with allreduces, persistent batches, ordered-
@@ -331,6 +332,62 @@ void create_free_cycles(int cycles) {
     if (mpixs_world_free(&w)) g_fail.store(1);
 }
 
+// Groups large enough that the waiting ranks help plan them: 8 ranks, each
+// sending 400 messages (64 bytes, a vector type on every third) to random
+// peers and receiving its own, as one-shot groups and one persistent batch.
+void large_groups(int reps) {
+    const int n = 8, per = 400;
+    mpixs_world w;
+    if (mpixs_world_create(n, nullptr, &w)) {
+        g_fail.store(1);
+        return;
+    }
+    auto R = setup(w, n);
+    mpixs_datatype vt;
+    CHECK(mpixs_type_vector(4, 2, 4, MPIXS_INT32, &vt));
+    CHECK(mpixs_type_commit(&vt));
+    // message i: from i % n to dest[i], tag i / n % 64
+    std::vector<int> dest(size_t(n) * per);
+    std::mt19937 g{7};
+    for (size_t i = 0; i < dest.size(); ++i) dest[i] = int((i % n + 1 + g() % (n - 1)) % n);
+    std::vector<char *> sb(static_cast<size_t>(n)), rb(static_cast<size_t>(n));
+    for (int r = 0; r < n; ++r) {
+        sb[size_t(r)] = dev_alloc(size_t(per) * 64);
+        rb[size_t(r)] = dev_alloc(dest.size() * 64);
+    }
+    auto record = [&](int r) -> int {
+        std::vector<mpixs_request> q;
+        int rc = mpixs_group_start(R[size_t(r)].comm);
+        for (size_t i = 0; !rc && i < dest.size(); ++i) {
+            const int src = int(i % n), tag = int(i / n % 64);
+            const bool vec = i % 3 == 0;
+            mpixs_request x = nullptr;
+            if (src == r)
+                rc = mpixs_isend_enqueue(sb[size_t(r)] + (i / n) * 64, vec ? 1 : 16, vec ? vt : MPIXS_INT32,
+                                         dest[i], tag, R[size_t(r)].comm, &x);
+            else if (dest[i] == r)
+                rc = mpixs_irecv_enqueue(rb[size_t(r)] + i * 64, vec ? 1 : 16, vec ? vt : MPIXS_INT32,
+                                         src, tag, R[size_t(r)].comm, &x);
+            if (x) q.push_back(x);
+        }
+        if (!rc) rc = mpixs_waitall_enqueue(int(q.size()), q.data(), nullptr);
+        return rc;
+    };
+    run_threads(n, [&](int r) {
+        for (int k = 0; k < reps; ++k) {
+            CHECK(record(r));
+            CHECK(mpixs_group_end(R[size_t(r)].comm));
+        }
+        mpixs_batch b;
+        CHECK(record(r));
+        CHECK(mpixs_group_end_init(R[size_t(r)].comm, &b));
+        for (int k = 0; k < reps; ++k) CHECK(mpixs_batch_start_enqueue(b));
+        CHECK(mpixs_batch_free(&b));
+    });
+    CHECK(mpixs_type_free(&vt));
+    teardown(w, R);
+}
+
 void types_everywhere(int reps) {
     run_threads(8, [&](int t) {
         std::mt19937 g{static_cast<uint32_t>(t)};
@@ -360,6 +417,7 @@ int main(int argc, char **argv) {
         {"plain batch, 32 ranks", [&] { plain_batch(3 * scale); }},
         {"enqueued allreduces, 16 ranks", [&] { allreduces(60 * scale); }},
         {"groups and persistent batches, 8 ranks", [&] { groups_and_batches(20 * scale); }},
+        {"large groups planned with help, 8 ranks", [&] { large_groups(4 * scale); }},
         {"wildcard receives, 8 ranks", [&] { wildcards(30 * scale); }},
         {"host-synchronised calls, 4 ranks", [&] { host_synced(30 * scale); }},
         {"stream and communicator cycles", [&] { create_free_cycles(300 * scale); }},
