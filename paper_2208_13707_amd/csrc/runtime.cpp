@@ -1543,8 +1543,14 @@ void plan_help(GroupRec *rec) {
     }
 }
 
+// Where a plan's descriptors and workgroup starts are written: given the
+// number of pairs and a bound on the starts, the caller provides both
+// arrays (or fails with an error code).
+using PlanPlace = std::function<int(size_t npairs, size_t max_starts, BatchDesc **descs,
+                                    BatchStart **starts)>;
+
 int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launcher, BatchArgs &a,
-               uint64_t *bytes) {
+               uint64_t *bytes, const PlanPlace *place = nullptr) {
     struct PlanTimer {   // host time of this plan, for the diagnostics counters
         World *w;
         std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -1644,21 +1650,32 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
         plan_multi_red(z.reds, z.mred);
     }
     const uint32_t tile = uint32_t(w->cfg.batch_tile);
-    std::vector<BatchDesc> &descs = z.descs;
-    descs.resize(npairs);
+    // descriptors and starts go where the caller places them (a launch's
+    // pinned arena range, written once), else into the plan's own arrays
+    BatchDesc *D = nullptr;
+    BatchStart *SB = nullptr;
+    z.nstarts = 0;
+    if (place && npairs > 0) {
+        const int prc = (*place)(npairs, size_t(w->cfg.batch_max_wg), &D, &SB);
+        if (prc) return prc;
+        z.descs.clear();
+    } else {
+        z.descs.resize(npairs);
+        D = z.descs.data();
+    }
     uint64_t total_tiles = 0;
     *bytes = 0;
     // descriptors in chunks of pairs; each chunk's tiles and bytes summed
     // apart (a channel's pairs share its tag, which every send carries)
     const size_t nchunks = (npairs + kPlanChunk - 1) / kPlanChunk;
     z.part.assign(2 * nchunks, 0);
-    auto chunk = [&descs, &z, tile, npairs](size_t c) {
+    auto chunk = [D, &z, tile, npairs](size_t c) {
         uint64_t tiles = 0, nbytes = 0;
         const size_t end = std::min(npairs, (c + 1) * kPlanChunk);
         for (size_t i = c * kPlanChunk; i < end; ++i) {
             GOp *S = z.s_of[i];
             GOp *R = z.r_of[i];
-            BatchDesc &d = descs[i];
+            BatchDesc &d = D[i];
             std::memset(&d, 0, sizeof(d));
             d.st = match_status(S->side, R->side, S->tag);
             int wsz = 16;
@@ -1693,27 +1710,32 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
         total_tiles += z.part[2 * c];
         *bytes += z.part[2 * c + 1];
     }
-    std::vector<BatchStart> &starts = z.starts;
     std::memset(&a, 0, sizeof(a));
     a.tile = tile;
-    starts.clear();
-    if (descs.empty()) return MPIXS_SUCCESS;
+    z.starts.clear();
+    if (npairs == 0) return MPIXS_SUCCESS;
     const uint64_t nwg = std::min<uint64_t>(total_tiles, uint64_t(w->cfg.batch_max_wg));
     const uint64_t base = total_tiles / nwg;
     const uint64_t extra = total_tiles % nwg;
-    starts.resize(size_t(nwg));
+    if (!SB) {
+        z.starts.resize(size_t(nwg));
+        SB = z.starts.data();
+    }
     uint32_t m = 0;
     uint64_t first_of_m = 0;   // global index of message m's first tile
     for (uint64_t b = 0; b < nwg; ++b) {
         const uint64_t t = b * base + std::min(b, extra);
-        while (first_of_m + descs[m].ntiles <= t) {
-            first_of_m += descs[m].ntiles;
+        while (first_of_m + D[m].ntiles <= t) {
+            first_of_m += D[m].ntiles;
             ++m;
         }
-        starts[size_t(b)].msg = m;
-        starts[size_t(b)].tile = uint32_t(t - first_of_m);
+        SB[b].msg = m;
+        SB[b].tile = uint32_t(t - first_of_m);
     }
-    a.nmsg = uint32_t(descs.size());
+    z.nstarts = size_t(nwg);
+    a.nmsg = uint32_t(npairs);
+    a.desc = D;
+    a.start = SB;
     a.base = base;
     a.extra = uint32_t(extra);
     a.tile = tile;
@@ -1728,8 +1750,6 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
 int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st, uint64_t g) {
     const int n = sh->size;
     std::lock_guard<std::mutex> plan_lock(sh->plan_mu);
-    const std::vector<BatchDesc> &descs = sh->plan.descs;
-    const std::vector<BatchStart> &starts = sh->plan.starts;
     BatchArgs a{};
     uint64_t bytes = 0;
     // producer first: the other ranks enqueue their arrival kernels outside
@@ -1738,37 +1758,35 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
     // threads slow a concurrent plan) and as fast on small ones.
     int rc = host_wait(w, &rec->posted, [&] { return rec->posted.load(std::memory_order_acquire) >= n - 1; });
     if (rc) return rc;
-    rc = plan_group(w, sh, rec, n, st, a, &bytes);
-    if (rc) return rc;
-    uint64_t *arrive = sh->d_grp;
-    uint64_t *done = sh->d_grp + 16 * n;
-    if (n > 1) {
-        WaitArgs wa;
-        std::memset(&wa, 0, sizeof(wa));
-        for (int q = 0; q < n; ++q) {
-            if (q == me) continue;
-            wa.ptr[wa.n] = arrive + 16 * q;
-            wa.target[wa.n] = g + 1;
-            wa.n++;
-        }
-        rc = do_wait(w, st, wa, MPIXS_TRACE_MATCH);
-        if (rc) return rc;
-    }
-    int flag = -1;
-    // arena range: batch descriptors, workgroup starts, merged-reduce
-    // descriptors and pointer table, each 256-byte aligned
+    // arena range: batch descriptors, workgroup starts (room for as many as a
+    // plan may have), merged-reduce descriptors and pointer table, each
+    // 256-byte aligned; the plan writes descriptors and starts in place
     const MultiRedPlan &mr = sh->plan.mred;
-    const size_t dbytes = descs.size() * sizeof(BatchDesc);
-    const size_t sbytes = starts.size() * sizeof(BatchStart);
-    const size_t bbytes = descs.empty() ? 0 : ((dbytes + 255) & ~size_t(255)) + ((sbytes + 255) & ~size_t(255));
-    const size_t mdbytes = mr.on ? (mr.desc.size() * sizeof(MultiRedDesc) + 255) & ~size_t(255) : 0;
-    const size_t mpbytes = mr.on ? mr.ptrs.size() * sizeof(void *) : 0;
+    int flag = -1;
     uint8_t *h = nullptr;
-    if (bbytes + mdbytes + mpbytes > 0) {
+    size_t bbytes = 0, mdbytes = 0, mpbytes = 0;
+    auto reserve = [&](size_t front) -> int {
+        bbytes = front;
+        mdbytes = mr.on ? (mr.desc.size() * sizeof(MultiRedDesc) + 255) & ~size_t(255) : 0;
+        mpbytes = mr.on ? mr.ptrs.size() * sizeof(void *) : 0;
         size_t off = 0;
-        rc = arena_alloc(w, bbytes + mdbytes + mpbytes, &off, &flag);
+        const int r = arena_alloc(w, bbytes + mdbytes + mpbytes, &off, &flag);
+        if (!r) h = reinterpret_cast<uint8_t *>(w->h_arena + off);
+        return r;
+    };
+    const PlanPlace place = [&](size_t npairs, size_t max_starts, BatchDesc **d, BatchStart **s) -> int {
+        const size_t dal = (npairs * sizeof(BatchDesc) + 255) & ~size_t(255);
+        const int r = reserve(dal + ((max_starts * sizeof(BatchStart) + 255) & ~size_t(255)));
+        if (r) return r;
+        *d = reinterpret_cast<BatchDesc *>(h);
+        *s = reinterpret_cast<BatchStart *>(h + dal);
+        return MPIXS_SUCCESS;
+    };
+    rc = plan_group(w, sh, rec, n, st, a, &bytes, &place);
+    if (rc) return rc;   // the plan fails only before it places anything
+    if (!h && mr.on) {
+        rc = reserve(0);
         if (rc) return rc;
-        h = reinterpret_cast<uint8_t *>(w->h_arena + off);
     }
     // A failed launch before anything that reads the arena range was
     // enqueued hands the range back at once (the ring frees in order, so a
@@ -1782,17 +1800,26 @@ int group_launch(World *w, CommShared *sh, GroupRec *rec, int me, StreamObj *st,
         if (range_read) mpixs_world_abort(reinterpret_cast<mpixs_world>(w));
         return code;
     };
-    if (!descs.empty()) {
-        BatchDesc *hd = reinterpret_cast<BatchDesc *>(h);
-        BatchStart *hs = reinterpret_cast<BatchStart *>(h + ((dbytes + 255) & ~size_t(255)));
-        std::memcpy(hd, descs.data(), dbytes);
-        std::memcpy(hs, starts.data(), sbytes);
-        a.desc = hd;
-        a.start = hs;
+    uint64_t *arrive = sh->d_grp;
+    uint64_t *done = sh->d_grp + 16 * n;
+    if (n > 1) {
+        WaitArgs wa;
+        std::memset(&wa, 0, sizeof(wa));
+        for (int q = 0; q < n; ++q) {
+            if (q == me) continue;
+            wa.ptr[wa.n] = arrive + 16 * q;
+            wa.target[wa.n] = g + 1;
+            wa.n++;
+        }
+        rc = do_wait(w, st, wa, MPIXS_TRACE_MATCH);
+        if (rc) return fail(rc);
+    }
+    const size_t nwg = sh->plan.nstarts;
+    if (nwg > 0) {
         a.me = st->dev;
         hipEvent_t e0 = nullptr;
         if (profile_on(w)) prof_begin(w, st->hs, &e0);
-        rc = gpu_err(launch_batch(st->hs, a, int(starts.size())));
+        rc = gpu_err(launch_batch(st->hs, a, int(nwg)));
         if (profile_on(w)) prof_end(w, st->hs, e0, 0);
         if (rc) return fail(rc);
         range_read = true;

@@ -327,6 +327,7 @@ struct PlanScratch {
     std::vector<BatchDesc> descs;
     std::vector<BatchStart> starts;
     std::vector<uint64_t> part;         // per descriptor chunk: tiles, bytes
+    size_t nstarts = 0;                 // workgroup starts of the last plan
     std::vector<RedPlan> reds;         // the group's allreduces, in order
     MultiRedPlan mred;                 // the same, merged when allowed
 };
