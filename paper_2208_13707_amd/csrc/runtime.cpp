@@ -1523,11 +1523,6 @@ int arena_alloc(World *w, size_t bytes, size_t *off, int *flag) {
     }
 }
 
-// Match every rank's recorded operations of a group (the i-th grouped send
-// of s to d with tag t pairs with the i-th grouped receive of d from s with
-// tag t), plan each copy, and cut the group into tiles: one descriptor per
-// message and, per workgroup, the (message, tile) it starts at.  Fills
-// everything of `a` except the descriptor / start pointers.
 // Descriptor chunks of a group's plan, and the size from which the waiting
 // ranks help with them (below it the wake-ups cost more than they save).
 constexpr size_t kPlanChunk = 256;
@@ -1549,6 +1544,12 @@ void plan_help(GroupRec *rec) {
 using PlanPlace = std::function<int(size_t npairs, size_t max_starts, BatchDesc **descs,
                                     BatchStart **starts)>;
 
+// Match every rank's recorded operations of a group (the i-th grouped send
+// of s to d with tag t pairs with the i-th grouped receive of d from s with
+// tag t), plan each copy, and cut the group into tiles: one descriptor per
+// message and, per workgroup, the (message, tile) it starts at, written
+// where `place` puts them (else into the plan's own arrays).  Fills `a`,
+// its descriptor / start pointers aimed at where they were written.
 int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launcher, BatchArgs &a,
                uint64_t *bytes, const PlanPlace *place = nullptr) {
     struct PlanTimer {   // host time of this plan, for the diagnostics counters
