@@ -131,7 +131,10 @@ typedef struct {
     int32_t max_channels;     /* device matching-table capacity in channels [1<<20] */
     int32_t profile;          /* 1: time copy and reduce kernels with HIP events */
     int32_t max_collectives;  /* device collective-slot capacity [4096] */
-    int32_t batch_arena_mib;  /* host-pinned memory for batch descriptors, MiB [64] */
+    int32_t batch_arena_mib;  /* host-pinned memory for batch descriptors, MiB [64]; a
+                                 one-shot group in flight holds 224 bytes per message
+                                 and 8 per batch_max_wg workgroup (a larger group
+                                 fails with MPIXS_ERR_NOMEM) */
     int32_t batch_tile;       /* tile of the batch kernel in 16-byte units: 256, 512, 1024,
                                  2048 or 4096 [256]; other values: MPIXS_ERR_ARG */
     int32_t batch_max_wg;     /* workgroups of one batch kernel, at most [32768] */
