@@ -230,6 +230,15 @@ def test_grouped_batch_config_size():
     check(C.batch(npairs=10000, nranks=32, grouped=True))
 
 
+@pytest.mark.parametrize("npairs,nranks,runs", [(2048, 2, 0), (2305, 3, 0), (2305, 2, 2)])
+def test_grouped_batch_planned_with_help(npairs, nranks, runs):
+    """Groups from 2,048 pairs are planned in chunks of 256 pairs that the
+    ranks waiting for the launch help with: the threshold itself with one
+    helper, a ragged last chunk, and a persistent batch."""
+    check(C.batch(npairs=npairs, nranks=nranks, max_bytes=4096, grouped=runs == 0, runs=runs),
+          name=f"batch {npairs} pairs over {nranks} ranks ({'persistent' if runs else 'one group'})")
+
+
 def test_group_head_to_head_and_unmatched():
     b = [{"s": as_bytes(np.array([10 + q, 20 + q], np.int32)), "r": np.full(8, 0xEE, np.uint8)}
          for q in range(2)]
