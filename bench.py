@@ -1454,7 +1454,61 @@ def bench_copy(args):
                             if nbytes == 1 << 30 else None,
                             "kernel": "k_copy<16,CONTIG,CONTIG>", "bytes_per_launch": 2 * nbytes,
                             "avg_launch_us": avg_us, "launches_timed": int(st.timed_copy)}
+    if args.sweep:
+        line["sweep"] = copy_sweep(args)
     return line
+
+
+def copy_sweep(args):
+    """Contiguous 2-rank send / recv from 1 MiB to 1 GiB: the enqueue path's
+    GB/s (blocking calls, about 4 GiB moved per size), its copy kernel's own
+    time (HIP events around each launch, a run of its own) and the
+    host-synchronised path's GB/s, as algorithmic bytes (2 x the message)
+    and fractions of 8 TB/s; the sizes from 512 MiB on exceed the 256 MB
+    Infinity Cache."""
+    import torch
+    from paper_2208_13707_amd import driver as D
+    from paper_2208_13707_amd import mpixs as M
+    rows = []
+    for nbytes in [1 << 20, 4 << 20, 16 << 20, 64 << 20, 256 << 20, 512 << 20, 1 << 30]:
+        src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        steps = max(4, min(2000, (4 << 30) // nbytes))
+
+        def ops(k):
+            r0 = [dict(kind=D.SEND, peer=1, tag=7, count=nbytes, datatype=M.UINT8,
+                       buf=src.data_ptr()) for _ in range(k)]
+            r1 = [dict(kind=D.RECV, peer=0, tag=7, count=nbytes, datatype=M.UINT8,
+                       buf=dst.data_ptr()) for _ in range(k)]
+            return [D.ops_array(r0), D.ops_array(r1)]
+
+        row = {"bytes": nbytes, "steps": steps}
+        for mode, key in ((0, "enqueue_GBps"), (1, "host_synced_GBps")):
+            sess = D.Session(2)
+            run_checked(sess, ops(2), mode=mode)
+            sec, _ = run_checked(sess, ops(steps), mode=mode)
+            close_checked(sess)
+            row[key] = 2 * nbytes * steps / sec / 1e9
+        cfg = M.Config()
+        cfg.profile = 1
+        sess = D.Session(2, cfg)
+        run_checked(sess, ops(min(steps, 200)))
+        torch.cuda.synchronize()
+        st = sess.stats()
+        close_checked(sess)
+        assert torch.equal(src, dst)
+        kus = 1000 * st.copy_ms / max(1, st.timed_copy)
+        row["kernel_us"] = kus
+        row["kernel_GBps"] = 2 * nbytes / (kus * 1e-6) / 1e9
+        row["kernel_frac"] = row["kernel_GBps"] / HBM_PEAK_GBS
+        row["enqueue_frac"] = row["enqueue_GBps"] / HBM_PEAK_GBS
+        log(f"[copy] {nbytes >> 20:5d} MiB: enqueue {row['enqueue_GBps']:7.0f} GB/s "
+            f"({row['enqueue_frac']:.2f}), kernel {kus:8.1f} us ({row['kernel_frac']:.2f}), "
+            f"host-synced {row['host_synced_GBps']:7.0f} GB/s")
+        rows.append(row)
+        del src, dst
+    return rows
 
 
 def extra_configs(args):
@@ -1551,7 +1605,8 @@ def main():
     ap.add_argument("--count", type=int, default=43690)
     ap.add_argument("--fuse-max-bytes", type=int, default=None,
                     help="halo: mpixs_config.fuse_max_bytes of the plain enqueue path")
-    ap.add_argument("--sweep", action="store_true", help="halo: also the other four counts")
+    ap.add_argument("--sweep", action="store_true",
+                    help="halo: also the other four counts; copy: message sizes 1 MiB .. 1 GiB")
     ap.add_argument("--tune-plain", action="store_true",
                     help="halo: choose the plain path's fuse threshold by a grid search first")
     ap.add_argument("--bytes", type=int, default=None)
