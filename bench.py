@@ -521,6 +521,10 @@ def bench_halo(args):
     log(f"[halo] 1 GiB copy kernel: {cp:.0f} GB/s; halo kernel at "
         f"{roof['frac_of_achievable']:.2f} of it")
     gbps_pay = value * h["payload_bytes"] / 1e9
+    # line-granular bytes: a message's extent in whole 128-byte lines, read
+    # on one side and written on the other
+    extent = (h["count"] - 1) * 32 + 12
+    line_bytes = 2 * (-(-extent // 128) * 128)
     hs = h.get("host_synced_msgs_per_s")
     line = {
         "metric": "enqueued msgs/s + GB/s (frac of HBM peak) vs host-synced path; p50/p99 latency",
@@ -541,6 +545,7 @@ def bench_halo(args):
                    "variant": vname},
         "gbps_payload": gbps_pay,
         "gbps_algorithmic": 2 * gbps_pay,
+        "gbps_line": value * line_bytes / 1e9,
         "hbm_frac": 2 * gbps_pay / HBM_PEAK_GBS,
         "plain_enqueue": {"value": h["msgs_per_s"], "ms_per_step": h["ms_per_step"],
                           "enqueue_ms_per_step": h["enqueue_ms_per_step"],
