@@ -980,6 +980,7 @@ def bench_batch(args):
                 raise AssertionError(f"rank {r}: batch result differs from the oracle")
         line["cpu_baseline"] = {"value": runs * npairs / dt, "unit": "msgs/s", "cores": 1,
                                 "kind": "oracle",
+                                "gbps_algorithmic": runs * 2 * bk_payload / dt / 1e9,
                                 "sample": f"the whole batch ({npairs} messages) {runs} times, "
                                           f"{dt:.1f} s"}
     return line
