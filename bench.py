@@ -1547,6 +1547,11 @@ def extra_configs(args):
         "persistent_enqueue": h["persistent_enqueue"],
         "host_synced": h["host_synced"],
         "plain_vs_host_synced": h["host_synced"]["plain_speedup"],
+        # the plain path's rates as payload, algorithmic (2 x payload) and
+        # line-granular bytes (the halo line's per-message ratios)
+        "gbps_payload": h["plain_enqueue"]["value"] * h["config"]["payload_bytes"] / 1e9,
+        "gbps_algorithmic": 2 * h["plain_enqueue"]["value"] * h["config"]["payload_bytes"] / 1e9,
+        "gbps_line": h["plain_enqueue"]["value"] * h["gbps_line"] / h["value"] if h["value"] else None,
         # the plain path's data kernel: one message's typemap copy
         "roofline": vector_copy_roofline(43690, 100),
         "roofline_batch_kernel": h["roofline"]}
