@@ -1587,7 +1587,6 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
     z.chan_of.resize(nops);
     z.nsend.clear();
     z.nrecv.clear();
-    z.ctag.clear();
     size_t k = 0;
     for (int q = 0; q < n; ++q)
         for (GOp &op : rec->ops[size_t(q)]) {
@@ -1601,7 +1600,6 @@ int plan_group(World *w, CommShared *sh, GroupRec *rec, int n, StreamObj *launch
                 z.table[h] = PlanScratch::Slot{key, uint32_t(z.nsend.size())};
                 z.nsend.push_back(0);
                 z.nrecv.push_back(0);
-                z.ctag.push_back(op.tag);
             }
             const uint32_t c = z.table[h].chan;
             z.chan_of[k++] = c;

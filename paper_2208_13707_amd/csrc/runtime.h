@@ -322,7 +322,6 @@ struct PlanScratch {
     std::vector<Slot> table;            // open addressing: channel key -> channel
     std::vector<uint32_t> chan_of;      // channel of every grouped operation
     std::vector<uint32_t> nsend, nrecv, first, fill_s, fill_r;
-    std::vector<int> ctag;
     std::vector<GOp *> s_of, r_of;      // pair i: its send and its receive
     std::vector<BatchDesc> descs;
     std::vector<BatchStart> starts;
